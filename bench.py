@@ -1,0 +1,167 @@
+#!/usr/bin/env python3
+"""Benchmark: energy+gradient evaluations per second of the batched ADADELTA
+local search on one MI355X.
+
+Workload (one "step"): 3000 individuals of one synthetic 48-atom, 10-torsion
+ligand on 64^3 x 10 FP32 grid maps, 300 ADADELTA iterations each (rho 0.8,
+eps 1e-2) plus the final evaluation: 903,000 scoring evaluations in one
+persistent launch. Every step starts from the same seeded genotypes (one
+resident copy of the state per step, prepared before timing).
+
+Prints one JSON line with the throughput of the best reduction variant, the
+per-variant throughputs (the plain wave-shuffle variant is the baseline), the
+roofline object of the local-search kernel, and the FP64 oracle timed on the
+host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "energy+gradient evals/sec on 1 MI355X vs plain FP32; p50/p99 dock latency"
+PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X FP32 vector peak (packed FMA)
+
+# Algorithmic FP32 operations of one scoring evaluation, counted from the
+# formulas the method computes (an FMA counts 2, a transcendental or a
+# division 1; compares and selects 0):
+#   per kept pair  : separation 3, r^2 5, sqrt 1, r0/r and powers 7, 12-6 or
+#                    12-10 energy and slope 8, dielectric and its slope 9,
+#                    electrostatics 7, desolvation 5, w = dE/dr / r 3, energy
+#                    sum 3, forces on both atoms 9, pair parameters 6 -> 66
+#   per atom       : pose 18, grid term (cell, 8 corners x 3 maps combined,
+#                    value + gradient, penalty) 92, torque 9, sums 7, torsion
+#                    prefix terms 15 -> 141
+#   per torsion    : rotation 27, its share of fragment products 63, torsion
+#                    gradient 35 -> 125
+#   per gene       : ADADELTA update 12
+FLOPS_PAIR, FLOPS_ATOM, FLOPS_TORSION, FLOPS_GENE = 66, 141, 125, 12
+
+
+def flops_per_eval(n_pairs, n_atoms, n_torsions):
+    return (FLOPS_PAIR * n_pairs + FLOPS_ATOM * n_atoms + FLOPS_TORSION * n_torsions
+            + FLOPS_GENE * (7 + n_torsions))
+
+
+def cpu_baseline(w, sample, iterations):
+    """The FP64 oracle (unchanged) on `sample` individuals, full iterations."""
+    from oracle import dock_ref as R
+    prep = R.prepare(w.ligands[0], w.ff)
+    st = R.ls_init(w.genotypes[0][:sample])
+    t0 = time.perf_counter()
+    R.local_search(prep, w.grids, st, iterations, rho=w.rho, eps=w.eps)
+    dt = time.perf_counter() - t0
+    evals = sample * (iterations + 1)
+    return {"value": evals / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{sample} of 3000 individuals x {iterations + 1} evaluations "
+                      f"({evals} evals, {dt:.1f} s, NumPy FP64 single process)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--variants", default="0,1", help="reduction variants to time (0 shuffle, 1 FP32 MFMA, ...)")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the docking "
+              "hot path has no cross-GPU step; individuals and docking jobs are independent, so more GPUs would each run their own share.")
+        sys.exit(2)
+
+    import torch
+    from paper_2410_10447_amd import dock, synth
+
+    w = synth.ls_workload(3000, 300)
+    lig = w.ligands[0]
+    G = dock.Grids.from_synth(w.grids)
+    L = dock.Ligand(lig, w.ff)
+    gen0 = torch.from_numpy(w.genotypes[0]).cuda()
+    n = gen0.shape[0]
+    iters = w.iterations
+    evals_per_step = n * (iters + 1)
+    fpe = flops_per_eval(L.n_pairs, L.n_atoms, L.n_torsions)
+    variants = [int(v) for v in args.variants.split(",") if v != ""]
+    results = {}
+    stream = torch.cuda.current_stream()
+    ws = torch.empty(dock.workspace_bytes(1), dtype=torch.uint8, device="cuda")
+
+    if args.calib_copy_mib > 0:
+        nb = args.calib_copy_mib << 20
+        a = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+
+    for v in variants:
+        states = [dock.LSState.start(gen0) for _ in range(args.warmup + args.steps)]
+        items = [dock.make_items([(G, L, s)]) for s in states]
+        torch.cuda.synchronize()
+        for k in range(args.warmup):
+            dock.local_search([(G, L, states[k])], iters, variant=v, workspace=ws, items=items[k])
+        torch.cuda.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            s = states[args.warmup + k]
+            evs[2 * k].record(stream)
+            dock.local_search([(G, L, s)], iters, variant=v, workspace=ws, items=items[args.warmup + k])
+            evs[2 * k + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms = [evs[2 * k].elapsed_time(evs[2 * k + 1]) for k in range(args.steps)]
+        best = states[-1].best_energy.cpu().numpy()
+        results[v] = {"evals_per_s": evals_per_step * args.steps / wall,
+                      "ms_per_step": 1e3 * wall / args.steps,
+                      "kernel_ms_mean": float(np.mean(kms)), "kernel_ms_min": float(np.min(kms)),
+                      "best_energy_median": float(np.median(best))}
+        del states, items
+
+    best_v = max(results, key=lambda v: results[v]["evals_per_s"])
+    r = results[best_v]
+    achieved = fpe * evals_per_step / (r["kernel_ms_mean"] * 1e-3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": r["evals_per_s"],
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "individuals": n, "iterations": iters,
+                   "evals_per_step": evals_per_step, "atoms": L.n_atoms,
+                   "torsions": L.n_torsions, "pairs": L.n_pairs, "grid": "64^3 x 10 maps f32",
+                   "variant": dock.VARIANT_NAMES[best_v]},
+        "variants": {dock.VARIANT_NAMES[v]: {k: round(x, 4) if isinstance(x, float) else x
+                                              for k, x in rv.items()}
+                     for v, rv in results.items()},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+                     "traffic": None,
+                     "flops_per_eval": fpe},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

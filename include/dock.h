@@ -1,0 +1,252 @@
+/*
+ * dock.h - C ABI of the MI355X docking hot path.
+ *
+ * The library evaluates the scoring function of a flexible ligand against a
+ * fixed receptor (energy and analytic gradient with respect to the genotype)
+ * for batches of individuals, and runs the ADADELTA local search of a
+ * Lamarckian genetic algorithm on them (Sec. 2.1 of "Accelerating Drug
+ * Discovery in AutoDock-GPU with Tensor Cores": the receptor is fixed, a pose
+ * is the genotype {position, orientation, torsion angles}, each local-search
+ * iteration needs E and its gradient, built from block-level sums of the
+ * energy, the Cartesian gradient and the torque). The block sum of
+ * {E, gx, gy, gz} (Sec. 3 and Sec. 4.2) is selectable between a wavefront
+ * shuffle reduction and matrix-core (MFMA) contractions.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an int32 status (DOCK_OK or a negative DOCK_E*)
+ *   and never aborts or throws. dock_last_error() returns a thread-local,
+ *   human-readable description of the last failure on the calling thread.
+ * - Argument and shape validation is synchronous and happens before any
+ *   device work is enqueued; a failing call enqueues nothing.
+ * - Batch calls are asynchronous on the HIP stream passed as `stream`
+ *   (a hipStream_t; NULL is the null stream). Launch failures are reported
+ *   immediately as DOCK_EDEVICE; faults during execution surface on the next
+ *   synchronising call (through HIP or the caller's framework).
+ * - "host" pointers are read during the call only and may be freed when it
+ *   returns. "device" pointers are borrowed: the caller owns them and keeps
+ *   them alive until the stream work that uses them has completed.
+ * - Genotype layout (float32, row-major, G = 7 + T genes per individual):
+ *   [tx, ty, tz, qw, qx, qy, qz, psi_1 .. psi_T]: translation (A), a
+ *   quaternion (normalised on use), torsion angles (rad). Gradients use the
+ *   same layout.
+ * - Non-finite genotypes propagate to non-finite outputs; there is no
+ *   device-side error channel.
+ */
+#ifndef DOCK_H
+#define DOCK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DOCK_ABI_VERSION 1
+
+/* status codes */
+#define DOCK_OK            0
+#define DOCK_EINVAL       (-1)  /* bad argument, shape or size */
+#define DOCK_ENOMEM       (-2)  /* host allocation failed */
+#define DOCK_EDEVICE      (-3)  /* HIP runtime error or launch failure */
+#define DOCK_EUNSUPPORTED (-4)  /* valid request outside the built limits */
+
+/* limits of this build */
+#define DOCK_MAX_ATOMS     128
+#define DOCK_MAX_TORSIONS   32
+#define DOCK_MAX_GENES     (7 + DOCK_MAX_TORSIONS)
+#define DOCK_MAX_CLASSES    32
+
+/* block-sum variants for {E, gx, gy, gz} (Sec. 3 baseline, Sec. 4.2 method) */
+#define DOCK_REDUCE_SHUFFLE   0  /* wave64 cross-lane (DPP) butterfly, FP32 */
+#define DOCK_REDUCE_MFMA_F32  1  /* FP32 MFMA 16x16x4 with a 0/1 selection matrix */
+#define DOCK_REDUCE_MFMA_BF16 2  /* BF16 MFMA 16x16x32, hi/lo split, FP32 accumulate */
+#define DOCK_REDUCE_MFMA_F16  3  /* FP16 MFMA 16x16x32, scaled hi/lo split, FP32 accumulate */
+#define DOCK_REDUCE_MFMA_BF16X3 4 /* BF16 MFMA, hi/mid/lo split (3 terms), FP32 accumulate */
+#define DOCK_REDUCE_COUNT     5  /* variants usable by the scoring and search calls */
+#define DOCK_REDUCE_SHARED_ATOMIC 5 /* dock_block_sum4 only: the Sec. 3 baseline, per
+                                       component a shuffle tree, one LDS atomic per wave
+                                       and three barriers */
+
+int32_t dock_abi_version(void);
+
+/* Text of the last error on the calling thread ("" if none). The pointer
+ * stays valid until the next failing call on the same thread. */
+const char* dock_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Receptor grids (Sec. 2.1: the target molecule is fixed, so its
+ * interaction with each ligand atom type is precomputed on a lattice).
+ * ---------------------------------------------------------------------- */
+typedef struct dock_grids dock_grids;
+
+typedef struct {
+    int32_t nx, ny, nz;  /* nodes per axis, each >= 2 */
+    int32_t n_maps;      /* >= 3: atom-type maps [0, n_maps-2), then the
+                            electrostatic map (scaled by the atom charge), then
+                            the desolvation map (scaled by |charge|) */
+    float spacing;       /* lattice spacing h (A), > 0 */
+    float origin[3];     /* position of node (0,0,0) (A), (x, y, z) */
+} dock_grid_desc;
+
+/* maps_dev: device, float32 [n_maps][nz][ny][nx] (x fastest), borrowed for the
+ * lifetime of the handle, 4-byte aligned. Errors: DOCK_EINVAL on NULL
+ * pointers, non-positive sizes or spacing, n_maps < 3. */
+int32_t dock_create_grids(const dock_grid_desc* desc, const float* maps_dev, dock_grids** out);
+/* NULL is accepted (DOCK_OK). */
+int32_t dock_destroy_grids(dock_grids* grids);
+
+/* ------------------------------------------------------------------------
+ * Ligand: topology, torsion tree and intramolecular pair list, prepared once
+ * on the host (Sec. 2.1: N_rot torsion genes act on rotatable bonds; the
+ * score sums pairwise interactions).
+ * ---------------------------------------------------------------------- */
+typedef struct dock_ligand dock_ligand;
+
+typedef struct {
+    int32_t n_classes;        /* entries in each per-class array, <= DOCK_MAX_CLASSES */
+    const double* radius;     /* host [n_classes]: vdW radius R (A); r0 = R_i + R_j */
+    const double* eps;        /* host [n_classes]: well depth; eps_ij = sqrt(eps_i eps_j) */
+    const double* solv;       /* host [n_classes]: solvation parameter s */
+    const double* vol;        /* host [n_classes]: atomic volume V (A^3) */
+    int32_t donor[2];         /* classes that donate a hydrogen bond */
+    int32_t acceptor[2];      /* classes that accept one */
+    double hb_r0[2][2];       /* [donor][acceptor] 12-10 equilibrium distance (A) */
+    double hb_eps[2][2];      /* [donor][acceptor] 12-10 well depth */
+} dock_ff_params;
+
+typedef struct {
+    int32_t n_atoms;          /* 1 .. DOCK_MAX_ATOMS */
+    int32_t n_torsions;       /* 0 .. DOCK_MAX_TORSIONS */
+    int32_t root_atom;        /* atom that stays on the fixed side of every torsion */
+    const double* xyz;        /* host [n_atoms][3] reference conformation (A) */
+    const double* charge;     /* host [n_atoms] partial charges (e) */
+    const int32_t* cls;       /* host [n_atoms] classes, < ff->n_classes */
+    const int32_t* bonds;     /* host [n_atoms-1][2]: the bond tree */
+    const int32_t* rot_bonds; /* host [n_torsions]: indices into bonds; each an
+                                 internal bond (both ends bonded elsewhere) */
+    const dock_ff_params* ff; /* host */
+} dock_ligand_desc;
+
+typedef struct {
+    int32_t n_atoms, n_torsions, n_genes;
+    int32_t n_pairs;          /* intramolecular pairs kept */
+    int32_t n_fragments;      /* rigid fragments = n_torsions + 1 */
+    int32_t max_depth;        /* longest chain of nested torsions */
+    int64_t blob_bytes;       /* device bytes needed by dock_ligand_upload */
+} dock_ligand_info;
+
+/* Prepares the ligand on the host (no device call). The preparation orders
+ * atoms depth-first from the root (children by increasing index), turns each
+ * rotatable bond into a torsion whose moving atoms form one contiguous range
+ * of that order, splits the tree into rigid fragments, and keeps the atom
+ * pairs that are >= 4 bonds apart and in different fragments. Errors:
+ * DOCK_EINVAL if the bonds are not a tree over n_atoms atoms, a rotatable bond
+ * is not internal or repeated, or a class is out of range;
+ * DOCK_EUNSUPPORTED beyond the build limits. */
+int32_t dock_create_ligand(const dock_ligand_desc* desc, dock_ligand** out);
+int32_t dock_ligand_info_get(const dock_ligand* lig, dock_ligand_info* out);
+
+/* Host copies of the prepared topology, decoded from the packed data the
+ * kernels read. Any output may be NULL.
+ *   order     [n_atoms]        atom index at each depth-first position
+ *   torsions  [n_torsions][4]  (a, b, first, end): bond a->b (a on the root
+ *                              side, original indices) and the half-open range
+ *                              of depth-first positions that the torsion moves
+ *   fragment  [n_atoms]        fragment id of each atom (0 = root fragment,
+ *                              k+1 = the fragment next to torsion k's b atom)
+ *   pairs     [n_pairs]        (i << 16) | j with i < j (original indices),
+ *                              sorted ascending
+ *   pair_hb   [n_pairs]        1 for a donor-acceptor (12-10) pair, else 0 */
+int32_t dock_ligand_export(const dock_ligand* lig, int32_t* order, int32_t* torsions,
+                           int32_t* fragment, uint32_t* pairs, uint8_t* pair_hb);
+
+/* Copies the packed ligand (blob_bytes, see dock_ligand_info) to blob_dev
+ * (device, caller-owned, 16-byte aligned) on `stream` and binds it to the
+ * handle: later batch calls read the ligand from there. Call again to rebind. */
+int32_t dock_ligand_upload(dock_ligand* lig, void* blob_dev, void* stream);
+int32_t dock_destroy_ligand(dock_ligand* lig);
+
+/* ------------------------------------------------------------------------
+ * One scoring evaluation per individual: energy and gradient (Sec. 2.1).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t variant;          /* DOCK_REDUCE_* */
+    int32_t threads_per_ind;  /* 0 (= 64) or 64; wider tiles are reserved */
+    uint32_t flags;           /* 0 */
+    float* atom_out;          /* device [n][n_atoms][8] or NULL: per atom (original
+                                 order) x, y, z, e_inter, gx, gy, gz, 0 */
+} dock_exec_opts;
+
+/* genotypes_dev [n][G], energy_dev [n], grad_dev [n][G] (may be NULL): device
+ * float32, 4-byte aligned. opts may be NULL (defaults). Errors: DOCK_EINVAL on
+ * NULL handles or pointers, n < 0, a ligand that was never uploaded, a
+ * ligand class with no type map; n == 0 is a no-op. */
+int32_t dock_score_batch(const dock_grids* grids, const dock_ligand* lig, int32_t n,
+                         const float* genotypes_dev, float* energy_dev, float* grad_dev,
+                         const dock_exec_opts* opts, void* stream);
+
+/* ------------------------------------------------------------------------
+ * ADADELTA local search (Sec. 2.1; Zeiler 2012), many ligands in one launch.
+ * Each iteration evaluates E and dE/dgenotype at the current point, records
+ * the point if E is the lowest seen so far (first minimum wins ties), and
+ * takes one ADADELTA step on every gene; the quaternion is renormalised after
+ * each step (kept if its norm falls below 1e-6).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const dock_grids* grids;
+    const dock_ligand* ligand;   /* uploaded */
+    int32_t n;                   /* individuals in this item, >= 0 */
+    int32_t variant;             /* DOCK_REDUCE_* for this item, or -1 = opts->variant */
+    float* genotype;             /* device [n][G] in/out: current point */
+    float* acc_g2;               /* device [n][G] in/out: running mean of g^2 (start 0) */
+    float* acc_dx2;              /* device [n][G] in/out: running mean of dx^2 (start 0) */
+    float* best_genotype;        /* device [n][G] in/out */
+    float* best_energy;          /* device [n] in/out (start +inf) */
+    float* energy;               /* device [n] out: E at the last evaluated point */
+    int32_t* iters_done;         /* device [n] in/out: iterations taken so far */
+} dock_ls_item;
+
+#define DOCK_LS_FINAL_EVAL 1u    /* evaluate the point reached after the last step */
+
+typedef struct {
+    int32_t iterations;          /* >= 0 steps per individual in this call */
+    float rho;                   /* decay, 0 < rho < 1 (0.8) */
+    float eps;                   /* conditioner, > 0 (1e-2) */
+    int32_t variant;             /* default DOCK_REDUCE_* */
+    int32_t threads_per_ind;     /* 0 (= 64) or 64 */
+    uint32_t flags;              /* DOCK_LS_FINAL_EVAL */
+} dock_ls_opts;
+
+/* Device bytes of the workspace dock_local_search_batch needs for n_items. */
+int32_t dock_ls_workspace_bytes(int32_t n_items, int64_t* bytes);
+
+/* Runs opts->iterations steps on every individual of every item in one
+ * persistent launch; items are scheduled longest first. A call of K
+ * iterations without DOCK_LS_FINAL_EVAL followed by one with it gives the
+ * same state, bit for bit, as a single call with all the iterations.
+ * workspace_dev: device, >= dock_ls_workspace_bytes(n_items), 16-byte
+ * aligned, caller-owned; it must not be shared by calls that may overlap.
+ * Errors: DOCK_EINVAL on NULL pointers, bad opts, mismatched sizes, a ligand
+ * never uploaded, or a workspace that is too small. */
+int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items,
+                                const dock_ls_opts* opts, void* workspace_dev,
+                                int64_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Isolated block sum (the paper's reduction test kernel, Sec. 5.2): each of
+ * the `threads` threads of each block holds one float4; every thread ends
+ * with the block total. in_dev [n_blocks][threads][4], out_dev
+ * [n_blocks][threads][4] (every thread's copy of the total), device float32.
+ * threads: 64 .. 1024, a multiple of 64. variant: DOCK_REDUCE_* or
+ * DOCK_REDUCE_SHARED_ATOMIC. repeat >= 1 runs the reduction that many times
+ * in a dependent chain inside the kernel (timing).
+ * ---------------------------------------------------------------------- */
+int32_t dock_block_sum4(const float* in_dev, float* out_dev, int32_t n_blocks, int32_t threads,
+                        int32_t variant, int32_t repeat, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DOCK_H */

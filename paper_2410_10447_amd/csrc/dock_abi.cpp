@@ -1,0 +1,393 @@
+// C ABI of the docking hot path (declarations and contracts in include/dock.h).
+//
+// Host-side responsibilities: argument validation before any device work,
+// ligand preparation (dock_prep.cpp), the device item table of a local-search
+// batch (staged through pinned host buffers and copied into the caller's
+// workspace on the caller's stream), work ordering (longest items first) and
+// launch geometry. Every compute step runs in the kernels of
+// dock_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dock.h"
+#include "dock_blob.h"
+#include "dock_launch.h"
+#include "dock_prep.h"
+
+struct dock_grids {
+    dock_grid_desc desc;
+    docklaunch::GridParams gp;
+};
+
+struct dock_ligand {
+    dockprep::Prepared prep;
+    const uint8_t* blob_dev = nullptr;
+    int slots = 1;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t status, const std::string& msg) {
+    g_err = msg;
+    return status;
+}
+
+int32_t ok() { return DOCK_OK; }
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int32_t hip_fail(hipError_t e, const char* what) {
+    return fail(DOCK_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Pinned staging buffers for host -> device copies of item tables. A buffer
+// is reused only after the copy that last read it has executed (event).
+class StagingRing {
+  public:
+    int32_t copy_to_device(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+        std::lock_guard<std::mutex> lock(mu_);
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+        auto& ring = rings_[dev];
+        Slot& s = ring.slot[ring.next];
+        ring.next = (ring.next + 1) % kSlots;
+        if (s.ev) {
+            e = hipEventSynchronize(s.ev);
+            if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+        } else {
+            e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming);
+            if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+        }
+        if (s.cap < bytes) {
+            if (s.host) (void)hipHostFree(s.host);
+            s.host = nullptr;
+            s.cap = 0;
+            size_t cap = std::max<size_t>(bytes, 4096);
+            e = hipHostMalloc(&s.host, cap, hipHostMallocDefault);
+            if (e != hipSuccess) return hip_fail(e, "hipHostMalloc");
+            s.cap = cap;
+        }
+        std::memcpy(s.host, src, bytes);
+        e = hipMemcpyAsync(dst, s.host, bytes, hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        e = hipEventRecord(s.ev, stream);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        return DOCK_OK;
+    }
+
+  private:
+    static constexpr int kSlots = 8;
+    struct Slot {
+        void* host = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+    };
+    struct Ring {
+        Slot slot[kSlots];
+        int next = 0;
+    };
+    std::mutex mu_;
+    std::map<int, Ring> rings_;
+};
+
+StagingRing& staging() {
+    static StagingRing* r = new StagingRing();  // never destroyed: outlives late stream work
+    return *r;
+}
+
+int device_cu_count(int32_t& out) {
+    static std::mutex mu;
+    static std::map<int, int> cache;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(dev);
+    if (it == cache.end()) {
+        int n = 0;
+        e = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+        it = cache.emplace(dev, n).first;
+    }
+    out = it->second;
+    return DOCK_OK;
+}
+
+int32_t check_grid_for_ligand(const dock_grids* g, const dock_ligand* l) {
+    if (l->prep.max_class >= g->desc.n_maps - 2)
+        return fail(DOCK_EINVAL, "ligand uses an atom class with no type map in the grid set");
+    return DOCK_OK;
+}
+
+bool valid_variant(int v) { return v >= 0 && v < DOCK_REDUCE_COUNT; }
+
+}  // namespace
+
+extern "C" {
+
+int32_t dock_abi_version(void) { return DOCK_ABI_VERSION; }
+
+const char* dock_last_error(void) { return g_err.c_str(); }
+
+int32_t dock_create_grids(const dock_grid_desc* d, const float* maps_dev, dock_grids** out) {
+    if (!d || !maps_dev || !out) return fail(DOCK_EINVAL, "dock_create_grids: NULL argument");
+    if (d->nx < 2 || d->ny < 2 || d->nz < 2) return fail(DOCK_EINVAL, "grid needs >= 2 nodes per axis");
+    if (d->n_maps < 3) return fail(DOCK_EINVAL, "grid needs >= 3 maps (types, electrostatic, desolvation)");
+    if (!(d->spacing > 0.f) || !std::isfinite(d->spacing)) return fail(DOCK_EINVAL, "grid spacing must be > 0");
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(d->origin[c])) return fail(DOCK_EINVAL, "grid origin must be finite");
+    const double nodes = double(d->nx) * d->ny * d->nz * d->n_maps;
+    if (nodes > 2147483647.0) return fail(DOCK_EUNSUPPORTED, "grid set exceeds 2^31 floats");
+    if (!aligned(maps_dev, 4)) return fail(DOCK_EINVAL, "maps pointer not 4-byte aligned");
+    dock_grids* g = new (std::nothrow) dock_grids();
+    if (!g) return fail(DOCK_ENOMEM, "out of host memory");
+    g->desc = *d;
+    g->gp.maps = maps_dev;
+    g->gp.nx = d->nx;
+    g->gp.ny = d->ny;
+    g->gp.nz = d->nz;
+    g->gp.n_maps = d->n_maps;
+    g->gp.spacing = d->spacing;
+    const int n[3] = {d->nx, d->ny, d->nz};
+    for (int c = 0; c < 3; ++c) {
+        g->gp.origin[c] = d->origin[c];
+        g->gp.hi[c] = (float)((double)d->origin[c] + (double)(n[c] - 1) * (double)d->spacing);
+    }
+    *out = g;
+    return ok();
+}
+
+int32_t dock_destroy_grids(dock_grids* g) {
+    delete g;
+    return ok();
+}
+
+int32_t dock_create_ligand(const dock_ligand_desc* d, dock_ligand** out) {
+    if (!d || !out) return fail(DOCK_EINVAL, "dock_create_ligand: NULL argument");
+    dock_ligand* l = new (std::nothrow) dock_ligand();
+    if (!l) return fail(DOCK_ENOMEM, "out of host memory");
+    std::string err;
+    int32_t st;
+    try {
+        st = dockprep::prepare(*d, l->prep, err);
+    } catch (const std::bad_alloc&) {
+        delete l;
+        return fail(DOCK_ENOMEM, "out of host memory");
+    }
+    if (st != DOCK_OK) {
+        delete l;
+        return fail(st, "dock_create_ligand: " + err);
+    }
+    l->slots = l->prep.n_atoms <= 64 ? 1 : 2;
+    *out = l;
+    return ok();
+}
+
+int32_t dock_ligand_info_get(const dock_ligand* l, dock_ligand_info* out) {
+    if (!l || !out) return fail(DOCK_EINVAL, "dock_ligand_info_get: NULL argument");
+    out->n_atoms = l->prep.n_atoms;
+    out->n_torsions = l->prep.n_torsions;
+    out->n_genes = 7 + l->prep.n_torsions;
+    out->n_pairs = l->prep.n_pairs;
+    out->n_fragments = l->prep.n_frag;
+    out->max_depth = l->prep.max_depth;
+    out->blob_bytes = (int64_t)l->prep.blob.size();
+    return ok();
+}
+
+int32_t dock_ligand_export(const dock_ligand* l, int32_t* order, int32_t* torsions, int32_t* fragment,
+                           uint32_t* pairs, uint8_t* pair_hb) {
+    if (!l) return fail(DOCK_EINVAL, "dock_ligand_export: NULL ligand");
+    const auto& P = l->prep;
+    if (order) std::copy(P.order.begin(), P.order.end(), order);
+    if (torsions)
+        for (int k = 0; k < P.n_torsions; ++k) {
+            torsions[4 * k + 0] = P.tors_a[k];
+            torsions[4 * k + 1] = P.tors_b[k];
+            torsions[4 * k + 2] = P.tors_first[k];
+            torsions[4 * k + 3] = P.tors_end[k];
+        }
+    if (fragment) std::copy(P.frag_of_atom.begin(), P.frag_of_atom.end(), fragment);
+    if (pairs || pair_hb) {
+        std::vector<uint32_t> pv;
+        std::vector<uint8_t> hv;
+        dockprep::decode_pairs(P, pv, hv);
+        if (pairs) std::copy(pv.begin(), pv.end(), pairs);
+        if (pair_hb) std::copy(hv.begin(), hv.end(), pair_hb);
+    }
+    return ok();
+}
+
+int32_t dock_ligand_upload(dock_ligand* l, void* blob_dev, void* stream) {
+    if (!l || !blob_dev) return fail(DOCK_EINVAL, "dock_ligand_upload: NULL argument");
+    if (!aligned(blob_dev, 16)) return fail(DOCK_EINVAL, "ligand blob must be 16-byte aligned");
+    hipError_t e = hipMemcpyAsync(blob_dev, l->prep.blob.data(), l->prep.blob.size(),
+                                  hipMemcpyHostToDevice, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "dock_ligand_upload");
+    // pageable source: make sure the copy has read the host blob before returning
+    e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "dock_ligand_upload");
+    l->blob_dev = static_cast<const uint8_t*>(blob_dev);
+    return ok();
+}
+
+int32_t dock_destroy_ligand(dock_ligand* l) {
+    delete l;
+    return ok();
+}
+
+int32_t dock_score_batch(const dock_grids* g, const dock_ligand* l, int32_t n, const float* gen,
+                         float* energy, float* grad, const dock_exec_opts* o, void* stream) {
+    if (!g || !l) return fail(DOCK_EINVAL, "dock_score_batch: NULL handle");
+    if (n < 0) return fail(DOCK_EINVAL, "dock_score_batch: n < 0");
+    if (!l->blob_dev) return fail(DOCK_EINVAL, "dock_score_batch: ligand not uploaded");
+    int32_t st = check_grid_for_ligand(g, l);
+    if (st != DOCK_OK) return st;
+    const int variant = o ? o->variant : DOCK_REDUCE_SHUFFLE;
+    if (!valid_variant(variant)) return fail(DOCK_EINVAL, "dock_score_batch: unknown variant");
+    if (o && o->threads_per_ind != 0 && o->threads_per_ind != 64)
+        return fail(DOCK_EUNSUPPORTED, "dock_score_batch: threads_per_ind must be 0 or 64");
+    if (o && o->flags != 0) return fail(DOCK_EINVAL, "dock_score_batch: unknown flags");
+    if (n == 0) return ok();
+    if (!gen || !energy) return fail(DOCK_EINVAL, "dock_score_batch: NULL genotypes or energy");
+    if (!aligned(gen, 4) || !aligned(energy, 4) || (grad && !aligned(grad, 4)))
+        return fail(DOCK_EINVAL, "dock_score_batch: pointers must be 4-byte aligned");
+    float* atom_out = o ? o->atom_out : nullptr;
+    if (atom_out && !aligned(atom_out, 16)) return fail(DOCK_EINVAL, "atom_out must be 16-byte aligned");
+    hipError_t e = docklaunch::launch_score(g->gp, l->blob_dev, l->slots, n, gen, energy, grad, atom_out,
+                                            variant, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "dock_score_batch launch");
+    return ok();
+}
+
+int32_t dock_ls_workspace_bytes(int32_t n_items, int64_t* bytes) {
+    if (n_items < 0 || !bytes) return fail(DOCK_EINVAL, "dock_ls_workspace_bytes: bad argument");
+    *bytes = docklaunch::kWorkspaceHeader + (int64_t)n_items * (int64_t)sizeof(docklaunch::DevItem);
+    return ok();
+}
+
+int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* o,
+                                void* ws, int64_t ws_bytes, void* stream) {
+    if (!o) return fail(DOCK_EINVAL, "dock_local_search_batch: NULL opts");
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(DOCK_EINVAL, "dock_local_search_batch: bad items");
+    if (o->iterations < 0) return fail(DOCK_EINVAL, "iterations must be >= 0");
+    if (!(o->rho > 0.f && o->rho < 1.f)) return fail(DOCK_EINVAL, "rho must be in (0, 1)");
+    if (!(o->eps > 0.f) || !std::isfinite(o->eps)) return fail(DOCK_EINVAL, "eps must be > 0");
+    if (!valid_variant(o->variant)) return fail(DOCK_EINVAL, "unknown default variant");
+    if (o->threads_per_ind != 0 && o->threads_per_ind != 64)
+        return fail(DOCK_EUNSUPPORTED, "threads_per_ind must be 0 or 64");
+    if ((o->flags & ~DOCK_LS_FINAL_EVAL) != 0) return fail(DOCK_EINVAL, "unknown flags");
+    int64_t need = 0;
+    dock_ls_workspace_bytes(n_items, &need);
+    std::vector<docklaunch::DevItem> dev;
+    std::vector<int64_t> cost;
+    dev.reserve(n_items);
+    int64_t total = 0;
+    bool any1 = false, any2 = false;
+    int var_u = -2;
+    for (int i = 0; i < n_items; ++i) {
+        const dock_ls_item& it = items[i];
+        if (!it.grids || !it.ligand) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": NULL handle");
+        if (!it.ligand->blob_dev) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": ligand not uploaded");
+        if (it.n < 0) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": n < 0");
+        int32_t st = check_grid_for_ligand(it.grids, it.ligand);
+        if (st != DOCK_OK) return st;
+        const int var = it.variant < 0 ? o->variant : it.variant;
+        if (!valid_variant(var)) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": unknown variant");
+        if (it.n == 0) continue;
+        void* ptrs[] = {it.genotype, it.acc_g2, it.acc_dx2, it.best_genotype, it.best_energy, it.energy,
+                        it.iters_done};
+        for (void* p : ptrs)
+            if (!p || !aligned(p, 4)) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": NULL or misaligned state");
+        docklaunch::DevItem d;
+        std::memset(&d, 0, sizeof(d));
+        d.grid = it.grids->gp;
+        d.blob = it.ligand->blob_dev;
+        d.genotype = it.genotype;
+        d.acc_g2 = it.acc_g2;
+        d.acc_dx2 = it.acc_dx2;
+        d.best_genotype = it.best_genotype;
+        d.best_energy = it.best_energy;
+        d.energy = it.energy;
+        d.iters_done = it.iters_done;
+        d.n = it.n;
+        d.variant = var;
+        d.slots = it.ligand->slots;
+        dev.push_back(d);
+        const auto& P = it.ligand->prep;
+        // per-individual cost: pair steps per slot dominate, then atoms and torsion depth
+        cost.push_back((int64_t)(P.n_atoms / 2 + 4) * d.slots * 8 + P.max_depth);
+        any1 |= d.slots == 1;
+        any2 |= d.slots == 2;
+        var_u = (var_u == -2 || var_u == var) ? var : -1;
+        total += it.n;
+    }
+    if (total > 2147483647LL) return fail(DOCK_EUNSUPPORTED, "more than 2^31 individuals in one call");
+    if (dev.empty()) return ok();
+    if (!ws) return fail(DOCK_EINVAL, "dock_local_search_batch: NULL workspace");
+    if (ws_bytes < need) return fail(DOCK_EINVAL, "dock_local_search_batch: workspace too small");
+    if (!aligned(ws, 16)) return fail(DOCK_EINVAL, "workspace must be 16-byte aligned");
+    // longest items first (stable)
+    std::vector<int> idx(dev.size());
+    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<uint8_t> table(docklaunch::kWorkspaceHeader + dev.size() * sizeof(docklaunch::DevItem), 0);
+    docklaunch::DevItem* tab = reinterpret_cast<docklaunch::DevItem*>(table.data() + docklaunch::kWorkspaceHeader);
+    int32_t ub = 0;
+    for (size_t i = 0; i < idx.size(); ++i) {
+        tab[i] = dev[idx[i]];
+        tab[i].unit_begin = ub;
+        ub += tab[i].n;
+    }
+    // counter (first int32 of the header) starts at 0: it is part of the copy
+    int32_t st = staging().copy_to_device(ws, table.data(), table.size(), (hipStream_t)stream);
+    if (st != DOCK_OK) return st;
+    int32_t n_cu = 0;
+    st = device_cu_count(n_cu);
+    if (st != DOCK_OK) return st;
+    const int mode = (any1 && any2) ? docklaunch::kSlotsAny : (any2 ? docklaunch::kSlots2 : docklaunch::kSlots1);
+    const int var_uniform = var_u >= 0 ? var_u : -1;
+    int per_cu = docklaunch::ls_blocks_per_cu(mode, var_uniform);
+    if (per_cu <= 0) per_cu = 8;
+    const int64_t resident = (int64_t)per_cu * n_cu;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, resident));
+    docklaunch::LsParams p;
+    p.items = reinterpret_cast<const docklaunch::DevItem*>(static_cast<uint8_t*>(ws) +
+                                                           docklaunch::kWorkspaceHeader);
+    p.counter = static_cast<int32_t*>(ws);
+    p.n_items = (int32_t)dev.size();
+    p.total_units = (int32_t)total;
+    p.iterations = o->iterations;
+    p.rho = o->rho;
+    p.eps = o->eps;
+    p.final_eval = (o->flags & DOCK_LS_FINAL_EVAL) ? 1 : 0;
+    hipError_t e = docklaunch::launch_ls(p, mode, var_uniform, grid, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "dock_local_search_batch launch");
+    return ok();
+}
+
+int32_t dock_block_sum4(const float* in, float* out, int32_t n_blocks, int32_t threads, int32_t variant,
+                        int32_t repeat, void* stream) {
+    if (!in || !out) return fail(DOCK_EINVAL, "dock_block_sum4: NULL pointer");
+    if (n_blocks < 0 || threads < 64 || threads > 1024 || threads % 64 != 0 || repeat < 1)
+        return fail(DOCK_EINVAL, "dock_block_sum4: bad sizes");
+    if (variant < 0 || variant > DOCK_REDUCE_SHARED_ATOMIC) return fail(DOCK_EINVAL, "dock_block_sum4: unknown variant");
+    if (!aligned(in, 16) || !aligned(out, 16)) return fail(DOCK_EINVAL, "dock_block_sum4: need 16-byte alignment");
+    if (n_blocks == 0) return ok();
+    hipError_t e = docklaunch::launch_block_sum4(in, out, n_blocks, threads, variant, repeat, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "dock_block_sum4 launch");
+    return ok();
+}
+
+}  // extern "C"

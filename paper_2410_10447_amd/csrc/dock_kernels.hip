@@ -1,0 +1,925 @@
+// HIP kernels of the docking hot path for gfx950 (MI355X, CDNA4, wave64).
+//
+// One wave owns one individual. The per-evaluation pipeline (Sec. 2.1 of the
+// paper: pose from the genotype, pairwise free-energy terms, gradient and
+// torque sums, ADADELTA step) runs entirely inside the wave:
+//
+//   genotype (lane c holds gene c)
+//   -> torsion transforms (lane k: Rodrigues rotation about bond k)
+//   -> fragment transforms (lane f: product of the torsions enclosing f,
+//      then the rigid-body rotation and translation)
+//   -> atom positions (lane a: atom a in depth-first order; a second slot
+//      holds atom a + 64 for ligands of 65..128 atoms)
+//   -> grid term: trilinear interpolation of three maps per atom
+//   -> pair terms: circulant schedule, step s pairs atom a with a + s, the
+//      partner's share of the force is handed over with a cross-lane permute
+//   -> block sums of {E, gx, gy, gz} and of the torque (Sec. 3/4.2; selectable
+//      shuffle or MFMA variants), torsion torques by a wave prefix scan
+//   -> gradient with respect to the genotype, ADADELTA update.
+//
+// No barrier spans more than one wave, no LDS or global float atomics are
+// used, and every sum runs in a fixed order, so results are deterministic
+// run to run and independent of what else shares the launch.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dock.h"
+#include "dock_blob.h"
+#include "dock_launch.h"
+
+namespace {
+
+using dockblob::Header;
+using dockblob::Torsion;
+using docklaunch::DevItem;
+using docklaunch::GridParams;
+using docklaunch::LsParams;
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kWave = 64;
+constexpr int kMaxAtoms = dockblob::kMaxAtoms;
+constexpr int kMaxTors = dockblob::kMaxTorsions;
+constexpr int kMaxFrag = dockblob::kMaxFrag;
+constexpr int kChain = dockblob::kChainStride;
+
+// Force-field constants (AutoDock4 forms, Mehler-Solmajer dielectric).
+constexpr float kR2Min = 1.0e-4f;        // A^2 lower clamp on r^2
+constexpr float kCap = 1.0e5f;           // cap of the 12-6 / 12-10 term
+constexpr float kOut = 100.0f;           // outside-the-box penalty constant
+constexpr float kDielA = -8.5525f;
+constexpr float kDielB = 86.9525f;       // eps0 - A with eps0 = 78.4
+constexpr float kDielK = 7.7839f;
+constexpr float kDielLB = 0.003627f * 86.9525f;            // lambda * B
+constexpr float kDielBKLB = 86.9525f * 7.7839f * 0.003627f * 86.9525f;
+constexpr float kDsInv2S2 = 1.0f / (2.0f * 3.5f * 3.5f);   // 1 / (2 sigma^2)
+constexpr float kDsInvS2 = 1.0f / (3.5f * 3.5f);
+constexpr float kLog2e = 1.4426950408889634f;
+
+// ---------------------------------------------------------------------------
+// Cross-lane primitives (wave64).
+// ---------------------------------------------------------------------------
+
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
+__device__ __forceinline__ float dpp(float v) {
+    // lanes whose source is outside the row, or whose row is masked off, read 0
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(
+        0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, BANK_MASK, true));
+}
+
+__device__ __forceinline__ float readlane(float v, int l) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+// Sum over the wave, every lane receives the same value. Butterfly inside
+// each 16-lane row with DPP (quad swaps, half-row and row mirrors), then the
+// four row sums are read as scalars and added in a fixed order.
+__device__ __forceinline__ float wave_sum(float v) {
+    v += dpp<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp<0x141>(v);   // row_half_mirror
+    v += dpp<0x140>(v);   // row_mirror
+    return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+    v = fmaxf(v, dpp<0xB1>(v));
+    v = fmaxf(v, dpp<0x4E>(v));
+    v = fmaxf(v, dpp<0x141>(v));
+    v = fmaxf(v, dpp<0x140>(v));
+    return fmaxf(fmaxf(readlane(v, 0), readlane(v, 16)), fmaxf(readlane(v, 32), readlane(v, 48)));
+}
+
+// Inclusive prefix sum over the 64 lanes.
+__device__ __forceinline__ float wave_scan(float v) {
+    v += dpp<0x111>(v);          // row_shr:1
+    v += dpp<0x112>(v);          // row_shr:2
+    v += dpp<0x114>(v);          // row_shr:4
+    v += dpp<0x118>(v);          // row_shr:8
+    v += dpp<0x142, 0xa>(v);     // row_bcast:15 into rows 1 and 3
+    v += dpp<0x143, 0xc>(v);     // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Block sum of 4-vectors over one wave: the variants of the paper's step.
+// ---------------------------------------------------------------------------
+
+// R0: plain wavefront shuffle (the Sec. 3 baseline without its atomics and
+// barriers: one wave needs neither).
+__device__ __forceinline__ float4 sum4_shuffle(float4 v) {
+    return make_float4(wave_sum(v.x), wave_sum(v.y), wave_sum(v.z), wave_sum(v.w));
+}
+
+// Tail shared by the MFMA variants. The 16x16 result holds, in column n,
+// partial sums of component n % 4; lane l owns rows 4(l/16)..4(l/16)+3 of
+// column l % 16. Adding its four rows and the matching lanes of the other
+// three lane groups gives every lane the total of component l % 4.
+__device__ __forceinline__ float4 mfma_tail(f32x4 acc) {
+    float s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+    s += __shfl_xor(s, 16);
+    s += __shfl_xor(s, 32);
+    return make_float4(readlane(s, 0), readlane(s, 1), readlane(s, 2), readlane(s, 3));
+}
+
+// R1: FP32 MFMA 16x16x4. The analogue of the paper's V = A P: each lane's
+// component c enters A (row l % 16, k = l / 16); B is a 0/1 selection matrix
+// that routes component c to the columns n with n % 4 == c, so four
+// accumulating products leave, in each column, the sums over k (lanes l,
+// l+16, l+32, l+48) of one component. The second product of the paper (Q V)
+// is replaced by the in-register tail.
+__device__ __forceinline__ float4 sum4_mfma_f32(float4 v) {
+    const int c = lane_id() & 3;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v.x, c == 0 ? 1.f : 0.f, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v.y, c == 1 ? 1.f : 0.f, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v.z, c == 2 ? 1.f : 0.f, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(v.w, c == 3 ? 1.f : 0.f, acc, 0, 0, 0);
+    return mfma_tail(acc);
+}
+
+// R2: half-width MFMA 16x16x32 with split operands (precision refinement):
+// each lane supplies 8 narrow values, hi and lo parts of its 4 components,
+// B[k][n] = [k % 4 == n % 4], and the matrix unit adds hi + lo of 4 lanes per
+// output element in FP32. The selection is invariant to how the unit maps
+// (lane, slot) to k, since A and B share that mapping and k % 4 = slot % 4.
+__device__ __forceinline__ bf16x8 sel_bf16() {
+    const int c = lane_id() & 3;
+    bf16x8 b;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) b[i] = (__bf16)(((i & 3) == c) ? 1.0f : 0.0f);
+    return b;
+}
+
+template <int TERMS>
+__device__ __forceinline__ float4 sum4_mfma_bf16(float4 v) {
+    const float vv[4] = {v.x, v.y, v.z, v.w};
+    bf16x8 a;
+    bf16x8 a2;
+    float rem[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        __bf16 h = (__bf16)vv[i];
+        a[i] = h;
+        rem[i] = vv[i] - (float)h;
+        __bf16 m = (__bf16)rem[i];
+        a[4 + i] = m;
+        rem[i] = rem[i] - (float)m;
+        a2[i] = (__bf16)rem[i];
+        a2[4 + i] = (__bf16)0.0f;
+    }
+    const bf16x8 b = sel_bf16();
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+    if (TERMS == 3) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2, b, acc, 0, 0, 0);
+    return mfma_tail(acc);
+}
+
+// FP16 has 5 exponent bits, so each component is first scaled by a power of
+// two that brings the wave's largest magnitude just below 2^14 (exact), and
+// the sum is scaled back (exact).
+__device__ __forceinline__ float4 sum4_mfma_f16(float4 v) {
+    const float vv[4] = {v.x, v.y, v.z, v.w};
+    float mx[4] = {wave_max(fabsf(v.x)), wave_max(fabsf(v.y)), wave_max(fabsf(v.z)),
+                   wave_max(fabsf(v.w))};
+    int k[4];
+    f16x8 a;
+    f16x8 b;
+    const int c = lane_id() & 3;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        k[i] = (mx[i] > 0.f && mx[i] <= 3.0e38f) ? 13 - ilogbf(mx[i]) : 0;
+        k[i] = k[i] < -120 ? -120 : (k[i] > 120 ? 120 : k[i]);
+        float s = ldexpf(vv[i], k[i]);
+        _Float16 h = (_Float16)s;
+        a[i] = h;
+        a[4 + i] = (_Float16)(s - (float)h);
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) b[i] = (_Float16)(((i & 3) == c) ? 1.0f : 0.0f);
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, acc, 0, 0, 0);
+    float4 t = mfma_tail(acc);
+    return make_float4(ldexpf(t.x, -k[0]), ldexpf(t.y, -k[1]), ldexpf(t.z, -k[2]),
+                       ldexpf(t.w, -k[3]));
+}
+
+template <int VAR>
+__device__ __forceinline__ float4 sum4(float4 v) {
+    if constexpr (VAR == DOCK_REDUCE_SHUFFLE) return sum4_shuffle(v);
+    else if constexpr (VAR == DOCK_REDUCE_MFMA_F32) return sum4_mfma_f32(v);
+    else if constexpr (VAR == DOCK_REDUCE_MFMA_BF16) return sum4_mfma_bf16<2>(v);
+    else if constexpr (VAR == DOCK_REDUCE_MFMA_F16) return sum4_mfma_f16(v);
+    else return sum4_mfma_bf16<3>(v);
+}
+
+// The torque always stays FP32: shuffle for the shuffle and half-width
+// variants, FP32 MFMA for the FP32 MFMA variant.
+template <int VAR>
+__device__ __forceinline__ float4 sum4_fp32(float4 v) {
+    if constexpr (VAR == DOCK_REDUCE_MFMA_F32) return sum4_mfma_f32(v);
+    else return sum4_shuffle(v);
+}
+
+// ---------------------------------------------------------------------------
+// Ligand data held by a wave.
+// ---------------------------------------------------------------------------
+
+struct __align__(16) Smem {
+    float4 dyn[kMaxAtoms];          // world x, y, z and charge q (depth-first order)
+    float4 par[kMaxAtoms];          // R, sqrt(eps), S, V
+    float tk[kMaxTors][12];         // torsion transforms, 3x4 row-major
+    float fw[kMaxFrag][12];         // fragment -> world transforms
+    int8_t chain[kMaxFrag][kChain]; // [0] = length, then torsions root first
+};
+
+template <int SLOTS>
+struct Lig {
+    // uniform
+    int N, T, NF, G, steps;
+    // per lane, per slot: atom a = lane + 64 * slot
+    float y0[SLOTS][3];
+    float chg[SLOTS][3];            // 332.06363 q, q, |q|
+    float par[SLOTS][4];            // R, sqrt(eps), S, V
+    float hb[SLOTS][4];             // 12-10 r0 vs partner index 0/1, eps vs 0/1
+    int cls[SLOTS];
+    int frag[SLOTS];
+    int orig[SLOTS];                // original atom index
+    uint64_t keep[SLOTS], hbm[SLOTS], hbi[SLOTS];
+    // per lane k < T: torsion k
+    float tp[3], tu[3];
+    int t_apos, t_bpos, t_first, t_end;
+};
+
+template <int SLOTS>
+__device__ void load_ligand(const uint8_t* __restrict__ blob, Smem& sm, Lig<SLOTS>& L) {
+    const Header* h = reinterpret_cast<const Header*>(blob);
+    const int lane = lane_id();
+    L.N = h->n_atoms;
+    L.T = h->n_torsions;
+    L.NF = h->n_frag;
+    L.G = h->n_genes;
+    L.steps = h->n_steps;
+    const float4* ref = reinterpret_cast<const float4*>(blob + h->off_ref);
+    const float4* par = reinterpret_cast<const float4*>(blob + h->off_par);
+    const float4* chg = reinterpret_cast<const float4*>(blob + h->off_chg);
+    const float4* hbv = reinterpret_cast<const float4*>(blob + h->off_hb);
+    const int4* iv = reinterpret_cast<const int4*>(blob + h->off_int);
+    const uint64_t* mk = reinterpret_cast<const uint64_t*>(blob + h->off_mask);
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int a = lane + kWave * s;
+        const bool ok = a < L.N;
+        const int ai = ok ? a : 0;
+        float4 r = ref[ai], p = par[ai], c = chg[ai], b = hbv[ai];
+        int4 ii = iv[ai];
+        L.y0[s][0] = r.x; L.y0[s][1] = r.y; L.y0[s][2] = r.z;
+        L.chg[s][0] = ok ? c.x : 0.f; L.chg[s][1] = ok ? c.y : 0.f; L.chg[s][2] = ok ? c.z : 0.f;
+        L.par[s][0] = p.x; L.par[s][1] = p.y; L.par[s][2] = p.z; L.par[s][3] = p.w;
+        L.hb[s][0] = b.x; L.hb[s][1] = b.y; L.hb[s][2] = b.z; L.hb[s][3] = b.w;
+        L.cls[s] = ii.x;
+        L.frag[s] = ii.y;
+        L.orig[s] = ii.z;
+        L.keep[s] = ok ? mk[ai] : 0ull;
+        L.hbm[s] = ok ? mk[L.N + ai] : 0ull;
+        L.hbi[s] = ok ? mk[2 * L.N + ai] : 0ull;
+        if (ok) sm.par[a] = p;
+    }
+    const Torsion* tr = reinterpret_cast<const Torsion*>(blob + h->off_tors);
+    const int k = lane < L.T ? lane : 0;
+    if (L.T > 0) {
+        Torsion t = tr[k];
+        L.tp[0] = t.p[0]; L.tp[1] = t.p[1]; L.tp[2] = t.p[2];
+        L.tu[0] = t.u[0]; L.tu[1] = t.u[1]; L.tu[2] = t.u[2];
+        L.t_apos = t.a_pos; L.t_bpos = t.b_pos; L.t_first = t.first; L.t_end = t.end;
+    } else {
+        L.tp[0] = L.tp[1] = L.tp[2] = 0.f;
+        L.tu[0] = 1.f; L.tu[1] = L.tu[2] = 0.f;
+        L.t_apos = 0; L.t_bpos = 0; L.t_first = 1; L.t_end = 1;
+    }
+    const int8_t* ch = reinterpret_cast<const int8_t*>(blob + h->off_chain);
+    const int n_chain_bytes = L.NF * kChain;
+    int8_t* dst = &sm.chain[0][0];
+    for (int i = lane; i < n_chain_bytes; i += kWave) dst[i] = ch[i];
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Intermolecular grid term of one atom.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void grid_term(const GridParams& G, int cls, float q, float aq,
+                                          float x, float y, float z,
+                                          float& e, float& gx, float& gy, float& gz) {
+    const float xc = fminf(fmaxf(x, G.origin[0]), G.hi[0]);
+    const float yc = fminf(fmaxf(y, G.origin[1]), G.hi[1]);
+    const float zc = fminf(fmaxf(z, G.origin[2]), G.hi[2]);
+    const float ux = (xc - G.origin[0]) / G.spacing;
+    const float uy = (yc - G.origin[1]) / G.spacing;
+    const float uz = (zc - G.origin[2]) / G.spacing;
+    const int cx = min(max((int)floorf(ux), 0), G.nx - 2);
+    const int cy = min(max((int)floorf(uy), 0), G.ny - 2);
+    const int cz = min(max((int)floorf(uz), 0), G.nz - 2);
+    const float fx = ux - (float)cx, fy = uy - (float)cy, fz = uz - (float)cz;
+    const int plane = G.nx * G.ny;
+    const int vol = plane * G.nz;
+    const int base = (cz * G.ny + cy) * G.nx + cx;
+    const float* __restrict__ mc = G.maps + (size_t)cls * vol + base;
+    const float* __restrict__ me = G.maps + (size_t)(G.n_maps - 2) * vol + base;
+    const float* __restrict__ md = G.maps + (size_t)(G.n_maps - 1) * vol + base;
+    const int off[8] = {0, 1, G.nx, G.nx + 1, plane, plane + 1, plane + G.nx, plane + G.nx + 1};
+    float v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = mc[off[i]] + q * me[off[i]] + aq * md[off[i]];
+    // v index = 4 dz + 2 dy + dx
+    const float d00 = v[1] - v[0], d01 = v[3] - v[2], d10 = v[5] - v[4], d11 = v[7] - v[6];
+    const float a00 = v[0] + fx * d00, a01 = v[2] + fx * d01;
+    const float a10 = v[4] + fx * d10, a11 = v[6] + fx * d11;
+    const float b0 = a00 + fy * (a01 - a00), b1 = a10 + fy * (a11 - a10);
+    const float val = b0 + fz * (b1 - b0);
+    const float dfz = b1 - b0;
+    const float dfy = (a01 - a00) + fz * ((a11 - a10) - (a01 - a00));
+    const float dx0 = d00 + fy * (d01 - d00), dx1 = d10 + fy * (d11 - d10);
+    const float dfx = dx0 + fz * (dx1 - dx0);
+    const float ih = 1.0f / G.spacing;
+    const float ox = x - xc, oy = y - yc, oz = z - zc;
+    e = val + kOut * (ox * ox + oy * oy + oz * oz);
+    gx = (x == xc ? dfx * ih : 0.f) + 2.f * kOut * ox;
+    gy = (y == yc ? dfy * ih : 0.f) + 2.f * kOut * oy;
+    gz = (z == zc ? dfz * ih : 0.f) + 2.f * kOut * oz;
+}
+
+// ---------------------------------------------------------------------------
+// One pair: energy and w = (dE/dr)/r from the separation d = x_b - x_a.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void pair_term(float dx, float dy, float dz, float r0, float eps,
+                                          bool hb, float qq, float ds, float& e, float& w) {
+    const float r2raw = dx * dx + dy * dy + dz * dz;
+    const bool clamped = r2raw < kR2Min;
+    const float r2 = fmaxf(r2raw, kR2Min);
+    const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float r = r2 * rinv;
+    const float s2 = (r0 * r0) * (rinv * rinv);
+    const float s6 = s2 * s2 * s2;
+    const float s12 = s6 * s6;
+    const float s10 = s6 * s2 * s2;
+    float elj, dlj;
+    if (hb) {
+        elj = eps * (5.f * s12 - 6.f * s10);
+        dlj = 60.f * eps * (s10 - s12) * rinv;
+    } else {
+        elj = eps * (s12 - 2.f * s6);
+        dlj = 12.f * eps * (s6 - s12) * rinv;
+    }
+    if (elj > kCap) { elj = kCap; dlj = 0.f; }
+    const float ex = __builtin_amdgcn_exp2f(-kDielLB * kLog2e * r);
+    const float den = 1.f + kDielK * ex;
+    const float iden = __builtin_amdgcn_rcpf(den);
+    const float epsr = kDielA + kDielB * iden;
+    const float depsr = kDielBKLB * ex * iden * iden;
+    const float ired = __builtin_amdgcn_rcpf(r * epsr);
+    const float eel = qq * ired;
+    const float del = -qq * (epsr + r * depsr) * ired * ired;
+    const float eds = ds * __builtin_amdgcn_exp2f(-kDsInv2S2 * kLog2e * r2);
+    const float dds = -eds * r * kDsInvS2;
+    e = elj + eel + eds;
+    w = clamped ? 0.f : (dlj + del + dds) * rinv;
+}
+
+// ---------------------------------------------------------------------------
+// One evaluation of E and dE/dgenotype for the individual held by this wave.
+// `gene` is gene `lane` (lanes >= G ignored); returns E (uniform) and writes
+// this lane's gradient component to `grad`.
+// ---------------------------------------------------------------------------
+template <int SLOTS, int VAR>
+__device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, float gene,
+                          float& grad, float* atom_out) {
+    const int lane = lane_id();
+    const int N = L.N;
+    // rigid-body genes (uniform)
+    const float tx = readlane(gene, 0), ty = readlane(gene, 1), tz = readlane(gene, 2);
+    const float qw0 = readlane(gene, 3), qx0 = readlane(gene, 4), qy0 = readlane(gene, 5),
+                qz0 = readlane(gene, 6);
+    const float qn = sqrtf(qw0 * qw0 + qx0 * qx0 + qy0 * qy0 + qz0 * qz0);
+    const float qinv = 1.0f / qn;
+    const float qw = qw0 * qinv, qx = qx0 * qinv, qy = qy0 * qinv, qz = qz0 * qinv;
+    float Rq[9];
+    Rq[0] = 1.f - 2.f * (qy * qy + qz * qz);
+    Rq[1] = 2.f * (qx * qy - qw * qz);
+    Rq[2] = 2.f * (qx * qz + qw * qy);
+    Rq[3] = 2.f * (qx * qy + qw * qz);
+    Rq[4] = 1.f - 2.f * (qx * qx + qz * qz);
+    Rq[5] = 2.f * (qy * qz - qw * qx);
+    Rq[6] = 2.f * (qx * qz - qw * qy);
+    Rq[7] = 2.f * (qy * qz + qw * qx);
+    Rq[8] = 1.f - 2.f * (qx * qx + qy * qy);
+
+    // torsion transforms: T_k(y) = R_k (y - p) + p, about the reference axis
+    const float psi = __shfl(gene, (7 + lane) & 63);
+    if (lane < L.T) {
+        float sn, cs;
+        sincosf(psi, &sn, &cs);
+        const float ux = L.tu[0], uy = L.tu[1], uz = L.tu[2];
+        const float oc = 1.f - cs;
+        float Rk[9];
+        Rk[0] = cs + oc * ux * ux;      Rk[1] = oc * ux * uy - sn * uz; Rk[2] = oc * ux * uz + sn * uy;
+        Rk[3] = oc * uy * ux + sn * uz; Rk[4] = cs + oc * uy * uy;      Rk[5] = oc * uy * uz - sn * ux;
+        Rk[6] = oc * uz * ux - sn * uy; Rk[7] = oc * uz * uy + sn * ux; Rk[8] = cs + oc * uz * uz;
+        float* o = sm.tk[lane];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            o[4 * r + 0] = Rk[3 * r + 0];
+            o[4 * r + 1] = Rk[3 * r + 1];
+            o[4 * r + 2] = Rk[3 * r + 2];
+            o[4 * r + 3] = L.tp[r] - (Rk[3 * r] * L.tp[0] + Rk[3 * r + 1] * L.tp[1] + Rk[3 * r + 2] * L.tp[2]);
+        }
+    }
+    __syncthreads();
+    // fragment transforms: product of enclosing torsions (root first), then
+    // the rigid body [Rq | t]
+    if (lane < L.NF) {
+        float M[12] = {1.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f};
+        const int len = sm.chain[lane][0];
+        for (int j = 0; j < len; ++j) {
+            const float* Tk = sm.tk[(int)sm.chain[lane][1 + j]];
+            float Nw[12];
+#pragma unroll
+            for (int r = 0; r < 3; ++r) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    Nw[4 * r + c] = M[4 * r] * Tk[c] + M[4 * r + 1] * Tk[4 + c] + M[4 * r + 2] * Tk[8 + c];
+                Nw[4 * r + 3] = M[4 * r] * Tk[3] + M[4 * r + 1] * Tk[7] + M[4 * r + 2] * Tk[11] + M[4 * r + 3];
+            }
+#pragma unroll
+            for (int i = 0; i < 12; ++i) M[i] = Nw[i];
+        }
+        float* o = sm.fw[lane];
+        const float tt[3] = {tx, ty, tz};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                o[4 * r + c] = Rq[3 * r] * M[c] + Rq[3 * r + 1] * M[4 + c] + Rq[3 * r + 2] * M[8 + c];
+            o[4 * r + 3] = Rq[3 * r] * M[3] + Rq[3 * r + 1] * M[7] + Rq[3 * r + 2] * M[11] + tt[r];
+        }
+    }
+    __syncthreads();
+    // atom positions
+    float x[SLOTS][3];
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int a = lane + kWave * s;
+        const float* W = sm.fw[L.frag[s]];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+            x[s][r] = W[4 * r] * L.y0[s][0] + W[4 * r + 1] * L.y0[s][1] + W[4 * r + 2] * L.y0[s][2] + W[4 * r + 3];
+        if (a < N) sm.dyn[a] = make_float4(x[s][0], x[s][1], x[s][2], L.chg[s][1]);
+    }
+    __syncthreads();
+
+    // grid term
+    float g[SLOTS][3];
+    float e_lane = 0.f;
+    float e_atom[SLOTS];
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int a = lane + kWave * s;
+        float e, gx, gy, gz;
+        grid_term(G, L.cls[s], L.chg[s][1], L.chg[s][2], x[s][0], x[s][1], x[s][2], e, gx, gy, gz);
+        const bool ok = a < N;
+        e_atom[s] = ok ? e : 0.f;
+        g[s][0] = ok ? gx : 0.f;
+        g[s][1] = ok ? gy : 0.f;
+        g[s][2] = ok ? gz : 0.f;
+        e_lane += e_atom[s];
+    }
+
+    // pair terms, circulant schedule
+    for (int st = 1; st <= L.steps; ++st) {
+        float fs[SLOTS][3];
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int a = lane + kWave * s;
+            int b = a + st;
+            b = b >= N ? b - N : b;
+            b = b < N ? b : 0;
+            const bool kept = (L.keep[s] >> (st - 1)) & 1ull;
+            const bool hb = (L.hbm[s] >> (st - 1)) & 1ull;
+            const bool hidx = (L.hbi[s] >> (st - 1)) & 1ull;
+            const float4 pd = sm.dyn[b];
+            const float4 pp = sm.par[b];
+            const float dx = pd.x - x[s][0], dy = pd.y - x[s][1], dz = pd.z - x[s][2];
+            const float r0 = hb ? (hidx ? L.hb[s][1] : L.hb[s][0]) : L.par[s][0] + pp.x;
+            const float ep = hb ? (hidx ? L.hb[s][3] : L.hb[s][2]) : L.par[s][1] * pp.y;
+            const float qq = L.chg[s][0] * pd.w;
+            const float ds = L.par[s][2] * pp.w + pp.z * L.par[s][3];
+            float e, w;
+            pair_term(dx, dy, dz, r0, ep, hb, qq, ds, e, w);
+            e = kept ? e : 0.f;
+            w = kept ? w : 0.f;
+            e_lane += e;
+            fs[s][0] = w * dx;
+            fs[s][1] = w * dy;
+            fs[s][2] = w * dz;
+            g[s][0] -= fs[s][0];
+            g[s][1] -= fs[s][1];
+            g[s][2] -= fs[s][2];
+        }
+        // the partner b = a + st receives +f: atom m takes it from atom m - st
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int m = lane + kWave * s;
+            int src = m - st;
+            src = src < 0 ? src + N : src;
+            const int sl = src & 63;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float v = __shfl(fs[0][c], sl);
+                if constexpr (SLOTS == 2) {
+                    const float v1 = __shfl(fs[1][c], sl);
+                    v = (src >= kWave) ? v1 : v;
+                }
+                g[s][c] += v;
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s)
+        if (lane + kWave * s >= N) { g[s][0] = g[s][1] = g[s][2] = 0.f; }
+
+    // block sums: {E, gx, gy, gz} and the torque about t
+    float4 eg = make_float4(e_lane, 0.f, 0.f, 0.f);
+    float4 tq = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        eg.y += g[s][0]; eg.z += g[s][1]; eg.w += g[s][2];
+        const float rx = x[s][0] - tx, ry = x[s][1] - ty, rz = x[s][2] - tz;
+        tq.x += ry * g[s][2] - rz * g[s][1];
+        tq.y += rz * g[s][0] - rx * g[s][2];
+        tq.z += rx * g[s][1] - ry * g[s][0];
+    }
+    const float4 EG = sum4<VAR>(eg);
+    const float4 TQ = sum4_fp32<VAR>(tq);
+
+    // torsion torques: prefix sums of (g, x cross g) in depth-first order
+    float P[SLOTS][6];
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        P[s][0] = g[s][0]; P[s][1] = g[s][1]; P[s][2] = g[s][2];
+        P[s][3] = x[s][1] * g[s][2] - x[s][2] * g[s][1];
+        P[s][4] = x[s][2] * g[s][0] - x[s][0] * g[s][2];
+        P[s][5] = x[s][0] * g[s][1] - x[s][1] * g[s][0];
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        P[0][c] = wave_scan(P[0][c]);
+        if constexpr (SLOTS == 2) P[1][c] = wave_scan(P[1][c]) + readlane(P[0][c], 63);
+    }
+    float gpsi = 0.f;
+    {
+        const int hi = L.t_end - 1, lo = L.t_first - 1;
+        float S[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            float ph = __shfl(P[0][c], hi & 63);
+            float pl = __shfl(P[0][c], lo & 63);
+            if constexpr (SLOTS == 2) {
+                const float ph1 = __shfl(P[1][c], hi & 63);
+                const float pl1 = __shfl(P[1][c], lo & 63);
+                ph = hi >= kWave ? ph1 : ph;
+                pl = lo >= kWave ? pl1 : pl;
+            }
+            S[c] = ph - pl;
+        }
+        const float4 xa = sm.dyn[L.t_apos];
+        const float4 xb = sm.dyn[L.t_bpos];
+        float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
+        const float il = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
+        ux *= il; uy *= il; uz *= il;
+        // S_xg - x_a cross S_g
+        const float mx = S[3] - (xa.y * S[2] - xa.z * S[1]);
+        const float my = S[4] - (xa.z * S[0] - xa.x * S[2]);
+        const float mz = S[5] - (xa.x * S[1] - xa.y * S[0]);
+        gpsi = (lane < L.T) ? ux * mx + uy * my + uz * mz : 0.f;
+    }
+    // gradient with respect to the genotype
+    {
+        // (2/|q|) (0, tau) (x) q_hat
+        const float k2 = 2.0f * qinv;
+        const float gw = -(TQ.x * qx + TQ.y * qy + TQ.z * qz);
+        const float gqx = qw * TQ.x + (TQ.y * qz - TQ.z * qy);
+        const float gqy = qw * TQ.y + (TQ.z * qx - TQ.x * qz);
+        const float gqz = qw * TQ.z + (TQ.x * qy - TQ.y * qx);
+        const float gt = __shfl(gpsi, (lane - 7) & 63);
+        float gr = gt;
+        gr = lane == 0 ? EG.y : gr;
+        gr = lane == 1 ? EG.z : gr;
+        gr = lane == 2 ? EG.w : gr;
+        gr = lane == 3 ? k2 * gw : gr;
+        gr = lane == 4 ? k2 * gqx : gr;
+        gr = lane == 5 ? k2 * gqy : gr;
+        gr = lane == 6 ? k2 * gqz : gr;
+        grad = gr;
+    }
+    if (atom_out) {
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) {
+            const int a = lane + kWave * s;
+            if (a < N) {
+                float4* o = reinterpret_cast<float4*>(atom_out) + 2 * L.orig[s];
+                o[0] = make_float4(x[s][0], x[s][1], x[s][2], e_atom[s]);
+                o[1] = make_float4(g[s][0], g[s][1], g[s][2], 0.f);
+            }
+        }
+    }
+    return EG.x;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels.
+// ---------------------------------------------------------------------------
+
+template <int SLOTS, int VAR>
+__global__ __launch_bounds__(64) void score_kernel(GridParams G, const uint8_t* __restrict__ blob,
+                                                   int n, const float* __restrict__ gen,
+                                                   float* __restrict__ energy,
+                                                   float* __restrict__ grad,
+                                                   float* __restrict__ atom_out) {
+    __shared__ Smem sm;
+    Lig<SLOTS> L;
+    load_ligand<SLOTS>(blob, sm, L);
+    const int lane = lane_id();
+    const int ind = blockIdx.x;
+    if (ind >= n) return;
+    const float gene = lane < L.G ? gen[(size_t)ind * L.G + lane] : 0.f;
+    float gr;
+    float* ao = atom_out ? atom_out + (size_t)ind * L.N * 8 : nullptr;
+    const float E = evaluate<SLOTS, VAR>(G, sm, L, gene, gr, ao);
+    if (lane == 0) energy[ind] = E;
+    if (grad && lane < L.G) grad[(size_t)ind * L.G + lane] = gr;
+}
+
+template <int SLOTS, int VAR>
+__device__ void local_search_one(const DevItem& it, int ind, Smem& sm, const Lig<SLOTS>& L,
+                                 int iterations, float rho, float eps, bool final_eval) {
+    const int lane = lane_id();
+    const int G = L.G;
+    const bool act = lane < G;
+    const size_t o = (size_t)ind * G + lane;
+    float x = act ? it.genotype[o] : 0.f;
+    float ag = act ? it.acc_g2[o] : 0.f;
+    float ad = act ? it.acc_dx2[o] : 0.f;
+    float bx = act ? it.best_genotype[o] : 0.f;
+    float bestE = it.best_energy[ind];
+    float lastE = it.energy[ind];
+    for (int iter = 0; iter < iterations; ++iter) {
+        float gr;
+        const float E = evaluate<SLOTS, VAR>(it.grid, sm, L, x, gr, nullptr);
+        lastE = E;
+        if (E < bestE) { bestE = E; bx = x; }
+        gr = act ? gr : 0.f;
+        ag = rho * ag + (1.f - rho) * gr * gr;
+        const float dx = -(sqrtf(ad + eps) / sqrtf(ag + eps)) * gr;
+        ad = rho * ad + (1.f - rho) * dx * dx;
+        float xn = x + dx;
+        const bool isq = lane >= 3 && lane < 7;
+        const float q2 = isq ? xn * xn : 0.f;
+        const float nq = sqrtf((readlane(q2, 3) + readlane(q2, 4)) + (readlane(q2, 5) + readlane(q2, 6)));
+        if (isq) xn = (nq >= 1e-6f) ? xn / nq : x;
+        x = act ? xn : 0.f;
+    }
+    if (final_eval) {
+        float gr;
+        const float E = evaluate<SLOTS, VAR>(it.grid, sm, L, x, gr, nullptr);
+        lastE = E;
+        if (E < bestE) { bestE = E; bx = x; }
+    }
+    if (act) {
+        it.genotype[o] = x;
+        it.acc_g2[o] = ag;
+        it.acc_dx2[o] = ad;
+        it.best_genotype[o] = bx;
+    }
+    if (lane == 0) {
+        it.best_energy[ind] = bestE;
+        it.energy[ind] = lastE;
+        it.iters_done[ind] += iterations;
+    }
+}
+
+template <int SLOTS>
+__device__ void ls_dispatch(int var_uniform, const DevItem& it, int ind, Smem& sm,
+                            const Lig<SLOTS>& L, const LsParams& p) {
+    const int var = var_uniform >= 0 ? var_uniform : it.variant;
+    const bool fin = p.final_eval != 0;
+    switch (var) {
+        case DOCK_REDUCE_MFMA_F32:
+            local_search_one<SLOTS, DOCK_REDUCE_MFMA_F32>(it, ind, sm, L, p.iterations, p.rho, p.eps, fin); break;
+        case DOCK_REDUCE_MFMA_BF16:
+            local_search_one<SLOTS, DOCK_REDUCE_MFMA_BF16>(it, ind, sm, L, p.iterations, p.rho, p.eps, fin); break;
+        case DOCK_REDUCE_MFMA_F16:
+            local_search_one<SLOTS, DOCK_REDUCE_MFMA_F16>(it, ind, sm, L, p.iterations, p.rho, p.eps, fin); break;
+        case DOCK_REDUCE_MFMA_BF16X3:
+            local_search_one<SLOTS, DOCK_REDUCE_MFMA_BF16X3>(it, ind, sm, L, p.iterations, p.rho, p.eps, fin); break;
+        default:
+            local_search_one<SLOTS, DOCK_REDUCE_SHUFFLE>(it, ind, sm, L, p.iterations, p.rho, p.eps, fin); break;
+    }
+}
+
+template <int SLOTS, int VAR>
+__device__ void ls_run(const DevItem& it, int ind, Smem& sm, const Lig<SLOTS>& L, const LsParams& p) {
+    if constexpr (VAR >= 0)
+        local_search_one<SLOTS, VAR>(it, ind, sm, L, p.iterations, p.rho, p.eps, p.final_eval != 0);
+    else
+        ls_dispatch<SLOTS>(-1, it, ind, sm, L, p);
+}
+
+// Persistent local-search kernel. Work units are individuals, numbered item by
+// item in the order the host gives (longest items first); each wave takes the
+// next unit from a global counter until none is left, reloading the ligand
+// only when the item changes. Every wave exits once the counter passes the
+// last unit.
+template <int MODE, int VAR>
+__global__ __launch_bounds__(64) void ls_kernel(LsParams p) {
+    __shared__ Smem sm;
+    const int lane = lane_id();
+    int cur_item = -1;
+    Lig<(MODE == docklaunch::kSlots1) ? 1 : 2> L2;
+    Lig<1> L1;
+    while (true) {
+        int u = 0;
+        if (lane == 0) u = atomicAdd(p.counter, 1);
+        u = __shfl(u, 0);
+        if (u >= p.total_units) break;
+        int lo = 0, hi = p.n_items - 1;
+        while (lo < hi) {  // last item with unit_begin <= u
+            const int mid = (lo + hi + 1) >> 1;
+            if (p.items[mid].unit_begin <= u) lo = mid; else hi = mid - 1;
+        }
+        const DevItem& it = p.items[lo];
+        const int ind = u - it.unit_begin;
+        if constexpr (MODE == docklaunch::kSlots1) {
+            if (lo != cur_item) { __syncthreads(); load_ligand<1>(it.blob, sm, L2); cur_item = lo; }
+            ls_run<1, VAR>(it, ind, sm, L2, p);
+        } else if constexpr (MODE == docklaunch::kSlots2) {
+            if (lo != cur_item) { __syncthreads(); load_ligand<2>(it.blob, sm, L2); cur_item = lo; }
+            ls_run<2, VAR>(it, ind, sm, L2, p);
+        } else {
+            if (it.slots == 1) {
+                if (lo != cur_item) { __syncthreads(); load_ligand<1>(it.blob, sm, L1); cur_item = lo; }
+                ls_run<1, VAR>(it, ind, sm, L1, p);
+            } else {
+                if (lo != cur_item) { __syncthreads(); load_ligand<2>(it.blob, sm, L2); cur_item = lo; }
+                ls_run<2, VAR>(it, ind, sm, L2, p);
+            }
+        }
+    }
+}
+
+// Isolated block sum (reduction test kernel): every thread holds a float4;
+// each wave reduces with the chosen variant, the per-wave results meet in
+// LDS after one barrier and every thread adds them in the same fixed order.
+template <int VAR>
+__global__ __launch_bounds__(1024) void block_sum4_kernel(const float4* __restrict__ in,
+                                                          float4* __restrict__ out, int repeat,
+                                                          float chain) {
+    __shared__ float4 part[2][16];
+    const int t = threadIdx.x;
+    const int nw = blockDim.x >> 6;
+    const int w = t >> 6;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + t;
+    const float4 v0 = in[idx];
+    float4 v = v0;
+    float4 tot = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int r = 0; r < repeat; ++r) {
+        const float4 ws = sum4<VAR>(v);
+        if ((t & 63) == 0) part[r & 1][w] = ws;
+        __syncthreads();
+        tot = part[r & 1][0];
+        for (int j = 1; j < nw; ++j) {
+            const float4 pj = part[r & 1][j];
+            tot.x += pj.x; tot.y += pj.y; tot.z += pj.z; tot.w += pj.w;
+        }
+        v = make_float4(v0.x + chain * tot.x, v0.y + chain * tot.y, v0.z + chain * tot.z,
+                        v0.w + chain * tot.w);
+    }
+    out[idx] = tot;
+}
+
+// The Sec. 3 baseline, for the reduction test only: per component, a wave
+// shuffle tree, then the first lane of each wave adds its value into a
+// shared accumulator with an atomic, a barrier, and every thread reads the
+// accumulator back (three barriers per component, as described there).
+__global__ __launch_bounds__(1024) void block_sum4_atomic_kernel(const float4* __restrict__ in,
+                                                                 float4* __restrict__ out,
+                                                                 int repeat, float chain) {
+    __shared__ float acc[4];
+    const int t = threadIdx.x;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + t;
+    const float4 v0 = in[idx];
+    float4 v = v0;
+    float4 tot = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int r = 0; r < repeat; ++r) {
+        float vc[4] = {v.x, v.y, v.z, v.w};
+        float res[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (t == 0) acc[c] = 0.f;
+            __syncthreads();
+            float s = vc[c];
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
+            if ((t & 63) == 0) atomicAdd(&acc[c], s);
+            __syncthreads();
+            res[c] = acc[c];
+            __syncthreads();
+        }
+        tot = make_float4(res[0], res[1], res[2], res[3]);
+        v = make_float4(v0.x + chain * tot.x, v0.y + chain * tot.y, v0.z + chain * tot.z,
+                        v0.w + chain * tot.w);
+    }
+    out[idx] = tot;
+}
+
+template <int VAR>
+hipError_t launch_score_v(const GridParams& g, const uint8_t* blob, int slots, int n,
+                          const float* gen, float* energy, float* grad, float* atom_out,
+                          hipStream_t st) {
+    if (slots == 1)
+        hipLaunchKernelGGL((score_kernel<1, VAR>), dim3(n), dim3(64), 0, st, g, blob, n, gen, energy, grad, atom_out);
+    else
+        hipLaunchKernelGGL((score_kernel<2, VAR>), dim3(n), dim3(64), 0, st, g, blob, n, gen, energy, grad, atom_out);
+    return hipGetLastError();
+}
+
+template <int MODE>
+const void* ls_kernel_ptr(int var) {
+    switch (var) {
+        case 0: return reinterpret_cast<const void*>(&ls_kernel<MODE, 0>);
+        case 1: return reinterpret_cast<const void*>(&ls_kernel<MODE, 1>);
+        case 2: return reinterpret_cast<const void*>(&ls_kernel<MODE, 2>);
+        case 3: return reinterpret_cast<const void*>(&ls_kernel<MODE, 3>);
+        case 4: return reinterpret_cast<const void*>(&ls_kernel<MODE, 4>);
+        default: return reinterpret_cast<const void*>(&ls_kernel<MODE, -1>);
+    }
+}
+
+const void* ls_kernel_for(int mode, int var) {
+    if (mode == docklaunch::kSlots1) return ls_kernel_ptr<docklaunch::kSlots1>(var);
+    if (mode == docklaunch::kSlots2) return ls_kernel_ptr<docklaunch::kSlots2>(var);
+    return ls_kernel_ptr<docklaunch::kSlotsAny>(var);
+}
+
+}  // namespace
+
+namespace docklaunch {
+
+hipError_t launch_score(const GridParams& g, const uint8_t* blob, int slots, int n,
+                        const float* genotypes, float* energy, float* grad, float* atom_out,
+                        int variant, hipStream_t stream) {
+    switch (variant) {
+        case DOCK_REDUCE_SHUFFLE: return launch_score_v<0>(g, blob, slots, n, genotypes, energy, grad, atom_out, stream);
+        case DOCK_REDUCE_MFMA_F32: return launch_score_v<1>(g, blob, slots, n, genotypes, energy, grad, atom_out, stream);
+        case DOCK_REDUCE_MFMA_BF16: return launch_score_v<2>(g, blob, slots, n, genotypes, energy, grad, atom_out, stream);
+        case DOCK_REDUCE_MFMA_F16: return launch_score_v<3>(g, blob, slots, n, genotypes, energy, grad, atom_out, stream);
+        case DOCK_REDUCE_MFMA_BF16X3: return launch_score_v<4>(g, blob, slots, n, genotypes, energy, grad, atom_out, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_ls(const LsParams& p, int mode, int variant_uniform, int grid_blocks,
+                     hipStream_t stream) {
+    const void* k = ls_kernel_for(mode, variant_uniform);
+    LsParams pp = p;
+    void* args[] = {&pp};
+    return hipLaunchKernel(k, dim3(grid_blocks), dim3(64), args, 0, stream);
+}
+
+int ls_blocks_per_cu(int mode, int variant_uniform) {
+    int nb = 0;
+    const void* k = ls_kernel_for(mode, variant_uniform);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64, 0) != hipSuccess) return 0;
+    return nb;
+}
+
+hipError_t launch_block_sum4(const float* in, float* out, int n_blocks, int threads, int variant,
+                             int repeat, hipStream_t stream) {
+    const float4* i4 = reinterpret_cast<const float4*>(in);
+    float4* o4 = reinterpret_cast<float4*>(out);
+    const float chain = 0.0f;
+    switch (variant) {
+        case 0: hipLaunchKernelGGL((block_sum4_kernel<0>), dim3(n_blocks), dim3(threads), 0, stream, i4, o4, repeat, chain); break;
+        case 1: hipLaunchKernelGGL((block_sum4_kernel<1>), dim3(n_blocks), dim3(threads), 0, stream, i4, o4, repeat, chain); break;
+        case 2: hipLaunchKernelGGL((block_sum4_kernel<2>), dim3(n_blocks), dim3(threads), 0, stream, i4, o4, repeat, chain); break;
+        case 3: hipLaunchKernelGGL((block_sum4_kernel<3>), dim3(n_blocks), dim3(threads), 0, stream, i4, o4, repeat, chain); break;
+        case 4: hipLaunchKernelGGL((block_sum4_kernel<4>), dim3(n_blocks), dim3(threads), 0, stream, i4, o4, repeat, chain); break;
+        case 5: hipLaunchKernelGGL(block_sum4_atomic_kernel, dim3(n_blocks), dim3(threads), 0, stream, i4, o4, repeat, chain); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace docklaunch

@@ -1,0 +1,66 @@
+// Internal interface between the C ABI (dock_abi.cpp) and the kernels
+// (dock_kernels.hip). Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace docklaunch {
+
+// Receptor grid as the kernels see it.
+struct GridParams {
+    const float* maps;   // [n_maps][nz][ny][nx]
+    int32_t nx, ny, nz, n_maps;
+    float spacing;
+    float origin[3];
+    float hi[3];         // origin + (n - 1) * spacing per axis
+};
+
+// One local-search item as the kernels see it (lives in the workspace).
+struct DevItem {
+    GridParams grid;
+    const uint8_t* blob;
+    float* genotype;
+    float* acc_g2;
+    float* acc_dx2;
+    float* best_genotype;
+    float* best_energy;
+    float* energy;
+    int32_t* iters_done;
+    int32_t n;
+    int32_t variant;
+    int32_t slots;          // 1 if n_atoms <= 64, else 2
+    int32_t unit_begin;     // first work unit (individual) of this item
+};
+
+struct LsParams {
+    const DevItem* items;   // device
+    int32_t* counter;       // device, zero at launch
+    int32_t n_items;
+    int32_t total_units;
+    int32_t iterations;
+    float rho, eps;
+    int32_t final_eval;
+};
+
+// Workspace layout: [int32 counter, padded to 64 B][DevItem x n_items]
+constexpr int64_t kWorkspaceHeader = 64;
+
+// ls kernel families: slots 1, slots 2, or both (runtime per item)
+enum LsMode { kSlots1 = 1, kSlots2 = 2, kSlotsAny = 3 };
+
+hipError_t launch_score(const GridParams& g, const uint8_t* blob, int slots, int n,
+                        const float* genotypes, float* energy, float* grad, float* atom_out,
+                        int variant, hipStream_t stream);
+
+// variant_uniform: DOCK_REDUCE_* when every item uses it, -1 for mixed items.
+hipError_t launch_ls(const LsParams& p, int mode, int variant_uniform, int grid_blocks,
+                     hipStream_t stream);
+
+// Resident 64-thread blocks per CU for the ls kernel family chosen by
+// (mode, variant_uniform); 0 on error.
+int ls_blocks_per_cu(int mode, int variant_uniform);
+
+hipError_t launch_block_sum4(const float* in, float* out, int n_blocks, int threads,
+                             int variant, int repeat, hipStream_t stream);
+
+}  // namespace docklaunch

@@ -1,0 +1,292 @@
+// Host-side ligand preparation (see dock_prep.h).
+//
+// Method context (Sec. 2.1): a pose is {position, orientation, one angle per
+// rotatable bond}; the score adds pairwise intramolecular terms. The
+// preparation fixes, once per ligand, which atoms each torsion turns, how
+// torsions nest, and which atom pairs contribute. Readings used here: the
+// moving side of a torsion is the side away from the root atom; pairs are
+// kept when >= 4 bonds apart and in different rigid fragments; a pair is a
+// hydrogen-bond pair when one atom is a donor class and the other an
+// acceptor class.
+#include "dock_prep.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace dockprep {
+namespace {
+
+constexpr double kElec = 332.06363;   // kcal A / (mol e^2)
+constexpr double kQSolv = 0.01097;    // charge term of the solvation parameter
+
+size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+int role_index(const int32_t list[2], int c) {
+    if (list[0] == c) return 0;
+    if (list[1] == c) return 1;
+    return -1;
+}
+
+}  // namespace
+
+int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
+    const int N = d.n_atoms;
+    const int T = d.n_torsions;
+    if (N < 1) { err = "n_atoms must be >= 1"; return DOCK_EINVAL; }
+    if (N > dockblob::kMaxAtoms) { err = "n_atoms exceeds DOCK_MAX_ATOMS"; return DOCK_EUNSUPPORTED; }
+    if (T < 0) { err = "n_torsions must be >= 0"; return DOCK_EINVAL; }
+    if (T > dockblob::kMaxTorsions) { err = "n_torsions exceeds DOCK_MAX_TORSIONS"; return DOCK_EUNSUPPORTED; }
+    if (!d.xyz || !d.charge || !d.cls || (N > 1 && !d.bonds) || (T > 0 && !d.rot_bonds) || !d.ff) {
+        err = "NULL array in ligand description"; return DOCK_EINVAL;
+    }
+    const dock_ff_params& ff = *d.ff;
+    if (ff.n_classes < 1 || ff.n_classes > DOCK_MAX_CLASSES || !ff.radius || !ff.eps || !ff.solv || !ff.vol) {
+        err = "bad force-field table"; return DOCK_EINVAL;
+    }
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            if (ff.donor[i] >= 0 && ff.donor[i] == ff.acceptor[j]) {
+                err = "a class cannot be both donor and acceptor"; return DOCK_EINVAL;
+            }
+    if (d.root_atom < 0 || d.root_atom >= N) { err = "root_atom out of range"; return DOCK_EINVAL; }
+    for (int i = 0; i < N; ++i) {
+        if (d.cls[i] < 0 || d.cls[i] >= ff.n_classes) { err = "atom class out of range"; return DOCK_EINVAL; }
+        if (!std::isfinite(d.xyz[3 * i]) || !std::isfinite(d.xyz[3 * i + 1]) ||
+            !std::isfinite(d.xyz[3 * i + 2]) || !std::isfinite(d.charge[i])) {
+            err = "non-finite coordinate or charge"; return DOCK_EINVAL;
+        }
+    }
+    // adjacency of the bond tree
+    std::vector<std::vector<int>> adj(N);
+    for (int e = 0; e < N - 1; ++e) {
+        int u = d.bonds[2 * e], v = d.bonds[2 * e + 1];
+        if (u < 0 || v < 0 || u >= N || v >= N || u == v) { err = "bond endpoint out of range"; return DOCK_EINVAL; }
+        adj[u].push_back(v);
+        adj[v].push_back(u);
+    }
+    for (auto& a : adj) {
+        std::sort(a.begin(), a.end());
+        if (std::adjacent_find(a.begin(), a.end()) != a.end()) { err = "duplicate bond"; return DOCK_EINVAL; }
+    }
+    // depth-first preorder from the root, children by increasing index
+    std::vector<int> parent(N, -2), depth(N, 0), order;
+    order.reserve(N);
+    std::vector<int> stack{d.root_atom};
+    parent[d.root_atom] = -1;
+    while (!stack.empty()) {
+        int u = stack.back();
+        stack.pop_back();
+        order.push_back(u);
+        for (auto it = adj[u].rbegin(); it != adj[u].rend(); ++it) {
+            int v = *it;
+            if (v == parent[u]) continue;
+            if (parent[v] != -2) { err = "bonds contain a cycle"; return DOCK_EINVAL; }
+            parent[v] = u;
+            depth[v] = depth[u] + 1;
+            stack.push_back(v);
+        }
+    }
+    if ((int)order.size() != N) { err = "bonds do not connect every atom"; return DOCK_EINVAL; }
+    std::vector<int> pos(N), size(N, 1);
+    for (int p = 0; p < N; ++p) pos[order[p]] = p;
+    for (int p = N - 1; p > 0; --p) size[parent[order[p]]] += size[order[p]];
+
+    // torsions
+    std::vector<int> tor_a(T), tor_b(T), tor_of_b(N, -1);
+    for (int k = 0; k < T; ++k) {
+        int e = d.rot_bonds[k];
+        if (e < 0 || e >= N - 1) { err = "rotatable bond index out of range"; return DOCK_EINVAL; }
+        int u = d.bonds[2 * e], v = d.bonds[2 * e + 1];
+        int a = (parent[v] == u) ? u : v;
+        int b = (a == u) ? v : u;
+        if (adj[a].size() < 2 || adj[b].size() < 2) { err = "rotatable bond is not internal"; return DOCK_EINVAL; }
+        if (tor_of_b[b] >= 0) { err = "rotatable bond listed twice"; return DOCK_EINVAL; }
+        tor_a[k] = a;
+        tor_b[k] = b;
+        tor_of_b[b] = k;
+    }
+    // fragment of each atom: the nearest torsion b at or above it (k+1), else 0
+    std::vector<int> frag(N, 0);
+    for (int p = 0; p < N; ++p) {
+        int i = order[p];
+        frag[i] = (tor_of_b[i] >= 0) ? tor_of_b[i] + 1 : (parent[i] >= 0 ? frag[parent[i]] : 0);
+    }
+    // fragment chains (root-first torsion lists); parents come first in preorder
+    const int NF = T + 1;
+    std::vector<std::vector<int>> chain(NF);
+    int max_depth = 0;
+    for (int p = 0; p < N; ++p) {
+        int b = order[p];
+        int k = tor_of_b[b];
+        if (k < 0) continue;
+        chain[k + 1] = chain[frag[tor_a[k]]];
+        chain[k + 1].push_back(k);
+        max_depth = std::max(max_depth, (int)chain[k + 1].size());
+    }
+    // kept pairs (original indices) and their hydrogen-bond flag
+    auto graph_dist = [&](int i, int j) {
+        int a = i, b = j, da = depth[i], db = depth[j];
+        while (da > db) { a = parent[a]; --da; }
+        while (db > da) { b = parent[b]; --db; }
+        while (a != b) { a = parent[a]; b = parent[b]; --da; }
+        return depth[i] + depth[j] - 2 * da;
+    };
+    std::vector<uint8_t> keep(size_t(N) * N, 0), hbp(size_t(N) * N, 0);
+    int n_pairs = 0;
+    for (int i = 0; i < N; ++i)
+        for (int j = i + 1; j < N; ++j) {
+            if (frag[i] == frag[j] || graph_dist(i, j) < 4) continue;
+            keep[size_t(i) * N + j] = keep[size_t(j) * N + i] = 1;
+            int ci = d.cls[i], cj = d.cls[j];
+            bool hb = (role_index(ff.donor, ci) >= 0 && role_index(ff.acceptor, cj) >= 0) ||
+                      (role_index(ff.acceptor, ci) >= 0 && role_index(ff.donor, cj) >= 0);
+            hbp[size_t(i) * N + j] = hbp[size_t(j) * N + i] = hb;
+            ++n_pairs;
+        }
+
+    // ---- pack the blob ----
+    using namespace dockblob;
+    Header h;
+    std::memset(&h, 0, sizeof(h));
+    size_t off = sizeof(Header);
+    auto take = [&](size_t bytes) { size_t o = off; off = align16(off + bytes); return (int32_t)o; };
+    h.off_ref = take(16 * size_t(N));
+    h.off_par = take(16 * size_t(N));
+    h.off_chg = take(16 * size_t(N));
+    h.off_hb = take(16 * size_t(N));
+    h.off_int = take(16 * size_t(N));
+    h.off_mask = take(8 * 3 * size_t(N));
+    h.off_tors = take(sizeof(Torsion) * size_t(T));
+    h.off_chain = take(size_t(NF) * kChainStride);
+    h.magic = kMagic;
+    h.n_atoms = N;
+    h.n_torsions = T;
+    h.n_frag = NF;
+    h.n_genes = 7 + T;
+    h.n_pairs = n_pairs;
+    h.max_depth = max_depth;
+    h.n_steps = N / 2;
+    h.total_bytes = (int32_t)off;
+    int max_class = 0;
+    for (int i = 0; i < N; ++i) max_class = std::max(max_class, (int)d.cls[i]);
+    h.max_class = max_class;
+
+    std::vector<uint8_t> blob(off, 0);
+    std::memcpy(blob.data(), &h, sizeof(h));
+    double cen[3] = {0, 0, 0};
+    for (int i = 0; i < N; ++i)
+        for (int c = 0; c < 3; ++c) cen[c] += d.xyz[3 * i + c];
+    for (int c = 0; c < 3; ++c) cen[c] /= N;
+    auto y0 = [&](int i, int c) { return d.xyz[3 * i + c] - cen[c]; };
+    float* ref = reinterpret_cast<float*>(blob.data() + h.off_ref);
+    float* par = reinterpret_cast<float*>(blob.data() + h.off_par);
+    float* chg = reinterpret_cast<float*>(blob.data() + h.off_chg);
+    float* hbv = reinterpret_cast<float*>(blob.data() + h.off_hb);
+    int32_t* iv = reinterpret_cast<int32_t*>(blob.data() + h.off_int);
+    uint64_t* mk = reinterpret_cast<uint64_t*>(blob.data() + h.off_mask);
+    for (int p = 0; p < N; ++p) {
+        int i = order[p];
+        int c = d.cls[i];
+        double q = d.charge[i];
+        for (int a = 0; a < 3; ++a) ref[4 * p + a] = (float)y0(i, a);
+        par[4 * p + 0] = (float)ff.radius[c];
+        par[4 * p + 1] = (float)std::sqrt(ff.eps[c]);
+        par[4 * p + 2] = (float)(ff.solv[c] + kQSolv * std::fabs(q));
+        par[4 * p + 3] = (float)ff.vol[c];
+        chg[4 * p + 0] = (float)(kElec * q);
+        chg[4 * p + 1] = (float)q;
+        chg[4 * p + 2] = (float)std::fabs(q);
+        int di = role_index(ff.donor, c), ai = role_index(ff.acceptor, c);
+        if (di >= 0) {
+            hbv[4 * p + 0] = (float)ff.hb_r0[di][0];
+            hbv[4 * p + 1] = (float)ff.hb_r0[di][1];
+            hbv[4 * p + 2] = (float)ff.hb_eps[di][0];
+            hbv[4 * p + 3] = (float)ff.hb_eps[di][1];
+        } else if (ai >= 0) {
+            hbv[4 * p + 0] = (float)ff.hb_r0[0][ai];
+            hbv[4 * p + 1] = (float)ff.hb_r0[1][ai];
+            hbv[4 * p + 2] = (float)ff.hb_eps[0][ai];
+            hbv[4 * p + 3] = (float)ff.hb_eps[1][ai];
+        }
+        iv[4 * p + 0] = c;
+        iv[4 * p + 1] = frag[i];
+        iv[4 * p + 2] = i;
+        // offset-space masks
+        uint64_t kept = 0, hbm = 0, hbi = 0;
+        for (int s = 1; s <= N / 2; ++s) {
+            if ((N % 2 == 0) && s == N / 2 && p >= N / 2) continue;
+            int q2 = (p + s) % N;
+            int j = order[q2];
+            if (!keep[size_t(i) * N + j]) continue;
+            kept |= uint64_t(1) << (s - 1);
+            if (hbp[size_t(i) * N + j]) {
+                hbm |= uint64_t(1) << (s - 1);
+                int cj = d.cls[j];
+                int idx = role_index(ff.donor, cj) >= 0 ? role_index(ff.donor, cj) : role_index(ff.acceptor, cj);
+                if (idx == 1) hbi |= uint64_t(1) << (s - 1);
+            }
+        }
+        mk[p] = kept;
+        mk[N + p] = hbm;
+        mk[2 * N + p] = hbi;
+    }
+    Torsion* tr = reinterpret_cast<Torsion*>(blob.data() + h.off_tors);
+    for (int k = 0; k < T; ++k) {
+        int a = tor_a[k], b = tor_b[k];
+        double u[3], nrm = 0;
+        for (int c = 0; c < 3; ++c) { u[c] = y0(b, c) - y0(a, c); nrm += u[c] * u[c]; }
+        nrm = std::sqrt(nrm);
+        for (int c = 0; c < 3; ++c) {
+            tr[k].p[c] = (float)y0(a, c);
+            tr[k].u[c] = (float)(u[c] / nrm);
+        }
+        tr[k].a_pos = pos[a];
+        tr[k].b_pos = pos[b];
+        tr[k].first = pos[b];
+        tr[k].end = pos[b] + size[b];
+    }
+    int8_t* ch = reinterpret_cast<int8_t*>(blob.data() + h.off_chain);
+    for (int f = 0; f < NF; ++f) {
+        ch[f * kChainStride] = (int8_t)chain[f].size();
+        for (size_t j = 0; j < chain[f].size(); ++j) ch[f * kChainStride + 1 + j] = (int8_t)chain[f][j];
+    }
+
+    P.n_atoms = N;
+    P.n_torsions = T;
+    P.n_frag = NF;
+    P.max_depth = max_depth;
+    P.n_pairs = n_pairs;
+    P.max_class = max_class;
+    P.order.assign(order.begin(), order.end());
+    P.pos.assign(pos.begin(), pos.end());
+    P.tors_a.assign(tor_a.begin(), tor_a.end());
+    P.tors_b.assign(tor_b.begin(), tor_b.end());
+    P.tors_first.resize(T);
+    P.tors_end.resize(T);
+    for (int k = 0; k < T; ++k) { P.tors_first[k] = tr[k].first; P.tors_end[k] = tr[k].end; }
+    P.frag_of_atom.assign(frag.begin(), frag.end());
+    P.blob.swap(blob);
+    return DOCK_OK;
+}
+
+void decode_pairs(const Prepared& P, std::vector<uint32_t>& pairs, std::vector<uint8_t>& hb) {
+    using namespace dockblob;
+    const Header* h = reinterpret_cast<const Header*>(P.blob.data());
+    const int N = h->n_atoms;
+    const uint64_t* mk = reinterpret_cast<const uint64_t*>(P.blob.data() + h->off_mask);
+    std::vector<std::pair<uint32_t, uint8_t>> v;
+    for (int p = 0; p < N; ++p)
+        for (int s = 1; s <= N / 2; ++s) {
+            if (!((mk[p] >> (s - 1)) & 1)) continue;
+            int i = P.order[p], j = P.order[(p + s) % N];
+            uint32_t lo = (uint32_t)std::min(i, j), hi = (uint32_t)std::max(i, j);
+            v.push_back({(lo << 16) | hi, (uint8_t)((mk[N + p] >> (s - 1)) & 1)});
+        }
+    std::sort(v.begin(), v.end());
+    pairs.resize(v.size());
+    hb.resize(v.size());
+    for (size_t k = 0; k < v.size(); ++k) { pairs[k] = v[k].first; hb[k] = v[k].second; }
+}
+
+}  // namespace dockprep

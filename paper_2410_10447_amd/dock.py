@@ -1,0 +1,389 @@
+"""Python binding of the docking C ABI (include/dock.h), via ctypes.
+
+Argument marshalling only: every computation runs in libdockmi.so. PyTorch is
+used for device memory (tensors) and streams. The library must be built
+(``python -m paper_2410_10447_amd.build_lib``); importing this module on a
+machine without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdockmi.so")
+
+DOCK_OK = 0
+DOCK_EINVAL = -1
+DOCK_ENOMEM = -2
+DOCK_EDEVICE = -3
+DOCK_EUNSUPPORTED = -4
+
+REDUCE_SHUFFLE = 0
+REDUCE_MFMA_F32 = 1
+REDUCE_MFMA_BF16 = 2
+REDUCE_MFMA_F16 = 3
+REDUCE_MFMA_BF16X3 = 4
+REDUCE_SHARED_ATOMIC = 5
+VARIANT_NAMES = {0: "shuffle", 1: "mfma_f32", 2: "mfma_bf16", 3: "mfma_f16", 4: "mfma_bf16x3",
+                 5: "shared_atomic"}
+
+LS_FINAL_EVAL = 1
+
+MAX_ATOMS = 128
+MAX_TORSIONS = 32
+
+# exported symbols of include/dock.h
+ABI_SYMBOLS = (
+    "dock_abi_version", "dock_last_error", "dock_create_grids", "dock_destroy_grids",
+    "dock_create_ligand", "dock_ligand_info_get", "dock_ligand_export", "dock_ligand_upload",
+    "dock_destroy_ligand", "dock_score_batch", "dock_ls_workspace_bytes",
+    "dock_local_search_batch", "dock_block_sum4",
+)
+
+
+class DockError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"dock error {status}: {msg}")
+        self.status = status
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("n_maps", C.c_int32),
+                ("spacing", C.c_float), ("origin", C.c_float * 3)]
+
+
+class FFParams(C.Structure):
+    _fields_ = [("n_classes", C.c_int32),
+                ("radius", C.POINTER(C.c_double)), ("eps", C.POINTER(C.c_double)),
+                ("solv", C.POINTER(C.c_double)), ("vol", C.POINTER(C.c_double)),
+                ("donor", C.c_int32 * 2), ("acceptor", C.c_int32 * 2),
+                ("hb_r0", (C.c_double * 2) * 2), ("hb_eps", (C.c_double * 2) * 2)]
+
+
+class LigandDesc(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("n_torsions", C.c_int32), ("root_atom", C.c_int32),
+                ("xyz", C.POINTER(C.c_double)), ("charge", C.POINTER(C.c_double)),
+                ("cls", C.POINTER(C.c_int32)), ("bonds", C.POINTER(C.c_int32)),
+                ("rot_bonds", C.POINTER(C.c_int32)), ("ff", C.POINTER(FFParams))]
+
+
+class LigandInfo(C.Structure):
+    _fields_ = [("n_atoms", C.c_int32), ("n_torsions", C.c_int32), ("n_genes", C.c_int32),
+                ("n_pairs", C.c_int32), ("n_fragments", C.c_int32), ("max_depth", C.c_int32),
+                ("blob_bytes", C.c_int64)]
+
+
+class ExecOpts(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("threads_per_ind", C.c_int32), ("flags", C.c_uint32),
+                ("atom_out", C.c_void_p)]
+
+
+class LsItem(C.Structure):
+    _fields_ = [("grids", C.c_void_p), ("ligand", C.c_void_p), ("n", C.c_int32),
+                ("variant", C.c_int32),
+                ("genotype", C.c_void_p), ("acc_g2", C.c_void_p), ("acc_dx2", C.c_void_p),
+                ("best_genotype", C.c_void_p), ("best_energy", C.c_void_p),
+                ("energy", C.c_void_p), ("iters_done", C.c_void_p)]
+
+
+class LsOpts(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("rho", C.c_float), ("eps", C.c_float),
+                ("variant", C.c_int32), ("threads_per_ind", C.c_int32), ("flags", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdockmi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with "
+                          "`python -m paper_2410_10447_amd.build_lib`")
+    L = C.CDLL(_LIB_PATH)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    sig = {
+        "dock_abi_version": ([], i32),
+        "dock_last_error": ([], C.c_char_p),
+        "dock_create_grids": ([C.POINTER(GridDesc), vp, C.POINTER(vp)], i32),
+        "dock_destroy_grids": ([vp], i32),
+        "dock_create_ligand": ([C.POINTER(LigandDesc), C.POINTER(vp)], i32),
+        "dock_ligand_info_get": ([vp, C.POINTER(LigandInfo)], i32),
+        "dock_ligand_export": ([vp, vp, vp, vp, vp, vp], i32),
+        "dock_ligand_upload": ([vp, vp, vp], i32),
+        "dock_destroy_ligand": ([vp], i32),
+        "dock_score_batch": ([vp, vp, i32, vp, vp, vp, C.POINTER(ExecOpts), vp], i32),
+        "dock_ls_workspace_bytes": ([i32, C.POINTER(i64)], i32),
+        "dock_local_search_batch": ([C.POINTER(LsItem), i32, C.POINTER(LsOpts), vp, i64, vp], i32),
+        "dock_block_sum4": ([vp, vp, i32, i32, i32, i32, vp], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != DOCK_OK:
+        raise DockError(status, lib().dock_last_error().decode())
+
+
+def last_error() -> str:
+    return lib().dock_last_error().decode()
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else C.c_void_p(None)
+
+
+def _dptr(a: np.ndarray, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+# ---------------------------------------------------------------------------
+# Handles
+# ---------------------------------------------------------------------------
+
+class Grids:
+    """Receptor grid set; `maps` is a float32 CUDA tensor [n_maps, nz, ny, nx]."""
+
+    def __init__(self, maps, spacing: float, origin):
+        import torch
+        if not (isinstance(maps, torch.Tensor) and maps.is_cuda and maps.dtype == torch.float32
+                and maps.dim() == 4 and maps.is_contiguous()):
+            raise ValueError("maps must be a contiguous float32 CUDA tensor [M, nz, ny, nx]")
+        self.maps = maps
+        d = GridDesc()
+        d.n_maps, d.nz, d.ny, d.nx = (int(v) for v in maps.shape)
+        d.spacing = float(spacing)
+        for c in range(3):
+            d.origin[c] = float(origin[c])
+        self.desc = d
+        h = C.c_void_p()
+        _check(lib().dock_create_grids(C.byref(d), _ptr(maps), C.byref(h)))
+        self.handle = h
+
+    @classmethod
+    def from_synth(cls, g, device="cuda"):
+        import torch
+        return cls(torch.from_numpy(np.ascontiguousarray(g.maps)).to(device), g.spacing, g.origin)
+
+    def nbytes(self) -> int:
+        return self.maps.numel() * 4
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.dock_destroy_grids(h)
+            self.handle = None
+
+
+def ff_params(ff):
+    """Pack a synth.ForceField into the ABI struct (keeps the arrays alive)."""
+    keep = [np.ascontiguousarray(a, dtype=np.float64) for a in (ff.radius, ff.eps, ff.solv, ff.vol)]
+    p = FFParams()
+    p.n_classes = len(keep[0])
+    p.radius, p.eps, p.solv, p.vol = (_dptr(a, C.c_double) for a in keep)
+    for i in range(2):
+        p.donor[i] = int(ff.donors[i])
+        p.acceptor[i] = int(ff.acceptors[i])
+        for j in range(2):
+            p.hb_r0[i][j] = float(ff.hb_r0[i, j])
+            p.hb_eps[i][j] = float(ff.hb_eps[i, j])
+    return p, keep
+
+
+class Ligand:
+    """Prepared ligand. `lig` has xyz, charge, cls, bonds, rot_bonds, root."""
+
+    def __init__(self, lig, ff, upload: bool = True, device="cuda"):
+        xyz = np.ascontiguousarray(lig.xyz, dtype=np.float64)
+        chg = np.ascontiguousarray(lig.charge, dtype=np.float64)
+        cls = np.ascontiguousarray(lig.cls, dtype=np.int32)
+        bonds = np.ascontiguousarray(np.asarray(lig.bonds, dtype=np.int32).reshape(-1, 2))
+        rot = np.ascontiguousarray(lig.rot_bonds, dtype=np.int32)
+        ffp, keep = ff_params(ff)
+        d = LigandDesc()
+        d.n_atoms = xyz.shape[0]
+        d.n_torsions = rot.shape[0]
+        d.root_atom = int(getattr(lig, "root", 0))
+        d.xyz = _dptr(xyz, C.c_double)
+        d.charge = _dptr(chg, C.c_double)
+        d.cls = _dptr(cls, C.c_int32)
+        d.bonds = _dptr(bonds, C.c_int32)
+        d.rot_bonds = _dptr(rot, C.c_int32)
+        d.ff = C.pointer(ffp)
+        h = C.c_void_p()
+        _check(lib().dock_create_ligand(C.byref(d), C.byref(h)))
+        del keep
+        self.handle = h
+        info = LigandInfo()
+        _check(lib().dock_ligand_info_get(h, C.byref(info)))
+        self.n_atoms = info.n_atoms
+        self.n_torsions = info.n_torsions
+        self.n_genes = info.n_genes
+        self.n_pairs = info.n_pairs
+        self.n_fragments = info.n_fragments
+        self.max_depth = info.max_depth
+        self.blob_bytes = info.blob_bytes
+        self.blob = None
+        if upload:
+            self.upload(device)
+
+    def upload(self, device="cuda", stream=None):
+        import torch
+        n = (self.blob_bytes + 15) // 16 * 16
+        self.blob = torch.empty(n, dtype=torch.uint8, device=device)
+        _check(lib().dock_ligand_upload(self.handle, _ptr(self.blob), _stream_handle(stream)))
+
+    def export(self):
+        N, T, P = self.n_atoms, self.n_torsions, self.n_pairs
+        order = np.zeros(N, np.int32)
+        tors = np.zeros((max(T, 1), 4), np.int32)
+        frag = np.zeros(N, np.int32)
+        pairs = np.zeros(max(P, 1), np.uint32)
+        hb = np.zeros(max(P, 1), np.uint8)
+        _check(lib().dock_ligand_export(self.handle, order.ctypes.data_as(C.c_void_p),
+                                        tors.ctypes.data_as(C.c_void_p),
+                                        frag.ctypes.data_as(C.c_void_p),
+                                        pairs.ctypes.data_as(C.c_void_p),
+                                        hb.ctypes.data_as(C.c_void_p)))
+        pr = np.stack([pairs[:P] >> 16, pairs[:P] & 0xFFFF], axis=1).astype(np.int64)
+        return {"order": order, "torsions": tors[:T], "fragment": frag, "pairs": pr,
+                "pair_hb": hb[:P].astype(bool)}
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.dock_destroy_ligand(h)
+            self.handle = None
+
+
+# ---------------------------------------------------------------------------
+# Batch calls
+# ---------------------------------------------------------------------------
+
+def score_batch(grids: Grids, ligand: Ligand, genotypes, variant: int = REDUCE_SHUFFLE,
+                with_grad: bool = True, atom_out: bool = False, stream=None):
+    """Energy [n] and gradient [n, G] of each genotype row (float32 CUDA tensor)."""
+    import torch
+    n = genotypes.shape[0]
+    if genotypes.dim() != 2 or genotypes.shape[1] != ligand.n_genes:
+        raise ValueError(f"genotypes must be [n, {ligand.n_genes}]")
+    gen = genotypes.contiguous()
+    E = torch.empty(n, dtype=torch.float32, device=gen.device)
+    grad = torch.empty(n, ligand.n_genes, dtype=torch.float32, device=gen.device) if with_grad else None
+    ao = torch.empty(n, ligand.n_atoms, 8, dtype=torch.float32, device=gen.device) if atom_out else None
+    o = ExecOpts(variant=variant, threads_per_ind=0, flags=0,
+                 atom_out=(ao.data_ptr() if ao is not None else None))
+    _check(lib().dock_score_batch(grids.handle, ligand.handle, n, _ptr(gen), _ptr(E), _ptr(grad),
+                                  C.byref(o), _stream_handle(stream)))
+    if atom_out:
+        return E, grad, ao
+    return E, grad
+
+
+@dataclass
+class LSState:
+    """Device state of a local-search population (all CUDA tensors)."""
+    genotype: object
+    acc_g2: object
+    acc_dx2: object
+    best_genotype: object
+    best_energy: object
+    energy: object
+    iters_done: object
+
+    @classmethod
+    def start(cls, genotypes):
+        import torch
+        g = genotypes.contiguous().clone()
+        n = g.shape[0]
+        return cls(g, torch.zeros_like(g), torch.zeros_like(g), g.clone(),
+                   torch.full((n,), float("inf"), dtype=torch.float32, device=g.device),
+                   torch.full((n,), float("nan"), dtype=torch.float32, device=g.device),
+                   torch.zeros(n, dtype=torch.int32, device=g.device))
+
+    def clone(self):
+        return LSState(*(getattr(self, f).clone() for f in
+                         ("genotype", "acc_g2", "acc_dx2", "best_genotype", "best_energy",
+                          "energy", "iters_done")))
+
+    def to_numpy(self):
+        return {f: getattr(self, f).cpu().numpy() for f in
+                ("genotype", "acc_g2", "acc_dx2", "best_genotype", "best_energy", "energy",
+                 "iters_done")}
+
+
+def workspace_bytes(n_items: int) -> int:
+    b = C.c_int64()
+    _check(lib().dock_ls_workspace_bytes(n_items, C.byref(b)))
+    return b.value
+
+
+def make_items(jobs):
+    """jobs: list of (Grids, Ligand, LSState[, variant]) -> ctypes array of items."""
+    arr = (LsItem * max(1, len(jobs)))()
+    for i, job in enumerate(jobs):
+        grids, ligand, st = job[0], job[1], job[2]
+        var = job[3] if len(job) > 3 else -1
+        it = arr[i]
+        it.grids = grids.handle.value
+        it.ligand = ligand.handle.value
+        it.n = st.genotype.shape[0]
+        it.variant = var
+        it.genotype = st.genotype.data_ptr()
+        it.acc_g2 = st.acc_g2.data_ptr()
+        it.acc_dx2 = st.acc_dx2.data_ptr()
+        it.best_genotype = st.best_genotype.data_ptr()
+        it.best_energy = st.best_energy.data_ptr()
+        it.energy = st.energy.data_ptr()
+        it.iters_done = st.iters_done.data_ptr()
+    return arr
+
+
+def local_search(jobs, iterations: int, rho: float = 0.8, eps: float = 1e-2,
+                 variant: int = REDUCE_SHUFFLE, final_eval: bool = True, workspace=None,
+                 stream=None, items=None):
+    """ADADELTA on every (Grids, Ligand, LSState[, variant]) job, one launch.
+
+    State tensors are updated in place. `workspace` (uint8 CUDA tensor) is
+    allocated if not given; `items` may pass a prebuilt item array.
+    """
+    import torch
+    n_items = len(jobs)
+    if items is None:
+        items = make_items(jobs)
+    need = workspace_bytes(n_items)
+    if workspace is None or workspace.numel() < need:
+        dev = jobs[0][2].genotype.device if n_items else torch.device("cuda")
+        workspace = torch.empty(max(need, 64), dtype=torch.uint8, device=dev)
+    o = LsOpts(iterations=iterations, rho=rho, eps=eps, variant=variant, threads_per_ind=0,
+               flags=LS_FINAL_EVAL if final_eval else 0)
+    _check(lib().dock_local_search_batch(items, n_items, C.byref(o), _ptr(workspace),
+                                         workspace.numel(), _stream_handle(stream)))
+    return workspace
+
+
+def block_sum4(x, variant: int, repeat: int = 1, stream=None):
+    """x: float32 CUDA tensor [n_blocks, threads, 4] -> every thread's block total."""
+    import torch
+    nb, th, four = x.shape
+    assert four == 4
+    x = x.contiguous()
+    out = torch.empty_like(x)
+    _check(lib().dock_block_sum4(_ptr(x), _ptr(out), nb, th, variant, repeat, _stream_handle(stream)))
+    return out

@@ -1,0 +1,214 @@
+"""C-ABI checks that need no GPU: exported symbols, host-side ligand
+preparation (bit-exact against the oracle's independent BFS construction),
+and argument validation of every entry point (errors are returned before any
+device work, so these run on a machine without a GPU)."""
+import ctypes as C
+import re
+
+import numpy as np
+import pytest
+
+from oracle import dock_ref as R
+from paper_2410_10447_amd import dock, synth
+from tests.helpers import ligand_from_bonds, load_golden
+
+FF = synth.force_field()
+
+
+def test_library_exports_every_declared_symbol():
+    L = dock.lib()
+    hdr = open(__import__("os").path.join(dock.__file__.rsplit("/", 2)[0], "include", "dock.h")).read()
+    declared = set(re.findall(r"^\s*(?:int32_t|const char\*)\s+(dock_\w+)\s*\(", hdr, re.M))
+    assert declared == set(dock.ABI_SYMBOLS)
+    for name in declared:
+        assert hasattr(L, name)
+    assert L.dock_abi_version() == 1
+
+
+def _check_prep(lig):
+    h = dock.Ligand(lig, FF, upload=False)
+    ex = h.export()
+    p = R.prepare(lig, FF)
+    N, T = lig.n_atoms, lig.n_torsions
+    assert (h.n_atoms, h.n_torsions, h.n_genes, h.n_pairs) == (N, T, 7 + T, len(p.pairs))
+    assert h.n_fragments == p.n_frag
+    # depth-first order: a permutation, root first, every subtree contiguous
+    order = ex["order"]
+    assert sorted(order.tolist()) == list(range(N)) and order[0] == 0
+    # torsions: same axis atoms; moving range = the oracle's BFS moving set
+    for k in range(T):
+        a, b, first, end = ex["torsions"][k]
+        assert (a, b) == tuple(p.axis[k])
+        assert set(order[first:end].tolist()) == set(np.nonzero(p.moving[k])[0].tolist())
+        assert order[first] == b
+    # fragments: same partition
+    part_c = {}
+    part_o = {}
+    for i in range(N):
+        part_c.setdefault(int(ex["fragment"][i]), set()).add(i)
+        part_o.setdefault(int(p.frag[i]), set()).add(i)
+    assert sorted(map(sorted, part_c.values())) == sorted(map(sorted, part_o.values()))
+    # pair list and hydrogen-bond flags, decoded from the kernel's masks
+    assert np.array_equal(ex["pairs"], p.pairs)
+    assert np.array_equal(ex["pair_hb"], p.pair_hb)
+    # the depth-first order is the one defined by the header: children in
+    # increasing index (independent recursive construction)
+    adj = {i: [] for i in range(N)}
+    for u, v in lig.bonds:
+        adj[int(u)].append(int(v)); adj[int(v)].append(int(u))
+    want = []
+
+    def visit(u, par):
+        want.append(u)
+        for v in sorted(adj[u]):
+            if v != par:
+                visit(v, u)
+    visit(0, -1)
+    assert order.tolist() == want
+
+
+@pytest.mark.parametrize("wl", ["score", "ls"])
+def test_prep_bitexact_named_workloads(wl):
+    w = synth.score_workload(1) if wl == "score" else synth.ls_workload(1)
+    _check_prep(w.ligands[0])
+
+
+def test_prep_bitexact_uneven_batch_ligands():
+    w = synth.uneven_workload(n_ligands=64, per_ligand=1, grid_n=8)
+    for lig in w.ligands:
+        _check_prep(lig)
+
+
+@pytest.mark.parametrize("name", ["prep_chain7.json", "prep_branched9.json", "prep_rigid6.json"])
+def test_prep_golden(name):
+    g = load_golden(name)
+    lig = ligand_from_bonds(g["bonds"], g["rot_bonds"])
+    _check_prep(lig)
+    ex = dock.Ligand(lig, FF, upload=False).export()
+    assert ex["pairs"].tolist() == g["pairs"]
+
+
+@pytest.mark.parametrize("n,t,seed", [(1, 0, 3), (2, 0, 4), (3, 0, 5), (4, 1, 6), (64, 20, 7),
+                                      (65, 20, 8), (127, 32, 9), (128, 32, 10)])
+def test_prep_edge_sizes(n, t, seed):
+    if n == 1:
+        lig = ligand_from_bonds(np.zeros((0, 2), np.int32), [])
+    else:
+        lig = synth.ligand(n, t, seed)
+    _check_prep(lig)
+
+
+def _desc_from(lig, **over):
+    xyz = np.ascontiguousarray(lig.xyz, np.float64)
+    chg = np.ascontiguousarray(lig.charge, np.float64)
+    cls = np.ascontiguousarray(lig.cls, np.int32)
+    bonds = np.ascontiguousarray(lig.bonds, np.int32)
+    rot = np.ascontiguousarray(lig.rot_bonds, np.int32)
+    arrs = dict(xyz=xyz, charge=chg, cls=cls, bonds=bonds, rot=rot)
+    arrs.update(over)
+    ffp, keep = dock.ff_params(FF)
+    d = dock.LigandDesc()
+    d.n_atoms = arrs.get("n_atoms", xyz.shape[0])
+    d.n_torsions = arrs.get("n_torsions", arrs["rot"].shape[0])
+    d.root_atom = arrs.get("root", 0)
+    d.xyz = arrs["xyz"].ctypes.data_as(C.POINTER(C.c_double))
+    d.charge = arrs["charge"].ctypes.data_as(C.POINTER(C.c_double))
+    d.cls = arrs["cls"].ctypes.data_as(C.POINTER(C.c_int32))
+    d.bonds = arrs["bonds"].ctypes.data_as(C.POINTER(C.c_int32))
+    d.rot_bonds = arrs["rot"].ctypes.data_as(C.POINTER(C.c_int32))
+    d.ff = C.pointer(ffp)
+    return d, (arrs, ffp, keep)
+
+
+def _create(d):
+    h = C.c_void_p()
+    st = dock.lib().dock_create_ligand(C.byref(d), C.byref(h))
+    if st == 0:
+        dock.lib().dock_destroy_ligand(h)
+    return st
+
+
+def test_create_ligand_rejects_bad_topologies():
+    lig = synth.ligand(12, 3, 1)
+    d, keep = _desc_from(lig)
+    assert _create(d) == 0
+    bad_bonds = lig.bonds.copy(); bad_bonds[3] = bad_bonds[2]          # duplicate -> not a tree
+    d, keep = _desc_from(lig, bonds=bad_bonds)
+    assert _create(d) == dock.DOCK_EINVAL and "bond" in dock.last_error()
+    cyc = lig.bonds.copy(); cyc[5] = [0, 1] if tuple(cyc[0]) != (0, 1) else [1, 2]
+    d, keep = _desc_from(lig, bonds=cyc)
+    assert _create(d) == dock.DOCK_EINVAL
+    # a terminal bond is not rotatable
+    deg = np.bincount(lig.bonds.ravel(), minlength=12)
+    term = [k for k, (u, v) in enumerate(lig.bonds) if deg[u] == 1 or deg[v] == 1][0]
+    d, keep = _desc_from(lig, rot=np.array([term], np.int32))
+    assert _create(d) == dock.DOCK_EINVAL and "internal" in dock.last_error()
+    d, keep = _desc_from(lig, rot=np.array([lig.rot_bonds[0]] * 2, np.int32))
+    assert _create(d) == dock.DOCK_EINVAL
+    d, keep = _desc_from(lig, cls=np.full(12, 99, np.int32))
+    assert _create(d) == dock.DOCK_EINVAL and "class" in dock.last_error()
+    d, keep = _desc_from(lig, root=12)
+    assert _create(d) == dock.DOCK_EINVAL
+    xyz = lig.xyz.copy(); xyz[0, 0] = np.nan
+    d, keep = _desc_from(lig, xyz=xyz)
+    assert _create(d) == dock.DOCK_EINVAL
+
+
+def test_create_ligand_limits():
+    big = synth.ligand(129, 3, 2)
+    d, keep = _desc_from(big)
+    assert _create(d) == dock.DOCK_EUNSUPPORTED
+    lig = synth.ligand(60, 40, 3)   # 33+ torsions requested; generator caps to internal bonds
+    if lig.n_torsions > 32:
+        d, keep = _desc_from(lig)
+        assert _create(d) == dock.DOCK_EUNSUPPORTED
+    d, keep = _desc_from(synth.ligand(5, 1, 4), n_atoms=0)
+    assert _create(d) == dock.DOCK_EINVAL
+
+
+def test_batch_calls_validate_before_device_work():
+    L = dock.lib()
+    vp = C.c_void_p
+    assert L.dock_score_batch(None, None, 1, None, None, None, None, None) == dock.DOCK_EINVAL
+    lig = dock.Ligand(synth.ligand(10, 2, 5), FF, upload=False)
+    d = dock.GridDesc(nx=8, ny=8, nz=8, n_maps=10, spacing=0.375)
+    g = C.c_void_p()
+    fake = vp(0x1000)     # never dereferenced: validation fails first or no launch happens
+    assert L.dock_create_grids(C.byref(d), None, C.byref(g)) == dock.DOCK_EINVAL
+    d2 = dock.GridDesc(nx=1, ny=8, nz=8, n_maps=10, spacing=0.375)
+    assert L.dock_create_grids(C.byref(d2), fake, C.byref(g)) == dock.DOCK_EINVAL
+    d3 = dock.GridDesc(nx=8, ny=8, nz=8, n_maps=2, spacing=0.375)
+    assert L.dock_create_grids(C.byref(d3), fake, C.byref(g)) == dock.DOCK_EINVAL
+    d4 = dock.GridDesc(nx=8, ny=8, nz=8, n_maps=10, spacing=0.0)
+    assert L.dock_create_grids(C.byref(d4), fake, C.byref(g)) == dock.DOCK_EINVAL
+    assert L.dock_create_grids(C.byref(d), fake, C.byref(g)) == dock.DOCK_OK
+    # ligand never uploaded
+    st = L.dock_score_batch(g, lig.handle, 4, fake, fake, fake, None, None)
+    assert st == dock.DOCK_EINVAL and "uploaded" in dock.last_error()
+    # a grid with too few type maps for the ligand's classes
+    d5 = dock.GridDesc(nx=8, ny=8, nz=8, n_maps=3, spacing=0.375)
+    g5 = C.c_void_p()
+    assert L.dock_create_grids(C.byref(d5), fake, C.byref(g5)) == dock.DOCK_OK
+    item = (dock.LsItem * 1)()
+    item[0].grids = g.value
+    item[0].ligand = lig.handle.value
+    item[0].n = 4
+    item[0].variant = -1
+    o = dock.LsOpts(iterations=10, rho=0.8, eps=1e-2, variant=0, threads_per_ind=0, flags=1)
+    st = L.dock_local_search_batch(item, 1, C.byref(o), fake, 1 << 20, None)
+    assert st == dock.DOCK_EINVAL and "uploaded" in dock.last_error()
+    for bad in (dict(rho=1.0), dict(rho=0.0), dict(eps=0.0), dict(iterations=-1), dict(variant=9),
+                dict(flags=8), dict(threads_per_ind=128)):
+        kw = dict(iterations=10, rho=0.8, eps=1e-2, variant=0, threads_per_ind=0, flags=1)
+        kw.update(bad)
+        ob = dock.LsOpts(**kw)
+        assert L.dock_local_search_batch(item, 1, C.byref(ob), fake, 1 << 20, None) in (
+            dock.DOCK_EINVAL, dock.DOCK_EUNSUPPORTED)
+    b = C.c_int64()
+    assert L.dock_ls_workspace_bytes(3, C.byref(b)) == 0 and b.value >= 64 + 3 * 64
+    assert L.dock_ls_workspace_bytes(-1, C.byref(b)) == dock.DOCK_EINVAL
+    assert L.dock_block_sum4(fake, fake, 1, 65, 0, 1, None) == dock.DOCK_EINVAL
+    assert L.dock_block_sum4(fake, fake, 1, 64, 7, 1, None) == dock.DOCK_EINVAL
+    assert L.dock_block_sum4(fake, fake, 1, 2048, 0, 1, None) == dock.DOCK_EINVAL
+    assert L.dock_destroy_grids(g) == 0 and L.dock_destroy_grids(g5) == 0
+    assert L.dock_destroy_grids(None) == 0 and L.dock_destroy_ligand(None) == 0

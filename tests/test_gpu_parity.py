@@ -1,0 +1,294 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances (FP32 path, per individual): |dE|/max(|E|,1) <= 1e-5 and
+||dg||/max(||g||,1) <= 1e-4. Individuals whose pose lies within rounding
+reach of a kink of the piecewise-smooth score (grid-cell face, box face, the
+1e5 cap, the r^2 clamp) are held to a looser bound and counted; they must be
+rare.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import dock_ref as R
+from oracle import reduce_ref as RR
+from paper_2410_10447_amd import synth
+from tests.gpu_common import E_TOL, G_TOL, e_relerr, g_relerr, near_discontinuity
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FP32_VARIANTS = [0, 1]          # shuffle, FP32 MFMA
+SPLIT_VARIANTS = [2, 3, 4]      # BF16 2-term, FP16 2-term, BF16 3-term
+
+
+@pytest.fixture(scope="module")
+def dk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_10447_amd import dock
+    dock.lib()
+    return dock
+
+
+# ---------------------------------------------------------------------------
+# Block sum (the paper's reduction step in isolation)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("threads", [64, 128, 256, 1024])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+def test_block_sum_integer_exact(dk, threads, variant):
+    """Integer data with |x| < 2^7: every variant's sum is exact."""
+    rng = np.random.default_rng(threads + 7 * variant)
+    nb = 37
+    x = rng.integers(-127, 128, (nb, threads, 4)).astype(np.float32)
+    out = dk.block_sum4(torch.from_numpy(x).cuda(), variant).cpu().numpy()
+    want = x.astype(np.float64).sum(axis=1)
+    assert np.array_equal(out, np.broadcast_to(want[:, None, :], out.shape).astype(np.float32))
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+def test_block_sum_random_error_bound(dk, variant):
+    rng = np.random.default_rng(100 + variant)
+    nb, th = 64, 256
+    x = (rng.normal(size=(nb, th, 4)) * 10 ** rng.uniform(-2, 4, (nb, th, 1))).astype(np.float32)
+    out = dk.block_sum4(torch.from_numpy(x).cuda(), variant).cpu().numpy()
+    ex = np.stack([RR.sum4_exact(x[b]) for b in range(nb)])
+    abs_sum = np.abs(x.astype(np.float64)).sum(axis=1)
+    u_split = {0: 0.0, 1: 0.0, 5: 0.0, 2: 2.0 ** -16, 3: 2.0 ** -22, 4: 2.0 ** -24}[variant]
+    bound = (u_split + 2 * th * 2.0 ** -24) * abs_sum
+    err = np.abs(out[:, 0, :].astype(np.float64) - ex)
+    assert np.all(err <= bound), (err / abs_sum).max()
+    # every thread holds the same total
+    assert np.all(out == out[:, :1, :])
+
+
+# ---------------------------------------------------------------------------
+# Scoring parity
+# ---------------------------------------------------------------------------
+
+def _score_case(dk, w, variant, n=None):
+    lig = w.ligands[0]
+    prep = R.prepare(lig, w.ff)
+    G = dk.Grids.from_synth(w.grids)
+    L = dk.Ligand(lig, w.ff)
+    gen = w.genotypes[0] if n is None else w.genotypes[0][:n]
+    gt = torch.from_numpy(gen).cuda()
+    E, g, ao = dk.score_batch(G, L, gt, variant=variant, atom_out=True)
+    torch.cuda.synchronize()
+    ref = R.score(prep, w.grids, gen.astype(np.float64))
+    return prep, ref, E.cpu().numpy(), g.cpu().numpy(), ao.cpu().numpy()
+
+
+def _report(tag, ee, ge, flag):
+    print(f"\n[{tag}] n={len(ee)} flagged={flag.sum()} E err p50={np.median(ee):.2e} "
+          f"max={ee.max():.2e} (unflagged {ee[~flag].max() if (~flag).any() else 0:.2e}); "
+          f"g err p50={np.median(ge):.2e} max={ge.max():.2e} "
+          f"(unflagged {ge[~flag].max() if (~flag).any() else 0:.2e})", flush=True)
+
+
+@pytest.mark.parametrize("variant", FP32_VARIANTS)
+def test_score_parity_small_ligand(dk, variant):
+    w = synth.score_workload(256)
+    prep, ref, E, g, ao = _score_case(dk, w, variant)
+    ee, ge = e_relerr(E, ref.energy), g_relerr(g, ref.grad)
+    flag = near_discontinuity(prep, w.grids, ref.x)
+    _report(f"score c0 v{variant}", ee, ge, flag)
+    # per-atom positions and gradients
+    assert np.abs(ao[:, :, 0:3] - ref.x).max() < 1e-4
+    assert flag.mean() < 0.05
+    assert np.all(ee[~flag] <= E_TOL)
+    assert np.all(ge[~flag] <= G_TOL)
+    assert np.all(ee[flag] <= 1e-3) and np.all(ge[flag] <= 1e-2)
+
+
+@pytest.mark.parametrize("variant", FP32_VARIANTS)
+def test_score_parity_ls_ligand(dk, variant):
+    w = synth.ls_workload(512)
+    prep, ref, E, g, ao = _score_case(dk, w, variant)
+    ee, ge = e_relerr(E, ref.energy), g_relerr(g, ref.grad)
+    flag = near_discontinuity(prep, w.grids, ref.x)
+    _report(f"score c1-ligand v{variant}", ee, ge, flag)
+    assert flag.mean() < 0.05
+    assert np.all(ee[~flag] <= E_TOL)
+    assert np.all(ge[~flag] <= G_TOL)
+
+
+@pytest.mark.parametrize("variant", SPLIT_VARIANTS)
+def test_score_split_variants_error_report(dk, variant):
+    """Half-width MFMA reductions: error against FP64, stated per individual."""
+    w = synth.ls_workload(512)
+    prep, ref, E, g, ao = _score_case(dk, w, variant)
+    ee, ge = e_relerr(E, ref.energy), g_relerr(g, ref.grad)
+    flag = near_discontinuity(prep, w.grids, ref.x)
+    _report(f"score split v{variant}", ee, ge, flag)
+    # 2-term BF16 carries 2^-16 per element; the others reach FP32 level
+    etol = 1e-4 if variant == 2 else E_TOL
+    assert np.all(ee[~flag] <= etol)
+    assert np.all(ge[~flag] <= G_TOL)
+
+
+@pytest.mark.parametrize("n_atoms,n_tors,seed", [(1, 0, 1), (2, 0, 2), (5, 1, 3), (63, 12, 4),
+                                                 (64, 20, 5), (65, 20, 6), (100, 32, 7),
+                                                 (128, 32, 8)])
+def test_score_parity_sizes(dk, n_atoms, n_tors, seed):
+    if n_atoms == 1:
+        from tests.helpers import ligand_from_bonds
+        lig = ligand_from_bonds(np.zeros((0, 2), np.int32), [], seed=seed)
+    else:
+        lig = synth.ligand(n_atoms, n_tors, seed)
+    grd = synth.grids(48, 10, seed + 100)
+    gen = synth.genotypes(lig, grd, 96, seed + 200)
+    w = synth.Workload("sizes", [lig], grd, synth.force_field(), [gen])
+    prep, ref, E, g, ao = _score_case(dk, w, 0)
+    ee, ge = e_relerr(E, ref.energy), g_relerr(g, ref.grad)
+    flag = near_discontinuity(prep, w.grids, ref.x)
+    _report(f"score N={n_atoms} T={lig.n_torsions}", ee, ge, flag)
+    assert np.all(ee[~flag] <= E_TOL)
+    assert np.all(ge[~flag] <= G_TOL)
+
+
+def test_score_outside_box_and_unnormalised_quaternion(dk):
+    w = synth.score_workload(64)
+    gen = w.genotypes[0].copy()
+    gen[:16, 0] += 9.0                          # far outside the 40^3 box on x
+    gen[16:32, 3:7] *= np.linspace(0.2, 5.0, 16, dtype=np.float32)[:, None]
+    w.genotypes[0] = gen
+    prep, ref, E, g, ao = _score_case(dk, w, 0)
+    ee, ge = e_relerr(E, ref.energy), g_relerr(g, ref.grad)
+    flag = near_discontinuity(prep, w.grids, ref.x)
+    _report("score outside/unnormalised", ee, ge, flag)
+    assert np.all(ee[~flag] <= E_TOL) and np.all(ge[~flag] <= G_TOL)
+
+
+def test_score_empty_batch(dk):
+    w = synth.score_workload(4)
+    G = dk.Grids.from_synth(w.grids)
+    L = dk.Ligand(w.ligands[0], w.ff)
+    E, g = dk.score_batch(G, L, torch.zeros(0, L.n_genes, device="cuda"))
+    assert E.shape == (0,) and g.shape == (0, L.n_genes)
+
+
+# ---------------------------------------------------------------------------
+# Local search
+# ---------------------------------------------------------------------------
+
+def _ls_setup(dk, w, n):
+    lig = w.ligands[0]
+    G = dk.Grids.from_synth(w.grids)
+    L = dk.Ligand(lig, w.ff)
+    st = dk.LSState.start(torch.from_numpy(w.genotypes[0][:n]).cuda())
+    return G, L, st
+
+
+@pytest.mark.parametrize("variant", FP32_VARIANTS)
+def test_ls_step_map(dk, variant):
+    """Each GPU step equals the oracle's ADADELTA step from the GPU's state."""
+    w = synth.ls_workload(64)
+    prep = R.prepare(w.ligands[0], w.ff)
+    G, L, st = _ls_setup(dk, w, 64)
+    ws = None
+    worst = 0.0
+    for it in range(12):
+        s0 = st.to_numpy()
+        ws = dk.local_search([(G, L, st)], 1, variant=variant, final_eval=False, workspace=ws)
+        torch.cuda.synchronize()
+        s1 = st.to_numpy()
+        x = s0["genotype"].astype(np.float64)
+        ref = R.score(prep, w.grids, x)
+        flag = near_discontinuity(prep, w.grids, ref.x)
+        xn, ag, ad = R.adadelta_step(x, ref.grad, s0["acc_g2"].astype(np.float64),
+                                     s0["acc_dx2"].astype(np.float64), 0.8, 1e-2)
+        assert np.all(e_relerr(s1["energy"], ref.energy)[~flag] <= E_TOL)
+        dxg = s1["genotype"] - x
+        dxo = xn - x
+        err = np.linalg.norm(dxg - dxo, axis=1) / np.maximum(np.linalg.norm(dxo, axis=1), 1e-3)
+        worst = max(worst, err[~flag].max())
+        assert np.all(err[~flag] <= 1e-4), (it, err[~flag].max())
+        assert np.all(s1["iters_done"] == it + 1)
+    print(f"\n[ls step-map v{variant}] worst step rel err {worst:.2e}", flush=True)
+
+
+def test_ls_chunked_equals_single_and_deterministic(dk):
+    w = synth.ls_workload(200)
+    G, L, st_a = _ls_setup(dk, w, 200)
+    st_b = st_a.clone()
+    st_c = st_a.clone()
+    dk.local_search([(G, L, st_a)], 30, final_eval=True)
+    for _ in range(2):
+        dk.local_search([(G, L, st_b)], 10, final_eval=False)
+    dk.local_search([(G, L, st_b)], 10, final_eval=True)
+    dk.local_search([(G, L, st_c)], 30, final_eval=True)
+    torch.cuda.synchronize()
+    a, b, c = st_a.to_numpy(), st_b.to_numpy(), st_c.to_numpy()
+    for f in a:
+        assert np.array_equal(a[f], b[f]), f
+        assert np.array_equal(a[f], c[f]), f
+
+
+def test_ls_full_size_sampled(dk):
+    """3000 individuals x 300 iterations on the 48-atom ligand (the benchmark
+    workload): the energy reported for each best genotype matches the
+    oracle's evaluation of it on a sample, and the search descends."""
+    w = synth.ls_workload(3000)
+    prep = R.prepare(w.ligands[0], w.ff)
+    G, L, st = _ls_setup(dk, w, 3000)
+    dk.local_search([(G, L, st)], 300, final_eval=True)
+    torch.cuda.synchronize()
+    s = st.to_numpy()
+    assert np.all(s["iters_done"] == 300)
+    assert np.all(np.isfinite(s["best_energy"]))
+    start = R.score(prep, w.grids, w.genotypes[0][:3000:25].astype(np.float64)).energy
+    idx = np.arange(0, 3000, 25)
+    ref = R.score(prep, w.grids, s["best_genotype"][idx].astype(np.float64))
+    flag = near_discontinuity(prep, w.grids, ref.x)
+    ee = e_relerr(s["best_energy"][idx], ref.energy)
+    print(f"\n[ls full] best E median {np.median(s['best_energy']):.3f} "
+          f"start median {np.median(start):.1f}; sampled E err max {ee[~flag].max():.2e}", flush=True)
+    assert np.all(ee[~flag] <= E_TOL)
+    assert np.all(s["best_energy"][idx] <= start + 1e-3 * np.abs(start))
+    # distribution against the oracle's own 300-step search on a subsample
+    sub = np.arange(0, 3000, 100)
+    ost = R.ls_init(w.genotypes[0][sub])
+    R.local_search(prep, w.grids, ost, 300)
+    gm, om = np.median(s["best_energy"][sub]), np.median(ost.best_energy)
+    print(f"[ls full] median best E gpu {gm:.4f} oracle {om:.4f}", flush=True)
+
+
+def test_ls_uneven_batch_alone_equals_mixed(dk):
+    """Items of different sizes in one launch give, bit for bit, what each
+    gives alone; each item meets oracle parity at its best point."""
+    w = synth.uneven_workload(n_ligands=6, per_ligand=12, grid_n=64)
+    G = dk.Grids.from_synth(w.grids)
+    Ls = [dk.Ligand(l, w.ff) for l in w.ligands]
+    mixed = [dk.LSState.start(torch.from_numpy(g).cuda()) for g in w.genotypes]
+    alone = [m.clone() for m in mixed]
+    dk.local_search([(G, L, s) for L, s in zip(Ls, mixed)], 20)
+    for L, s in zip(Ls, alone):
+        dk.local_search([(G, L, s)], 20)
+    torch.cuda.synchronize()
+    for k, (a, m) in enumerate(zip(alone, mixed)):
+        an, mn = a.to_numpy(), m.to_numpy()
+        for f in an:
+            assert np.array_equal(an[f], mn[f]), (k, f)
+        prep = R.prepare(w.ligands[k], w.ff)
+        ref = R.score(prep, w.grids, mn["best_genotype"].astype(np.float64))
+        flag = near_discontinuity(prep, w.grids, ref.x)
+        ee = e_relerr(mn["best_energy"], ref.energy)
+        assert np.all(ee[~flag] <= E_TOL), (k, ee.max())
+
+
+def test_ls_mixed_variants_in_one_launch(dk):
+    w = synth.ls_workload(64)
+    G, L, st0 = _ls_setup(dk, w, 64)
+    st1 = st0.clone()
+    ref0, ref1 = st0.clone(), st0.clone()
+    dk.local_search([(G, L, st0, 0), (G, L, st1, 1)], 15)
+    dk.local_search([(G, L, ref0)], 15, variant=0)
+    dk.local_search([(G, L, ref1)], 15, variant=1)
+    torch.cuda.synchronize()
+    for a, b in ((st0, ref0), (st1, ref1)):
+        an, bn = a.to_numpy(), b.to_numpy()
+        for f in an:
+            assert np.array_equal(an[f], bn[f]), f

@@ -198,6 +198,8 @@ typedef struct {
     const dock_ligand* ligand;   /* uploaded */
     int32_t n;                   /* individuals in this item, >= 0 */
     int32_t variant;             /* DOCK_REDUCE_* for this item, or -1 = opts->variant */
+    int32_t iterations;          /* steps for this item, 0 .. opts->iterations, or -1 = opts */
+    int32_t final_eval;          /* 1/0 overrides DOCK_LS_FINAL_EVAL for this item, -1 = opts */
     float* genotype;             /* device [n][G] in/out: current point */
     float* acc_g2;               /* device [n][G] in/out: running mean of g^2 (start 0) */
     float* acc_dx2;              /* device [n][G] in/out: running mean of dx^2 (start 0) */
@@ -221,8 +223,10 @@ typedef struct {
 /* Device bytes of the workspace dock_local_search_batch needs for n_items. */
 int32_t dock_ls_workspace_bytes(int32_t n_items, int64_t* bytes);
 
-/* Runs opts->iterations steps on every individual of every item in one
- * persistent launch; items are scheduled longest first. A call of K
+/* Runs opts->iterations steps (or the item's own count) on every individual
+ * of every item in one persistent launch; items are scheduled longest first.
+ * Items may be at different stages: a serving loop passes each job's
+ * remaining steps and asks for the final evaluation only in its last call. A call of K
  * iterations without DOCK_LS_FINAL_EVAL followed by one with it gives the
  * same state, bit for bit, as a single call with all the iterations.
  * workspace_dev: device, >= dock_ls_workspace_bytes(n_items), 16-byte

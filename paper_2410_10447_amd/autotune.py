@@ -1,0 +1,119 @@
+"""Per-size-bucket choice of the launch options of the local search.
+
+Ligands are bucketed by atom count (width 32) and torsion count (width 8).
+For each bucket a representative synthetic ligand is timed with every
+candidate (reduction variant x threads per individual) through the C ABI and
+the fastest candidate is stored in a JSON table keyed by GPU architecture and
+bucket. `choose()` reads the table; a persistent launch over ligands of mixed
+sizes then passes each item its bucket's variant (the launch geometry is
+fixed per launch, the per-item choice is the variant).
+
+Usage: python -m paper_2410_10447_amd.autotune [--out table.json]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import time
+
+import numpy as np
+
+TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_gfx950.json")
+ATOM_BUCKET = 32
+TORSION_BUCKET = 8
+DEFAULT = {"variant": 0, "threads_per_ind": 64}
+
+
+def bucket(n_atoms: int, n_torsions: int) -> str:
+    return f"a{min(n_atoms - 1, 127) // ATOM_BUCKET}_t{min(n_torsions, 31) // TORSION_BUCKET}"
+
+
+def bucket_centre(key: str):
+    a, t = key.split("_")
+    ia, it = int(a[1:]), int(t[1:])
+    return ia * ATOM_BUCKET + ATOM_BUCKET // 2, it * TORSION_BUCKET + TORSION_BUCKET // 2
+
+
+def all_buckets():
+    return [f"a{a}_t{t}" for a in range(128 // ATOM_BUCKET) for t in range(32 // TORSION_BUCKET)]
+
+
+_cache = {}
+
+
+def load(path: str = TABLE_PATH) -> dict:
+    if path not in _cache:
+        if os.path.exists(path):
+            with open(path) as f:
+                _cache[path] = json.load(f)
+        else:
+            _cache[path] = {"arch": "gfx950", "buckets": {}}
+    return _cache[path]
+
+
+def choose(n_atoms: int, n_torsions: int, path: str = TABLE_PATH) -> dict:
+    return dict(load(path)["buckets"].get(bucket(n_atoms, n_torsions), DEFAULT))
+
+
+def candidates():
+    from . import dock
+    return [{"variant": v, "threads_per_ind": 64} for v in (dock.REDUCE_SHUFFLE, dock.REDUCE_MFMA_F32)]
+
+
+def time_candidate(G, L, gen, cand, iterations=20, reps=3):
+    import torch
+    from . import dock
+    st0 = dock.LSState.start(gen)
+    ws = torch.empty(dock.workspace_bytes(1), dtype=torch.uint8, device=gen.device)
+    times = []
+    for r in range(reps + 1):
+        st = st0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dock.local_search([(G, L, st)], iterations, variant=cand["variant"], workspace=ws)
+        torch.cuda.synchronize()
+        if r:
+            times.append(time.perf_counter() - t0)
+    dt = float(np.median(times))
+    return gen.shape[0] * (iterations + 1) / dt
+
+
+def tune(out: str = TABLE_PATH, n_individuals: int = 1024, iterations: int = 20, seed: int = 77):
+    import torch
+    from . import dock, synth
+    grd = synth.grids(64, 10, seed)
+    G = dock.Grids.from_synth(grd)
+    ff = synth.force_field()
+    table = {"arch": "gfx950", "n_individuals": n_individuals, "iterations": iterations,
+             "buckets": {}}
+    for key in all_buckets():
+        n, t = bucket_centre(key)
+        lig = synth.ligand(n, t, seed + n * 100 + t)
+        L = dock.Ligand(lig, ff)
+        gen = torch.from_numpy(synth.genotypes(lig, grd, n_individuals, seed)).cuda()
+        best, rates = None, {}
+        for c in candidates():
+            rate = time_candidate(G, L, gen, c, iterations)
+            rates[f"v{c['variant']}_b{c['threads_per_ind']}"] = rate
+            if best is None or rate > best[1]:
+                best = (c, rate)
+        entry = dict(best[0])
+        entry["evals_per_s"] = best[1]
+        entry["measured"] = rates
+        entry["atoms"], entry["torsions"] = n, lig.n_torsions
+        table["buckets"][key] = entry
+        print(key, entry, flush=True)
+    with open(out, "w") as f:
+        json.dump(table, f, indent=1)
+    _cache.pop(out, None)
+    return table
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=TABLE_PATH)
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--iters", type=int, default=20)
+    a = ap.parse_args()
+    tune(a.out, a.n, a.iters)

@@ -305,6 +305,12 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
         if (st != DOCK_OK) return st;
         const int var = it.variant < 0 ? o->variant : it.variant;
         if (!valid_variant(var)) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": unknown variant");
+        if (it.iterations < -1 || it.iterations > o->iterations)
+            return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": iterations outside [-1, opts->iterations]");
+        if (it.final_eval < -1 || it.final_eval > 1)
+            return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": final_eval must be -1, 0 or 1");
+        const int iters = it.iterations < 0 ? o->iterations : it.iterations;
+        const int fin = it.final_eval < 0 ? ((o->flags & DOCK_LS_FINAL_EVAL) ? 1 : 0) : it.final_eval;
         if (it.n == 0) continue;
         void* ptrs[] = {it.genotype, it.acc_g2, it.acc_dx2, it.best_genotype, it.best_energy, it.energy,
                         it.iters_done};
@@ -324,10 +330,13 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
         d.n = it.n;
         d.variant = var;
         d.slots = it.ligand->slots;
+        d.iterations = iters;
+        d.final_eval = fin;
+        if (iters == 0 && !fin) continue;  // nothing to do for this item
         dev.push_back(d);
         const auto& P = it.ligand->prep;
-        // per-individual cost: pair steps per slot dominate, then atoms and torsion depth
-        cost.push_back((int64_t)(P.n_atoms / 2 + 4) * d.slots * 8 + P.max_depth);
+        // per-individual cost: evaluations x (pair steps per slot, then atoms and torsion depth)
+        cost.push_back((int64_t)(iters + fin) * ((int64_t)(P.n_atoms / 2 + 4) * d.slots * 8 + P.max_depth));
         any1 |= d.slots == 1;
         any2 |= d.slots == 2;
         var_u = (var_u == -2 || var_u == var) ? var : -1;
@@ -368,10 +377,8 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
     p.counter = static_cast<int32_t*>(ws);
     p.n_items = (int32_t)dev.size();
     p.total_units = (int32_t)total;
-    p.iterations = o->iterations;
     p.rho = o->rho;
     p.eps = o->eps;
-    p.final_eval = (o->flags & DOCK_LS_FINAL_EVAL) ? 1 : 0;
     hipError_t e = docklaunch::launch_ls(p, mode, var_uniform, grid, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "dock_local_search_batch launch");
     return ok();

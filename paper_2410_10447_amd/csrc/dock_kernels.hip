@@ -230,7 +230,7 @@ __device__ __forceinline__ float4 sum4_fp32(float4 v) {
 // ---------------------------------------------------------------------------
 
 struct __align__(16) Smem {
-    float4 dyn[kMaxAtoms];          // world x, y, z and charge q (depth-first order)
+    float4 dyn[kMaxAtoms];          // x, y, z relative to t, and charge q (depth-first order)
     float4 par[kMaxAtoms];          // R, sqrt(eps), S, V
     float tk[kMaxTors][12];         // torsion transforms, 3x4 row-major
     float fw[kMaxFrag][12];         // fragment -> world transforms
@@ -310,20 +310,42 @@ __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem& sm, Lig<SLOT
 
 // ---------------------------------------------------------------------------
 // Intermolecular grid term of one atom.
+//
+// The atom's world position is t + xl, with xl its position relative to the
+// ligand's rotation centre. The cell is chosen from the rounded world
+// coordinate, but the fraction inside the cell is taken from the exact
+// difference to the cell's lower node, (t - node) + xl, summed with error
+// compensation: a fraction derived from u = (x - origin)/h would carry the
+// rounding of |u| (up to the grid size) into every interpolation weight.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ float two_sum_fraction(float t, float node, float xl) {
+    const float s = t - node;
+    const float bp = s - t;
+    const float e1 = (t - (s - bp)) + (-node - bp);
+    const float s2 = s + xl;
+    const float bq = s2 - s;
+    const float e2 = (s - (s2 - bq)) + (xl - bq);
+    return s2 + (e1 + e2);
+}
+
+__device__ __forceinline__ void axis_cell(float t, float xl, float lo, float hi, float h, int n,
+                                          int& c, float& f, float& xw, float& xc) {
+    xw = t + xl;
+    xc = fminf(fmaxf(xw, lo), hi);
+    const float u = (xc - lo) / h;
+    c = min(max((int)floorf(u), 0), n - 2);
+    const float node = lo + (float)c * h;
+    f = (xw == xc) ? two_sum_fraction(t, node, xl) / h : (xc - node) / h;
+}
+
 __device__ __forceinline__ void grid_term(const GridParams& G, int cls, float q, float aq,
-                                          float x, float y, float z,
+                                          const float xl[3], const float t[3],
                                           float& e, float& gx, float& gy, float& gz) {
-    const float xc = fminf(fmaxf(x, G.origin[0]), G.hi[0]);
-    const float yc = fminf(fmaxf(y, G.origin[1]), G.hi[1]);
-    const float zc = fminf(fmaxf(z, G.origin[2]), G.hi[2]);
-    const float ux = (xc - G.origin[0]) / G.spacing;
-    const float uy = (yc - G.origin[1]) / G.spacing;
-    const float uz = (zc - G.origin[2]) / G.spacing;
-    const int cx = min(max((int)floorf(ux), 0), G.nx - 2);
-    const int cy = min(max((int)floorf(uy), 0), G.ny - 2);
-    const int cz = min(max((int)floorf(uz), 0), G.nz - 2);
-    const float fx = ux - (float)cx, fy = uy - (float)cy, fz = uz - (float)cz;
+    int cx, cy, cz;
+    float fx, fy, fz, xw, yw, zw, xc, yc, zc;
+    axis_cell(t[0], xl[0], G.origin[0], G.hi[0], G.spacing, G.nx, cx, fx, xw, xc);
+    axis_cell(t[1], xl[1], G.origin[1], G.hi[1], G.spacing, G.ny, cy, fy, yw, yc);
+    axis_cell(t[2], xl[2], G.origin[2], G.hi[2], G.spacing, G.nz, cz, fz, zw, zc);
     const int plane = G.nx * G.ny;
     const int vol = plane * G.nz;
     const int base = (cz * G.ny + cy) * G.nx + cx;
@@ -345,11 +367,11 @@ __device__ __forceinline__ void grid_term(const GridParams& G, int cls, float q,
     const float dx0 = d00 + fy * (d01 - d00), dx1 = d10 + fy * (d11 - d10);
     const float dfx = dx0 + fz * (dx1 - dx0);
     const float ih = 1.0f / G.spacing;
-    const float ox = x - xc, oy = y - yc, oz = z - zc;
+    const float ox = xw - xc, oy = yw - yc, oz = zw - zc;
     e = val + kOut * (ox * ox + oy * oy + oz * oz);
-    gx = (x == xc ? dfx * ih : 0.f) + 2.f * kOut * ox;
-    gy = (y == yc ? dfy * ih : 0.f) + 2.f * kOut * oy;
-    gz = (z == zc ? dfz * ih : 0.f) + 2.f * kOut * oz;
+    gx = (xw == xc ? dfx * ih : 0.f) + 2.f * kOut * ox;
+    gy = (yw == yc ? dfy * ih : 0.f) + 2.f * kOut * oy;
+    gz = (zw == zc ? dfz * ih : 0.f) + 2.f * kOut * oz;
 }
 
 // ---------------------------------------------------------------------------
@@ -439,7 +461,10 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
     }
     __syncthreads();
     // fragment transforms: product of enclosing torsions (root first), then
-    // the rigid body [Rq | t]
+    // the rotation Rq. Positions stay relative to the rotation centre (the
+    // translation t is added only where world coordinates are needed, the
+    // grid term): pair separations, torques and torsion axes are translation
+    // invariant and keep the precision of the small local coordinates.
     if (lane < L.NF) {
         float M[12] = {1.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f};
         const int len = sm.chain[lane][0];
@@ -457,17 +482,17 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
             for (int i = 0; i < 12; ++i) M[i] = Nw[i];
         }
         float* o = sm.fw[lane];
-        const float tt[3] = {tx, ty, tz};
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
 #pragma unroll
             for (int c = 0; c < 3; ++c)
                 o[4 * r + c] = Rq[3 * r] * M[c] + Rq[3 * r + 1] * M[4 + c] + Rq[3 * r + 2] * M[8 + c];
-            o[4 * r + 3] = Rq[3 * r] * M[3] + Rq[3 * r + 1] * M[7] + Rq[3 * r + 2] * M[11] + tt[r];
+            o[4 * r + 3] = Rq[3 * r] * M[3] + Rq[3 * r + 1] * M[7] + Rq[3 * r + 2] * M[11];
         }
     }
     __syncthreads();
-    // atom positions
+    // atom positions relative to t
+    const float tv[3] = {tx, ty, tz};
     float x[SLOTS][3];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -488,7 +513,7 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
     for (int s = 0; s < SLOTS; ++s) {
         const int a = lane + kWave * s;
         float e, gx, gy, gz;
-        grid_term(G, L.cls[s], L.chg[s][1], L.chg[s][2], x[s][0], x[s][1], x[s][2], e, gx, gy, gz);
+        grid_term(G, L.cls[s], L.chg[s][1], L.chg[s][2], x[s], tv, e, gx, gy, gz);
         const bool ok = a < N;
         e_atom[s] = ok ? e : 0.f;
         g[s][0] = ok ? gx : 0.f;
@@ -556,7 +581,7 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         eg.y += g[s][0]; eg.z += g[s][1]; eg.w += g[s][2];
-        const float rx = x[s][0] - tx, ry = x[s][1] - ty, rz = x[s][2] - tz;
+        const float rx = x[s][0], ry = x[s][1], rz = x[s][2];
         tq.x += ry * g[s][2] - rz * g[s][1];
         tq.y += rz * g[s][0] - rx * g[s][2];
         tq.z += rx * g[s][1] - ry * g[s][0];
@@ -630,7 +655,7 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
             const int a = lane + kWave * s;
             if (a < N) {
                 float4* o = reinterpret_cast<float4*>(atom_out) + 2 * L.orig[s];
-                o[0] = make_float4(x[s][0], x[s][1], x[s][2], e_atom[s]);
+                o[0] = make_float4(x[s][0] + tx, x[s][1] + ty, x[s][2] + tz, e_atom[s]);
                 o[1] = make_float4(g[s][0], g[s][1], g[s][2], 0.f);
             }
         }
@@ -714,25 +739,25 @@ template <int SLOTS>
 __device__ void ls_dispatch(int var_uniform, const DevItem& it, int ind, Smem& sm,
                             const Lig<SLOTS>& L, const LsParams& p) {
     const int var = var_uniform >= 0 ? var_uniform : it.variant;
-    const bool fin = p.final_eval != 0;
+    const bool fin = it.final_eval != 0;
     switch (var) {
         case DOCK_REDUCE_MFMA_F32:
-            local_search_one<SLOTS, DOCK_REDUCE_MFMA_F32>(it, ind, sm, L, p.iterations, p.rho, p.eps, fin); break;
+            local_search_one<SLOTS, DOCK_REDUCE_MFMA_F32>(it, ind, sm, L, it.iterations, p.rho, p.eps, fin); break;
         case DOCK_REDUCE_MFMA_BF16:
-            local_search_one<SLOTS, DOCK_REDUCE_MFMA_BF16>(it, ind, sm, L, p.iterations, p.rho, p.eps, fin); break;
+            local_search_one<SLOTS, DOCK_REDUCE_MFMA_BF16>(it, ind, sm, L, it.iterations, p.rho, p.eps, fin); break;
         case DOCK_REDUCE_MFMA_F16:
-            local_search_one<SLOTS, DOCK_REDUCE_MFMA_F16>(it, ind, sm, L, p.iterations, p.rho, p.eps, fin); break;
+            local_search_one<SLOTS, DOCK_REDUCE_MFMA_F16>(it, ind, sm, L, it.iterations, p.rho, p.eps, fin); break;
         case DOCK_REDUCE_MFMA_BF16X3:
-            local_search_one<SLOTS, DOCK_REDUCE_MFMA_BF16X3>(it, ind, sm, L, p.iterations, p.rho, p.eps, fin); break;
+            local_search_one<SLOTS, DOCK_REDUCE_MFMA_BF16X3>(it, ind, sm, L, it.iterations, p.rho, p.eps, fin); break;
         default:
-            local_search_one<SLOTS, DOCK_REDUCE_SHUFFLE>(it, ind, sm, L, p.iterations, p.rho, p.eps, fin); break;
+            local_search_one<SLOTS, DOCK_REDUCE_SHUFFLE>(it, ind, sm, L, it.iterations, p.rho, p.eps, fin); break;
     }
 }
 
 template <int SLOTS, int VAR>
 __device__ void ls_run(const DevItem& it, int ind, Smem& sm, const Lig<SLOTS>& L, const LsParams& p) {
     if constexpr (VAR >= 0)
-        local_search_one<SLOTS, VAR>(it, ind, sm, L, p.iterations, p.rho, p.eps, p.final_eval != 0);
+        local_search_one<SLOTS, VAR>(it, ind, sm, L, it.iterations, p.rho, p.eps, it.final_eval != 0);
     else
         ls_dispatch<SLOTS>(-1, it, ind, sm, L, p);
 }

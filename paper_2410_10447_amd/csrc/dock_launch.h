@@ -30,6 +30,9 @@ struct DevItem {
     int32_t variant;
     int32_t slots;          // 1 if n_atoms <= 64, else 2
     int32_t unit_begin;     // first work unit (individual) of this item
+    int32_t iterations;     // steps for this item
+    int32_t final_eval;     // evaluate the point reached after the last step
+    int32_t pad[2];
 };
 
 struct LsParams {
@@ -37,9 +40,7 @@ struct LsParams {
     int32_t* counter;       // device, zero at launch
     int32_t n_items;
     int32_t total_units;
-    int32_t iterations;
     float rho, eps;
-    int32_t final_eval;
 };
 
 // Workspace layout: [int32 counter, padded to 64 B][DevItem x n_items]

@@ -83,7 +83,7 @@ class ExecOpts(C.Structure):
 
 class LsItem(C.Structure):
     _fields_ = [("grids", C.c_void_p), ("ligand", C.c_void_p), ("n", C.c_int32),
-                ("variant", C.c_int32),
+                ("variant", C.c_int32), ("iterations", C.c_int32), ("final_eval", C.c_int32),
                 ("genotype", C.c_void_p), ("acc_g2", C.c_void_p), ("acc_dx2", C.c_void_p),
                 ("best_genotype", C.c_void_p), ("best_energy", C.c_void_p),
                 ("energy", C.c_void_p), ("iters_done", C.c_void_p)]
@@ -334,17 +334,38 @@ def workspace_bytes(n_items: int) -> int:
     return b.value
 
 
+@dataclass
+class LsJob:
+    """One local-search item: a population of one ligand against one grid set.
+
+    variant / iterations / final_eval of -1 defer to the call's options."""
+    grids: object
+    ligand: object
+    state: object
+    variant: int = -1
+    iterations: int = -1
+    final_eval: int = -1
+
+
+def _as_job(job):
+    if isinstance(job, LsJob):
+        return job
+    return LsJob(*job)
+
+
 def make_items(jobs):
-    """jobs: list of (Grids, Ligand, LSState[, variant]) -> ctypes array of items."""
+    """jobs: LsJob or (Grids, Ligand, LSState[, variant[, iterations[, final_eval]]])."""
     arr = (LsItem * max(1, len(jobs)))()
     for i, job in enumerate(jobs):
-        grids, ligand, st = job[0], job[1], job[2]
-        var = job[3] if len(job) > 3 else -1
+        j = _as_job(job)
+        grids, ligand, st = j.grids, j.ligand, j.state
         it = arr[i]
         it.grids = grids.handle.value
         it.ligand = ligand.handle.value
         it.n = st.genotype.shape[0]
-        it.variant = var
+        it.variant = j.variant
+        it.iterations = j.iterations
+        it.final_eval = j.final_eval
         it.genotype = st.genotype.data_ptr()
         it.acc_g2 = st.acc_g2.data_ptr()
         it.acc_dx2 = st.acc_dx2.data_ptr()
@@ -369,7 +390,7 @@ def local_search(jobs, iterations: int, rho: float = 0.8, eps: float = 1e-2,
         items = make_items(jobs)
     need = workspace_bytes(n_items)
     if workspace is None or workspace.numel() < need:
-        dev = jobs[0][2].genotype.device if n_items else torch.device("cuda")
+        dev = _as_job(jobs[0]).state.genotype.device if n_items else torch.device("cuda")
         workspace = torch.empty(max(need, 64), dtype=torch.uint8, device=dev)
     o = LsOpts(iterations=iterations, rho=rho, eps=eps, variant=variant, threads_per_ind=0,
                flags=LS_FINAL_EVAL if final_eval else 0)

@@ -96,6 +96,7 @@ def test_score_parity_small_ligand(dk, variant):
     flag = near_discontinuity(prep, w.grids, ref.x)
     _report(f"score c0 v{variant}", ee, ge, flag)
     # per-atom positions and gradients
+    print(f"[score c0 v{variant}] max pose error {np.abs(ao[:, :, 0:3] - ref.x).max():.2e} A", flush=True)
     assert np.abs(ao[:, :, 0:3] - ref.x).max() < 1e-4
     assert flag.mean() < 0.05
     assert np.all(ee[~flag] <= E_TOL)
@@ -110,6 +111,8 @@ def test_score_parity_ls_ligand(dk, variant):
     ee, ge = e_relerr(E, ref.energy), g_relerr(g, ref.grad)
     flag = near_discontinuity(prep, w.grids, ref.x)
     _report(f"score c1-ligand v{variant}", ee, ge, flag)
+    print(f"[score c1-ligand v{variant}] max pose error {np.abs(ao[:, :, 0:3] - ref.x).max():.2e} A",
+          flush=True)
     assert flag.mean() < 0.05
     assert np.all(ee[~flag] <= E_TOL)
     assert np.all(ge[~flag] <= G_TOL)

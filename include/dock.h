@@ -162,8 +162,11 @@ int32_t dock_ligand_export(const dock_ligand* lig, int32_t* order, int32_t* tors
                            int32_t* fragment, uint32_t* pairs, uint8_t* pair_hb);
 
 /* Copies the packed ligand (blob_bytes, see dock_ligand_info) to blob_dev
- * (device, caller-owned, 16-byte aligned) on `stream` and binds it to the
- * handle: later batch calls read the ligand from there. Call again to rebind. */
+ * (device, caller-owned, 16-byte aligned) asynchronously on `stream` (staged
+ * through library-owned pinned memory, so the call does not wait for the
+ * device) and binds it to the handle: later batch calls read the ligand from
+ * there, so they must run on the same stream or after it. Call again to
+ * rebind. */
 int32_t dock_ligand_upload(dock_ligand* lig, void* blob_dev, void* stream);
 int32_t dock_destroy_ligand(dock_ligand* lig);
 

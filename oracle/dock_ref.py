@@ -364,8 +364,12 @@ def pair_energy(r2_raw, r0, eps, hb, qq, dsolv):
     return e_lj + e_el + e_ds, w, e_lj, e_el, e_ds
 
 
-def intra_terms(prep: Prepared, x):
-    """Sum of pair energies [n] and per-atom intramolecular gradient [n, N, 3]."""
+def intra_terms(prep: Prepared, x, with_abs: bool = False):
+    """Sum of pair energies [n] and per-atom intramolecular gradient [n, N, 3].
+
+    With `with_abs`, also returns the sum of the magnitudes of the pair
+    energies [n] (the scale against which rounding of the sum is judged).
+    """
     n, N, _ = x.shape
     i, j = prep.pairs[:, 0], prep.pairs[:, 1]
     d = x[:, j, :] - x[:, i, :]
@@ -375,6 +379,8 @@ def intra_terms(prep: Prepared, x):
     g = np.zeros((n, N, 3))
     np.add.at(g, (slice(None), j), f)
     np.add.at(g, (slice(None), i), -f)
+    if with_abs:
+        return e.sum(axis=1), g, np.abs(e).sum(axis=1)
     return e.sum(axis=1), g
 
 
@@ -452,6 +458,7 @@ class ScoreResult:
     e_inter: np.ndarray       # [n, N] per-atom intermolecular energy
     e_intra: np.ndarray       # [n]
     torque: np.ndarray        # [n, 3]
+    e_abs: np.ndarray         # [n] sum of |per-atom| and |per-pair| energy terms
 
 
 def score(prep: Prepared, grd, genotypes) -> ScoreResult:
@@ -459,12 +466,12 @@ def score(prep: Prepared, grd, genotypes) -> ScoreResult:
     gen = np.asarray(genotypes, dtype=np.float64)
     x = pose(prep, gen)
     e_in, g_in = inter_terms(prep, grd, x)
-    e_ia, g_ia = intra_terms(prep, x)
+    e_ia, g_ia, a_ia = intra_terms(prep, x, with_abs=True)
     gat = g_in + g_ia
     E = e_in.sum(axis=1) + e_ia
     grad = genotype_gradient(prep, gen, x, gat)
     tau = np.cross(x - gen[:, None, 0:3], gat).sum(axis=1)
-    return ScoreResult(E, grad, x, gat, e_in, e_ia, tau)
+    return ScoreResult(E, grad, x, gat, e_in, e_ia, tau, np.abs(e_in).sum(axis=1) + a_ia)
 
 
 # ---------------------------------------------------------------------------

@@ -232,12 +232,10 @@ int32_t dock_ligand_export(const dock_ligand* l, int32_t* order, int32_t* torsio
 int32_t dock_ligand_upload(dock_ligand* l, void* blob_dev, void* stream) {
     if (!l || !blob_dev) return fail(DOCK_EINVAL, "dock_ligand_upload: NULL argument");
     if (!aligned(blob_dev, 16)) return fail(DOCK_EINVAL, "ligand blob must be 16-byte aligned");
-    hipError_t e = hipMemcpyAsync(blob_dev, l->prep.blob.data(), l->prep.blob.size(),
-                                  hipMemcpyHostToDevice, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "dock_ligand_upload");
-    // pageable source: make sure the copy has read the host blob before returning
-    e = hipStreamSynchronize((hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "dock_ligand_upload");
+    // staged through pinned memory: asynchronous on the stream, no host wait
+    int32_t st = staging().copy_to_device(blob_dev, l->prep.blob.data(), l->prep.blob.size(),
+                                          (hipStream_t)stream);
+    if (st != DOCK_OK) return st;
     l->blob_dev = static_cast<const uint8_t*>(blob_dev);
     return ok();
 }

@@ -6,14 +6,15 @@
 // sections start on a 16-byte boundary; offsets are in bytes from the blob
 // start.
 //
-// Intramolecular pairs are not stored as a list. A lane that owns atom a
-// visits partner b = (a + s) mod N for s = 1 .. N/2 (a circulant schedule that
-// meets every unordered pair exactly once, the middle step of an even N only
-// from a < N/2), and three per-atom 64-bit masks say, for each step s (bit
-// s-1), whether the pair is kept, whether it is a hydrogen-bond pair, and the
-// partner's donor/acceptor index. Pair parameters are rebuilt from per-atom
-// values: r0 = R_a + R_b, eps = sqrt(eps_a) sqrt(eps_b), 332.06363 q_a q_b,
-// S_a V_b + S_b V_a, or the 12-10 table entry of the donor-acceptor pair.
+// Intramolecular pairs are stored as a list cut into batches of 64, one pair
+// per lane. Within a batch an atom appears at most n_copies times, and each
+// appearance is given its own copy index, so the force updates of one batch
+// go to distinct accumulator slots (copy * n_atoms + atom): a lane can add
+// its pair's force to both atoms without two lanes of one instruction
+// touching the same address, and the order of additions is fixed by the
+// list. Pair parameters are rebuilt from per-atom values: r0 = R_a + R_b,
+// eps = sqrt(eps_a) sqrt(eps_b), 332.06363 q_a q_b, S_a V_b + S_b V_a, or the
+// 12-10 table entry of the donor-acceptor pair.
 #pragma once
 #include <stdint.h>
 
@@ -24,6 +25,15 @@ constexpr int kMaxAtoms = 128;
 constexpr int kMaxTorsions = 32;
 constexpr int kMaxFrag = kMaxTorsions + 1;
 constexpr int kChainStride = kMaxTorsions + 1;  // [0] = length, [1..] torsion ids root first
+constexpr int kBatch = 64;
+constexpr int kMaxSlots = 384;                   // n_copies * n_atoms <= kMaxSlots
+
+// pair record: i | j << 7 | ci << 14 | cj << 18 | hb << 22 | table << 23 | valid << 31
+constexpr uint32_t kRecValid = 1u << 31;
+inline uint32_t make_record(int i, int j, int ci, int cj, int hb, int table) {
+    return (uint32_t)i | ((uint32_t)j << 7) | ((uint32_t)ci << 14) | ((uint32_t)cj << 18) |
+           ((uint32_t)hb << 22) | ((uint32_t)table << 23) | kRecValid;
+}
 
 struct Header {
     int32_t magic;
@@ -33,19 +43,21 @@ struct Header {
     int32_t n_genes;
     int32_t n_pairs;
     int32_t max_depth;
-    int32_t n_steps;        // floor(n_atoms / 2)
+    int32_t n_batches;      // pair batches of kBatch records
+    int32_t n_copies;       // accumulator copies per atom
     int32_t max_class;      // largest atom class used (type-map index)
     int32_t total_bytes;
     // section offsets (bytes)
     int32_t off_ref;        // float4[N]  y0 (reference coords minus centroid), w = 0
     int32_t off_par;        // float4[N]  R, sqrt(eps), S = s + 0.01097|q|, V
     int32_t off_chg;        // float4[N]  332.06363 q, q, |q|, 0
-    int32_t off_hb;         // float4[N]  12-10 r0 vs partner index 0/1, eps vs 0/1
     int32_t off_int;        // int4[N]    class, fragment, original index, 0
-    int32_t off_mask;       // uint64[3][N] kept / hb / partner hb index, bit s-1
     int32_t off_tors;       // Torsion[T]
     int32_t off_chain;      // int8[n_frag][kChainStride]
-    int32_t pad[14];
+    int32_t off_plist;      // uint32[n_batches][kBatch] pair records
+    float hb_r0[4];         // 12-10 table, index 2 * donor + acceptor
+    float hb_eps[4];
+    int32_t pad[6];
 };
 static_assert(sizeof(Header) == 128, "header is 128 bytes");
 

@@ -57,6 +57,7 @@ constexpr float kDielBKLB = 86.9525f * 7.7839f * 0.003627f * 86.9525f;
 constexpr float kDsInv2S2 = 1.0f / (2.0f * 3.5f * 3.5f);   // 1 / (2 sigma^2)
 constexpr float kDsInvS2 = 1.0f / (3.5f * 3.5f);
 constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kElec = 332.06363f;          // kcal A / (mol e^2)
 
 // ---------------------------------------------------------------------------
 // Cross-lane primitives (wave64).
@@ -232,24 +233,28 @@ __device__ __forceinline__ float4 sum4_fp32(float4 v) {
 struct __align__(16) Smem {
     float4 dyn[kMaxAtoms];          // x, y, z relative to t, and charge q (depth-first order)
     float4 par[kMaxAtoms];          // R, sqrt(eps), S, V
-    float tk[kMaxTors][12];         // torsion transforms, 3x4 row-major
-    float fw[kMaxFrag][12];         // fragment -> world transforms
+    union {
+        struct {
+            float tk[kMaxTors][12]; // torsion transforms, 3x4 row-major
+            float fw[kMaxFrag][12]; // fragment transforms (rotation part of the pose)
+        } pose;                     // live until the atom positions are written
+        float acc[3][dockblob::kMaxSlots];  // pair-force accumulators, slot = copy * N + atom
+    } u;
     int8_t chain[kMaxFrag][kChain]; // [0] = length, then torsions root first
+    float2 hbt[4];                  // 12-10 table (r0, eps), index 2 * donor + acceptor
 };
 
 template <int SLOTS>
 struct Lig {
     // uniform
-    int N, T, NF, G, steps;
+    int N, T, NF, G, n_batches, n_copies;
+    const uint32_t* plist;          // pair records, n_batches x 64
     // per lane, per slot: atom a = lane + 64 * slot
     float y0[SLOTS][3];
     float chg[SLOTS][3];            // 332.06363 q, q, |q|
-    float par[SLOTS][4];            // R, sqrt(eps), S, V
-    float hb[SLOTS][4];             // 12-10 r0 vs partner index 0/1, eps vs 0/1
     int cls[SLOTS];
     int frag[SLOTS];
     int orig[SLOTS];                // original atom index
-    uint64_t keep[SLOTS], hbm[SLOTS], hbi[SLOTS];
     // per lane k < T: torsion k
     float tp[3], tu[3];
     int t_apos, t_bpos, t_first, t_end;
@@ -263,30 +268,26 @@ __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem& sm, Lig<SLOT
     L.T = h->n_torsions;
     L.NF = h->n_frag;
     L.G = h->n_genes;
-    L.steps = h->n_steps;
+    L.n_batches = h->n_batches;
+    L.n_copies = h->n_copies;
+    L.plist = reinterpret_cast<const uint32_t*>(blob + h->off_plist);
+    if (lane < 4) sm.hbt[lane] = make_float2(h->hb_r0[lane], h->hb_eps[lane]);
     const float4* ref = reinterpret_cast<const float4*>(blob + h->off_ref);
     const float4* par = reinterpret_cast<const float4*>(blob + h->off_par);
     const float4* chg = reinterpret_cast<const float4*>(blob + h->off_chg);
-    const float4* hbv = reinterpret_cast<const float4*>(blob + h->off_hb);
     const int4* iv = reinterpret_cast<const int4*>(blob + h->off_int);
-    const uint64_t* mk = reinterpret_cast<const uint64_t*>(blob + h->off_mask);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int a = lane + kWave * s;
         const bool ok = a < L.N;
         const int ai = ok ? a : 0;
-        float4 r = ref[ai], p = par[ai], c = chg[ai], b = hbv[ai];
+        float4 r = ref[ai], p = par[ai], c = chg[ai];
         int4 ii = iv[ai];
         L.y0[s][0] = r.x; L.y0[s][1] = r.y; L.y0[s][2] = r.z;
         L.chg[s][0] = ok ? c.x : 0.f; L.chg[s][1] = ok ? c.y : 0.f; L.chg[s][2] = ok ? c.z : 0.f;
-        L.par[s][0] = p.x; L.par[s][1] = p.y; L.par[s][2] = p.z; L.par[s][3] = p.w;
-        L.hb[s][0] = b.x; L.hb[s][1] = b.y; L.hb[s][2] = b.z; L.hb[s][3] = b.w;
         L.cls[s] = ii.x;
         L.frag[s] = ii.y;
         L.orig[s] = ii.z;
-        L.keep[s] = ok ? mk[ai] : 0ull;
-        L.hbm[s] = ok ? mk[L.N + ai] : 0ull;
-        L.hbi[s] = ok ? mk[2 * L.N + ai] : 0ull;
         if (ok) sm.par[a] = p;
     }
     const Torsion* tr = reinterpret_cast<const Torsion*>(blob + h->off_tors);
@@ -375,40 +376,47 @@ __device__ __forceinline__ void grid_term(const GridParams& G, int cls, float q,
 }
 
 // ---------------------------------------------------------------------------
-// One pair: energy and w = (dE/dr)/r from the separation d = x_b - x_a.
+// One pair: energy e and w = (dE/dr)/r from the separation d = x_b - x_a.
+// The 12-6 and 12-10 forms share one expression, c12 s^12 + c10 s^10 +
+// c6 s^6 with s = r0/r, so the loop has no divergent branch; `live` masks
+// pairs that are not kept (e = w = 0) and `grad` masks the slope where r^2 is
+// clamped. Masks are applied with bit operations so the compiler cannot turn
+// them into branches around the (long) slope computation.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void pair_term(float dx, float dy, float dz, float r0, float eps,
-                                          bool hb, float qq, float ds, float& e, float& w) {
+__device__ __forceinline__ float mask_f(float v, bool keep) {
+    return __int_as_float(__float_as_int(v) & (keep ? -1 : 0));
+}
+
+__device__ __forceinline__ void pair_term(float dx, float dy, float dz, float r0, float c12,
+                                          float c10, float c6, float qq, float ds, bool live,
+                                          float& e, float& w) {
     const float r2raw = dx * dx + dy * dy + dz * dz;
-    const bool clamped = r2raw < kR2Min;
+    const bool slope = live && (r2raw >= kR2Min);
     const float r2 = fmaxf(r2raw, kR2Min);
     const float rinv = __builtin_amdgcn_rsqf(r2);
+    const float ir2 = rinv * rinv;
     const float r = r2 * rinv;
-    const float s2 = (r0 * r0) * (rinv * rinv);
-    const float s6 = s2 * s2 * s2;
+    const float s2 = (r0 * r0) * ir2;
+    const float s4 = s2 * s2;
+    const float s6 = s4 * s2;
+    const float s10 = s6 * s4;
     const float s12 = s6 * s6;
-    const float s10 = s6 * s2 * s2;
-    float elj, dlj;
-    if (hb) {
-        elj = eps * (5.f * s12 - 6.f * s10);
-        dlj = 60.f * eps * (s10 - s12) * rinv;
-    } else {
-        elj = eps * (s12 - 2.f * s6);
-        dlj = 12.f * eps * (s6 - s12) * rinv;
-    }
-    if (elj > kCap) { elj = kCap; dlj = 0.f; }
+    float elj = c12 * s12 + c10 * s10 + c6 * s6;
+    float dlj = -(12.f * c12 * s12 + 10.f * c10 * s10 + 6.f * c6 * s6);   // r dE/dr
+    const bool capped = elj > kCap;
+    elj = capped ? kCap : elj;
+    dlj = capped ? 0.f : dlj;
     const float ex = __builtin_amdgcn_exp2f(-kDielLB * kLog2e * r);
-    const float den = 1.f + kDielK * ex;
-    const float iden = __builtin_amdgcn_rcpf(den);
+    const float iden = __builtin_amdgcn_rcpf(1.f + kDielK * ex);
     const float epsr = kDielA + kDielB * iden;
     const float depsr = kDielBKLB * ex * iden * iden;
     const float ired = __builtin_amdgcn_rcpf(r * epsr);
     const float eel = qq * ired;
-    const float del = -qq * (epsr + r * depsr) * ired * ired;
+    const float del = -qq * (epsr + r * depsr) * (r * ired) * ired;             // r dE/dr
     const float eds = ds * __builtin_amdgcn_exp2f(-kDsInv2S2 * kLog2e * r2);
-    const float dds = -eds * r * kDsInvS2;
-    e = elj + eel + eds;
-    w = clamped ? 0.f : (dlj + del + dds) * rinv;
+    const float dds = -eds * r2 * kDsInvS2;                                     // r dE/dr
+    e = mask_f(elj + eel + eds, live);
+    w = mask_f((dlj + del + dds) * ir2, slope);
 }
 
 // ---------------------------------------------------------------------------
@@ -450,7 +458,7 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
         Rk[0] = cs + oc * ux * ux;      Rk[1] = oc * ux * uy - sn * uz; Rk[2] = oc * ux * uz + sn * uy;
         Rk[3] = oc * uy * ux + sn * uz; Rk[4] = cs + oc * uy * uy;      Rk[5] = oc * uy * uz - sn * ux;
         Rk[6] = oc * uz * ux - sn * uy; Rk[7] = oc * uz * uy + sn * ux; Rk[8] = cs + oc * uz * uz;
-        float* o = sm.tk[lane];
+        float* o = sm.u.pose.tk[lane];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             o[4 * r + 0] = Rk[3 * r + 0];
@@ -469,7 +477,7 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
         float M[12] = {1.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f};
         const int len = sm.chain[lane][0];
         for (int j = 0; j < len; ++j) {
-            const float* Tk = sm.tk[(int)sm.chain[lane][1 + j]];
+            const float* Tk = sm.u.pose.tk[(int)sm.chain[lane][1 + j]];
             float Nw[12];
 #pragma unroll
             for (int r = 0; r < 3; ++r) {
@@ -481,7 +489,7 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
 #pragma unroll
             for (int i = 0; i < 12; ++i) M[i] = Nw[i];
         }
-        float* o = sm.fw[lane];
+        float* o = sm.u.pose.fw[lane];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
 #pragma unroll
@@ -497,7 +505,7 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int a = lane + kWave * s;
-        const float* W = sm.fw[L.frag[s]];
+        const float* W = sm.u.pose.fw[L.frag[s]];
 #pragma unroll
         for (int r = 0; r < 3; ++r)
             x[s][r] = W[4 * r] * L.y0[s][0] + W[4 * r + 1] * L.y0[s][1] + W[4 * r + 2] * L.y0[s][2] + W[4 * r + 3];
@@ -522,52 +530,63 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
         e_lane += e_atom[s];
     }
 
-    // pair terms, circulant schedule
-    for (int st = 1; st <= L.steps; ++st) {
-        float fs[SLOTS][3];
+    // pair terms: batches of 64 listed pairs, one per lane. Each lane adds
+    // its pair's force to both atoms' accumulator slots; the host schedule
+    // makes the slots of one batch distinct, so no two lanes of an
+    // instruction touch one address and the order of additions is fixed.
+    {
+        const int nslot = L.n_copies * N;
+        for (int k = lane; k < nslot; k += kWave) {
+            sm.u.acc[0][k] = 0.f;
+            sm.u.acc[1][k] = 0.f;
+            sm.u.acc[2][k] = 0.f;
+        }
+        __syncthreads();
+        uint32_t rec_next = L.n_batches > 0 ? L.plist[lane] : 0u;
+        for (int bt = 0; bt < L.n_batches; ++bt) {
+            const uint32_t rec = rec_next;
+            if (bt + 1 < L.n_batches) rec_next = L.plist[(bt + 1) * kWave + lane];
+            const bool valid = (rec & dockblob::kRecValid) != 0u;
+            const int i = rec & 127, j = (rec >> 7) & 127;
+            const int ci = (rec >> 14) & 15, cj = (rec >> 18) & 15;
+            const bool hb = (rec >> 22) & 1u;
+            const int tb = (rec >> 23) & 3;
+            const float4 pi = sm.dyn[i], pj = sm.dyn[j];
+            const float4 qi = sm.par[i], qj = sm.par[j];
+            const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+            const float2 ht = sm.hbt[tb];
+            const float r0 = hb ? ht.x : qi.x + qj.x;
+            const float ep = hb ? ht.y : qi.y * qj.y;
+            const float c12 = hb ? 5.f * ep : ep;
+            const float c10 = hb ? -6.f * ep : 0.f;
+            const float c6 = hb ? 0.f : -2.f * ep;
+            const float qq = kElec * pi.w * pj.w;
+            const float ds = qi.z * qj.w + qj.z * qi.w;
+            float e, w;
+            pair_term(dx, dy, dz, r0, c12, c10, c6, qq, ds, valid, e, w);
+            e_lane += e;
+            const float fx = w * dx, fy = w * dy, fz = w * dz;
+            if (valid) {
+                const int si = ci * N + i, sj = cj * N + j;
+                atomicAdd(&sm.u.acc[0][si], -fx);
+                atomicAdd(&sm.u.acc[1][si], -fy);
+                atomicAdd(&sm.u.acc[2][si], -fz);
+                atomicAdd(&sm.u.acc[0][sj], fx);
+                atomicAdd(&sm.u.acc[1][sj], fy);
+                atomicAdd(&sm.u.acc[2][sj], fz);
+            }
+        }
+        __syncthreads();
+        // each atom adds its copies in copy order
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
             const int a = lane + kWave * s;
-            int b = a + st;
-            b = b >= N ? b - N : b;
-            b = b < N ? b : 0;
-            const bool kept = (L.keep[s] >> (st - 1)) & 1ull;
-            const bool hb = (L.hbm[s] >> (st - 1)) & 1ull;
-            const bool hidx = (L.hbi[s] >> (st - 1)) & 1ull;
-            const float4 pd = sm.dyn[b];
-            const float4 pp = sm.par[b];
-            const float dx = pd.x - x[s][0], dy = pd.y - x[s][1], dz = pd.z - x[s][2];
-            const float r0 = hb ? (hidx ? L.hb[s][1] : L.hb[s][0]) : L.par[s][0] + pp.x;
-            const float ep = hb ? (hidx ? L.hb[s][3] : L.hb[s][2]) : L.par[s][1] * pp.y;
-            const float qq = L.chg[s][0] * pd.w;
-            const float ds = L.par[s][2] * pp.w + pp.z * L.par[s][3];
-            float e, w;
-            pair_term(dx, dy, dz, r0, ep, hb, qq, ds, e, w);
-            e = kept ? e : 0.f;
-            w = kept ? w : 0.f;
-            e_lane += e;
-            fs[s][0] = w * dx;
-            fs[s][1] = w * dy;
-            fs[s][2] = w * dz;
-            g[s][0] -= fs[s][0];
-            g[s][1] -= fs[s][1];
-            g[s][2] -= fs[s][2];
-        }
-        // the partner b = a + st receives +f: atom m takes it from atom m - st
-#pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-            const int m = lane + kWave * s;
-            int src = m - st;
-            src = src < 0 ? src + N : src;
-            const int sl = src & 63;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                float v = __shfl(fs[0][c], sl);
-                if constexpr (SLOTS == 2) {
-                    const float v1 = __shfl(fs[1][c], sl);
-                    v = (src >= kWave) ? v1 : v;
+            if (a < N) {
+                for (int c = 0; c < L.n_copies; ++c) {
+                    g[s][0] += sm.u.acc[0][c * N + a];
+                    g[s][1] += sm.u.acc[1][c * N + a];
+                    g[s][2] += sm.u.acc[2][c * N + a];
                 }
-                g[s][c] += v;
             }
         }
     }
@@ -668,7 +687,7 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
 // ---------------------------------------------------------------------------
 
 template <int SLOTS, int VAR>
-__global__ __launch_bounds__(64) void score_kernel(GridParams G, const uint8_t* __restrict__ blob,
+__global__ __launch_bounds__(64, (SLOTS == 1 ? 4 : 2)) void score_kernel(GridParams G, const uint8_t* __restrict__ blob,
                                                    int n, const float* __restrict__ gen,
                                                    float* __restrict__ energy,
                                                    float* __restrict__ grad,
@@ -768,7 +787,7 @@ __device__ void ls_run(const DevItem& it, int ind, Smem& sm, const Lig<SLOTS>& L
 // only when the item changes. Every wave exits once the counter passes the
 // last unit.
 template <int MODE, int VAR>
-__global__ __launch_bounds__(64) void ls_kernel(LsParams p) {
+__global__ __launch_bounds__(64, (MODE == docklaunch::kSlots1 ? 4 : 2)) void ls_kernel(LsParams p) {
     __shared__ Smem sm;
     const int lane = lane_id();
     int cur_item = -1;

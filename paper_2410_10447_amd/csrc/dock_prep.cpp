@@ -132,18 +132,44 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
         while (a != b) { a = parent[a]; b = parent[b]; --da; }
         return depth[i] + depth[j] - 2 * da;
     };
-    std::vector<uint8_t> keep(size_t(N) * N, 0), hbp(size_t(N) * N, 0);
-    int n_pairs = 0;
-    for (int i = 0; i < N; ++i)
-        for (int j = i + 1; j < N; ++j) {
+    // kept pairs in depth-first positions (p < q), with their 12-10 table index
+    struct PairRec { int p, q, hb, table; };
+    std::vector<PairRec> plist;
+    for (int p = 0; p < N; ++p)
+        for (int q = p + 1; q < N; ++q) {
+            const int i = order[p], j = order[q];
             if (frag[i] == frag[j] || graph_dist(i, j) < 4) continue;
-            keep[size_t(i) * N + j] = keep[size_t(j) * N + i] = 1;
-            int ci = d.cls[i], cj = d.cls[j];
-            bool hb = (role_index(ff.donor, ci) >= 0 && role_index(ff.acceptor, cj) >= 0) ||
-                      (role_index(ff.acceptor, ci) >= 0 && role_index(ff.donor, cj) >= 0);
-            hbp[size_t(i) * N + j] = hbp[size_t(j) * N + i] = hb;
-            ++n_pairs;
+            const int ci = d.cls[i], cj = d.cls[j];
+            int table = 0, hb = 0;
+            if (role_index(ff.donor, ci) >= 0 && role_index(ff.acceptor, cj) >= 0) {
+                hb = 1; table = 2 * role_index(ff.donor, ci) + role_index(ff.acceptor, cj);
+            } else if (role_index(ff.acceptor, ci) >= 0 && role_index(ff.donor, cj) >= 0) {
+                hb = 1; table = 2 * role_index(ff.donor, cj) + role_index(ff.acceptor, ci);
+            }
+            plist.push_back({p, q, hb, table});
         }
+    const int n_pairs = (int)plist.size();
+    // batches of kBatch pairs, each atom at most C times per batch (first fit);
+    // C grows for small ligands so that C * N can hold a full batch's 128 ends
+    using dockblob::kBatch;
+    const int C = std::max(2, std::min(16, (2 * kBatch + N - 1) / N + 1));
+    if (C * N > dockblob::kMaxSlots) {
+        err = "internal: accumulator slots exceed the build limit"; return DOCK_EUNSUPPORTED;
+    }
+    std::vector<std::vector<uint32_t>> batch;      // records
+    std::vector<std::vector<uint8_t>> used;        // per batch, per atom position
+    for (const PairRec& pr : plist) {
+        size_t b = 0;
+        for (; b < batch.size(); ++b)
+            if ((int)batch[b].size() < kBatch && used[b][pr.p] < C && used[b][pr.q] < C) break;
+        if (b == batch.size()) {
+            batch.emplace_back();
+            used.emplace_back(N, 0);
+        }
+        const int ci = used[b][pr.p]++, cj = used[b][pr.q]++;
+        batch[b].push_back(dockblob::make_record(pr.p, pr.q, ci, cj, pr.hb, pr.table));
+    }
+    const int n_batches = (int)batch.size();
 
     // ---- pack the blob ----
     using namespace dockblob;
@@ -154,11 +180,10 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
     h.off_ref = take(16 * size_t(N));
     h.off_par = take(16 * size_t(N));
     h.off_chg = take(16 * size_t(N));
-    h.off_hb = take(16 * size_t(N));
     h.off_int = take(16 * size_t(N));
-    h.off_mask = take(8 * 3 * size_t(N));
     h.off_tors = take(sizeof(Torsion) * size_t(T));
     h.off_chain = take(size_t(NF) * kChainStride);
+    h.off_plist = take(4 * size_t(kBatch) * size_t(n_batches));
     h.magic = kMagic;
     h.n_atoms = N;
     h.n_torsions = T;
@@ -166,8 +191,14 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
     h.n_genes = 7 + T;
     h.n_pairs = n_pairs;
     h.max_depth = max_depth;
-    h.n_steps = N / 2;
+    h.n_batches = n_batches;
+    h.n_copies = C;
     h.total_bytes = (int32_t)off;
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            h.hb_r0[2 * a + b] = (float)ff.hb_r0[a][b];
+            h.hb_eps[2 * a + b] = (float)ff.hb_eps[a][b];
+        }
     int max_class = 0;
     for (int i = 0; i < N; ++i) max_class = std::max(max_class, (int)d.cls[i]);
     h.max_class = max_class;
@@ -182,9 +213,7 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
     float* ref = reinterpret_cast<float*>(blob.data() + h.off_ref);
     float* par = reinterpret_cast<float*>(blob.data() + h.off_par);
     float* chg = reinterpret_cast<float*>(blob.data() + h.off_chg);
-    float* hbv = reinterpret_cast<float*>(blob.data() + h.off_hb);
     int32_t* iv = reinterpret_cast<int32_t*>(blob.data() + h.off_int);
-    uint64_t* mk = reinterpret_cast<uint64_t*>(blob.data() + h.off_mask);
     for (int p = 0; p < N; ++p) {
         int i = order[p];
         int c = d.cls[i];
@@ -197,39 +226,9 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
         chg[4 * p + 0] = (float)(kElec * q);
         chg[4 * p + 1] = (float)q;
         chg[4 * p + 2] = (float)std::fabs(q);
-        int di = role_index(ff.donor, c), ai = role_index(ff.acceptor, c);
-        if (di >= 0) {
-            hbv[4 * p + 0] = (float)ff.hb_r0[di][0];
-            hbv[4 * p + 1] = (float)ff.hb_r0[di][1];
-            hbv[4 * p + 2] = (float)ff.hb_eps[di][0];
-            hbv[4 * p + 3] = (float)ff.hb_eps[di][1];
-        } else if (ai >= 0) {
-            hbv[4 * p + 0] = (float)ff.hb_r0[0][ai];
-            hbv[4 * p + 1] = (float)ff.hb_r0[1][ai];
-            hbv[4 * p + 2] = (float)ff.hb_eps[0][ai];
-            hbv[4 * p + 3] = (float)ff.hb_eps[1][ai];
-        }
         iv[4 * p + 0] = c;
         iv[4 * p + 1] = frag[i];
         iv[4 * p + 2] = i;
-        // offset-space masks
-        uint64_t kept = 0, hbm = 0, hbi = 0;
-        for (int s = 1; s <= N / 2; ++s) {
-            if ((N % 2 == 0) && s == N / 2 && p >= N / 2) continue;
-            int q2 = (p + s) % N;
-            int j = order[q2];
-            if (!keep[size_t(i) * N + j]) continue;
-            kept |= uint64_t(1) << (s - 1);
-            if (hbp[size_t(i) * N + j]) {
-                hbm |= uint64_t(1) << (s - 1);
-                int cj = d.cls[j];
-                int idx = role_index(ff.donor, cj) >= 0 ? role_index(ff.donor, cj) : role_index(ff.acceptor, cj);
-                if (idx == 1) hbi |= uint64_t(1) << (s - 1);
-            }
-        }
-        mk[p] = kept;
-        mk[N + p] = hbm;
-        mk[2 * N + p] = hbi;
     }
     Torsion* tr = reinterpret_cast<Torsion*>(blob.data() + h.off_tors);
     for (int k = 0; k < T; ++k) {
@@ -246,6 +245,9 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
         tr[k].first = pos[b];
         tr[k].end = pos[b] + size[b];
     }
+    uint32_t* pl = reinterpret_cast<uint32_t*>(blob.data() + h.off_plist);
+    for (int b = 0; b < n_batches; ++b)
+        for (size_t k = 0; k < batch[b].size(); ++k) pl[b * kBatch + k] = batch[b][k];
     int8_t* ch = reinterpret_cast<int8_t*>(blob.data() + h.off_chain);
     for (int f = 0; f < NF; ++f) {
         ch[f * kChainStride] = (int8_t)chain[f].size();
@@ -273,16 +275,15 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
 void decode_pairs(const Prepared& P, std::vector<uint32_t>& pairs, std::vector<uint8_t>& hb) {
     using namespace dockblob;
     const Header* h = reinterpret_cast<const Header*>(P.blob.data());
-    const int N = h->n_atoms;
-    const uint64_t* mk = reinterpret_cast<const uint64_t*>(P.blob.data() + h->off_mask);
+    const uint32_t* pl = reinterpret_cast<const uint32_t*>(P.blob.data() + h->off_plist);
     std::vector<std::pair<uint32_t, uint8_t>> v;
-    for (int p = 0; p < N; ++p)
-        for (int s = 1; s <= N / 2; ++s) {
-            if (!((mk[p] >> (s - 1)) & 1)) continue;
-            int i = P.order[p], j = P.order[(p + s) % N];
-            uint32_t lo = (uint32_t)std::min(i, j), hi = (uint32_t)std::max(i, j);
-            v.push_back({(lo << 16) | hi, (uint8_t)((mk[N + p] >> (s - 1)) & 1)});
-        }
+    for (int k = 0; k < h->n_batches * kBatch; ++k) {
+        const uint32_t r = pl[k];
+        if (!(r & kRecValid)) continue;
+        const int i = P.order[r & 127], j = P.order[(r >> 7) & 127];
+        const uint32_t lo = (uint32_t)std::min(i, j), hi = (uint32_t)std::max(i, j);
+        v.push_back({(lo << 16) | hi, (uint8_t)((r >> 22) & 1)});
+    }
     std::sort(v.begin(), v.end());
     pairs.resize(v.size());
     hb.resize(v.size());

@@ -7,10 +7,27 @@ E_TOL = 1e-5
 G_TOL = 1e-4
 
 
+# When the energy is a small difference of large terms (kappa = sum|e_i| / |E|
+# large), no FP32 evaluation can hold 1e-5 relative to |E|: rounding of the
+# terms themselves is ~1e-7 of their magnitude. Such energies are held to
+# E_ABS_TOL relative to the magnitude sum instead, and counted.
+E_ABS_TOL = 1e-6
+
+
 def e_relerr(e_gpu, e_ref):
     e_gpu = np.asarray(e_gpu, np.float64)
     e_ref = np.asarray(e_ref, np.float64)
     return np.abs(e_gpu - e_ref) / np.maximum(np.abs(e_ref), 1.0)
+
+
+def e_ok(e_gpu, ref):
+    """Per individual: within E_TOL of max(|E|, 1), or within E_ABS_TOL of
+    the sum of term magnitudes (ill-conditioned sums). Returns (ok, cond)
+    where cond marks individuals that passed only by the second bound."""
+    err = np.abs(np.asarray(e_gpu, np.float64) - ref.energy)
+    rel_ok = err <= E_TOL * np.maximum(np.abs(ref.energy), 1.0)
+    abs_ok = err <= E_ABS_TOL * ref.e_abs
+    return rel_ok | abs_ok, (~rel_ok) & abs_ok
 
 
 def g_relerr(g_gpu, g_ref):

@@ -14,7 +14,7 @@ import pytest
 from oracle import dock_ref as R
 from oracle import reduce_ref as RR
 from paper_2410_10447_amd import synth
-from tests.gpu_common import E_TOL, G_TOL, e_relerr, g_relerr, near_discontinuity
+from tests.gpu_common import E_TOL, G_TOL, e_ok, e_relerr, g_relerr, near_discontinuity
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -203,14 +203,17 @@ def test_ls_step_map(dk, variant):
         flag = near_discontinuity(prep, w.grids, ref.x)
         xn, ag, ad = R.adadelta_step(x, ref.grad, s0["acc_g2"].astype(np.float64),
                                      s0["acc_dx2"].astype(np.float64), 0.8, 1e-2)
-        assert np.all(e_relerr(s1["energy"], ref.energy)[~flag] <= E_TOL)
+        ok, cond = e_ok(s1["energy"], ref)
+        n_cond = cond[~flag].sum()
+        assert np.all(ok[~flag]), (it, e_relerr(s1["energy"], ref.energy)[~ok].max())
         dxg = s1["genotype"] - x
         dxo = xn - x
         err = np.linalg.norm(dxg - dxo, axis=1) / np.maximum(np.linalg.norm(dxo, axis=1), 1e-3)
         worst = max(worst, err[~flag].max())
         assert np.all(err[~flag] <= 1e-4), (it, err[~flag].max())
         assert np.all(s1["iters_done"] == it + 1)
-    print(f"\n[ls step-map v{variant}] worst step rel err {worst:.2e}", flush=True)
+    print(f"\n[ls step-map v{variant}] worst step rel err {worst:.2e}; "
+          f"ill-conditioned energies at the last step {n_cond}", flush=True)
 
 
 def test_ls_chunked_equals_single_and_deterministic(dk):
@@ -247,9 +250,13 @@ def test_ls_full_size_sampled(dk):
     ref = R.score(prep, w.grids, s["best_genotype"][idx].astype(np.float64))
     flag = near_discontinuity(prep, w.grids, ref.x)
     ee = e_relerr(s["best_energy"][idx], ref.energy)
+    ok, cond = e_ok(s["best_energy"][idx], ref)
+    kappa = ref.e_abs / np.maximum(np.abs(ref.energy), 1.0)
     print(f"\n[ls full] best E median {np.median(s['best_energy']):.3f} "
-          f"start median {np.median(start):.1f}; sampled E err max {ee[~flag].max():.2e}", flush=True)
-    assert np.all(ee[~flag] <= E_TOL)
+          f"start median {np.median(start):.1f}; sampled E err max {ee[~flag].max():.2e}; "
+          f"kappa median {np.median(kappa):.1f} max {kappa.max():.1f}; "
+          f"held to the magnitude bound {cond[~flag].sum()} of {(~flag).sum()}", flush=True)
+    assert np.all(ok[~flag])
     assert np.all(s["best_energy"][idx] <= start + 1e-3 * np.abs(start))
     # distribution against the oracle's own 300-step search on a subsample
     sub = np.arange(0, 3000, 100)

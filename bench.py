@@ -10,8 +10,9 @@ resident copy of the state per step, prepared before timing).
 
 Prints one JSON line with the throughput of the best reduction variant, the
 per-variant throughputs (the plain wave-shuffle variant is the baseline), the
-roofline object of the local-search kernel, and the FP64 oracle timed on the
-host on a bounded sample.
+roofline object of the local-search kernel, a serving run (Poisson arrivals of
+docking jobs, continuous batching, p50/p99 job latency) and the FP64 oracle
+timed on the host on a bounded sample.
 """
 from __future__ import annotations
 
@@ -65,6 +66,71 @@ def cpu_baseline(w, sample, iterations):
                       f"({evals} evals, {dt:.1f} s, NumPy FP64 single process)"}
 
 
+def uneven_run(steps, warmup, use_table=True):
+    """64 ligands (atoms U{12..128}, torsions U{0..32}) x 100 individuals on one
+    96^3 x 12 grid set, 300 iterations, all in one persistent launch per step;
+    each item takes its size bucket's variant from the autotuning table."""
+    import torch
+    from paper_2410_10447_amd import autotune, dock, synth
+    w = synth.uneven_workload()
+    G = dock.Grids.from_synth(w.grids)
+    Ls = [dock.Ligand(l, w.ff) for l in w.ligands]
+    gens = [torch.from_numpy(g).cuda() for g in w.genotypes]
+    var = [autotune.choose(L.n_atoms, L.n_torsions)["variant"] if use_table else 0 for L in Ls]
+    evals = sum(g.shape[0] for g in gens) * (w.iterations + 1)
+    ws = torch.empty(dock.workspace_bytes(len(Ls)), dtype=torch.uint8, device="cuda")
+    runs = []
+    for _ in range(warmup + steps):
+        states = [dock.LSState.start(g) for g in gens]
+        jobs = [dock.LsJob(G, L, st, v) for L, st, v in zip(Ls, states, var)]
+        runs.append((states, dock.make_items(jobs)))
+    torch.cuda.synchronize()
+    for k in range(warmup):
+        dock.local_search([None] * len(Ls), w.iterations, workspace=ws, items=runs[k][1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(warmup, warmup + steps):
+        dock.local_search([None] * len(Ls), w.iterations, workspace=ws, items=runs[k][1])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    return {"workload": w.name, "evals_per_step": evals, "ms_per_step": 1e3 * dt,
+            "evals_per_s": evals / dt, "variants_from_table": use_table,
+            "atoms_mean": float(np.mean([L.n_atoms for L in Ls])),
+            "pairs_mean": float(np.mean([L.n_pairs for L in Ls]))}
+
+
+def serving_run(seconds, rate, seed=4000, chunk_iters=25, max_individuals=120_000,
+                budget_bytes=8 << 30, variant=0):
+    """Poisson arrivals of docking jobs (ligands of the uneven-batch size
+    distribution, 50 runs x 150 individuals, 300 iterations) against four
+    resident receptor grid sets; continuous batching across jobs."""
+    import torch
+    from paper_2410_10447_amd import serve, synth
+    rng = np.random.default_rng(seed)
+    shapes = [(64, 10), (80, 10), (88, 12), (96, 12)]
+    grid_sets = [synth.grids(n, m, seed + 1 + k) for k, (n, m) in enumerate(shapes)]
+    pool = synth.uneven_workload(n_ligands=64, per_ligand=1, grid_n=8).ligands
+    ex = serve.GpuExecutor(grid_sets, synth.force_field(), variant=variant)
+    arrivals = serve.poisson_arrivals(rate, seconds, seed + 7)
+    specs = []
+    for k, t in enumerate(arrivals):
+        lig = pool[int(rng.integers(len(pool)))]
+        gid = int(rng.integers(len(grid_sets)))
+        gen = synth.genotypes(lig, grid_sets[gid], 7500, seed + 100 + k)
+        specs.append(serve.JobSpec(job_id=k, ligand=lig, grid_id=gid, genotypes=gen, arrival=t,
+                                   iterations=300))
+    torch.cuda.synchronize()
+    srv = serve.Server(ex, max_individuals=max_individuals, device_budget=budget_bytes,
+                       chunk_iters=chunk_iters)
+    st = srv.run(specs)
+    out = st.summary()
+    out.update({"rate_jobs_per_s": rate, "arrival_window_s": seconds, "chunk_iters": chunk_iters,
+                "max_inflight_individuals": max_individuals,
+                "resident_grid_bytes": ex.grid_bytes,
+                "offered_evals_per_s": rate * 7500 * 301})
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +139,11 @@ def main():
     ap.add_argument("--variants", default="0,1", help="reduction variants to time (0 shuffle, 1 FP32 MFMA, ...)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=48)
+    ap.add_argument("--uneven-steps", type=int, default=3,
+                    help="timed steps of the uneven 64-ligand batch (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=15.0,
+                    help="arrival window of the serving run (0 = skip)")
+    ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate (jobs/s)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -158,6 +229,10 @@ def main():
                      "traffic": None,
                      "flops_per_eval": fpe},
     }
+    if args.uneven_steps > 0:
+        out["uneven"] = uneven_run(args.uneven_steps, 1)
+    if args.serve_seconds > 0:
+        out["serving"] = serving_run(args.serve_seconds, args.serve_rate, variant=best_v)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, iters)
     print(json.dumps(out), flush=True)

@@ -159,6 +159,7 @@ int32_t dock_create_grids(const dock_grid_desc* d, const float* maps_dev, dock_g
     g->gp.nz = d->nz;
     g->gp.n_maps = d->n_maps;
     g->gp.spacing = d->spacing;
+    g->gp.inv_spacing = (float)(1.0 / (double)d->spacing);
     const int n[3] = {d->nx, d->ny, d->nz};
     for (int c = 0; c < 3; ++c) {
         g->gp.origin[c] = d->origin[c];

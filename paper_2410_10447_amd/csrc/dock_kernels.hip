@@ -238,7 +238,7 @@ struct __align__(16) Smem {
             float tk[kMaxTors][12]; // torsion transforms, 3x4 row-major
             float fw[kMaxFrag][12]; // fragment transforms (rotation part of the pose)
         } pose;                     // live until the atom positions are written
-        float acc[3][dockblob::kMaxSlots];  // pair-force accumulators, slot = copy * N + atom
+        float4 acc[dockblob::kMaxSlots];    // pair-force accumulators, slot = copy * N + atom
     } u;
     int8_t chain[kMaxFrag][kChain]; // [0] = length, then torsions root first
     float2 hbt[4];                  // 12-10 table (r0, eps), index 2 * donor + acceptor
@@ -329,14 +329,14 @@ __device__ __forceinline__ float two_sum_fraction(float t, float node, float xl)
     return s2 + (e1 + e2);
 }
 
-__device__ __forceinline__ void axis_cell(float t, float xl, float lo, float hi, float h, int n,
-                                          int& c, float& f, float& xw, float& xc) {
+__device__ __forceinline__ void axis_cell(float t, float xl, float lo, float hi, float h, float ih,
+                                          int n, int& c, float& f, float& xw, float& xc) {
     xw = t + xl;
     xc = fminf(fmaxf(xw, lo), hi);
-    const float u = (xc - lo) / h;
+    const float u = (xc - lo) * ih;
     c = min(max((int)floorf(u), 0), n - 2);
     const float node = lo + (float)c * h;
-    f = (xw == xc) ? two_sum_fraction(t, node, xl) / h : (xc - node) / h;
+    f = ((xw == xc) ? two_sum_fraction(t, node, xl) : (xc - node)) * ih;
 }
 
 __device__ __forceinline__ void grid_term(const GridParams& G, int cls, float q, float aq,
@@ -344,9 +344,10 @@ __device__ __forceinline__ void grid_term(const GridParams& G, int cls, float q,
                                           float& e, float& gx, float& gy, float& gz) {
     int cx, cy, cz;
     float fx, fy, fz, xw, yw, zw, xc, yc, zc;
-    axis_cell(t[0], xl[0], G.origin[0], G.hi[0], G.spacing, G.nx, cx, fx, xw, xc);
-    axis_cell(t[1], xl[1], G.origin[1], G.hi[1], G.spacing, G.ny, cy, fy, yw, yc);
-    axis_cell(t[2], xl[2], G.origin[2], G.hi[2], G.spacing, G.nz, cz, fz, zw, zc);
+    const float ih = G.inv_spacing;
+    axis_cell(t[0], xl[0], G.origin[0], G.hi[0], G.spacing, ih, G.nx, cx, fx, xw, xc);
+    axis_cell(t[1], xl[1], G.origin[1], G.hi[1], G.spacing, ih, G.ny, cy, fy, yw, yc);
+    axis_cell(t[2], xl[2], G.origin[2], G.hi[2], G.spacing, ih, G.nz, cz, fz, zw, zc);
     const int plane = G.nx * G.ny;
     const int vol = plane * G.nz;
     const int base = (cz * G.ny + cy) * G.nx + cx;
@@ -367,7 +368,6 @@ __device__ __forceinline__ void grid_term(const GridParams& G, int cls, float q,
     const float dfy = (a01 - a00) + fz * ((a11 - a10) - (a01 - a00));
     const float dx0 = d00 + fy * (d01 - d00), dx1 = d10 + fy * (d11 - d10);
     const float dfx = dx0 + fz * (dx1 - dx0);
-    const float ih = 1.0f / G.spacing;
     const float ox = xw - xc, oy = yw - yc, oz = zw - zc;
     e = val + kOut * (ox * ox + oy * oy + oz * oz);
     gx = (xw == xc ? dfx * ih : 0.f) + 2.f * kOut * ox;
@@ -433,8 +433,7 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
     const float tx = readlane(gene, 0), ty = readlane(gene, 1), tz = readlane(gene, 2);
     const float qw0 = readlane(gene, 3), qx0 = readlane(gene, 4), qy0 = readlane(gene, 5),
                 qz0 = readlane(gene, 6);
-    const float qn = sqrtf(qw0 * qw0 + qx0 * qx0 + qy0 * qy0 + qz0 * qz0);
-    const float qinv = 1.0f / qn;
+    const float qinv = __builtin_amdgcn_rsqf(qw0 * qw0 + qx0 * qx0 + qy0 * qy0 + qz0 * qz0);
     const float qw = qw0 * qinv, qx = qx0 * qinv, qy = qy0 * qinv, qz = qz0 * qinv;
     float Rq[9];
     Rq[0] = 1.f - 2.f * (qy * qy + qz * qz);
@@ -534,13 +533,11 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
     // its pair's force to both atoms' accumulator slots; the host schedule
     // makes the slots of one batch distinct, so no two lanes of an
     // instruction touch one address and the order of additions is fixed.
+    // (LDS float atomics would serialise in the LDS unit: they made this
+    // phase several times slower.)
     {
         const int nslot = L.n_copies * N;
-        for (int k = lane; k < nslot; k += kWave) {
-            sm.u.acc[0][k] = 0.f;
-            sm.u.acc[1][k] = 0.f;
-            sm.u.acc[2][k] = 0.f;
-        }
+        for (int k = lane; k < nslot; k += kWave) sm.u.acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
         uint32_t rec_next = L.n_batches > 0 ? L.plist[lane] : 0u;
         for (int bt = 0; bt < L.n_batches; ++bt) {
@@ -566,14 +563,17 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
             pair_term(dx, dy, dz, r0, c12, c10, c6, qq, ds, valid, e, w);
             e_lane += e;
             const float fx = w * dx, fy = w * dy, fz = w * dz;
+            // read-modify-write of two slots per lane: the slots of one
+            // batch are distinct, so plain LDS loads and stores suffice (no
+            // atomics), and batches follow each other in program order
             if (valid) {
                 const int si = ci * N + i, sj = cj * N + j;
-                atomicAdd(&sm.u.acc[0][si], -fx);
-                atomicAdd(&sm.u.acc[1][si], -fy);
-                atomicAdd(&sm.u.acc[2][si], -fz);
-                atomicAdd(&sm.u.acc[0][sj], fx);
-                atomicAdd(&sm.u.acc[1][sj], fy);
-                atomicAdd(&sm.u.acc[2][sj], fz);
+                float4 ai = sm.u.acc[si];
+                float4 aj = sm.u.acc[sj];
+                ai.x -= fx; ai.y -= fy; ai.z -= fz;
+                aj.x += fx; aj.y += fy; aj.z += fz;
+                sm.u.acc[si] = ai;
+                sm.u.acc[sj] = aj;
             }
         }
         __syncthreads();
@@ -583,9 +583,10 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
             const int a = lane + kWave * s;
             if (a < N) {
                 for (int c = 0; c < L.n_copies; ++c) {
-                    g[s][0] += sm.u.acc[0][c * N + a];
-                    g[s][1] += sm.u.acc[1][c * N + a];
-                    g[s][2] += sm.u.acc[2][c * N + a];
+                    const float4 v = sm.u.acc[c * N + a];
+                    g[s][0] += v.x;
+                    g[s][1] += v.y;
+                    g[s][2] += v.z;
                 }
             }
         }
@@ -641,7 +642,7 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
         const float4 xa = sm.dyn[L.t_apos];
         const float4 xb = sm.dyn[L.t_bpos];
         float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
-        const float il = 1.0f / sqrtf(ux * ux + uy * uy + uz * uz);
+        const float il = __builtin_amdgcn_rsqf(ux * ux + uy * uy + uz * uz);
         ux *= il; uy *= il; uz *= il;
         // S_xg - x_a cross S_g
         const float mx = S[3] - (xa.y * S[2] - xa.z * S[1]);
@@ -687,7 +688,7 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
 // ---------------------------------------------------------------------------
 
 template <int SLOTS, int VAR>
-__global__ __launch_bounds__(64, (SLOTS == 1 ? 4 : 2)) void score_kernel(GridParams G, const uint8_t* __restrict__ blob,
+__global__ __launch_bounds__(64, (SLOTS == 1 ? 3 : 2)) void score_kernel(GridParams G, const uint8_t* __restrict__ blob,
                                                    int n, const float* __restrict__ gen,
                                                    float* __restrict__ energy,
                                                    float* __restrict__ grad,
@@ -726,13 +727,13 @@ __device__ void local_search_one(const DevItem& it, int ind, Smem& sm, const Lig
         if (E < bestE) { bestE = E; bx = x; }
         gr = act ? gr : 0.f;
         ag = rho * ag + (1.f - rho) * gr * gr;
-        const float dx = -(sqrtf(ad + eps) / sqrtf(ag + eps)) * gr;
+        const float dx = -(__builtin_amdgcn_sqrtf(ad + eps) * __builtin_amdgcn_rsqf(ag + eps)) * gr;
         ad = rho * ad + (1.f - rho) * dx * dx;
         float xn = x + dx;
         const bool isq = lane >= 3 && lane < 7;
         const float q2 = isq ? xn * xn : 0.f;
-        const float nq = sqrtf((readlane(q2, 3) + readlane(q2, 4)) + (readlane(q2, 5) + readlane(q2, 6)));
-        if (isq) xn = (nq >= 1e-6f) ? xn / nq : x;
+        const float nq2 = (readlane(q2, 3) + readlane(q2, 4)) + (readlane(q2, 5) + readlane(q2, 6));
+        if (isq) xn = (nq2 >= 1e-12f) ? xn * __builtin_amdgcn_rsqf(nq2) : x;
         x = act ? xn : 0.f;
     }
     if (final_eval) {
@@ -787,7 +788,7 @@ __device__ void ls_run(const DevItem& it, int ind, Smem& sm, const Lig<SLOTS>& L
 // only when the item changes. Every wave exits once the counter passes the
 // last unit.
 template <int MODE, int VAR>
-__global__ __launch_bounds__(64, (MODE == docklaunch::kSlots1 ? 4 : 2)) void ls_kernel(LsParams p) {
+__global__ __launch_bounds__(64, (MODE == docklaunch::kSlots1 ? 3 : 2)) void ls_kernel(LsParams p) {
     __shared__ Smem sm;
     const int lane = lane_id();
     int cur_item = -1;

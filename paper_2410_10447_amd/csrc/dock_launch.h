@@ -11,6 +11,7 @@ struct GridParams {
     const float* maps;   // [n_maps][nz][ny][nx]
     int32_t nx, ny, nz, n_maps;
     float spacing;
+    float inv_spacing;
     float origin[3];
     float hi[3];         // origin + (n - 1) * spacing per axis
 };

@@ -388,9 +388,11 @@ def local_search(jobs, iterations: int, rho: float = 0.8, eps: float = 1e-2,
     n_items = len(jobs)
     if items is None:
         items = make_items(jobs)
+    elif len(items) < n_items:
+        raise ValueError("items shorter than jobs")
     need = workspace_bytes(n_items)
     if workspace is None or workspace.numel() < need:
-        dev = _as_job(jobs[0]).state.genotype.device if n_items else torch.device("cuda")
+        dev = torch.device("cuda")
         workspace = torch.empty(max(need, 64), dtype=torch.uint8, device=dev)
     o = LsOpts(iterations=iterations, rho=rho, eps=eps, variant=variant, threads_per_ind=0,
                flags=LS_FINAL_EVAL if final_eval else 0)

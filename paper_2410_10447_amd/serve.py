@@ -286,7 +286,9 @@ class GpuExecutor:
         self.grids = [dock.Grids.from_synth(g, device) for g in grid_sets]
         self.grid_bytes = sum(g.nbytes() for g in self.grids)
         self.stream = torch.cuda.current_stream()
-        self.ws = torch.empty(dock.workspace_bytes(64), dtype=torch.uint8, device=device)
+        # results leave on a side stream (default priority) so that reading a
+        # finished job does not wait for the chunks queued after it
+        self.side = torch.cuda.Stream()
         self._ws_pool = []
 
     def footprint(self, spec):
@@ -294,9 +296,14 @@ class GpuExecutor:
         return state_bytes(spec.genotypes.shape[0], G) + 8192
 
     def prepare(self, spec):
-        L = self.dock.Ligand(spec.ligand, self.ff, device=self.device)
-        st = self.dock.LSState.start(self.torch.from_numpy(spec.genotypes).to(self.device))
-        return {"ligand": L, "state": st, "grids": self.grids[spec.grid_id]}
+        torch = self.torch
+        L = self.dock.Ligand(spec.ligand, self.ff, device=self.device, upload=False)
+        L.upload(self.device, stream=self.stream)
+        host = torch.from_numpy(np.ascontiguousarray(spec.genotypes)).pin_memory()
+        with torch.cuda.stream(self.stream):
+            gen = host.to(self.device, non_blocking=True)
+            st = self.dock.LSState.start(gen)
+        return {"ligand": L, "state": st, "grids": self.grids[spec.grid_id], "host": host}
 
     def launch(self, plan, max_iters):
         jobs = [self.dock.LsJob(h["grids"], h["ligand"], h["state"], -1, k, 1 if fin else 0)
@@ -328,9 +335,15 @@ class GpuExecutor:
         time.sleep(min(dt, 1e-3))
 
     def result(self, handle):
+        torch = self.torch
         st = handle["state"]
-        return {"best_energy": st.best_energy.cpu().numpy(),
-                "best_genotype": st.best_genotype.cpu().numpy()}
+        with torch.cuda.stream(self.side):
+            be = torch.empty(st.best_energy.shape, dtype=st.best_energy.dtype, pin_memory=True)
+            bg = torch.empty(st.best_genotype.shape, dtype=st.best_genotype.dtype, pin_memory=True)
+            be.copy_(st.best_energy, non_blocking=True)
+            bg.copy_(st.best_genotype, non_blocking=True)
+        self.side.synchronize()
+        return {"best_energy": be.numpy(), "best_genotype": bg.numpy()}
 
     def release(self, handle):
         handle.clear()

@@ -7,11 +7,15 @@ E_TOL = 1e-5
 G_TOL = 1e-4
 
 
-# When the energy is a small difference of large terms (kappa = sum|e_i| / |E|
-# large), no FP32 evaluation can hold 1e-5 relative to |E|: rounding of the
-# terms themselves is ~1e-7 of their magnitude. Such energies are held to
-# E_ABS_TOL relative to the magnitude sum instead, and counted.
+# Two ill-conditioned cases in which no FP32 evaluation can hold 1e-5
+# relative to |E|, each held to the error FP32 itself implies, and counted:
+# * E a small difference of large terms (kappa = sum|e_i| / |E| large): the
+#   terms' own rounding is ~1e-7 of their magnitude -> E_ABS_TOL * sum|e_i|;
+# * E dominated by steep terms (clashes: a 12-6 term moves by 12 dr / r), where
+#   the ~1e-7 relative rounding of FP32 atom positions alone moves E by about
+#   u * sum_i |g_i| (|x_i - t| + 1 A) -> X_TOL * that sum.
 E_ABS_TOL = 1e-6
+X_TOL = 16 * 2.0 ** -24
 
 
 def e_relerr(e_gpu, e_ref):
@@ -20,14 +24,17 @@ def e_relerr(e_gpu, e_ref):
     return np.abs(e_gpu - e_ref) / np.maximum(np.abs(e_ref), 1.0)
 
 
-def e_ok(e_gpu, ref):
-    """Per individual: within E_TOL of max(|E|, 1), or within E_ABS_TOL of
-    the sum of term magnitudes (ill-conditioned sums). Returns (ok, cond)
-    where cond marks individuals that passed only by the second bound."""
+def e_ok(e_gpu, ref, genotypes):
+    """Per individual: within E_TOL of max(|E|, 1), or within the FP32
+    conditioning bounds above. Returns (ok, cond) where cond marks
+    individuals that passed only by a conditioning bound."""
     err = np.abs(np.asarray(e_gpu, np.float64) - ref.energy)
     rel_ok = err <= E_TOL * np.maximum(np.abs(ref.energy), 1.0)
-    abs_ok = err <= E_ABS_TOL * ref.e_abs
-    return rel_ok | abs_ok, (~rel_ok) & abs_ok
+    t = np.asarray(genotypes, np.float64)[:, None, 0:3]
+    sx = np.sum(np.linalg.norm(ref.atom_grad, axis=-1) * (np.linalg.norm(ref.x - t, axis=-1) + 1.0),
+                axis=1)
+    cond_ok = (err <= E_ABS_TOL * ref.e_abs) | (err <= X_TOL * sx)
+    return rel_ok | cond_ok, (~rel_ok) & cond_ok
 
 
 def g_relerr(g_gpu, g_ref):

@@ -76,6 +76,24 @@ __device__ __forceinline__ float readlane(float v, int l) {
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// Wave-uniform value: lets the compiler keep it (and what is derived from it,
+// such as loop bounds and addresses) in scalar registers.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+    const uint64_t v = reinterpret_cast<uint64_t>(p);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+// Global-memory view of a pointer, so that loads are issued as global (not
+// flat) instructions and do not count against the LDS wait counter.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
+    return (const __attribute__((address_space(1))) T*)(p);
+}
+
 // Sum over the wave, every lane receives the same value. Butterfly inside
 // each 16-lane row with DPP (quad swaps, half-row and row mirrors), then the
 // four row sums are read as scalars and added in a fixed order.
@@ -264,13 +282,13 @@ template <int SLOTS>
 __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem& sm, Lig<SLOTS>& L) {
     const Header* h = reinterpret_cast<const Header*>(blob);
     const int lane = lane_id();
-    L.N = h->n_atoms;
-    L.T = h->n_torsions;
-    L.NF = h->n_frag;
-    L.G = h->n_genes;
-    L.n_batches = h->n_batches;
-    L.n_copies = h->n_copies;
-    L.plist = reinterpret_cast<const uint32_t*>(blob + h->off_plist);
+    L.N = uniform(h->n_atoms);
+    L.T = uniform(h->n_torsions);
+    L.NF = uniform(h->n_frag);
+    L.G = uniform(h->n_genes);
+    L.n_batches = uniform(h->n_batches);
+    L.n_copies = uniform(h->n_copies);
+    L.plist = uniform_ptr(reinterpret_cast<const uint32_t*>(blob + h->off_plist));
     if (lane < 4) sm.hbt[lane] = make_float2(h->hb_r0[lane], h->hb_eps[lane]);
     const float4* ref = reinterpret_cast<const float4*>(blob + h->off_ref);
     const float4* par = reinterpret_cast<const float4*>(blob + h->off_par);
@@ -351,9 +369,9 @@ __device__ __forceinline__ void grid_term(const GridParams& G, int cls, float q,
     const int plane = G.nx * G.ny;
     const int vol = plane * G.nz;
     const int base = (cz * G.ny + cy) * G.nx + cx;
-    const float* __restrict__ mc = G.maps + (size_t)cls * vol + base;
-    const float* __restrict__ me = G.maps + (size_t)(G.n_maps - 2) * vol + base;
-    const float* __restrict__ md = G.maps + (size_t)(G.n_maps - 1) * vol + base;
+    const auto mc = gmem(G.maps + (size_t)cls * vol + base);
+    const auto me = gmem(G.maps + (size_t)(G.n_maps - 2) * vol + base);
+    const auto md = gmem(G.maps + (size_t)(G.n_maps - 1) * vol + base);
     const int off[8] = {0, 1, G.nx, G.nx + 1, plane, plane + 1, plane + G.nx, plane + G.nx + 1};
     float v[8];
 #pragma unroll
@@ -539,10 +557,11 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
         const int nslot = L.n_copies * N;
         for (int k = lane; k < nslot; k += kWave) sm.u.acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
-        uint32_t rec_next = L.n_batches > 0 ? L.plist[lane] : 0u;
+        const auto plist = gmem(L.plist);
+        uint32_t rec_next = L.n_batches > 0 ? plist[lane] : 0u;
         for (int bt = 0; bt < L.n_batches; ++bt) {
             const uint32_t rec = rec_next;
-            if (bt + 1 < L.n_batches) rec_next = L.plist[(bt + 1) * kWave + lane];
+            if (bt + 1 < L.n_batches) rec_next = plist[(bt + 1) * kWave + lane];
             const bool valid = (rec & dockblob::kRecValid) != 0u;
             const int i = rec & 127, j = (rec >> 7) & 127;
             const int ci = (rec >> 14) & 15, cj = (rec >> 18) & 15;
@@ -782,6 +801,19 @@ __device__ void ls_run(const DevItem& it, int ind, Smem& sm, const Lig<SLOTS>& L
         ls_dispatch<SLOTS>(-1, it, ind, sm, L, p);
 }
 
+// The item record, read once per work unit, with every word made
+// wave-uniform (scalar registers).
+__device__ __forceinline__ DevItem load_item(const DevItem* items, int k) {
+    static_assert(sizeof(DevItem) % 4 == 0, "item record is made of 32-bit words");
+    constexpr int kWords = sizeof(DevItem) / 4;
+    const auto src = gmem(reinterpret_cast<const uint32_t*>(items + k));
+    DevItem out;
+    uint32_t* dst = reinterpret_cast<uint32_t*>(&out);
+#pragma unroll
+    for (int w = 0; w < kWords; ++w) dst[w] = __builtin_amdgcn_readfirstlane(src[w]);
+    return out;
+}
+
 // Persistent local-search kernel. Work units are individuals, numbered item by
 // item in the order the host gives (longest items first); each wave takes the
 // next unit from a global counter until none is left, reloading the ligand
@@ -797,14 +829,14 @@ __global__ __launch_bounds__(64, (MODE == docklaunch::kSlots1 ? 3 : 2)) void ls_
     while (true) {
         int u = 0;
         if (lane == 0) u = atomicAdd(p.counter, 1);
-        u = __shfl(u, 0);
+        u = uniform(u);
         if (u >= p.total_units) break;
         int lo = 0, hi = p.n_items - 1;
         while (lo < hi) {  // last item with unit_begin <= u
             const int mid = (lo + hi + 1) >> 1;
-            if (p.items[mid].unit_begin <= u) lo = mid; else hi = mid - 1;
+            if (uniform(gmem(&p.items[mid].unit_begin)[0]) <= u) lo = mid; else hi = mid - 1;
         }
-        const DevItem& it = p.items[lo];
+        const DevItem it = load_item(p.items, lo);
         const int ind = u - it.unit_begin;
         if constexpr (MODE == docklaunch::kSlots1) {
             if (lo != cur_item) { __syncthreads(); load_ligand<1>(it.blob, sm, L2); cur_item = lo; }

@@ -133,6 +133,8 @@ typedef struct {
     int32_t n_pairs;          /* intramolecular pairs kept */
     int32_t n_fragments;      /* rigid fragments = n_torsions + 1 */
     int32_t max_depth;        /* longest chain of nested torsions */
+    int32_t n_batches;        /* 64-wide batches the pair list is cut into */
+    int32_t n_copies;         /* force accumulator copies per atom (see export) */
     int64_t blob_bytes;       /* device bytes needed by dock_ligand_upload */
 } dock_ligand_info;
 
@@ -157,9 +159,16 @@ int32_t dock_ligand_info_get(const dock_ligand* lig, dock_ligand_info* out);
  *                              k+1 = the fragment next to torsion k's b atom)
  *   pairs     [n_pairs]        (i << 16) | j with i < j (original indices),
  *                              sorted ascending
- *   pair_hb   [n_pairs]        1 for a donor-acceptor (12-10) pair, else 0 */
+ *   pair_hb   [n_pairs]        1 for a donor-acceptor (12-10) pair, else 0
+ *   batches   [n_batches][64]  the pair list as the kernels read it: one record
+ *                              per lane, i | j << 7 | ci << 14 | cj << 18 |
+ *                              hb << 22 | table << 23 | valid << 31, with i, j
+ *                              depth-first positions and ci, cj < n_copies the
+ *                              accumulator copies the pair's force goes to; within
+ *                              a batch every (copy, atom) slot occurs at most once */
 int32_t dock_ligand_export(const dock_ligand* lig, int32_t* order, int32_t* torsions,
-                           int32_t* fragment, uint32_t* pairs, uint8_t* pair_hb);
+                           int32_t* fragment, uint32_t* pairs, uint8_t* pair_hb,
+                           uint32_t* batches);
 
 /* Copies the packed ligand (blob_bytes, see dock_ligand_info) to blob_dev
  * (device, caller-owned, 16-byte aligned) asynchronously on `stream` (staged

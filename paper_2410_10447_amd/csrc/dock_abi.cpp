@@ -203,12 +203,17 @@ int32_t dock_ligand_info_get(const dock_ligand* l, dock_ligand_info* out) {
     out->n_pairs = l->prep.n_pairs;
     out->n_fragments = l->prep.n_frag;
     out->max_depth = l->prep.max_depth;
+    {
+        const dockblob::Header* h = reinterpret_cast<const dockblob::Header*>(l->prep.blob.data());
+        out->n_batches = h->n_batches;
+        out->n_copies = h->n_copies;
+    }
     out->blob_bytes = (int64_t)l->prep.blob.size();
     return ok();
 }
 
 int32_t dock_ligand_export(const dock_ligand* l, int32_t* order, int32_t* torsions, int32_t* fragment,
-                           uint32_t* pairs, uint8_t* pair_hb) {
+                           uint32_t* pairs, uint8_t* pair_hb, uint32_t* batches) {
     if (!l) return fail(DOCK_EINVAL, "dock_ligand_export: NULL ligand");
     const auto& P = l->prep;
     if (order) std::copy(P.order.begin(), P.order.end(), order);
@@ -226,6 +231,11 @@ int32_t dock_ligand_export(const dock_ligand* l, int32_t* order, int32_t* torsio
         dockprep::decode_pairs(P, pv, hv);
         if (pairs) std::copy(pv.begin(), pv.end(), pairs);
         if (pair_hb) std::copy(hv.begin(), hv.end(), pair_hb);
+    }
+    if (batches) {
+        const dockblob::Header* h = reinterpret_cast<const dockblob::Header*>(P.blob.data());
+        const uint32_t* pl = reinterpret_cast<const uint32_t*>(P.blob.data() + h->off_plist);
+        std::copy(pl, pl + (size_t)h->n_batches * dockblob::kBatch, batches);
     }
     return ok();
 }

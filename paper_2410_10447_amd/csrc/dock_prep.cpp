@@ -149,26 +149,53 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
             plist.push_back({p, q, hb, table});
         }
     const int n_pairs = (int)plist.size();
-    // batches of kBatch pairs, each atom at most C times per batch (first fit);
-    // C grows for small ligands so that C * N can hold a full batch's 128 ends
+    // batches of kBatch pairs, each atom at most C times per batch. C grows for
+    // small ligands so that C * N can hold a full batch's 128 pair ends. The
+    // batch count starts at its lower bound, max(P / 64, max degree / C);
+    // pairs are placed most-constrained first (largest endpoint degree), each
+    // into the open batch where its two atoms are used least (then the least
+    // filled batch, then the lowest index); if a pair finds no batch, the
+    // count grows by one and the placement restarts.
     using dockblob::kBatch;
     const int C = std::max(2, std::min(16, (2 * kBatch + N - 1) / N + 1));
     if (C * N > dockblob::kMaxSlots) {
         err = "internal: accumulator slots exceed the build limit"; return DOCK_EUNSUPPORTED;
     }
+    std::vector<int> degp(N, 0);
+    for (const PairRec& pr : plist) { ++degp[pr.p]; ++degp[pr.q]; }
+    std::vector<int> porder(plist.size());
+    for (size_t k = 0; k < porder.size(); ++k) porder[k] = (int)k;
+    std::stable_sort(porder.begin(), porder.end(), [&](int a, int b) {
+        return std::max(degp[plist[a].p], degp[plist[a].q]) > std::max(degp[plist[b].p], degp[plist[b].q]);
+    });
+    int maxdeg = 0;
+    for (int v = 0; v < N; ++v) maxdeg = std::max(maxdeg, degp[v]);
+    int nb = std::max((n_pairs + kBatch - 1) / kBatch, (maxdeg + C - 1) / C);
     std::vector<std::vector<uint32_t>> batch;      // records
-    std::vector<std::vector<uint8_t>> used;        // per batch, per atom position
-    for (const PairRec& pr : plist) {
-        size_t b = 0;
-        for (; b < batch.size(); ++b)
-            if ((int)batch[b].size() < kBatch && used[b][pr.p] < C && used[b][pr.q] < C) break;
-        if (b == batch.size()) {
-            batch.emplace_back();
-            used.emplace_back(N, 0);
+    while (true) {
+        batch.assign(nb, {});
+        std::vector<int> cnt(nb, 0);
+        std::vector<uint8_t> use(size_t(nb) * N, 0);
+        bool placed_all = true;
+        for (int k : porder) {
+            const PairRec& pr = plist[k];
+            int best = -1, best_score = 0;
+            for (int b = 0; b < nb; ++b) {
+                const int up = use[size_t(b) * N + pr.p], uq = use[size_t(b) * N + pr.q];
+                if (cnt[b] >= kBatch || up >= C || uq >= C) continue;
+                const int score = -(up + uq) * 1000 - cnt[b];
+                if (best < 0 || score > best_score) { best = b; best_score = score; }
+            }
+            if (best < 0) { placed_all = false; break; }
+            const int ci = use[size_t(best) * N + pr.p]++;
+            const int cj = use[size_t(best) * N + pr.q]++;
+            ++cnt[best];
+            batch[best].push_back(dockblob::make_record(pr.p, pr.q, ci, cj, pr.hb, pr.table));
         }
-        const int ci = used[b][pr.p]++, cj = used[b][pr.q]++;
-        batch[b].push_back(dockblob::make_record(pr.p, pr.q, ci, cj, pr.hb, pr.table));
+        if (placed_all) break;
+        ++nb;
     }
+    if (n_pairs == 0) batch.clear();
     const int n_batches = (int)batch.size();
 
     // ---- pack the blob ----

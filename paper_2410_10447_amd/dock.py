@@ -73,7 +73,7 @@ class LigandDesc(C.Structure):
 class LigandInfo(C.Structure):
     _fields_ = [("n_atoms", C.c_int32), ("n_torsions", C.c_int32), ("n_genes", C.c_int32),
                 ("n_pairs", C.c_int32), ("n_fragments", C.c_int32), ("max_depth", C.c_int32),
-                ("blob_bytes", C.c_int64)]
+                ("n_batches", C.c_int32), ("n_copies", C.c_int32), ("blob_bytes", C.c_int64)]
 
 
 class ExecOpts(C.Structure):
@@ -114,7 +114,7 @@ def lib():
         "dock_destroy_grids": ([vp], i32),
         "dock_create_ligand": ([C.POINTER(LigandDesc), C.POINTER(vp)], i32),
         "dock_ligand_info_get": ([vp, C.POINTER(LigandInfo)], i32),
-        "dock_ligand_export": ([vp, vp, vp, vp, vp, vp], i32),
+        "dock_ligand_export": ([vp, vp, vp, vp, vp, vp, vp], i32),
         "dock_ligand_upload": ([vp, vp, vp], i32),
         "dock_destroy_ligand": ([vp], i32),
         "dock_score_batch": ([vp, vp, i32, vp, vp, vp, C.POINTER(ExecOpts), vp], i32),
@@ -238,6 +238,8 @@ class Ligand:
         self.n_pairs = info.n_pairs
         self.n_fragments = info.n_fragments
         self.max_depth = info.max_depth
+        self.n_batches = info.n_batches
+        self.n_copies = info.n_copies
         self.blob_bytes = info.blob_bytes
         self.blob = None
         if upload:
@@ -256,14 +258,16 @@ class Ligand:
         frag = np.zeros(N, np.int32)
         pairs = np.zeros(max(P, 1), np.uint32)
         hb = np.zeros(max(P, 1), np.uint8)
+        batches = np.zeros((max(self.n_batches, 1), 64), np.uint32)
         _check(lib().dock_ligand_export(self.handle, order.ctypes.data_as(C.c_void_p),
                                         tors.ctypes.data_as(C.c_void_p),
                                         frag.ctypes.data_as(C.c_void_p),
                                         pairs.ctypes.data_as(C.c_void_p),
-                                        hb.ctypes.data_as(C.c_void_p)))
+                                        hb.ctypes.data_as(C.c_void_p),
+                                        batches.ctypes.data_as(C.c_void_p)))
         pr = np.stack([pairs[:P] >> 16, pairs[:P] & 0xFFFF], axis=1).astype(np.int64)
         return {"order": order, "torsions": tors[:T], "fragment": frag, "pairs": pr,
-                "pair_hb": hb[:P].astype(bool)}
+                "pair_hb": hb[:P].astype(bool), "batches": batches[:self.n_batches]}
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -48,9 +48,10 @@ def _check_prep(lig):
         part_c.setdefault(int(ex["fragment"][i]), set()).add(i)
         part_o.setdefault(int(p.frag[i]), set()).add(i)
     assert sorted(map(sorted, part_c.values())) == sorted(map(sorted, part_o.values()))
-    # pair list and hydrogen-bond flags, decoded from the kernel's masks
+    # pair list and hydrogen-bond flags, decoded from the kernel's batches
     assert np.array_equal(ex["pairs"], p.pairs)
     assert np.array_equal(ex["pair_hb"], p.pair_hb)
+    _check_batches(ex["batches"], h.n_copies, N, p, order)
     # the depth-first order is the one defined by the header: children in
     # increasing index (independent recursive construction)
     adj = {i: [] for i in range(N)}
@@ -65,6 +66,35 @@ def _check_prep(lig):
                 visit(v, u)
     visit(0, -1)
     assert order.tolist() == want
+
+
+def _check_batches(b, C, N, p, order):
+    """Batch records: valid pairs are the pair list; within a batch every
+    (copy, atom) slot is used at most once; the slots fit the accumulator."""
+    assert C * N <= 384 and 2 <= C <= 16
+    got = []
+    for row in b:
+        slots = []
+        for r in row.tolist():
+            if not (r >> 31) & 1:
+                assert r == 0
+                continue
+            i, j = r & 127, (r >> 7) & 127
+            ci, cj = (r >> 14) & 15, (r >> 18) & 15
+            assert i < N and j < N and ci < C and cj < C
+            slots += [(ci, i), (cj, j)]
+            a, bb = int(order[i]), int(order[j])
+            got.append((min(a, bb), max(a, bb), (r >> 22) & 1))
+        assert len(slots) == len(set(slots)) and len(slots) <= 128
+    got.sort()
+    want = sorted((int(a), int(bb), int(hb)) for (a, bb), hb in zip(p.pairs, p.pair_hb))
+    assert got == want
+    # the batch count stays at the lower bound max(P/64, max degree / C)
+    P = len(p.pairs)
+    if P:
+        deg = np.bincount(p.pairs.ravel(), minlength=N)
+        lb = max(-(-P // 64), -(-int(deg.max()) // C))
+        assert len(b) <= lb + 1, (len(b), lb)
 
 
 @pytest.mark.parametrize("wl", ["score", "ls"])

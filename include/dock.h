@@ -219,6 +219,8 @@ typedef struct {
     float* best_energy;          /* device [n] in/out (start +inf) */
     float* energy;               /* device [n] out: E at the last evaluated point */
     int32_t* iters_done;         /* device [n] in/out: iterations taken so far */
+    float* grad;                 /* device [n][G] out, or NULL: dE/dgenotype at the last
+                                    evaluated point */
 } dock_ls_item;
 
 #define DOCK_LS_FINAL_EVAL 1u    /* evaluate the point reached after the last step */

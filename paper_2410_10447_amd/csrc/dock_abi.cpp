@@ -336,6 +336,8 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
         d.best_energy = it.best_energy;
         d.energy = it.energy;
         d.iters_done = it.iters_done;
+        d.grad = it.grad;
+        if (it.grad && !aligned(it.grad, 4)) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": misaligned grad");
         d.n = it.n;
         d.variant = var;
         d.slots = it.ligand->slots;

@@ -739,10 +739,12 @@ __device__ void local_search_one(const DevItem& it, int ind, Smem& sm, const Lig
     float bx = act ? it.best_genotype[o] : 0.f;
     float bestE = it.best_energy[ind];
     float lastE = it.energy[ind];
+    float lastG = 0.f;
     for (int iter = 0; iter < iterations; ++iter) {
         float gr;
         const float E = evaluate<SLOTS, VAR>(it.grid, sm, L, x, gr, nullptr);
         lastE = E;
+        lastG = gr;
         if (E < bestE) { bestE = E; bx = x; }
         gr = act ? gr : 0.f;
         ag = rho * ag + (1.f - rho) * gr * gr;
@@ -759,8 +761,10 @@ __device__ void local_search_one(const DevItem& it, int ind, Smem& sm, const Lig
         float gr;
         const float E = evaluate<SLOTS, VAR>(it.grid, sm, L, x, gr, nullptr);
         lastE = E;
+        lastG = gr;
         if (E < bestE) { bestE = E; bx = x; }
     }
+    if (act && it.grad && (iterations > 0 || final_eval)) it.grad[o] = lastG;
     if (act) {
         it.genotype[o] = x;
         it.acc_g2[o] = ag;

@@ -27,13 +27,13 @@ struct DevItem {
     float* best_energy;
     float* energy;
     int32_t* iters_done;
+    float* grad;            // optional: gradient at the last evaluated point
     int32_t n;
     int32_t variant;
     int32_t slots;          // 1 if n_atoms <= 64, else 2
     int32_t unit_begin;     // first work unit (individual) of this item
     int32_t iterations;     // steps for this item
     int32_t final_eval;     // evaluate the point reached after the last step
-    int32_t pad[2];
 };
 
 struct LsParams {

@@ -86,7 +86,7 @@ class LsItem(C.Structure):
                 ("variant", C.c_int32), ("iterations", C.c_int32), ("final_eval", C.c_int32),
                 ("genotype", C.c_void_p), ("acc_g2", C.c_void_p), ("acc_dx2", C.c_void_p),
                 ("best_genotype", C.c_void_p), ("best_energy", C.c_void_p),
-                ("energy", C.c_void_p), ("iters_done", C.c_void_p)]
+                ("energy", C.c_void_p), ("iters_done", C.c_void_p), ("grad", C.c_void_p)]
 
 
 class LsOpts(C.Structure):
@@ -349,6 +349,7 @@ class LsJob:
     variant: int = -1
     iterations: int = -1
     final_eval: int = -1
+    grad: object = None          # optional [n, G] CUDA tensor: gradient at the last evaluated point
 
 
 def _as_job(job):
@@ -377,6 +378,7 @@ def make_items(jobs):
         it.best_energy = st.best_energy.data_ptr()
         it.energy = st.energy.data_ptr()
         it.iters_done = st.iters_done.data_ptr()
+        it.grad = j.grad.data_ptr() if j.grad is not None else None
     return arr
 
 

@@ -190,33 +190,48 @@ def _ls_setup(dk, w, n):
 
 @pytest.mark.parametrize("variant", FP32_VARIANTS)
 def test_ls_step_map(dk, variant):
-    """Each GPU step equals the oracle's ADADELTA step from the GPU's state."""
+    """Each GPU step is the ADADELTA update (Zeiler Alg. 1) of the GPU's own
+    state and gradient, and that gradient and energy match the oracle's at the
+    same point. (Comparing with a step taken on the oracle's gradient would mix
+    the two: ADADELTA passes small gradient components through almost
+    unscaled, so their absolute FP32 error, ~1e-4 of |g|, would dominate.)"""
     w = synth.ls_workload(64)
     prep = R.prepare(w.ligands[0], w.ff)
     G, L, st = _ls_setup(dk, w, 64)
+    grad = torch.zeros_like(st.genotype)
     ws = None
-    worst = 0.0
+    worst_step = worst_g = 0.0
+    n_cond = 0
     for it in range(12):
         s0 = st.to_numpy()
-        ws = dk.local_search([(G, L, st)], 1, variant=variant, final_eval=False, workspace=ws)
+        ws = dk.local_search([dk.LsJob(G, L, st, variant, grad=grad)], 1, variant=variant,
+                             final_eval=False, workspace=ws)
         torch.cuda.synchronize()
         s1 = st.to_numpy()
+        g_gpu = grad.cpu().numpy().astype(np.float64)
         x = s0["genotype"].astype(np.float64)
         ref = R.score(prep, w.grids, x)
         flag = near_discontinuity(prep, w.grids, ref.x)
-        xn, ag, ad = R.adadelta_step(x, ref.grad, s0["acc_g2"].astype(np.float64),
-                                     s0["acc_dx2"].astype(np.float64), 0.8, 1e-2)
         ok, cond = e_ok(s1["energy"], ref, x)
-        n_cond = cond[~flag].sum()
+        n_cond += cond[~flag].sum()
         assert np.all(ok[~flag]), (it, e_relerr(s1["energy"], ref.energy)[~ok].max())
-        dxg = s1["genotype"] - x
-        dxo = xn - x
-        err = np.linalg.norm(dxg - dxo, axis=1) / np.maximum(np.linalg.norm(dxo, axis=1), 1e-3)
-        worst = max(worst, err[~flag].max())
-        assert np.all(err[~flag] <= 1e-4), (it, err[~flag].max())
+        ge = g_relerr(g_gpu, ref.grad)
+        worst_g = max(worst_g, ge[~flag].max())
+        assert np.all(ge[~flag] <= G_TOL), (it, ge[~flag].max())
+        xn, ag, ad = R.adadelta_step(x, g_gpu, s0["acc_g2"].astype(np.float64),
+                                     s0["acc_dx2"].astype(np.float64), 0.8, 1e-2)
+        # accumulators are sums of non-negative terms (relative error is
+        # meaningful); a gene is x + dx, judged against max(|x|, |dx|)
+        gscale = np.maximum(np.maximum(np.abs(xn), np.abs(x)), np.maximum(np.abs(xn - x), 1e-3))
+        for name, got, want, scale in (("genotype", s1["genotype"], xn, gscale),
+                                       ("acc_g2", s1["acc_g2"], ag, np.abs(ag)),
+                                       ("acc_dx2", s1["acc_dx2"], ad, np.abs(ad))):
+            err = np.abs(got - want) / np.maximum(scale, 1e-30)
+            worst_step = max(worst_step, err.max())
+            assert np.all(err <= 1e-5), (it, name, err.max())
         assert np.all(s1["iters_done"] == it + 1)
-    print(f"\n[ls step-map v{variant}] worst step rel err {worst:.2e}; "
-          f"ill-conditioned energies at the last step {n_cond}", flush=True)
+    print(f"\n[ls step-map v{variant}] worst update rel err {worst_step:.2e}, worst gradient err "
+          f"{worst_g:.2e}; energies held to a conditioning bound {n_cond}", flush=True)
 
 
 def test_ls_chunked_equals_single_and_deterministic(dk):
@@ -288,8 +303,8 @@ def test_ls_uneven_batch_alone_equals_mixed(dk):
         prep = R.prepare(w.ligands[k], w.ff)
         ref = R.score(prep, w.grids, mn["best_genotype"].astype(np.float64))
         flag = near_discontinuity(prep, w.grids, ref.x)
-        ee = e_relerr(mn["best_energy"], ref.energy)
-        assert np.all(ee[~flag] <= E_TOL), (k, ee.max())
+        ok, cond = e_ok(mn["best_energy"], ref, mn["best_genotype"])
+        assert np.all(ok[~flag]), (k, e_relerr(mn["best_energy"], ref.energy).max())
 
 
 def test_ls_mixed_variants_in_one_launch(dk):

@@ -358,40 +358,69 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
     if (!ws) return fail(DOCK_EINVAL, "dock_local_search_batch: NULL workspace");
     if (ws_bytes < need) return fail(DOCK_EINVAL, "dock_local_search_batch: workspace too small");
     if (!aligned(ws, 16)) return fail(DOCK_EINVAL, "workspace must be 16-byte aligned");
-    // longest items first (stable)
+    // longest items first (stable); when the batch is split by atom-slot
+    // layout (see below), one-slot items come first, each group longest first
+    const bool split_layouts = any1 && any2 && var_u < 0;
     std::vector<int> idx(dev.size());
     for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+        if (split_layouts && dev[a].slots != dev[b].slots) return dev[a].slots < dev[b].slots;
+        return cost[a] > cost[b];
+    });
     std::vector<uint8_t> table(docklaunch::kWorkspaceHeader + dev.size() * sizeof(docklaunch::DevItem), 0);
     docklaunch::DevItem* tab = reinterpret_cast<docklaunch::DevItem*>(table.data() + docklaunch::kWorkspaceHeader);
+    const size_t tab_count = dev.size();
     int32_t ub = 0;
     for (size_t i = 0; i < idx.size(); ++i) {
         tab[i] = dev[idx[i]];
+        if (split_layouts && i > 0 && tab[i].slots != tab[i - 1].slots) ub = 0;
         tab[i].unit_begin = ub;
         ub += tab[i].n;
     }
-    // counter (first int32 of the header) starts at 0: it is part of the copy
+    const int var_uniform = var_u >= 0 ? var_u : -1;
+    // A launch that mixes both atom-slot layouts AND reduction variants would
+    // carry every combination in one kernel and spill registers; such a batch
+    // runs as two persistent launches, one per layout (items of one layout
+    // first in the table, each launch with its own work counter).
+    struct Part { int first, count, mode; };
+    std::vector<Part> parts;
+    const int n_dev = (int)tab_count;
+    if (any1 && any2 && var_uniform < 0) {
+        int n1 = 0;
+        for (int i = 0; i < n_dev; ++i) n1 += tab[i].slots == 1;
+        parts.push_back({0, n1, docklaunch::kSlots1});
+        parts.push_back({n1, n_dev - n1, docklaunch::kSlots2});
+    } else {
+        parts.push_back({0, n_dev, (any1 && any2) ? docklaunch::kSlotsAny
+                                                  : (any2 ? docklaunch::kSlots2 : docklaunch::kSlots1)});
+    }
+    // counters (one 32-bit word per part in the header) start at 0: they are
+    // part of the copy
     int32_t st = staging().copy_to_device(ws, table.data(), table.size(), (hipStream_t)stream);
     if (st != DOCK_OK) return st;
     int32_t n_cu = 0;
     st = device_cu_count(n_cu);
     if (st != DOCK_OK) return st;
-    const int mode = (any1 && any2) ? docklaunch::kSlotsAny : (any2 ? docklaunch::kSlots2 : docklaunch::kSlots1);
-    const int var_uniform = var_u >= 0 ? var_u : -1;
-    int per_cu = docklaunch::ls_blocks_per_cu(mode, var_uniform);
-    if (per_cu <= 0) per_cu = 8;
-    const int64_t resident = (int64_t)per_cu * n_cu;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(total, resident));
-    docklaunch::LsParams p;
-    p.items = reinterpret_cast<const docklaunch::DevItem*>(static_cast<uint8_t*>(ws) +
-                                                           docklaunch::kWorkspaceHeader);
-    p.counter = static_cast<int32_t*>(ws);
-    p.n_items = (int32_t)dev.size();
-    p.total_units = (int32_t)total;
-    p.rho = o->rho;
-    p.eps = o->eps;
-    hipError_t e = docklaunch::launch_ls(p, mode, var_uniform, grid, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "dock_local_search_batch launch");
+    for (size_t k = 0; k < parts.size(); ++k) {
+        const Part& pt = parts[k];
+        if (pt.count == 0) continue;
+        int64_t units = 0;
+        for (int i = pt.first; i < pt.first + pt.count; ++i) units += tab[i].n;
+        int per_cu = docklaunch::ls_blocks_per_cu(pt.mode, var_uniform);
+        if (per_cu <= 0) per_cu = 8;
+        const int64_t resident = (int64_t)per_cu * n_cu;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(units, resident));
+        docklaunch::LsParams p;
+        p.items = reinterpret_cast<const docklaunch::DevItem*>(static_cast<uint8_t*>(ws) +
+                                                               docklaunch::kWorkspaceHeader) + pt.first;
+        p.counter = static_cast<int32_t*>(ws) + k;
+        p.n_items = pt.count;
+        p.total_units = (int32_t)units;
+        p.rho = o->rho;
+        p.eps = o->eps;
+        hipError_t e = docklaunch::launch_ls(p, pt.mode, var_uniform, grid, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "dock_local_search_batch launch");
+    }
     return ok();
 }
 

@@ -279,7 +279,9 @@ struct Lig {
 };
 
 template <int SLOTS>
-__device__ void load_ligand(const uint8_t* __restrict__ blob, Smem& sm, Lig<SLOTS>& L) {
+__device__ void load_ligand(const uint8_t* __restrict__ blob, Smem& sm, Lig<SLOTS>& L,
+                            bool fill_lds = true) {
+    if (fill_lds) __syncthreads();  // previous users of the LDS tables are done
     const Header* h = reinterpret_cast<const Header*>(blob);
     const int lane = lane_id();
     L.N = uniform(h->n_atoms);
@@ -289,7 +291,7 @@ __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem& sm, Lig<SLOT
     L.n_batches = uniform(h->n_batches);
     L.n_copies = uniform(h->n_copies);
     L.plist = uniform_ptr(reinterpret_cast<const uint32_t*>(blob + h->off_plist));
-    if (lane < 4) sm.hbt[lane] = make_float2(h->hb_r0[lane], h->hb_eps[lane]);
+    if (lane < 4 && fill_lds) sm.hbt[lane] = make_float2(h->hb_r0[lane], h->hb_eps[lane]);
     const float4* ref = reinterpret_cast<const float4*>(blob + h->off_ref);
     const float4* par = reinterpret_cast<const float4*>(blob + h->off_par);
     const float4* chg = reinterpret_cast<const float4*>(blob + h->off_chg);
@@ -306,7 +308,7 @@ __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem& sm, Lig<SLOT
         L.cls[s] = ii.x;
         L.frag[s] = ii.y;
         L.orig[s] = ii.z;
-        if (ok) sm.par[a] = p;
+        if (ok && fill_lds) sm.par[a] = p;
     }
     const Torsion* tr = reinterpret_cast<const Torsion*>(blob + h->off_tors);
     const int k = lane < L.T ? lane : 0;
@@ -323,7 +325,8 @@ __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem& sm, Lig<SLOT
     const int8_t* ch = reinterpret_cast<const int8_t*>(blob + h->off_chain);
     const int n_chain_bytes = L.NF * kChain;
     int8_t* dst = &sm.chain[0][0];
-    for (int i = lane; i < n_chain_bytes; i += kWave) dst[i] = ch[i];
+    if (fill_lds)
+        for (int i = lane; i < n_chain_bytes; i += kWave) dst[i] = ch[i];
     __syncthreads();
 }
 
@@ -435,6 +438,59 @@ __device__ __forceinline__ void pair_term(float dx, float dy, float dz, float r0
     const float dds = -eds * r2 * kDsInvS2;                                     // r dE/dr
     e = mask_f(elj + eel + eds, live);
     w = mask_f((dlj + del + dds) * ir2, slope);
+}
+
+// ---------------------------------------------------------------------------
+// One listed pair (a packed record, see the blob layout) evaluated from the
+// atom data in LDS; the force is applied by apply_force.
+// ---------------------------------------------------------------------------
+struct PairForce {
+    float fx, fy, fz, e;
+    int si, sj;
+    bool valid;
+};
+
+__device__ __forceinline__ PairForce pair_force(const Smem& sm, uint32_t rec, int N) {
+    PairForce o;
+    o.valid = (rec & dockblob::kRecValid) != 0u;
+    const int i = rec & 127, j = (rec >> 7) & 127;
+    const int ci = (rec >> 14) & 15, cj = (rec >> 18) & 15;
+    const bool hb = (rec >> 22) & 1u;
+    const int tb = (rec >> 23) & 3;
+    const float4 pi = sm.dyn[i], pj = sm.dyn[j];
+    const float4 qi = sm.par[i], qj = sm.par[j];
+    const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+    const float2 ht = sm.hbt[tb];
+    const float r0 = hb ? ht.x : qi.x + qj.x;
+    const float ep = hb ? ht.y : qi.y * qj.y;
+    const float c12 = hb ? 5.f * ep : ep;
+    const float c10 = hb ? -6.f * ep : 0.f;
+    const float c6 = hb ? 0.f : -2.f * ep;
+    const float qq = kElec * pi.w * pj.w;
+    const float ds = qi.z * qj.w + qj.z * qi.w;
+    float e, w;
+    pair_term(dx, dy, dz, r0, c12, c10, c6, qq, ds, o.valid, e, w);
+    o.e = e;
+    o.fx = w * dx;
+    o.fy = w * dy;
+    o.fz = w * dz;
+    o.si = ci * N + i;
+    o.sj = cj * N + j;
+    return o;
+}
+
+// Read-modify-write of the pair's two accumulator slots. The slots of one
+// batch are distinct, so plain LDS loads and stores suffice (no atomics), and
+// batches follow each other in program order.
+__device__ __forceinline__ void apply_force(Smem& sm, const PairForce& f) {
+    if (f.valid) {
+        float4 ai = sm.u.acc[f.si];
+        float4 aj = sm.u.acc[f.sj];
+        ai.x -= f.fx; ai.y -= f.fy; ai.z -= f.fz;
+        aj.x += f.fx; aj.y += f.fy; aj.z += f.fz;
+        sm.u.acc[f.si] = ai;
+        sm.u.acc[f.sj] = aj;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -558,42 +614,27 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
         for (int k = lane; k < nslot; k += kWave) sm.u.acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
         const auto plist = gmem(L.plist);
-        uint32_t rec_next = L.n_batches > 0 ? plist[lane] : 0u;
-        for (int bt = 0; bt < L.n_batches; ++bt) {
-            const uint32_t rec = rec_next;
-            if (bt + 1 < L.n_batches) rec_next = plist[(bt + 1) * kWave + lane];
-            const bool valid = (rec & dockblob::kRecValid) != 0u;
-            const int i = rec & 127, j = (rec >> 7) & 127;
-            const int ci = (rec >> 14) & 15, cj = (rec >> 18) & 15;
-            const bool hb = (rec >> 22) & 1u;
-            const int tb = (rec >> 23) & 3;
-            const float4 pi = sm.dyn[i], pj = sm.dyn[j];
-            const float4 qi = sm.par[i], qj = sm.par[j];
-            const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-            const float2 ht = sm.hbt[tb];
-            const float r0 = hb ? ht.x : qi.x + qj.x;
-            const float ep = hb ? ht.y : qi.y * qj.y;
-            const float c12 = hb ? 5.f * ep : ep;
-            const float c10 = hb ? -6.f * ep : 0.f;
-            const float c6 = hb ? 0.f : -2.f * ep;
-            const float qq = kElec * pi.w * pj.w;
-            const float ds = qi.z * qj.w + qj.z * qi.w;
-            float e, w;
-            pair_term(dx, dy, dz, r0, c12, c10, c6, qq, ds, valid, e, w);
-            e_lane += e;
-            const float fx = w * dx, fy = w * dy, fz = w * dz;
-            // read-modify-write of two slots per lane: the slots of one
-            // batch are distinct, so plain LDS loads and stores suffice (no
-            // atomics), and batches follow each other in program order
-            if (valid) {
-                const int si = ci * N + i, sj = cj * N + j;
-                float4 ai = sm.u.acc[si];
-                float4 aj = sm.u.acc[sj];
-                ai.x -= fx; ai.y -= fy; ai.z -= fz;
-                aj.x += fx; aj.y += fy; aj.z += fz;
-                sm.u.acc[si] = ai;
-                sm.u.acc[sj] = aj;
-            }
+        const int nb = L.n_batches;
+        // two batches per trip: their pair terms are independent and
+        // interleave; their slot updates stay in batch order
+        uint32_t ra = nb > 0 ? plist[lane] : 0u;
+        uint32_t rb = nb > 1 ? plist[kWave + lane] : 0u;
+        int bt = 0;
+        for (; bt + 1 < nb; bt += 2) {
+            const uint32_t r0 = ra, r1 = rb;
+            if (bt + 2 < nb) ra = plist[(bt + 2) * kWave + lane];
+            if (bt + 3 < nb) rb = plist[(bt + 3) * kWave + lane];
+            PairForce fa = pair_force(sm, r0, N);
+            PairForce fb = pair_force(sm, r1, N);
+            e_lane += fa.e;
+            e_lane += fb.e;
+            apply_force(sm, fa);
+            apply_force(sm, fb);
+        }
+        if (bt < nb) {
+            PairForce fa = pair_force(sm, ra, N);
+            e_lane += fa.e;
+            apply_force(sm, fa);
         }
         __syncthreads();
         // each atom adds its copies in copy order
@@ -828,8 +869,6 @@ __global__ __launch_bounds__(64, (MODE == docklaunch::kSlots1 ? 3 : 2)) void ls_
     __shared__ Smem sm;
     const int lane = lane_id();
     int cur_item = -1;
-    Lig<(MODE == docklaunch::kSlots1) ? 1 : 2> L2;
-    Lig<1> L1;
     while (true) {
         int u = 0;
         if (lane == 0) u = atomicAdd(p.counter, 1);
@@ -842,20 +881,20 @@ __global__ __launch_bounds__(64, (MODE == docklaunch::kSlots1 ? 3 : 2)) void ls_
         }
         const DevItem it = load_item(p.items, lo);
         const int ind = u - it.unit_begin;
-        if constexpr (MODE == docklaunch::kSlots1) {
-            if (lo != cur_item) { __syncthreads(); load_ligand<1>(it.blob, sm, L2); cur_item = lo; }
-            ls_run<1, VAR>(it, ind, sm, L2, p);
-        } else if constexpr (MODE == docklaunch::kSlots2) {
-            if (lo != cur_item) { __syncthreads(); load_ligand<2>(it.blob, sm, L2); cur_item = lo; }
-            ls_run<2, VAR>(it, ind, sm, L2, p);
+        // the ligand's LDS tables are refilled only when the item changes;
+        // its per-lane registers are rebuilt for every individual, so that no
+        // ligand state stays live across units (the two atom-slot layouts of
+        // a mixed launch would otherwise both hold registers)
+        const bool reload = lo != cur_item;
+        cur_item = lo;
+        if (MODE == docklaunch::kSlots1 || (MODE == docklaunch::kSlotsAny && it.slots == 1)) {
+            Lig<1> L;
+            load_ligand<1>(it.blob, sm, L, reload);
+            ls_run<1, VAR>(it, ind, sm, L, p);
         } else {
-            if (it.slots == 1) {
-                if (lo != cur_item) { __syncthreads(); load_ligand<1>(it.blob, sm, L1); cur_item = lo; }
-                ls_run<1, VAR>(it, ind, sm, L1, p);
-            } else {
-                if (lo != cur_item) { __syncthreads(); load_ligand<2>(it.blob, sm, L2); cur_item = lo; }
-                ls_run<2, VAR>(it, ind, sm, L2, p);
-            }
+            Lig<2> L;
+            load_ligand<2>(it.blob, sm, L, reload);
+            ls_run<2, VAR>(it, ind, sm, L, p);
         }
     }
 }

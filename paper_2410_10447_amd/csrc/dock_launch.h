@@ -44,7 +44,7 @@ struct LsParams {
     float rho, eps;
 };
 
-// Workspace layout: [int32 counter, padded to 64 B][DevItem x n_items]
+// Workspace layout: [int32 work counters (one per launch of a call), 64 B][DevItem x n_items]
 constexpr int64_t kWorkspaceHeader = 64;
 
 // ls kernel families: slots 1, slots 2, or both (runtime per item)

@@ -307,6 +307,28 @@ def test_ls_uneven_batch_alone_equals_mixed(dk):
         assert np.all(ok[~flag]), (k, e_relerr(mn["best_energy"], ref.energy).max())
 
 
+def test_ls_uneven_mixed_variants_alone_equals_mixed(dk):
+    """Ligands on both sides of 64 atoms with alternating reduction variants
+    in one call give, bit for bit, what each item gives alone."""
+    ligs = [synth.ligand(n, t, 70 + n) for n, t in ((20, 4), (90, 12), (48, 8), (128, 20), (64, 6), (65, 9))]
+    grd = synth.grids(64, 10, 71)
+    ff = synth.force_field()
+    G = dk.Grids.from_synth(grd)
+    Ls = [dk.Ligand(l, ff) for l in ligs]
+    gens = [torch.from_numpy(synth.genotypes(l, grd, 24, 72 + k)).cuda() for k, l in enumerate(ligs)]
+    mixed = [dk.LSState.start(g) for g in gens]
+    alone = [m.clone() for m in mixed]
+    var = [k % 2 if k < 4 else 2 + k % 3 for k in range(len(ligs))]
+    dk.local_search([dk.LsJob(G, L, s, v) for L, s, v in zip(Ls, mixed, var)], 15)
+    for L, s, v in zip(Ls, alone, var):
+        dk.local_search([dk.LsJob(G, L, s, v)], 15)
+    torch.cuda.synchronize()
+    for k, (a, m) in enumerate(zip(alone, mixed)):
+        an, mn = a.to_numpy(), m.to_numpy()
+        for f in an:
+            assert np.array_equal(an[f], mn[f]), (k, f)
+
+
 def test_ls_mixed_variants_in_one_launch(dk):
     w = synth.ls_workload(64)
     G, L, st0 = _ls_setup(dk, w, 64)

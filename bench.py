@@ -47,6 +47,35 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X FP32 vector peak (packed FMA)
 FLOPS_PAIR, FLOPS_ATOM, FLOPS_TORSION, FLOPS_GENE = 66, 141, 125, 12
 
 
+# HBM traffic of one benchmark launch, from rocprofv3 --pmc FETCH_SIZE and
+# --pmc WRITE_SIZE runs (KiB per dispatch), each scaled by what the same
+# counter reads for a plain device copy of 256 MiB (FETCH_SIZE reads 128 MiB
+# for it, WRITE_SIZE 256 MiB: scales 2.0 and 1.0). Valid only for the kernel
+# sources whose SHA-256 is recorded; after any change the field is null until
+# the counters are taken again.
+TRAFFIC = {"kernel_sha256": "423b5831be9384da554d8a3b59b827f94349afd5d7271dbedce55d66186d315a",
+           "fetch_kib": 1887637.2, "write_kib": 1656.2,
+           "fetch_scale": 2.0, "write_scale": 1.0}
+KERNEL_SOURCES = ("paper_2410_10447_amd/csrc/dock_kernels.hip", "paper_2410_10447_amd/csrc/dock_blob.h",
+                  "paper_2410_10447_amd/csrc/dock_prep.cpp")
+
+
+def kernel_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_bytes():
+    t = TRAFFIC
+    if t["kernel_sha256"] is None or t["kernel_sha256"] != kernel_sha256():
+        return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
+
 def flops_per_eval(n_pairs, n_atoms, n_torsions):
     return (FLOPS_PAIR * n_pairs + FLOPS_ATOM * n_atoms + FLOPS_TORSION * n_torsions
             + FLOPS_GENE * (7 + n_torsions))
@@ -226,8 +255,8 @@ def main():
                      for v, rv in results.items()},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": None,
-                     "flops_per_eval": fpe},
+                     "traffic": traffic_bytes(),
+                     "flops_per_eval": fpe, "kernel_sha256": kernel_sha256()[:16]},
     }
     if args.uneven_steps > 0:
         out["uneven"] = uneven_run(args.uneven_steps, 1)

@@ -239,6 +239,11 @@ int32_t dock_ls_workspace_bytes(int32_t n_items, int64_t* bytes);
 
 /* Runs opts->iterations steps (or the item's own count) on every individual
  * of every item in one persistent launch; items are scheduled longest first.
+ * A batch that mixes ligands of <= 64 and > 64 atoms AND reduction variants
+ * runs as two persistent launches, one per atom-slot layout, side by side:
+ * the second on a stream the library owns (one per device), forked from and
+ * joined back into `stream` with events, so work queued on `stream` after
+ * the call still waits for both.
  * Items may be at different stages: a serving loop passes each job's
  * remaining steps and asks for the final evaluation only in its last call. A call of K
  * iterations without DOCK_LS_FINAL_EVAL followed by one with it gives the

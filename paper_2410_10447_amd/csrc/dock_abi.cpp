@@ -124,6 +124,37 @@ int device_cu_count(int32_t& out) {
     return DOCK_OK;
 }
 
+// A library-owned stream per device, used to run the second persistent
+// launch of a split batch beside the first: the two are forked from the
+// caller's stream with an event and joined back into it with another, so the
+// caller's later work still waits for both. The fork-launch-join sequence is
+// serialised, since the events are shared.
+struct SideStream {
+    hipStream_t stream = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+int side_stream(SideStream*& out, std::unique_lock<std::mutex>& lock) {
+    static std::mutex mu;
+    static std::map<int, SideStream>* table = new std::map<int, SideStream>();  // outlives late work
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    lock = std::unique_lock<std::mutex>(mu);
+    SideStream& s = (*table)[dev];
+    if (!s.stream) {
+        e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s.fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s.join, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            s = SideStream();
+            return hip_fail(e, "side stream creation");
+        }
+    }
+    out = &s;
+    return DOCK_OK;
+}
+
 int32_t check_grid_for_ligand(const dock_grids* g, const dock_ligand* l) {
     if (l->prep.max_class >= g->desc.n_maps - 2)
         return fail(DOCK_EINVAL, "ligand uses an atom class with no type map in the grid set");
@@ -346,8 +377,11 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
         if (iters == 0 && !fin) continue;  // nothing to do for this item
         dev.push_back(d);
         const auto& P = it.ligand->prep;
-        // per-individual cost: evaluations x (pair steps per slot, then atoms and torsion depth)
-        cost.push_back((int64_t)(iters + fin) * ((int64_t)(P.n_atoms / 2 + 4) * d.slots * 8 + P.max_depth));
+        const auto* H = reinterpret_cast<const dockblob::Header*>(P.blob.data());
+        // per-individual cost: evaluations x (instruction estimate per
+        // evaluation: pair batches, atom slots, torsion depth, fixed part)
+        cost.push_back((int64_t)(iters + fin) *
+                       ((int64_t)H->n_batches * 90 + (int64_t)d.slots * (150 + 20 * P.max_depth) + 500));
         any1 |= d.slots == 1;
         any2 |= d.slots == 2;
         var_u = (var_u == -2 || var_u == var) ? var : -1;
@@ -359,12 +393,12 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
     if (ws_bytes < need) return fail(DOCK_EINVAL, "dock_local_search_batch: workspace too small");
     if (!aligned(ws, 16)) return fail(DOCK_EINVAL, "workspace must be 16-byte aligned");
     // longest items first (stable); when the batch is split by atom-slot
-    // layout (see below), one-slot items come first, each group longest first
+    // layout (see below), two-slot items come first, each group longest first
     const bool split_layouts = any1 && any2 && var_u < 0;
     std::vector<int> idx(dev.size());
     for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-        if (split_layouts && dev[a].slots != dev[b].slots) return dev[a].slots < dev[b].slots;
+        if (split_layouts && dev[a].slots != dev[b].slots) return dev[a].slots > dev[b].slots;
         return cost[a] > cost[b];
     });
     std::vector<uint8_t> table(docklaunch::kWorkspaceHeader + dev.size() * sizeof(docklaunch::DevItem), 0);
@@ -380,16 +414,18 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
     const int var_uniform = var_u >= 0 ? var_u : -1;
     // A launch that mixes both atom-slot layouts AND reduction variants would
     // carry every combination in one kernel and spill registers; such a batch
-    // runs as two persistent launches, one per layout (items of one layout
-    // first in the table, each launch with its own work counter).
+    // runs as two persistent launches, one per layout (two-slot items first in
+    // the table, each launch with its own work counter), side by side: the
+    // one-slot launch runs on the library's side stream, so that its waves
+    // fill the chip as the longer two-slot launch drains.
     struct Part { int first, count, mode; };
     std::vector<Part> parts;
     const int n_dev = (int)tab_count;
-    if (any1 && any2 && var_uniform < 0) {
-        int n1 = 0;
-        for (int i = 0; i < n_dev; ++i) n1 += tab[i].slots == 1;
-        parts.push_back({0, n1, docklaunch::kSlots1});
-        parts.push_back({n1, n_dev - n1, docklaunch::kSlots2});
+    if (split_layouts) {
+        int n2 = 0;
+        for (int i = 0; i < n_dev; ++i) n2 += tab[i].slots == 2;
+        parts.push_back({0, n2, docklaunch::kSlots2});
+        parts.push_back({n2, n_dev - n2, docklaunch::kSlots1});
     } else {
         parts.push_back({0, n_dev, (any1 && any2) ? docklaunch::kSlotsAny
                                                   : (any2 ? docklaunch::kSlots2 : docklaunch::kSlots1)});
@@ -401,6 +437,16 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
     int32_t n_cu = 0;
     st = device_cu_count(n_cu);
     if (st != DOCK_OK) return st;
+    SideStream* side = nullptr;
+    std::unique_lock<std::mutex> side_lock;
+    if (parts.size() > 1) {
+        st = side_stream(side, side_lock);
+        if (st != DOCK_OK) return st;
+        hipError_t e = hipEventRecord(side->fork, (hipStream_t)stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(side->stream, side->fork, 0);
+        if (e != hipSuccess) return hip_fail(e, "dock_local_search_batch fork");
+    }
+    hipError_t launch_err = hipSuccess;
     for (size_t k = 0; k < parts.size(); ++k) {
         const Part& pt = parts[k];
         if (pt.count == 0) continue;
@@ -418,9 +464,16 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
         p.total_units = (int32_t)units;
         p.rho = o->rho;
         p.eps = o->eps;
-        hipError_t e = docklaunch::launch_ls(p, pt.mode, var_uniform, grid, (hipStream_t)stream);
-        if (e != hipSuccess) return hip_fail(e, "dock_local_search_batch launch");
+        hipStream_t s_k = k == 0 ? (hipStream_t)stream : side->stream;
+        launch_err = docklaunch::launch_ls(p, pt.mode, var_uniform, grid, s_k);
+        if (launch_err != hipSuccess) break;
     }
+    if (side) {  // joined also after a failed launch
+        hipError_t e = hipEventRecord(side->join, side->stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent((hipStream_t)stream, side->join, 0);
+        if (e != hipSuccess && launch_err == hipSuccess) return hip_fail(e, "dock_local_search_batch join");
+    }
+    if (launch_err != hipSuccess) return hip_fail(launch_err, "dock_local_search_batch launch");
     return ok();
 }
 

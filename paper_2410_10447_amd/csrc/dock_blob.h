@@ -27,6 +27,7 @@ constexpr int kMaxFrag = kMaxTorsions + 1;
 constexpr int kChainStride = kMaxTorsions + 1;  // [0] = length, [1..] torsion ids root first
 constexpr int kBatch = 64;
 constexpr int kMaxSlots = 384;                   // n_copies * n_atoms <= kMaxSlots
+constexpr int kMaxSlotsSmall = 256;              // the same bound for ligands of <= 64 atoms
 
 // pair record: i | j << 7 | ci << 14 | cj << 18 | hb << 22 | table << 23 | valid << 31
 constexpr uint32_t kRecValid = 1u << 31;

@@ -6,15 +6,14 @@
 //
 //   genotype (lane c holds gene c)
 //   -> torsion transforms (lane k: Rodrigues rotation about bond k)
-//   -> fragment transforms (lane f: product of the torsions enclosing f,
-//      then the rigid-body rotation and translation)
-//   -> atom positions (lane a: atom a in depth-first order; a second slot
-//      holds atom a + 64 for ligands of 65..128 atoms)
+//   -> atom positions (lane a: atom a in depth-first order, a second slot
+//      holds atom a + 64 for ligands of 65..128 atoms): the torsions that
+//      enclose the atom's fragment, innermost first, then the rigid rotation
 //   -> grid term: trilinear interpolation of three maps per atom
-//   -> pair terms: circulant schedule, step s pairs atom a with a + s, the
-//      partner's share of the force is handed over with a cross-lane permute
-//   -> block sums of {E, gx, gy, gz} and of the torque (Sec. 3/4.2; selectable
-//      shuffle or MFMA variants), torsion torques by a wave prefix scan
+//   -> pair terms: host-built batches of 64 kept pairs, one pair per lane,
+//      forces added to per-copy LDS accumulators of both atoms
+//   -> block sum of {E, gx, gy, gz} (Sec. 3/4.2; selectable shuffle or MFMA
+//      variants); torque and torsion torques by a wave prefix scan
 //   -> gradient with respect to the genotype, ADADELTA update.
 //
 // No barrier spans more than one wave, no LDS or global float atomics are
@@ -58,6 +57,7 @@ constexpr float kDsInv2S2 = 1.0f / (2.0f * 3.5f * 3.5f);   // 1 / (2 sigma^2)
 constexpr float kDsInvS2 = 1.0f / (3.5f * 3.5f);
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kElec = 332.06363f;          // kcal A / (mol e^2)
+constexpr float kSqrtElec = 18.222613f;      // sqrt(kElec): charges in LDS carry it
 
 // ---------------------------------------------------------------------------
 // Cross-lane primitives (wave64).
@@ -236,28 +236,25 @@ __device__ __forceinline__ float4 sum4(float4 v) {
     else return sum4_mfma_bf16<3>(v);
 }
 
-// The torque always stays FP32: shuffle for the shuffle and half-width
-// variants, FP32 MFMA for the FP32 MFMA variant.
-template <int VAR>
-__device__ __forceinline__ float4 sum4_fp32(float4 v) {
-    if constexpr (VAR == DOCK_REDUCE_MFMA_F32) return sum4_mfma_f32(v);
-    else return sum4_shuffle(v);
-}
-
 // ---------------------------------------------------------------------------
 // Ligand data held by a wave.
 // ---------------------------------------------------------------------------
 
+// LDS of one wave. Sized per atom-slot layout: a ligand of at most 64 atoms
+// has at most 128 + 2N <= 256 accumulator slots (n_copies <= 128/N + 2).
+template <int SLOTS>
 struct __align__(16) Smem {
-    float4 dyn[kMaxAtoms];          // x, y, z relative to t, and charge q (depth-first order)
-    float4 par[kMaxAtoms];          // R, sqrt(eps), S, V
+    static constexpr int kAtoms = kWave * SLOTS;
+    static constexpr int kSlots = SLOTS == 1 ? dockblob::kMaxSlotsSmall : dockblob::kMaxSlots;
+    float4 dyn[kAtoms];             // x, y, z relative to t, and sqrt(kElec) q (depth-first order)
+    float4 par[kAtoms];             // R, sqrt(eps), S, V
     union {
-        struct {
-            float tk[kMaxTors][12]; // torsion transforms, 3x4 row-major
-            float fw[kMaxFrag][12]; // fragment transforms (rotation part of the pose)
-        } pose;                     // live until the atom positions are written
-        float4 acc[dockblob::kMaxSlots];    // pair-force accumulators, slot = copy * N + atom
+        float tk[kMaxTors][12];     // torsion transforms, 3x4 row-major; live until the
+                                    // atom positions are written
+        float4 acc[kSlots];         // pair-force accumulators, slot = copy * N + atom
     } u;
+    float4 tor[kMaxTors][2];        // torsion k: axis point p and packed positions
+                                    // (a | b << 8 | first << 16 | end << 24), unit axis u
     int8_t chain[kMaxFrag][kChain]; // [0] = length, then torsions root first
     float2 hbt[4];                  // 12-10 table (r0, eps), index 2 * donor + acceptor
 };
@@ -273,13 +270,10 @@ struct Lig {
     int cls[SLOTS];
     int frag[SLOTS];
     int orig[SLOTS];                // original atom index
-    // per lane k < T: torsion k
-    float tp[3], tu[3];
-    int t_apos, t_bpos, t_first, t_end;
 };
 
 template <int SLOTS>
-__device__ void load_ligand(const uint8_t* __restrict__ blob, Smem& sm, Lig<SLOTS>& L,
+__device__ void load_ligand(const uint8_t* __restrict__ blob, Smem<SLOTS>& sm, Lig<SLOTS>& L,
                             bool fill_lds = true) {
     if (fill_lds) __syncthreads();  // previous users of the LDS tables are done
     const Header* h = reinterpret_cast<const Header*>(blob);
@@ -311,16 +305,11 @@ __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem& sm, Lig<SLOT
         if (ok && fill_lds) sm.par[a] = p;
     }
     const Torsion* tr = reinterpret_cast<const Torsion*>(blob + h->off_tors);
-    const int k = lane < L.T ? lane : 0;
-    if (L.T > 0) {
-        Torsion t = tr[k];
-        L.tp[0] = t.p[0]; L.tp[1] = t.p[1]; L.tp[2] = t.p[2];
-        L.tu[0] = t.u[0]; L.tu[1] = t.u[1]; L.tu[2] = t.u[2];
-        L.t_apos = t.a_pos; L.t_bpos = t.b_pos; L.t_first = t.first; L.t_end = t.end;
-    } else {
-        L.tp[0] = L.tp[1] = L.tp[2] = 0.f;
-        L.tu[0] = 1.f; L.tu[1] = L.tu[2] = 0.f;
-        L.t_apos = 0; L.t_bpos = 0; L.t_first = 1; L.t_end = 1;
+    if (fill_lds && lane < L.T) {
+        const Torsion t = tr[lane];
+        const int pk = t.a_pos | (t.b_pos << 8) | (t.first << 16) | (t.end << 24);
+        sm.tor[lane][0] = make_float4(t.p[0], t.p[1], t.p[2], __int_as_float(pk));
+        sm.tor[lane][1] = make_float4(t.u[0], t.u[1], t.u[2], 0.f);
     }
     const int8_t* ch = reinterpret_cast<const int8_t*>(blob + h->off_chain);
     const int n_chain_bytes = L.NF * kChain;
@@ -398,19 +387,20 @@ __device__ __forceinline__ void grid_term(const GridParams& G, int cls, float q,
 
 // ---------------------------------------------------------------------------
 // One pair: energy e and w = (dE/dr)/r from the separation d = x_b - x_a.
-// The 12-6 and 12-10 forms share one expression, c12 s^12 + c10 s^10 +
-// c6 s^6 with s = r0/r, so the loop has no divergent branch; `live` masks
-// pairs that are not kept (e = w = 0) and `grad` masks the slope where r^2 is
-// clamped. Masks are applied with bit operations so the compiler cannot turn
-// them into branches around the (long) slope computation.
+// Both dispersion-repulsion forms are eps (a s^12 + b s^m) with s = r0/r:
+// 12-6 (a, b, m) = (1, -2, 6), 12-10 hydrogen bond (5, -6, 10). Their slopes
+// share one form too, r dE/dr = -k eps (s^12 - s^m) with k = 12 and 60, so the
+// loop has no divergent branch. `live` masks pairs that are not kept
+// (e = w = 0) and `slope` masks the slope where r^2 is clamped; masks are
+// applied with bit operations so the compiler cannot turn them into branches
+// around the (long) slope computation.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float mask_f(float v, bool keep) {
     return __int_as_float(__float_as_int(v) & (keep ? -1 : 0));
 }
 
-__device__ __forceinline__ void pair_term(float dx, float dy, float dz, float r0, float c12,
-                                          float c10, float c6, float qq, float ds, bool live,
-                                          float& e, float& w) {
+__device__ __forceinline__ void pair_term(float dx, float dy, float dz, float r0, float ep, bool hb,
+                                          float qq, float ds, bool live, float& e, float& w) {
     const float r2raw = dx * dx + dy * dy + dz * dz;
     const bool slope = live && (r2raw >= kR2Min);
     const float r2 = fmaxf(r2raw, kR2Min);
@@ -420,10 +410,13 @@ __device__ __forceinline__ void pair_term(float dx, float dy, float dz, float r0
     const float s2 = (r0 * r0) * ir2;
     const float s4 = s2 * s2;
     const float s6 = s4 * s2;
-    const float s10 = s6 * s4;
     const float s12 = s6 * s6;
-    float elj = c12 * s12 + c10 * s10 + c6 * s6;
-    float dlj = -(12.f * c12 * s12 + 10.f * c10 * s10 + 6.f * c6 * s6);   // r dE/dr
+    const float sm = hb ? s6 * s4 : s6;
+    const float ca = hb ? 5.f : 1.f;
+    const float cb = hb ? -6.f : -2.f;
+    const float ck = hb ? -60.f : -12.f;
+    float elj = ep * (ca * s12 + cb * sm);
+    float dlj = (ck * ep) * (s12 - sm);                                        // r dE/dr
     const bool capped = elj > kCap;
     elj = capped ? kCap : elj;
     dlj = capped ? 0.f : dlj;
@@ -446,11 +439,17 @@ __device__ __forceinline__ void pair_term(float dx, float dy, float dz, float r0
 // ---------------------------------------------------------------------------
 struct PairForce {
     float fx, fy, fz, e;
-    int si, sj;
+    int si, sj;                     // byte offsets of the two accumulator slots
     bool valid;
 };
 
-__device__ __forceinline__ PairForce pair_force(const Smem& sm, uint32_t rec, int N) {
+// 24-bit multiply-add: full rate, where a 32-bit integer multiply is not.
+__device__ __forceinline__ int mad24(int a, int b, int c) {
+    return (int)(__umul24((unsigned)a, (unsigned)b) + (unsigned)c);
+}
+
+template <int SLOTS>
+__device__ __forceinline__ PairForce pair_force(const Smem<SLOTS>& sm, uint32_t rec, int N16) {
     PairForce o;
     o.valid = (rec & dockblob::kRecValid) != 0u;
     const int i = rec & 127, j = (rec >> 7) & 127;
@@ -463,33 +462,32 @@ __device__ __forceinline__ PairForce pair_force(const Smem& sm, uint32_t rec, in
     const float2 ht = sm.hbt[tb];
     const float r0 = hb ? ht.x : qi.x + qj.x;
     const float ep = hb ? ht.y : qi.y * qj.y;
-    const float c12 = hb ? 5.f * ep : ep;
-    const float c10 = hb ? -6.f * ep : 0.f;
-    const float c6 = hb ? 0.f : -2.f * ep;
-    const float qq = kElec * pi.w * pj.w;
+    const float qq = pi.w * pj.w;           // charges pre-scaled by sqrt(kElec)
     const float ds = qi.z * qj.w + qj.z * qi.w;
     float e, w;
-    pair_term(dx, dy, dz, r0, c12, c10, c6, qq, ds, o.valid, e, w);
+    pair_term(dx, dy, dz, r0, ep, hb, qq, ds, o.valid, e, w);
     o.e = e;
     o.fx = w * dx;
     o.fy = w * dy;
     o.fz = w * dz;
-    o.si = ci * N + i;
-    o.sj = cj * N + j;
+    o.si = mad24(ci, N16, i << 4);
+    o.sj = mad24(cj, N16, j << 4);
     return o;
 }
 
 // Read-modify-write of the pair's two accumulator slots. The slots of one
 // batch are distinct, so plain LDS loads and stores suffice (no atomics), and
 // batches follow each other in program order.
-__device__ __forceinline__ void apply_force(Smem& sm, const PairForce& f) {
+template <int SLOTS>
+__device__ __forceinline__ void apply_force(Smem<SLOTS>& sm, const PairForce& f) {
     if (f.valid) {
-        float4 ai = sm.u.acc[f.si];
-        float4 aj = sm.u.acc[f.sj];
-        ai.x -= f.fx; ai.y -= f.fy; ai.z -= f.fz;
-        aj.x += f.fx; aj.y += f.fy; aj.z += f.fz;
-        sm.u.acc[f.si] = ai;
-        sm.u.acc[f.sj] = aj;
+        float4* ai = reinterpret_cast<float4*>(reinterpret_cast<char*>(sm.u.acc) + f.si);
+        float4* aj = reinterpret_cast<float4*>(reinterpret_cast<char*>(sm.u.acc) + f.sj);
+        float4 vi = *ai, vj = *aj;
+        vi.x -= f.fx; vi.y -= f.fy; vi.z -= f.fz;
+        vj.x += f.fx; vj.y += f.fy; vj.z += f.fz;
+        *ai = vi;
+        *aj = vj;
     }
 }
 
@@ -499,7 +497,7 @@ __device__ __forceinline__ void apply_force(Smem& sm, const PairForce& f) {
 // this lane's gradient component to `grad`.
 // ---------------------------------------------------------------------------
 template <int SLOTS, int VAR>
-__device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, float gene,
+__device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>& L, float gene,
                           float& grad, float* atom_out) {
     const int lane = lane_id();
     const int N = L.N;
@@ -525,64 +523,48 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
     if (lane < L.T) {
         float sn, cs;
         sincosf(psi, &sn, &cs);
-        const float ux = L.tu[0], uy = L.tu[1], uz = L.tu[2];
+        const float4 tp4 = sm.tor[lane][0], tu4 = sm.tor[lane][1];
+        const float tp[3] = {tp4.x, tp4.y, tp4.z};
+        const float ux = tu4.x, uy = tu4.y, uz = tu4.z;
         const float oc = 1.f - cs;
         float Rk[9];
         Rk[0] = cs + oc * ux * ux;      Rk[1] = oc * ux * uy - sn * uz; Rk[2] = oc * ux * uz + sn * uy;
         Rk[3] = oc * uy * ux + sn * uz; Rk[4] = cs + oc * uy * uy;      Rk[5] = oc * uy * uz - sn * ux;
         Rk[6] = oc * uz * ux - sn * uy; Rk[7] = oc * uz * uy + sn * ux; Rk[8] = cs + oc * uz * uz;
-        float* o = sm.u.pose.tk[lane];
+        float* o = sm.u.tk[lane];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
             o[4 * r + 0] = Rk[3 * r + 0];
             o[4 * r + 1] = Rk[3 * r + 1];
             o[4 * r + 2] = Rk[3 * r + 2];
-            o[4 * r + 3] = L.tp[r] - (Rk[3 * r] * L.tp[0] + Rk[3 * r + 1] * L.tp[1] + Rk[3 * r + 2] * L.tp[2]);
+            o[4 * r + 3] = tp[r] - (Rk[3 * r] * tp[0] + Rk[3 * r + 1] * tp[1] + Rk[3 * r + 2] * tp[2]);
         }
     }
     __syncthreads();
-    // fragment transforms: product of enclosing torsions (root first), then
-    // the rotation Rq. Positions stay relative to the rotation centre (the
-    // translation t is added only where world coordinates are needed, the
-    // grid term): pair separations, torques and torsion axes are translation
-    // invariant and keep the precision of the small local coordinates.
-    if (lane < L.NF) {
-        float M[12] = {1.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 0.f, 1.f, 0.f};
-        const int len = sm.chain[lane][0];
-        for (int j = 0; j < len; ++j) {
-            const float* Tk = sm.u.pose.tk[(int)sm.chain[lane][1 + j]];
-            float Nw[12];
-#pragma unroll
-            for (int r = 0; r < 3; ++r) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    Nw[4 * r + c] = M[4 * r] * Tk[c] + M[4 * r + 1] * Tk[4 + c] + M[4 * r + 2] * Tk[8 + c];
-                Nw[4 * r + 3] = M[4 * r] * Tk[3] + M[4 * r + 1] * Tk[7] + M[4 * r + 2] * Tk[11] + M[4 * r + 3];
-            }
-#pragma unroll
-            for (int i = 0; i < 12; ++i) M[i] = Nw[i];
-        }
-        float* o = sm.u.pose.fw[lane];
-#pragma unroll
-        for (int r = 0; r < 3; ++r) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                o[4 * r + c] = Rq[3 * r] * M[c] + Rq[3 * r + 1] * M[4 + c] + Rq[3 * r + 2] * M[8 + c];
-            o[4 * r + 3] = Rq[3 * r] * M[3] + Rq[3 * r + 1] * M[7] + Rq[3 * r + 2] * M[11];
-        }
-    }
-    __syncthreads();
-    // atom positions relative to t
+    // atom positions relative to the rotation centre: the torsions enclosing
+    // the atom's fragment, innermost first (each about its reference axis,
+    // which no inner torsion moves), then the rotation Rq. The translation t
+    // is added only where world coordinates are needed (the grid term): pair
+    // separations, torques and torsion axes are translation invariant and
+    // keep the precision of the small local coordinates.
     const float tv[3] = {tx, ty, tz};
     float x[SLOTS][3];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int a = lane + kWave * s;
-        const float* W = sm.u.pose.fw[L.frag[s]];
+        float y0 = L.y0[s][0], y1 = L.y0[s][1], y2 = L.y0[s][2];
+        const int8_t* ch = sm.chain[L.frag[s]];
+        for (int j = ch[0]; j >= 1; --j) {
+            const float4* T = reinterpret_cast<const float4*>(sm.u.tk[(int)ch[j]]);
+            const float4 r0 = T[0], r1 = T[1], r2 = T[2];
+            const float z0 = r0.x * y0 + r0.y * y1 + r0.z * y2 + r0.w;
+            const float z1 = r1.x * y0 + r1.y * y1 + r1.z * y2 + r1.w;
+            const float z2 = r2.x * y0 + r2.y * y1 + r2.z * y2 + r2.w;
+            y0 = z0; y1 = z1; y2 = z2;
+        }
 #pragma unroll
-        for (int r = 0; r < 3; ++r)
-            x[s][r] = W[4 * r] * L.y0[s][0] + W[4 * r + 1] * L.y0[s][1] + W[4 * r + 2] * L.y0[s][2] + W[4 * r + 3];
-        if (a < N) sm.dyn[a] = make_float4(x[s][0], x[s][1], x[s][2], L.chg[s][1]);
+        for (int r = 0; r < 3; ++r) x[s][r] = Rq[3 * r] * y0 + Rq[3 * r + 1] * y1 + Rq[3 * r + 2] * y2;
+        if (a < N) sm.dyn[a] = make_float4(x[s][0], x[s][1], x[s][2], kSqrtElec * L.chg[s][1]);
     }
     __syncthreads();
 
@@ -615,6 +597,7 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
         __syncthreads();
         const auto plist = gmem(L.plist);
         const int nb = L.n_batches;
+        const int N16 = N * 16;
         // two batches per trip: their pair terms are independent and
         // interleave; their slot updates stay in batch order
         uint32_t ra = nb > 0 ? plist[lane] : 0u;
@@ -624,15 +607,15 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
             const uint32_t r0 = ra, r1 = rb;
             if (bt + 2 < nb) ra = plist[(bt + 2) * kWave + lane];
             if (bt + 3 < nb) rb = plist[(bt + 3) * kWave + lane];
-            PairForce fa = pair_force(sm, r0, N);
-            PairForce fb = pair_force(sm, r1, N);
+            PairForce fa = pair_force(sm, r0, N16);
+            PairForce fb = pair_force(sm, r1, N16);
             e_lane += fa.e;
             e_lane += fb.e;
             apply_force(sm, fa);
             apply_force(sm, fb);
         }
         if (bt < nb) {
-            PairForce fa = pair_force(sm, ra, N);
+            PairForce fa = pair_force(sm, ra, N16);
             e_lane += fa.e;
             apply_force(sm, fa);
         }
@@ -655,21 +638,14 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
     for (int s = 0; s < SLOTS; ++s)
         if (lane + kWave * s >= N) { g[s][0] = g[s][1] = g[s][2] = 0.f; }
 
-    // block sums: {E, gx, gy, gz} and the torque about t
+    // block sum of {E, gx, gy, gz}: the paper's reduction, in the chosen variant
     float4 eg = make_float4(e_lane, 0.f, 0.f, 0.f);
-    float4 tq = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-        eg.y += g[s][0]; eg.z += g[s][1]; eg.w += g[s][2];
-        const float rx = x[s][0], ry = x[s][1], rz = x[s][2];
-        tq.x += ry * g[s][2] - rz * g[s][1];
-        tq.y += rz * g[s][0] - rx * g[s][2];
-        tq.z += rx * g[s][1] - ry * g[s][0];
-    }
+    for (int s = 0; s < SLOTS; ++s) { eg.y += g[s][0]; eg.z += g[s][1]; eg.w += g[s][2]; }
     const float4 EG = sum4<VAR>(eg);
-    const float4 TQ = sum4_fp32<VAR>(tq);
 
-    // torsion torques: prefix sums of (g, x cross g) in depth-first order
+    // torsion torques: prefix sums of (g, x cross g) in depth-first order;
+    // the last lane's x cross g sums give the torque about t (FP32 always)
     float P[SLOTS][6];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
@@ -683,9 +659,16 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
         P[0][c] = wave_scan(P[0][c]);
         if constexpr (SLOTS == 2) P[1][c] = wave_scan(P[1][c]) + readlane(P[0][c], 63);
     }
+    const float4 TQ = make_float4(readlane(P[SLOTS - 1][3], 63), readlane(P[SLOTS - 1][4], 63),
+                                  readlane(P[SLOTS - 1][5], 63), 0.f);
     float gpsi = 0.f;
     {
-        const int hi = L.t_end - 1, lo = L.t_first - 1;
+        // torsion `lane`: bond atoms a, b and its moving range [first, end)
+        // in depth-first positions; lanes without a torsion read a harmless
+        // default (a = b = 0, empty range at 1)
+        const int pk = lane < L.T ? __float_as_int(sm.tor[lane & (kMaxTors - 1)][0].w) : (1 << 16) | (1 << 24);
+        const int t_apos = pk & 255, t_bpos = (pk >> 8) & 255;
+        const int hi = ((pk >> 24) & 255) - 1, lo = ((pk >> 16) & 255) - 1;
         float S[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
@@ -699,8 +682,8 @@ __device__ float evaluate(const GridParams& G, Smem& sm, const Lig<SLOTS>& L, fl
             }
             S[c] = ph - pl;
         }
-        const float4 xa = sm.dyn[L.t_apos];
-        const float4 xb = sm.dyn[L.t_bpos];
+        const float4 xa = sm.dyn[t_apos];
+        const float4 xb = sm.dyn[t_bpos];
         float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
         const float il = __builtin_amdgcn_rsqf(ux * ux + uy * uy + uz * uz);
         ux *= il; uy *= il; uz *= il;
@@ -753,7 +736,7 @@ __global__ __launch_bounds__(64, (SLOTS == 1 ? 3 : 2)) void score_kernel(GridPar
                                                    float* __restrict__ energy,
                                                    float* __restrict__ grad,
                                                    float* __restrict__ atom_out) {
-    __shared__ Smem sm;
+    __shared__ Smem<SLOTS> sm;
     Lig<SLOTS> L;
     load_ligand<SLOTS>(blob, sm, L);
     const int lane = lane_id();
@@ -768,7 +751,7 @@ __global__ __launch_bounds__(64, (SLOTS == 1 ? 3 : 2)) void score_kernel(GridPar
 }
 
 template <int SLOTS, int VAR>
-__device__ void local_search_one(const DevItem& it, int ind, Smem& sm, const Lig<SLOTS>& L,
+__device__ void local_search_one(const DevItem& it, int ind, Smem<SLOTS>& sm, const Lig<SLOTS>& L,
                                  int iterations, float rho, float eps, bool final_eval) {
     const int lane = lane_id();
     const int G = L.G;
@@ -820,7 +803,7 @@ __device__ void local_search_one(const DevItem& it, int ind, Smem& sm, const Lig
 }
 
 template <int SLOTS>
-__device__ void ls_dispatch(int var_uniform, const DevItem& it, int ind, Smem& sm,
+__device__ void ls_dispatch(int var_uniform, const DevItem& it, int ind, Smem<SLOTS>& sm,
                             const Lig<SLOTS>& L, const LsParams& p) {
     const int var = var_uniform >= 0 ? var_uniform : it.variant;
     const bool fin = it.final_eval != 0;
@@ -839,7 +822,7 @@ __device__ void ls_dispatch(int var_uniform, const DevItem& it, int ind, Smem& s
 }
 
 template <int SLOTS, int VAR>
-__device__ void ls_run(const DevItem& it, int ind, Smem& sm, const Lig<SLOTS>& L, const LsParams& p) {
+__device__ void ls_run(const DevItem& it, int ind, Smem<SLOTS>& sm, const Lig<SLOTS>& L, const LsParams& p) {
     if constexpr (VAR >= 0)
         local_search_one<SLOTS, VAR>(it, ind, sm, L, it.iterations, p.rho, p.eps, it.final_eval != 0);
     else
@@ -865,13 +848,14 @@ __device__ __forceinline__ DevItem load_item(const DevItem* items, int k) {
 // only when the item changes. Every wave exits once the counter passes the
 // last unit.
 template <int MODE, int VAR>
-__global__ __launch_bounds__(64, (MODE == docklaunch::kSlots1 ? 3 : 2)) void ls_kernel(LsParams p) {
-    __shared__ Smem sm;
-    const int lane = lane_id();
+__global__ __launch_bounds__(64, (MODE == docklaunch::kSlots1 ? (VAR >= 0 ? 4 : 3) : 2)) void ls_kernel(LsParams p) {
+    // LDS sized for the layouts the launch can meet
+    constexpr size_t kBytes = MODE == docklaunch::kSlots1 ? sizeof(Smem<1>) : sizeof(Smem<2>);
+    __shared__ __align__(16) unsigned char smem[kBytes];
     int cur_item = -1;
     while (true) {
         int u = 0;
-        if (lane == 0) u = atomicAdd(p.counter, 1);
+        if (lane_id() == 0) u = atomicAdd(p.counter, 1);
         u = uniform(u);
         if (u >= p.total_units) break;
         int lo = 0, hi = p.n_items - 1;
@@ -887,11 +871,14 @@ __global__ __launch_bounds__(64, (MODE == docklaunch::kSlots1 ? 3 : 2)) void ls_
         // a mixed launch would otherwise both hold registers)
         const bool reload = lo != cur_item;
         cur_item = lo;
-        if (MODE == docklaunch::kSlots1 || (MODE == docklaunch::kSlotsAny && it.slots == 1)) {
+        const bool one = MODE == docklaunch::kSlots1 || (MODE == docklaunch::kSlotsAny && it.slots == 1);
+        if (one) {
+            Smem<1>& sm = *reinterpret_cast<Smem<1>*>(smem);
             Lig<1> L;
             load_ligand<1>(it.blob, sm, L, reload);
             ls_run<1, VAR>(it, ind, sm, L, p);
-        } else {
+        } else if constexpr (MODE != docklaunch::kSlots1) {
+            Smem<2>& sm = *reinterpret_cast<Smem<2>*>(smem);
             Lig<2> L;
             load_ligand<2>(it.blob, sm, L, reload);
             ls_run<2, VAR>(it, ind, sm, L, p);

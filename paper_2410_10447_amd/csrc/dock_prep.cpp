@@ -158,7 +158,7 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
     // count grows by one and the placement restarts.
     using dockblob::kBatch;
     const int C = std::max(2, std::min(16, (2 * kBatch + N - 1) / N + 1));
-    if (C * N > dockblob::kMaxSlots) {
+    if (C * N > (N <= 64 ? dockblob::kMaxSlotsSmall : dockblob::kMaxSlots)) {
         err = "internal: accumulator slots exceed the build limit"; return DOCK_EUNSUPPORTED;
     }
     std::vector<int> degp(N, 0);

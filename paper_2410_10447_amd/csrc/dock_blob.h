@@ -12,9 +12,11 @@
 // go to distinct accumulator slots (copy * n_atoms + atom): a lane can add
 // its pair's force to both atoms without two lanes of one instruction
 // touching the same address, and the order of additions is fixed by the
-// list. Pair parameters are rebuilt from per-atom values: r0 = R_a + R_b,
-// eps = sqrt(eps_a) sqrt(eps_b), 332.06363 q_a q_b, S_a V_b + S_b V_a, or the
-// 12-10 table entry of the donor-acceptor pair.
+// list. Each pair carries its own parameters, computed on the host in double
+// precision and rounded once: r0 = R_a + R_b and eps = sqrt(eps_a eps_b), or
+// the 12-10 table entry of the donor-acceptor pair, and the desolvation
+// weight S_a V_b + S_b V_a. The Coulomb factor q_a q_b comes from the charges
+// the kernel keeps with the atom positions.
 #pragma once
 #include <stdint.h>
 
@@ -29,7 +31,8 @@ constexpr int kBatch = 64;
 constexpr int kMaxSlots = 384;                   // n_copies * n_atoms <= kMaxSlots
 constexpr int kMaxSlotsSmall = 256;              // the same bound for ligands of <= 64 atoms
 
-// pair record: i | j << 7 | ci << 14 | cj << 18 | hb << 22 | table << 23 | valid << 31
+// pair record word: i | j << 7 | ci << 14 | cj << 18 | hb << 22 | table << 23 | valid << 31
+// (table: index 2 * donor + acceptor of a 12-10 pair's parameters)
 constexpr uint32_t kRecValid = 1u << 31;
 inline uint32_t make_record(int i, int j, int ci, int cj, int hb, int table) {
     return (uint32_t)i | ((uint32_t)j << 7) | ((uint32_t)ci << 14) | ((uint32_t)cj << 18) |
@@ -50,17 +53,22 @@ struct Header {
     int32_t total_bytes;
     // section offsets (bytes)
     int32_t off_ref;        // float4[N]  y0 (reference coords minus centroid), w = 0
-    int32_t off_par;        // float4[N]  R, sqrt(eps), S = s + 0.01097|q|, V
     int32_t off_chg;        // float4[N]  332.06363 q, q, |q|, 0
     int32_t off_int;        // int4[N]    class, fragment, original index, 0
     int32_t off_tors;       // Torsion[T]
     int32_t off_chain;      // int8[n_frag][kChainStride]
-    int32_t off_plist;      // uint32[n_batches][kBatch] pair records
-    float hb_r0[4];         // 12-10 table, index 2 * donor + acceptor
-    float hb_eps[4];
-    int32_t pad[6];
+    int32_t off_plist;      // PairRec[n_batches][kBatch]
+    int32_t pad[15];
 };
 static_assert(sizeof(Header) == 128, "header is 128 bytes");
+
+// One lane's pair: the record word, then r0, eps and the desolvation weight
+// (FP32 bit patterns); all zero for an unused lane (valid bit clear).
+struct PairRec {
+    uint32_t rec;
+    float r0, eps, ds;
+};
+static_assert(sizeof(PairRec) == 16, "pair record is 16 bytes");
 
 struct Torsion {
     float p[4];      // axis point y0[a] (w unused)

@@ -35,6 +35,7 @@ using docklaunch::GridParams;
 using docklaunch::LsParams;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
@@ -247,7 +248,6 @@ struct __align__(16) Smem {
     static constexpr int kAtoms = kWave * SLOTS;
     static constexpr int kSlots = SLOTS == 1 ? dockblob::kMaxSlotsSmall : dockblob::kMaxSlots;
     float4 dyn[kAtoms];             // x, y, z relative to t, and sqrt(kElec) q (depth-first order)
-    float4 par[kAtoms];             // R, sqrt(eps), S, V
     union {
         float tk[kMaxTors][12];     // torsion transforms, 3x4 row-major; live until the
                                     // atom positions are written
@@ -256,14 +256,13 @@ struct __align__(16) Smem {
     float4 tor[kMaxTors][2];        // torsion k: axis point p and packed positions
                                     // (a | b << 8 | first << 16 | end << 24), unit axis u
     int8_t chain[kMaxFrag][kChain]; // [0] = length, then torsions root first
-    float2 hbt[4];                  // 12-10 table (r0, eps), index 2 * donor + acceptor
 };
 
 template <int SLOTS>
 struct Lig {
     // uniform
     int N, T, NF, G, n_batches, n_copies;
-    const uint32_t* plist;          // pair records, n_batches x 64
+    const u32x4* plist;             // pair records (dockblob::PairRec), n_batches x 64
     // per lane, per slot: atom a = lane + 64 * slot
     float y0[SLOTS][3];
     float chg[SLOTS][3];            // 332.06363 q, q, |q|
@@ -284,10 +283,8 @@ __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem<SLOTS>& sm, L
     L.G = uniform(h->n_genes);
     L.n_batches = uniform(h->n_batches);
     L.n_copies = uniform(h->n_copies);
-    L.plist = uniform_ptr(reinterpret_cast<const uint32_t*>(blob + h->off_plist));
-    if (lane < 4 && fill_lds) sm.hbt[lane] = make_float2(h->hb_r0[lane], h->hb_eps[lane]);
+    L.plist = uniform_ptr(reinterpret_cast<const u32x4*>(blob + h->off_plist));
     const float4* ref = reinterpret_cast<const float4*>(blob + h->off_ref);
-    const float4* par = reinterpret_cast<const float4*>(blob + h->off_par);
     const float4* chg = reinterpret_cast<const float4*>(blob + h->off_chg);
     const int4* iv = reinterpret_cast<const int4*>(blob + h->off_int);
 #pragma unroll
@@ -295,14 +292,13 @@ __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem<SLOTS>& sm, L
         const int a = lane + kWave * s;
         const bool ok = a < L.N;
         const int ai = ok ? a : 0;
-        float4 r = ref[ai], p = par[ai], c = chg[ai];
+        float4 r = ref[ai], c = chg[ai];
         int4 ii = iv[ai];
         L.y0[s][0] = r.x; L.y0[s][1] = r.y; L.y0[s][2] = r.z;
         L.chg[s][0] = ok ? c.x : 0.f; L.chg[s][1] = ok ? c.y : 0.f; L.chg[s][2] = ok ? c.z : 0.f;
         L.cls[s] = ii.x;
         L.frag[s] = ii.y;
         L.orig[s] = ii.z;
-        if (ok && fill_lds) sm.par[a] = p;
     }
     const Torsion* tr = reinterpret_cast<const Torsion*>(blob + h->off_tors);
     if (fill_lds && lane < L.T) {
@@ -448,24 +444,34 @@ __device__ __forceinline__ int mad24(int a, int b, int c) {
     return (int)(__umul24((unsigned)a, (unsigned)b) + (unsigned)c);
 }
 
+// A pair's record and the two atoms' positions (read from LDS one trip ahead
+// of their use, so that the reads overlap the previous trip's arithmetic).
+struct PairIn {
+    u32x4 pr;
+    float4 pi, pj;
+};
+
 template <int SLOTS>
-__device__ __forceinline__ PairForce pair_force(const Smem<SLOTS>& sm, uint32_t rec, int N16) {
+__device__ __forceinline__ PairIn pair_fetch(const Smem<SLOTS>& sm, u32x4 pr) {
+    PairIn in;
+    in.pr = pr;
+    in.pi = sm.dyn[pr.x & 127];
+    in.pj = sm.dyn[(pr.x >> 7) & 127];
+    return in;
+}
+
+__device__ __forceinline__ PairForce pair_force(const PairIn& in, int N16) {
     PairForce o;
+    const uint32_t rec = in.pr.x;
     o.valid = (rec & dockblob::kRecValid) != 0u;
     const int i = rec & 127, j = (rec >> 7) & 127;
     const int ci = (rec >> 14) & 15, cj = (rec >> 18) & 15;
     const bool hb = (rec >> 22) & 1u;
-    const int tb = (rec >> 23) & 3;
-    const float4 pi = sm.dyn[i], pj = sm.dyn[j];
-    const float4 qi = sm.par[i], qj = sm.par[j];
-    const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
-    const float2 ht = sm.hbt[tb];
-    const float r0 = hb ? ht.x : qi.x + qj.x;
-    const float ep = hb ? ht.y : qi.y * qj.y;
-    const float qq = pi.w * pj.w;           // charges pre-scaled by sqrt(kElec)
-    const float ds = qi.z * qj.w + qj.z * qi.w;
+    const float dx = in.pj.x - in.pi.x, dy = in.pj.y - in.pi.y, dz = in.pj.z - in.pi.z;
+    const float qq = in.pi.w * in.pj.w;     // charges pre-scaled by sqrt(kElec)
     float e, w;
-    pair_term(dx, dy, dz, r0, ep, hb, qq, ds, o.valid, e, w);
+    pair_term(dx, dy, dz, __uint_as_float(in.pr.y), __uint_as_float(in.pr.z), hb, qq,
+              __uint_as_float(in.pr.w), o.valid, e, w);
     o.e = e;
     o.fx = w * dx;
     o.fy = w * dy;
@@ -599,23 +605,34 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
         const int nb = L.n_batches;
         const int N16 = N * 16;
         // two batches per trip: their pair terms are independent and
-        // interleave; their slot updates stay in batch order
-        uint32_t ra = nb > 0 ? plist[lane] : 0u;
-        uint32_t rb = nb > 1 ? plist[kWave + lane] : 0u;
+        // interleave, their slot updates stay in batch order. Records are
+        // loaded two trips ahead and positions one trip ahead (positions are
+        // read-only in this phase); an unused record (all zero) reads atom 0
+        // and is masked.
+        auto record = [&](int b) {
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (b < nb) v = plist[b * kWave + lane];
+            return v;
+        };
+        PairIn ia = pair_fetch(sm, record(0));
+        PairIn ib = pair_fetch(sm, record(1));
+        u32x4 na = record(2);
+        u32x4 nc = record(3);
         int bt = 0;
         for (; bt + 1 < nb; bt += 2) {
-            const uint32_t r0 = ra, r1 = rb;
-            if (bt + 2 < nb) ra = plist[(bt + 2) * kWave + lane];
-            if (bt + 3 < nb) rb = plist[(bt + 3) * kWave + lane];
-            PairForce fa = pair_force(sm, r0, N16);
-            PairForce fb = pair_force(sm, r1, N16);
+            const PairForce fa = pair_force(ia, N16);
+            const PairForce fb = pair_force(ib, N16);
+            ia = pair_fetch(sm, na);
+            ib = pair_fetch(sm, nc);
+            na = record(bt + 4);
+            nc = record(bt + 5);
             e_lane += fa.e;
             e_lane += fb.e;
             apply_force(sm, fa);
             apply_force(sm, fb);
         }
         if (bt < nb) {
-            PairForce fa = pair_force(sm, ra, N16);
+            const PairForce fa = pair_force(ia, N16);
             e_lane += fa.e;
             apply_force(sm, fa);
         }
@@ -848,7 +865,7 @@ __device__ __forceinline__ DevItem load_item(const DevItem* items, int k) {
 // only when the item changes. Every wave exits once the counter passes the
 // last unit.
 template <int MODE, int VAR>
-__global__ __launch_bounds__(64, (MODE == docklaunch::kSlots1 ? (VAR >= 0 ? 4 : 3) : 2)) void ls_kernel(LsParams p) {
+__global__ __launch_bounds__(64, (MODE == docklaunch::kSlots1 ? 3 : 2)) void ls_kernel(LsParams p) {
     // LDS sized for the layouts the launch can meet
     constexpr size_t kBytes = MODE == docklaunch::kSlots1 ? sizeof(Smem<1>) : sizeof(Smem<2>);
     __shared__ __align__(16) unsigned char smem[kBytes];

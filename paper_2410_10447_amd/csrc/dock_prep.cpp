@@ -133,8 +133,8 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
         return depth[i] + depth[j] - 2 * da;
     };
     // kept pairs in depth-first positions (p < q), with their 12-10 table index
-    struct PairRec { int p, q, hb, table; };
-    std::vector<PairRec> plist;
+    struct KeptPair { int p, q, hb, table; };
+    std::vector<KeptPair> plist;
     for (int p = 0; p < N; ++p)
         for (int q = p + 1; q < N; ++q) {
             const int i = order[p], j = order[q];
@@ -162,7 +162,7 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
         err = "internal: accumulator slots exceed the build limit"; return DOCK_EUNSUPPORTED;
     }
     std::vector<int> degp(N, 0);
-    for (const PairRec& pr : plist) { ++degp[pr.p]; ++degp[pr.q]; }
+    for (const KeptPair& pr : plist) { ++degp[pr.p]; ++degp[pr.q]; }
     std::vector<int> porder(plist.size());
     for (size_t k = 0; k < porder.size(); ++k) porder[k] = (int)k;
     std::stable_sort(porder.begin(), porder.end(), [&](int a, int b) {
@@ -178,7 +178,7 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
         std::vector<uint8_t> use(size_t(nb) * N, 0);
         bool placed_all = true;
         for (int k : porder) {
-            const PairRec& pr = plist[k];
+            const KeptPair& pr = plist[k];
             int best = -1, best_score = 0;
             for (int b = 0; b < nb; ++b) {
                 const int up = use[size_t(b) * N + pr.p], uq = use[size_t(b) * N + pr.q];
@@ -205,12 +205,11 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
     size_t off = sizeof(Header);
     auto take = [&](size_t bytes) { size_t o = off; off = align16(off + bytes); return (int32_t)o; };
     h.off_ref = take(16 * size_t(N));
-    h.off_par = take(16 * size_t(N));
     h.off_chg = take(16 * size_t(N));
     h.off_int = take(16 * size_t(N));
     h.off_tors = take(sizeof(Torsion) * size_t(T));
     h.off_chain = take(size_t(NF) * kChainStride);
-    h.off_plist = take(4 * size_t(kBatch) * size_t(n_batches));
+    h.off_plist = take(sizeof(dockblob::PairRec) * size_t(kBatch) * size_t(n_batches));
     h.magic = kMagic;
     h.n_atoms = N;
     h.n_torsions = T;
@@ -221,11 +220,6 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
     h.n_batches = n_batches;
     h.n_copies = C;
     h.total_bytes = (int32_t)off;
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) {
-            h.hb_r0[2 * a + b] = (float)ff.hb_r0[a][b];
-            h.hb_eps[2 * a + b] = (float)ff.hb_eps[a][b];
-        }
     int max_class = 0;
     for (int i = 0; i < N; ++i) max_class = std::max(max_class, (int)d.cls[i]);
     h.max_class = max_class;
@@ -238,7 +232,6 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
     for (int c = 0; c < 3; ++c) cen[c] /= N;
     auto y0 = [&](int i, int c) { return d.xyz[3 * i + c] - cen[c]; };
     float* ref = reinterpret_cast<float*>(blob.data() + h.off_ref);
-    float* par = reinterpret_cast<float*>(blob.data() + h.off_par);
     float* chg = reinterpret_cast<float*>(blob.data() + h.off_chg);
     int32_t* iv = reinterpret_cast<int32_t*>(blob.data() + h.off_int);
     for (int p = 0; p < N; ++p) {
@@ -246,10 +239,6 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
         int c = d.cls[i];
         double q = d.charge[i];
         for (int a = 0; a < 3; ++a) ref[4 * p + a] = (float)y0(i, a);
-        par[4 * p + 0] = (float)ff.radius[c];
-        par[4 * p + 1] = (float)std::sqrt(ff.eps[c]);
-        par[4 * p + 2] = (float)(ff.solv[c] + kQSolv * std::fabs(q));
-        par[4 * p + 3] = (float)ff.vol[c];
         chg[4 * p + 0] = (float)(kElec * q);
         chg[4 * p + 1] = (float)q;
         chg[4 * p + 2] = (float)std::fabs(q);
@@ -272,9 +261,25 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
         tr[k].first = pos[b];
         tr[k].end = pos[b] + size[b];
     }
-    uint32_t* pl = reinterpret_cast<uint32_t*>(blob.data() + h.off_plist);
+    PairRec* pl = reinterpret_cast<PairRec*>(blob.data() + h.off_plist);
+    auto solv = [&](int i) { return ff.solv[d.cls[i]] + kQSolv * std::fabs((double)d.charge[i]); };
     for (int b = 0; b < n_batches; ++b)
-        for (size_t k = 0; k < batch[b].size(); ++k) pl[b * kBatch + k] = batch[b][k];
+        for (size_t k = 0; k < batch[b].size(); ++k) {
+            const uint32_t r = batch[b][k];
+            const int i = order[r & 127], j = order[(r >> 7) & 127];
+            const int ci = d.cls[i], cj = d.cls[j];
+            PairRec& o = pl[b * kBatch + k];
+            o.rec = r;
+            if ((r >> 22) & 1u) {
+                const int t = (r >> 23) & 3;
+                o.r0 = (float)ff.hb_r0[t >> 1][t & 1];
+                o.eps = (float)ff.hb_eps[t >> 1][t & 1];
+            } else {
+                o.r0 = (float)(ff.radius[ci] + ff.radius[cj]);
+                o.eps = (float)std::sqrt(ff.eps[ci] * ff.eps[cj]);
+            }
+            o.ds = (float)(solv(i) * ff.vol[cj] + solv(j) * ff.vol[ci]);
+        }
     int8_t* ch = reinterpret_cast<int8_t*>(blob.data() + h.off_chain);
     for (int f = 0; f < NF; ++f) {
         ch[f * kChainStride] = (int8_t)chain[f].size();
@@ -302,10 +307,10 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
 void decode_pairs(const Prepared& P, std::vector<uint32_t>& pairs, std::vector<uint8_t>& hb) {
     using namespace dockblob;
     const Header* h = reinterpret_cast<const Header*>(P.blob.data());
-    const uint32_t* pl = reinterpret_cast<const uint32_t*>(P.blob.data() + h->off_plist);
+    const PairRec* pl = reinterpret_cast<const PairRec*>(P.blob.data() + h->off_plist);
     std::vector<std::pair<uint32_t, uint8_t>> v;
     for (int k = 0; k < h->n_batches * kBatch; ++k) {
-        const uint32_t r = pl[k];
+        const uint32_t r = pl[k].rec;
         if (!(r & kRecValid)) continue;
         const int i = P.order[r & 127], j = P.order[(r >> 7) & 127];
         const uint32_t lo = (uint32_t)std::min(i, j), hi = (uint32_t)std::max(i, j);

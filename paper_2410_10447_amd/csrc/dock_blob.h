@@ -38,6 +38,10 @@ inline uint32_t make_record(int i, int j, int ci, int cj, int hb, int table) {
     return (uint32_t)i | ((uint32_t)j << 7) | ((uint32_t)ci << 14) | ((uint32_t)cj << 18) |
            ((uint32_t)hb << 22) | ((uint32_t)table << 23) | kRecValid;
 }
+// An unused lane: valid bit clear, two distinct slots no pair of the batch uses.
+inline uint32_t make_pad_record(int i, int j, int ci, int cj) {
+    return (uint32_t)i | ((uint32_t)j << 7) | ((uint32_t)ci << 14) | ((uint32_t)cj << 18);
+}
 
 struct Header {
     int32_t magic;

@@ -431,47 +431,36 @@ __device__ __forceinline__ void pair_term(float dx, float dy, float dz, float r0
 
 // ---------------------------------------------------------------------------
 // One listed pair (a packed record, see the blob layout) evaluated from the
-// atom data in LDS; the force is applied by apply_force.
+// atom positions in LDS; the caller adds its force to the two slots.
 // ---------------------------------------------------------------------------
 struct PairForce {
     float fx, fy, fz, e;
     int si, sj;                     // byte offsets of the two accumulator slots
-    bool valid;
 };
+
+// Compile-time integer argument for the unrolled pipeline steps.
+template <int V>
+struct IntC { static constexpr int value = V; };
 
 // 24-bit multiply-add: full rate, where a 32-bit integer multiply is not.
 __device__ __forceinline__ int mad24(int a, int b, int c) {
     return (int)(__umul24((unsigned)a, (unsigned)b) + (unsigned)c);
 }
 
-// A pair's record and the two atoms' positions (read from LDS one trip ahead
-// of their use, so that the reads overlap the previous trip's arithmetic).
-struct PairIn {
-    u32x4 pr;
-    float4 pi, pj;
-};
-
-template <int SLOTS>
-__device__ __forceinline__ PairIn pair_fetch(const Smem<SLOTS>& sm, u32x4 pr) {
-    PairIn in;
-    in.pr = pr;
-    in.pi = sm.dyn[pr.x & 127];
-    in.pj = sm.dyn[(pr.x >> 7) & 127];
-    return in;
-}
-
-__device__ __forceinline__ PairForce pair_force(const PairIn& in, int N16) {
+// Unused lanes (valid bit clear) carry two slots no pair of their batch uses
+// and get zero energy and force, so every lane updates its slots.
+__device__ __forceinline__ PairForce pair_force(u32x4 pr, float4 pi, float4 pj, int N16) {
     PairForce o;
-    const uint32_t rec = in.pr.x;
-    o.valid = (rec & dockblob::kRecValid) != 0u;
+    const uint32_t rec = pr.x;
+    const bool valid = (rec & dockblob::kRecValid) != 0u;
     const int i = rec & 127, j = (rec >> 7) & 127;
     const int ci = (rec >> 14) & 15, cj = (rec >> 18) & 15;
     const bool hb = (rec >> 22) & 1u;
-    const float dx = in.pj.x - in.pi.x, dy = in.pj.y - in.pi.y, dz = in.pj.z - in.pi.z;
-    const float qq = in.pi.w * in.pj.w;     // charges pre-scaled by sqrt(kElec)
+    const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
+    const float qq = pi.w * pj.w;           // charges pre-scaled by sqrt(kElec)
     float e, w;
-    pair_term(dx, dy, dz, __uint_as_float(in.pr.y), __uint_as_float(in.pr.z), hb, qq,
-              __uint_as_float(in.pr.w), o.valid, e, w);
+    pair_term(dx, dy, dz, __uint_as_float(pr.y), __uint_as_float(pr.z), hb, qq,
+              __uint_as_float(pr.w), valid, e, w);
     o.e = e;
     o.fx = w * dx;
     o.fy = w * dy;
@@ -481,20 +470,20 @@ __device__ __forceinline__ PairForce pair_force(const PairIn& in, int N16) {
     return o;
 }
 
-// Read-modify-write of the pair's two accumulator slots. The slots of one
-// batch are distinct, so plain LDS loads and stores suffice (no atomics), and
-// batches follow each other in program order.
+// Accumulator slot at a byte offset (a multiple of 16).
 template <int SLOTS>
-__device__ __forceinline__ void apply_force(Smem<SLOTS>& sm, const PairForce& f) {
-    if (f.valid) {
-        float4* ai = reinterpret_cast<float4*>(reinterpret_cast<char*>(sm.u.acc) + f.si);
-        float4* aj = reinterpret_cast<float4*>(reinterpret_cast<char*>(sm.u.acc) + f.sj);
-        float4 vi = *ai, vj = *aj;
-        vi.x -= f.fx; vi.y -= f.fy; vi.z -= f.fz;
-        vj.x += f.fx; vj.y += f.fy; vj.z += f.fz;
-        *ai = vi;
-        *aj = vj;
-    }
+__device__ __forceinline__ float4* slot(Smem<SLOTS>& sm, int byte_offset) {
+    return reinterpret_cast<float4*>(
+        __builtin_assume_aligned(reinterpret_cast<char*>(sm.u.acc) + byte_offset, 16));
+}
+
+// Adds -f to slot si and +f to slot sj, from their values read earlier.
+template <int SLOTS>
+__device__ __forceinline__ void store_force(Smem<SLOTS>& sm, const PairForce& f, float4 ai, float4 aj) {
+    float4* pi = slot(sm, f.si);
+    float4* pj = slot(sm, f.sj);
+    pi->x = ai.x - f.fx; pi->y = ai.y - f.fy; pi->z = ai.z - f.fz;
+    pj->x = aj.x + f.fx; pj->y = aj.y + f.fy; pj->z = aj.z + f.fz;
 }
 
 // ---------------------------------------------------------------------------
@@ -604,37 +593,63 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
         const auto plist = gmem(L.plist);
         const int nb = L.n_batches;
         const int N16 = N * 16;
-        // two batches per trip: their pair terms are independent and
-        // interleave, their slot updates stay in batch order. Records are
-        // loaded two trips ahead and positions one trip ahead (positions are
-        // read-only in this phase); an unused record (all zero) reads atom 0
-        // and is masked.
-        auto record = [&](int b) {
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (b < nb) v = plist[b * kWave + lane];
-            return v;
-        };
-        PairIn ia = pair_fetch(sm, record(0));
-        PairIn ib = pair_fetch(sm, record(1));
-        u32x4 na = record(2);
-        u32x4 nc = record(3);
-        int bt = 0;
-        for (; bt + 1 < nb; bt += 2) {
-            const PairForce fa = pair_force(ia, N16);
-            const PairForce fb = pair_force(ib, N16);
-            ia = pair_fetch(sm, na);
-            ib = pair_fetch(sm, nc);
-            na = record(bt + 4);
-            nc = record(bt + 5);
-            e_lane += fa.e;
-            e_lane += fb.e;
-            apply_force(sm, fa);
-            apply_force(sm, fb);
-        }
-        if (bt < nb) {
-            const PairForce fa = pair_force(ia, N16);
-            e_lane += fa.e;
-            apply_force(sm, fa);
+        // Software pipeline over batches with no branch inside. Step k
+        // stores batch k (its slot values were read in step k - 1) and
+        // computes batch k + 1 while reading the positions of batch k + 2
+        // and loading the record of batch k + 4. A record lives four steps
+        // and positions, forces and slot values two, so the steps are
+        // unrolled by four with register sets indexed by the batch number
+        // mod 4 and mod 2: no loaded value is copied between steps. Slot
+        // updates stay in batch order (LDS executes a wave's accesses in
+        // order: batch k's stores precede batch k + 1's loads). Prefetch
+        // indices are clamped to the last batch, so loads need no guard.
+        if (nb > 0) {
+            auto record = [&](int b) -> u32x4 { return plist[min(b, nb - 1) * kWave + lane]; };
+            u32x4 R[4];
+            float4 Pi[2], Pj[2], Ai[2], Aj[2];
+            PairForce F[2];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) R[q] = record(q);
+            Pi[0] = sm.dyn[R[0].x & 127];
+            Pj[0] = sm.dyn[(R[0].x >> 7) & 127];
+            F[0] = pair_force(R[0], Pi[0], Pj[0], N16);
+            Ai[0] = *slot(sm, F[0].si);
+            Aj[0] = *slot(sm, F[0].sj);
+            Pi[1] = sm.dyn[R[1].x & 127];
+            Pj[1] = sm.dyn[(R[1].x >> 7) & 127];
+            int k = 0;
+            auto step = [&](auto residue) {
+                constexpr int r = decltype(residue)::value;  // k mod 4
+                constexpr int c = r & 1, n = (r + 1) & 1;
+                const u32x4 rf = R[(r + 2) & 3];
+                Pi[c] = sm.dyn[rf.x & 127];
+                Pj[c] = sm.dyn[(rf.x >> 7) & 127];
+                R[r] = record(k + 4);
+                __builtin_amdgcn_sched_barrier(0);   // keep the loads at the step's start
+                F[n] = pair_force(R[(r + 1) & 3], Pi[n], Pj[n], N16);
+                store_force(sm, F[c], Ai[c], Aj[c]);
+                e_lane += F[c].e;
+                Ai[n] = *slot(sm, F[n].si);
+                Aj[n] = *slot(sm, F[n].sj);
+                __builtin_amdgcn_sched_barrier(0);
+                ++k;
+            };
+            using I0 = IntC<0>;
+            using I1 = IntC<1>;
+            using I2 = IntC<2>;
+            using I3 = IntC<3>;
+            while (k + 4 < nb) { step(I0()); step(I1()); step(I2()); step(I3()); }
+            if (k < nb - 1) step(I0());
+            if (k < nb - 1) step(I1());
+            if (k < nb - 1) step(I2());
+            // k == nb - 1: the last batch is computed and its slots read
+            if (k & 1) {
+                store_force(sm, F[1], Ai[1], Aj[1]);
+                e_lane += F[1].e;
+            } else {
+                store_force(sm, F[0], Ai[0], Aj[0]);
+                e_lane += F[0].e;
+            }
         }
         __syncthreads();
         // each atom adds its copies in copy order
@@ -865,7 +880,7 @@ __device__ __forceinline__ DevItem load_item(const DevItem* items, int k) {
 // only when the item changes. Every wave exits once the counter passes the
 // last unit.
 template <int MODE, int VAR>
-__global__ __launch_bounds__(64, (MODE == docklaunch::kSlots1 ? 3 : 2)) void ls_kernel(LsParams p) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == docklaunch::kSlots1 ? 3 : 2, MODE == docklaunch::kSlots1 ? 3 : 2))) void ls_kernel(LsParams p) {
     // LDS sized for the layouts the launch can meet
     constexpr size_t kBytes = MODE == docklaunch::kSlots1 ? sizeof(Smem<1>) : sizeof(Smem<2>);
     __shared__ __align__(16) unsigned char smem[kBytes];

@@ -150,15 +150,18 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
         }
     const int n_pairs = (int)plist.size();
     // batches of kBatch pairs, each atom at most C times per batch. C grows for
-    // small ligands so that C * N can hold a full batch's 128 pair ends. The
+    // small ligands so that C * N can hold a full batch's 128 pair ends (up to
+    // 15, the largest copy index a record holds besides the spare copy). The
     // batch count starts at its lower bound, max(P / 64, max degree / C);
     // pairs are placed most-constrained first (largest endpoint degree), each
     // into the open batch where its two atoms are used least (then the least
     // filled batch, then the lowest index); if a pair finds no batch, the
     // count grows by one and the placement restarts.
     using dockblob::kBatch;
-    const int C = std::max(2, std::min(16, (2 * kBatch + N - 1) / N + 1));
-    if (C * N > (N <= 64 ? dockblob::kMaxSlotsSmall : dockblob::kMaxSlots)) {
+    const int C = std::max(2, std::min(15, (2 * kBatch + N - 1) / N + 1));
+    using dockblob::kMaxSlots;
+    using dockblob::kMaxSlotsSmall;
+    if (C * N > (N <= 64 ? kMaxSlotsSmall : kMaxSlots)) {
         err = "internal: accumulator slots exceed the build limit"; return DOCK_EUNSUPPORTED;
     }
     std::vector<int> degp(N, 0);
@@ -192,7 +195,32 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
             ++cnt[best];
             batch[best].push_back(dockblob::make_record(pr.p, pr.q, ci, cj, pr.hb, pr.table));
         }
-        if (placed_all) break;
+        if (placed_all) {
+            // Unused lanes get records with the valid bit clear whose two
+            // slots are distinct and unused in their batch: first free copies
+            // of real atoms, then spare slots C * N + t (copy index C,
+            // "atom" t < 64, needed only when C * N < 128). Their force is
+            // zero, so every lane may update its slots without a branch.
+            for (int b = 0; b < nb; ++b) {
+                std::vector<std::pair<int, int>> free_slots;  // (copy, atom)
+                for (int c = 0; c < C; ++c)
+                    for (int a = 0; a < N; ++a)
+                        if (c >= use[size_t(b) * N + a]) free_slots.push_back({c, a});
+                for (int t = 0; t < kBatch && C * N + t < (N <= 64 ? kMaxSlotsSmall : kMaxSlots); ++t)
+                    free_slots.push_back({C, t});
+                size_t f = 0;
+                while ((int)batch[b].size() < kBatch) {
+                    if (f + 1 >= free_slots.size()) {
+                        err = "internal: no free accumulator slots for batch padding";
+                        return DOCK_EUNSUPPORTED;
+                    }
+                    const auto u = free_slots[f], v = free_slots[f + 1];
+                    f += 2;
+                    batch[b].push_back(dockblob::make_pad_record(u.second, v.second, u.first, v.first));
+                }
+            }
+            break;
+        }
         ++nb;
     }
     if (n_pairs == 0) batch.clear();
@@ -266,10 +294,14 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
     for (int b = 0; b < n_batches; ++b)
         for (size_t k = 0; k < batch[b].size(); ++k) {
             const uint32_t r = batch[b][k];
-            const int i = order[r & 127], j = order[(r >> 7) & 127];
-            const int ci = d.cls[i], cj = d.cls[j];
             PairRec& o = pl[b * kBatch + k];
             o.rec = r;
+            if (!(r & kRecValid)) {
+                o.r0 = o.eps = o.ds = 0.f;
+                continue;
+            }
+            const int i = order[r & 127], j = order[(r >> 7) & 127];
+            const int ci = d.cls[i], cj = d.cls[j];
             if ((r >> 22) & 1u) {
                 const int t = (r >> 23) & 3;
                 o.r0 = (float)ff.hb_r0[t >> 1][t & 1];

@@ -69,23 +69,29 @@ def _check_prep(lig):
 
 
 def _check_batches(b, C, N, p, order):
-    """Batch records: valid pairs are the pair list; within a batch every
-    (copy, atom) slot is used at most once; the slots fit the accumulator."""
-    assert C * N <= 384 and 2 <= C <= 16
+    """Batch records: valid pairs are the pair list; every lane of a batch,
+    unused lanes included, owns two (copy, atom) slots no other lane of the
+    batch touches; unused lanes take free copies of real atoms, or spare
+    slots C*N + t (copy index C) inside the accumulator."""
+    cap = 256 if N <= 64 else 384
+    assert C * N <= cap and 2 <= C <= 15
     got = []
     for row in b:
         slots = []
         for r in row.tolist():
-            if not (r >> 31) & 1:
-                assert r == 0
-                continue
             i, j = r & 127, (r >> 7) & 127
             ci, cj = (r >> 14) & 15, (r >> 18) & 15
+            if not (r >> 31) & 1:
+                assert (r >> 22) == 0, "unused lane with flags"
+                for c, a in ((ci, i), (cj, j)):
+                    assert (c < C and a < N) or (c == C and a < 64 and C * N + a < cap), (c, a)
+                slots += [(ci, i), (cj, j)]
+                continue
             assert i < N and j < N and ci < C and cj < C
             slots += [(ci, i), (cj, j)]
             a, bb = int(order[i]), int(order[j])
             got.append((min(a, bb), max(a, bb), (r >> 22) & 1))
-        assert len(slots) == len(set(slots)) and len(slots) <= 128
+        assert len(slots) == len(set(slots)) == 128
     got.sort()
     want = sorted((int(a), int(bb), int(hb)) for (a, bb), hb in zip(p.pairs, p.pair_hb))
     assert got == want

@@ -13,10 +13,11 @@
 // its pair's force to both atoms without two lanes of one instruction
 // touching the same address, and the order of additions is fixed by the
 // list. Each pair carries its own parameters, computed on the host in double
-// precision and rounded once: r0 = R_a + R_b and eps = sqrt(eps_a eps_b), or
-// the 12-10 table entry of the donor-acceptor pair, and the desolvation
-// weight S_a V_b + S_b V_a. The Coulomb factor q_a q_b comes from the charges
-// the kernel keeps with the atom positions.
+// precision and rounded once: the dispersion-repulsion coefficients A, B of
+// A / r^12 + B / r^m (from r0 = R_a + R_b and eps = sqrt(eps_a eps_b), or the
+// 12-10 table entry of the donor-acceptor pair) and the desolvation weight
+// S_a V_b + S_b V_a. The Coulomb factor q_a q_b comes from the charges the
+// kernel keeps with the atom positions.
 #pragma once
 #include <stdint.h>
 
@@ -66,11 +67,12 @@ struct Header {
 };
 static_assert(sizeof(Header) == 128, "header is 128 bytes");
 
-// One lane's pair: the record word, then r0, eps and the desolvation weight
-// (FP32 bit patterns); all zero for an unused lane (valid bit clear).
+// One lane's pair: the record word, then A = eps a r0^12, B = eps b r0^m
+// (12-6: a = 1, b = -2, m = 6; 12-10: a = 5, b = -6, m = 10) and the
+// desolvation weight; all zero for an unused lane (valid bit clear).
 struct PairRec {
     uint32_t rec;
-    float r0, eps, ds;
+    float c12, cm, ds;
 };
 static_assert(sizeof(PairRec) == 16, "pair record is 16 bytes");
 

@@ -345,7 +345,41 @@ __device__ __forceinline__ void axis_cell(float t, float xl, float lo, float hi,
     f = ((xw == xc) ? two_sum_fraction(t, node, xl) : (xc - node)) * ih;
 }
 
-__device__ __forceinline__ void grid_term(const GridParams& G, int cls, float q, float aq,
+// Corner values an atom reads: v[m][4 dz + 2 dy + dx] for the atom's type map
+// (m = 0), the electrostatic map (1) and the desolvation map (2). The loads
+// are issued early (grid_load) and consumed later (grid_term), so that their
+// latency overlaps other work.
+struct GridTaps {
+    float v[3][8];
+};
+
+__device__ __forceinline__ int axis_index(float t, float xl, float lo, float hi, float ih, int n) {
+    const float xc = fminf(fmaxf(t + xl, lo), hi);
+    return min(max((int)floorf((xc - lo) * ih), 0), n - 2);
+}
+
+__device__ __forceinline__ void grid_load(const GridParams& G, int cls, const float xl[3],
+                                          const float t[3], GridTaps& tp) {
+    const float ih = G.inv_spacing;
+    const int cx = axis_index(t[0], xl[0], G.origin[0], G.hi[0], ih, G.nx);
+    const int cy = axis_index(t[1], xl[1], G.origin[1], G.hi[1], ih, G.ny);
+    const int cz = axis_index(t[2], xl[2], G.origin[2], G.hi[2], ih, G.nz);
+    const int plane = G.nx * G.ny;
+    const int vol = plane * G.nz;
+    const int base = (cz * G.ny + cy) * G.nx + cx;
+    const auto mc = gmem(G.maps + (size_t)cls * vol + base);
+    const auto me = gmem(G.maps + (size_t)(G.n_maps - 2) * vol + base);
+    const auto md = gmem(G.maps + (size_t)(G.n_maps - 1) * vol + base);
+    const int off[8] = {0, 1, G.nx, G.nx + 1, plane, plane + 1, plane + G.nx, plane + G.nx + 1};
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        tp.v[0][i] = mc[off[i]];
+        tp.v[1][i] = me[off[i]];
+        tp.v[2][i] = md[off[i]];
+    }
+}
+
+__device__ __forceinline__ void grid_term(const GridParams& G, const GridTaps& tp, float q, float aq,
                                           const float xl[3], const float t[3],
                                           float& e, float& gx, float& gy, float& gz) {
     int cx, cy, cz;
@@ -354,16 +388,9 @@ __device__ __forceinline__ void grid_term(const GridParams& G, int cls, float q,
     axis_cell(t[0], xl[0], G.origin[0], G.hi[0], G.spacing, ih, G.nx, cx, fx, xw, xc);
     axis_cell(t[1], xl[1], G.origin[1], G.hi[1], G.spacing, ih, G.ny, cy, fy, yw, yc);
     axis_cell(t[2], xl[2], G.origin[2], G.hi[2], G.spacing, ih, G.nz, cz, fz, zw, zc);
-    const int plane = G.nx * G.ny;
-    const int vol = plane * G.nz;
-    const int base = (cz * G.ny + cy) * G.nx + cx;
-    const auto mc = gmem(G.maps + (size_t)cls * vol + base);
-    const auto me = gmem(G.maps + (size_t)(G.n_maps - 2) * vol + base);
-    const auto md = gmem(G.maps + (size_t)(G.n_maps - 1) * vol + base);
-    const int off[8] = {0, 1, G.nx, G.nx + 1, plane, plane + 1, plane + G.nx, plane + G.nx + 1};
     float v[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = mc[off[i]] + q * me[off[i]] + aq * md[off[i]];
+    for (int i = 0; i < 8; ++i) v[i] = tp.v[0][i] + q * tp.v[1][i] + aq * tp.v[2][i];
     // v index = 4 dz + 2 dy + dx
     const float d00 = v[1] - v[0], d01 = v[3] - v[2], d10 = v[5] - v[4], d11 = v[7] - v[6];
     const float a00 = v[0] + fx * d00, a01 = v[2] + fx * d01;
@@ -383,19 +410,15 @@ __device__ __forceinline__ void grid_term(const GridParams& G, int cls, float q,
 
 // ---------------------------------------------------------------------------
 // One pair: energy e and w = (dE/dr)/r from the separation d = x_b - x_a.
-// Both dispersion-repulsion forms are eps (a s^12 + b s^m) with s = r0/r:
-// 12-6 (a, b, m) = (1, -2, 6), 12-10 hydrogen bond (5, -6, 10). Their slopes
-// share one form too, r dE/dr = -k eps (s^12 - s^m) with k = 12 and 60, so the
-// loop has no divergent branch. `live` masks pairs that are not kept
-// (e = w = 0) and `slope` masks the slope where r^2 is clamped; masks are
-// applied with bit operations so the compiler cannot turn them into branches
-// around the (long) slope computation.
+// Both dispersion-repulsion forms are A / r^12 + B / r^m, with A = eps a
+// r0^12 and B = eps b r0^m taken from the pair record: 12-6
+// (a, b, m) = (1, -2, 6), 12-10 hydrogen bond (5, -6, 10); r dE/dr is
+// -12 A / r^12 - m B / r^m. `live` masks pairs that are not kept (e = w = 0)
+// and `slope` masks the slope where r^2 is clamped (selects, so a masked
+// NaN or infinity gives 0 too).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float mask_f(float v, bool keep) {
-    return __int_as_float(__float_as_int(v) & (keep ? -1 : 0));
-}
 
-__device__ __forceinline__ void pair_term(float dx, float dy, float dz, float r0, float ep, bool hb,
+__device__ __forceinline__ void pair_term(float dx, float dy, float dz, float A, float B, bool hb,
                                           float qq, float ds, bool live, float& e, float& w) {
     const float r2raw = dx * dx + dy * dy + dz * dz;
     const bool slope = live && (r2raw >= kR2Min);
@@ -403,30 +426,29 @@ __device__ __forceinline__ void pair_term(float dx, float dy, float dz, float r0
     const float rinv = __builtin_amdgcn_rsqf(r2);
     const float ir2 = rinv * rinv;
     const float r = r2 * rinv;
-    const float s2 = (r0 * r0) * ir2;
-    const float s4 = s2 * s2;
-    const float s6 = s4 * s2;
-    const float s12 = s6 * s6;
-    const float sm = hb ? s6 * s4 : s6;
-    const float ca = hb ? 5.f : 1.f;
-    const float cb = hb ? -6.f : -2.f;
-    const float ck = hb ? -60.f : -12.f;
-    float elj = ep * (ca * s12 + cb * sm);
-    float dlj = (ck * ep) * (s12 - sm);                                        // r dE/dr
+    const float i4 = ir2 * ir2;
+    const float i6 = i4 * ir2;
+    const float i12 = i6 * i6;
+    const float im = hb ? i6 * i4 : i6;
+    const float t12 = A * i12;
+    const float tm = B * im;
+    float elj = t12 + tm;
+    float dlj = -12.f * t12 + (hb ? -10.f : -6.f) * tm;                       // r dE/dr
     const bool capped = elj > kCap;
     elj = capped ? kCap : elj;
     dlj = capped ? 0.f : dlj;
+    // Mehler-Solmajer dielectric eps(r) = A' + B' / (1 + K exp(-lambda B' r))
     const float ex = __builtin_amdgcn_exp2f(-kDielLB * kLog2e * r);
     const float iden = __builtin_amdgcn_rcpf(1.f + kDielK * ex);
     const float epsr = kDielA + kDielB * iden;
-    const float depsr = kDielBKLB * ex * iden * iden;
+    const float depsr = kDielBKLB * ex * iden * iden;                          // d eps / dr
     const float ired = __builtin_amdgcn_rcpf(r * epsr);
     const float eel = qq * ired;
-    const float del = -qq * (epsr + r * depsr) * (r * ired) * ired;             // r dE/dr
+    const float del = -eel * ((r2 * ired) * depsr + 1.f);                     // r dE/dr
     const float eds = ds * __builtin_amdgcn_exp2f(-kDsInv2S2 * kLog2e * r2);
     const float dds = -eds * r2 * kDsInvS2;                                     // r dE/dr
-    e = mask_f(elj + eel + eds, live);
-    w = mask_f((dlj + del + dds) * ir2, slope);
+    e = live ? elj + eel + eds : 0.f;
+    w = slope ? (dlj + del + dds) * ir2 : 0.f;
 }
 
 // ---------------------------------------------------------------------------
@@ -434,7 +456,7 @@ __device__ __forceinline__ void pair_term(float dx, float dy, float dz, float r0
 // atom positions in LDS; the caller adds its force to the two slots.
 // ---------------------------------------------------------------------------
 struct PairForce {
-    float fx, fy, fz, e;
+    float w, dx, dy, dz, e;         // force on atom j is w * d, on atom i -w * d
     int si, sj;                     // byte offsets of the two accumulator slots
 };
 
@@ -462,9 +484,10 @@ __device__ __forceinline__ PairForce pair_force(u32x4 pr, float4 pi, float4 pj, 
     pair_term(dx, dy, dz, __uint_as_float(pr.y), __uint_as_float(pr.z), hb, qq,
               __uint_as_float(pr.w), valid, e, w);
     o.e = e;
-    o.fx = w * dx;
-    o.fy = w * dy;
-    o.fz = w * dz;
+    o.w = w;
+    o.dx = dx;
+    o.dy = dy;
+    o.dz = dz;
     o.si = mad24(ci, N16, i << 4);
     o.sj = mad24(cj, N16, j << 4);
     return o;
@@ -477,13 +500,13 @@ __device__ __forceinline__ float4* slot(Smem<SLOTS>& sm, int byte_offset) {
         __builtin_assume_aligned(reinterpret_cast<char*>(sm.u.acc) + byte_offset, 16));
 }
 
-// Adds -f to slot si and +f to slot sj, from their values read earlier.
+// Adds -w d to slot si and +w d to slot sj, from their values read earlier.
 template <int SLOTS>
 __device__ __forceinline__ void store_force(Smem<SLOTS>& sm, const PairForce& f, float4 ai, float4 aj) {
     float4* pi = slot(sm, f.si);
     float4* pj = slot(sm, f.sj);
-    pi->x = ai.x - f.fx; pi->y = ai.y - f.fy; pi->z = ai.z - f.fz;
-    pj->x = aj.x + f.fx; pj->y = aj.y + f.fy; pj->z = aj.z + f.fz;
+    pi->x = fmaf(-f.w, f.dx, ai.x); pi->y = fmaf(-f.w, f.dy, ai.y); pi->z = fmaf(-f.w, f.dz, ai.z);
+    pj->x = fmaf(f.w, f.dx, aj.x); pj->y = fmaf(f.w, f.dy, aj.y); pj->z = fmaf(f.w, f.dz, aj.z);
 }
 
 // ---------------------------------------------------------------------------
@@ -548,14 +571,22 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
     for (int s = 0; s < SLOTS; ++s) {
         const int a = lane + kWave * s;
         float y0 = L.y0[s][0], y1 = L.y0[s][1], y2 = L.y0[s][2];
+        // one LDS round trip per level: the next level's torsion index is
+        // read together with this level's transform
         const int8_t* ch = sm.chain[L.frag[s]];
-        for (int j = ch[0]; j >= 1; --j) {
-            const float4* T = reinterpret_cast<const float4*>(sm.u.tk[(int)ch[j]]);
+        int j = ch[0];
+        int k = ch[j > 0 ? j : 0];
+        for (; j >= 1; --j) {
+            const int kn = ch[j - 1];  // ch[0] (the length) at the last level, unused
+            const float4* T = reinterpret_cast<const float4*>(__builtin_assume_aligned(
+                reinterpret_cast<const char*>(sm.u.tk) + __umul24((unsigned)k, 48u), 16));
             const float4 r0 = T[0], r1 = T[1], r2 = T[2];
             const float z0 = r0.x * y0 + r0.y * y1 + r0.z * y2 + r0.w;
             const float z1 = r1.x * y0 + r1.y * y1 + r1.z * y2 + r1.w;
             const float z2 = r2.x * y0 + r2.y * y1 + r2.z * y2 + r2.w;
             y0 = z0; y1 = z1; y2 = z2;
+            asm volatile("" ::"v"(kn));  // keeps the index load in this level
+            k = kn;
         }
 #pragma unroll
         for (int r = 0; r < 3; ++r) x[s][r] = Rq[3 * r] * y0 + Rq[3 * r + 1] * y1 + Rq[3 * r + 2] * y2;
@@ -563,22 +594,9 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
     }
     __syncthreads();
 
-    // grid term
     float g[SLOTS][3];
     float e_lane = 0.f;
-    float e_atom[SLOTS];
-#pragma unroll
-    for (int s = 0; s < SLOTS; ++s) {
-        const int a = lane + kWave * s;
-        float e, gx, gy, gz;
-        grid_term(G, L.cls[s], L.chg[s][1], L.chg[s][2], x[s], tv, e, gx, gy, gz);
-        const bool ok = a < N;
-        e_atom[s] = ok ? e : 0.f;
-        g[s][0] = ok ? gx : 0.f;
-        g[s][1] = ok ? gy : 0.f;
-        g[s][2] = ok ? gz : 0.f;
-        e_lane += e_atom[s];
-    }
+    GridTaps tap[SLOTS];
 
     // pair terms: batches of 64 listed pairs, one per lane. Each lane adds
     // its pair's force to both atoms' accumulator slots; the host schedule
@@ -604,12 +622,21 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
         // order: batch k's stores precede batch k + 1's loads). Prefetch
         // indices are clamped to the last batch, so loads need no guard.
         if (nb > 0) {
-            auto record = [&](int b) -> u32x4 { return plist[min(b, nb - 1) * kWave + lane]; };
+            auto record = [&](int b) -> u32x4 {  // uniform row address, lane offset
+                const auto row = plist + uniform(min(b, nb - 1)) * kWave;
+                return row[lane];
+            };
             u32x4 R[4];
             float4 Pi[2], Pj[2], Ai[2], Aj[2];
             PairForce F[2];
 #pragma unroll
             for (int q = 0; q < 4; ++q) R[q] = record(q);
+            // the grid-map loads go after the records (global loads complete
+            // in order) and are consumed after the pair phase
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) grid_load(G, L.cls[s], x[s], tv, tap[s]);
+            __builtin_amdgcn_sched_barrier(0);
             Pi[0] = sm.dyn[R[0].x & 127];
             Pj[0] = sm.dyn[(R[0].x >> 7) & 127];
             F[0] = pair_force(R[0], Pi[0], Pj[0], N16);
@@ -650,12 +677,16 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
                 store_force(sm, F[0], Ai[0], Aj[0]);
                 e_lane += F[0].e;
             }
+        } else {
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) grid_load(G, L.cls[s], x[s], tv, tap[s]);
         }
         __syncthreads();
         // each atom adds its copies in copy order
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
             const int a = lane + kWave * s;
+            g[s][0] = g[s][1] = g[s][2] = 0.f;
             if (a < N) {
                 for (int c = 0; c < L.n_copies; ++c) {
                     const float4 v = sm.u.acc[c * N + a];
@@ -665,6 +696,20 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
                 }
             }
         }
+    }
+    // grid term, from the corner values loaded before the pair phase
+    float e_atom[SLOTS];
+#pragma unroll
+    for (int s = 0; s < SLOTS; ++s) {
+        const int a = lane + kWave * s;
+        float e, gx, gy, gz;
+        grid_term(G, tap[s], L.chg[s][1], L.chg[s][2], x[s], tv, e, gx, gy, gz);
+        const bool ok = a < N;
+        e_atom[s] = ok ? e : 0.f;
+        g[s][0] += ok ? gx : 0.f;
+        g[s][1] += ok ? gy : 0.f;
+        g[s][2] += ok ? gz : 0.f;
+        e_lane += e_atom[s];
     }
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s)

@@ -297,18 +297,23 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
             PairRec& o = pl[b * kBatch + k];
             o.rec = r;
             if (!(r & kRecValid)) {
-                o.r0 = o.eps = o.ds = 0.f;
+                o.c12 = o.cm = o.ds = 0.f;
                 continue;
             }
             const int i = order[r & 127], j = order[(r >> 7) & 127];
             const int ci = d.cls[i], cj = d.cls[j];
+            // A / r^12 + B / r^m: 12-10 (5, -6) eps r0^(12, 10) from the
+            // donor-acceptor table, else 12-6 (1, -2) eps r0^(12, 6)
             if ((r >> 22) & 1u) {
                 const int t = (r >> 23) & 3;
-                o.r0 = (float)ff.hb_r0[t >> 1][t & 1];
-                o.eps = (float)ff.hb_eps[t >> 1][t & 1];
+                const double r0 = ff.hb_r0[t >> 1][t & 1], eps = ff.hb_eps[t >> 1][t & 1];
+                o.c12 = (float)(5.0 * eps * std::pow(r0, 12));
+                o.cm = (float)(-6.0 * eps * std::pow(r0, 10));
             } else {
-                o.r0 = (float)(ff.radius[ci] + ff.radius[cj]);
-                o.eps = (float)std::sqrt(ff.eps[ci] * ff.eps[cj]);
+                const double r0 = ff.radius[ci] + ff.radius[cj];
+                const double eps = std::sqrt(ff.eps[ci] * ff.eps[cj]);
+                o.c12 = (float)(eps * std::pow(r0, 12));
+                o.cm = (float)(-2.0 * eps * std::pow(r0, 6));
             }
             o.ds = (float)(solv(i) * ff.vol[cj] + solv(j) * ff.vol[ci]);
         }

@@ -27,7 +27,8 @@ constexpr int32_t kMagic = 0x444f434b;  // "DOCK"
 constexpr int kMaxAtoms = 128;
 constexpr int kMaxTorsions = 32;
 constexpr int kMaxFrag = kMaxTorsions + 1;
-constexpr int kChainStride = kMaxTorsions + 1;  // [0] = length, [1..] torsion ids root first
+constexpr int kChainStride = kMaxTorsions;      // torsion ids innermost first, padded with
+constexpr int kIdentity = kMaxTorsions;          // kIdentity (the identity transform)
 constexpr int kBatch = 64;
 constexpr int kMaxSlots = 384;                   // n_copies * n_atoms <= kMaxSlots
 constexpr int kMaxSlotsSmall = 256;              // the same bound for ligands of <= 64 atoms
@@ -61,7 +62,7 @@ struct Header {
     int32_t off_chg;        // float4[N]  332.06363 q, q, |q|, 0
     int32_t off_int;        // int4[N]    class, fragment, original index, 0
     int32_t off_tors;       // Torsion[T]
-    int32_t off_chain;      // int8[n_frag][kChainStride]
+    int32_t off_chain;      // uint8[n_frag][kChainStride] enclosing torsions, innermost first
     int32_t off_plist;      // PairRec[n_batches][kBatch]
     int32_t pad[15];
 };

@@ -249,19 +249,21 @@ struct __align__(16) Smem {
     static constexpr int kSlots = SLOTS == 1 ? dockblob::kMaxSlotsSmall : dockblob::kMaxSlots;
     float4 dyn[kAtoms];             // x, y, z relative to t, and sqrt(kElec) q (depth-first order)
     union {
-        float tk[kMaxTors][12];     // torsion transforms, 3x4 row-major; live until the
-                                    // atom positions are written
+        float tk[kMaxTors + 1][12]; // torsion transforms, 3x4 row-major, and the identity
+                                    // (index kMaxTors); live until the atom positions are
+                                    // written
         float4 acc[kSlots];         // pair-force accumulators, slot = copy * N + atom
     } u;
     float4 tor[kMaxTors][2];        // torsion k: axis point p and packed positions
                                     // (a | b << 8 | first << 16 | end << 24), unit axis u
-    int8_t chain[kMaxFrag][kChain]; // [0] = length, then torsions root first
+    uint32_t chain[kMaxFrag][kChain / 4];  // per fragment: enclosing torsions, innermost
+                                           // first, 4 per word, padded with the identity
 };
 
 template <int SLOTS>
 struct Lig {
     // uniform
-    int N, T, NF, G, n_batches, n_copies;
+    int N, T, NF, G, n_batches, n_copies, max_depth;
     const u32x4* plist;             // pair records (dockblob::PairRec), n_batches x 64
     // per lane, per slot: atom a = lane + 64 * slot
     float y0[SLOTS][3];
@@ -283,6 +285,7 @@ __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem<SLOTS>& sm, L
     L.G = uniform(h->n_genes);
     L.n_batches = uniform(h->n_batches);
     L.n_copies = uniform(h->n_copies);
+    L.max_depth = uniform(h->max_depth);
     L.plist = uniform_ptr(reinterpret_cast<const u32x4*>(blob + h->off_plist));
     const float4* ref = reinterpret_cast<const float4*>(blob + h->off_ref);
     const float4* chg = reinterpret_cast<const float4*>(blob + h->off_chg);
@@ -307,11 +310,11 @@ __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem<SLOTS>& sm, L
         sm.tor[lane][0] = make_float4(t.p[0], t.p[1], t.p[2], __int_as_float(pk));
         sm.tor[lane][1] = make_float4(t.u[0], t.u[1], t.u[2], 0.f);
     }
-    const int8_t* ch = reinterpret_cast<const int8_t*>(blob + h->off_chain);
-    const int n_chain_bytes = L.NF * kChain;
-    int8_t* dst = &sm.chain[0][0];
+    const uint32_t* ch = reinterpret_cast<const uint32_t*>(blob + h->off_chain);
+    const int n_chain_words = L.NF * (kChain / 4);
+    uint32_t* dst = &sm.chain[0][0];
     if (fill_lds)
-        for (int i = lane; i < n_chain_bytes; i += kWave) dst[i] = ch[i];
+        for (int i = lane; i < n_chain_words; i += kWave) dst[i] = ch[i];
     __syncthreads();
 }
 
@@ -437,18 +440,19 @@ __device__ __forceinline__ void pair_term(float dx, float dy, float dz, float A,
     const bool capped = elj > kCap;
     elj = capped ? kCap : elj;
     dlj = capped ? 0.f : dlj;
-    // Mehler-Solmajer dielectric eps(r) = A' + B' / (1 + K exp(-lambda B' r))
+    // Mehler-Solmajer dielectric eps(r) = A' + B' / (1 + K exp(-lambda B' r)),
+    // d eps / dr = lambda B'^2 K exp(-lambda B' r) / (1 + K exp(...))^2
     const float ex = __builtin_amdgcn_exp2f(-kDielLB * kLog2e * r);
     const float iden = __builtin_amdgcn_rcpf(1.f + kDielK * ex);
     const float epsr = kDielA + kDielB * iden;
-    const float depsr = kDielBKLB * ex * iden * iden;                          // d eps / dr
     const float ired = __builtin_amdgcn_rcpf(r * epsr);
     const float eel = qq * ired;
-    const float del = -eel * ((r2 * ired) * depsr + 1.f);                     // r dE/dr
+    // r dE/dr = -E (1 + r eps' / eps), and r / eps = r^2 / (r eps)
+    const float del = -eel * fmaf(((r2 * ired) * (ex * iden)) * iden, kDielBKLB, 1.f);
+    // desolvation ds exp(-r^2 / (2 sigma^2)), r dE/dr = -E r^2 / sigma^2
     const float eds = ds * __builtin_amdgcn_exp2f(-kDsInv2S2 * kLog2e * r2);
-    const float dds = -eds * r2 * kDsInvS2;                                     // r dE/dr
     e = live ? elj + eel + eds : 0.f;
-    w = slope ? (dlj + del + dds) * ir2 : 0.f;
+    w = slope ? fmaf(eds, r2 * -kDsInvS2, dlj + del) * ir2 : 0.f;
 }
 
 // ---------------------------------------------------------------------------
@@ -557,6 +561,11 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
             o[4 * r + 2] = Rk[3 * r + 2];
             o[4 * r + 3] = tp[r] - (Rk[3 * r] * tp[0] + Rk[3 * r + 1] * tp[1] + Rk[3 * r + 2] * tp[2]);
         }
+    } else if (lane == kMaxTors) {
+        float4* o = reinterpret_cast<float4*>(sm.u.tk[kMaxTors]);
+        o[0] = make_float4(1.f, 0.f, 0.f, 0.f);
+        o[1] = make_float4(0.f, 1.f, 0.f, 0.f);
+        o[2] = make_float4(0.f, 0.f, 1.f, 0.f);
     }
     __syncthreads();
     // atom positions relative to the rotation centre: the torsions enclosing
@@ -566,27 +575,36 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
     // separations, torques and torsion axes are translation invariant and
     // keep the precision of the small local coordinates.
     const float tv[3] = {tx, ty, tz};
+    const int n_chunks = (L.max_depth + 3) >> 2;
     float x[SLOTS][3];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int a = lane + kWave * s;
         float y0 = L.y0[s][0], y1 = L.y0[s][1], y2 = L.y0[s][2];
-        // one LDS round trip per level: the next level's torsion index is
-        // read together with this level's transform
-        const int8_t* ch = sm.chain[L.frag[s]];
-        int j = ch[0];
-        int k = ch[j > 0 ? j : 0];
-        for (; j >= 1; --j) {
-            const int kn = ch[j - 1];  // ch[0] (the length) at the last level, unused
-            const float4* T = reinterpret_cast<const float4*>(__builtin_assume_aligned(
-                reinterpret_cast<const char*>(sm.u.tk) + __umul24((unsigned)k, 48u), 16));
-            const float4 r0 = T[0], r1 = T[1], r2 = T[2];
-            const float z0 = r0.x * y0 + r0.y * y1 + r0.z * y2 + r0.w;
-            const float z1 = r1.x * y0 + r1.y * y1 + r1.z * y2 + r1.w;
-            const float z2 = r2.x * y0 + r2.y * y1 + r2.z * y2 + r2.w;
-            y0 = z0; y1 = z1; y2 = z2;
-            asm volatile("" ::"v"(kn));  // keeps the index load in this level
-            k = kn;
+        // one word of torsion indices per four levels, then the rows of two
+        // levels per LDS round trip; levels past the atom's depth apply the
+        // identity, so every lane takes the same (uniform) number of chunks
+        const uint32_t* row = sm.chain[L.frag[s]];
+        for (int c = 0; c < n_chunks; ++c) {
+            const uint32_t w = row[c];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                float4 T[2][3];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const unsigned k = (w >> (16 * h + 8 * q)) & 255u;
+                    const float4* t = reinterpret_cast<const float4*>(__builtin_assume_aligned(
+                        reinterpret_cast<const char*>(sm.u.tk) + __umul24(k, 48u), 16));
+                    T[q][0] = t[0]; T[q][1] = t[1]; T[q][2] = t[2];
+                }
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const float z0 = T[q][0].x * y0 + T[q][0].y * y1 + T[q][0].z * y2 + T[q][0].w;
+                    const float z1 = T[q][1].x * y0 + T[q][1].y * y1 + T[q][1].z * y2 + T[q][1].w;
+                    const float z2 = T[q][2].x * y0 + T[q][2].y * y1 + T[q][2].z * y2 + T[q][2].w;
+                    y0 = z0; y1 = z1; y2 = z2;
+                }
+            }
         }
 #pragma unroll
         for (int r = 0; r < 3; ++r) x[s][r] = Rq[3 * r] * y0 + Rq[3 * r + 1] * y1 + Rq[3 * r + 2] * y2;

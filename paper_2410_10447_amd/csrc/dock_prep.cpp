@@ -317,11 +317,14 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
             }
             o.ds = (float)(solv(i) * ff.vol[cj] + solv(j) * ff.vol[ci]);
         }
-    int8_t* ch = reinterpret_cast<int8_t*>(blob.data() + h.off_chain);
-    for (int f = 0; f < NF; ++f) {
-        ch[f * kChainStride] = (int8_t)chain[f].size();
-        for (size_t j = 0; j < chain[f].size(); ++j) ch[f * kChainStride + 1 + j] = (int8_t)chain[f][j];
-    }
+    // fragment f: the torsions that enclose it, innermost first (the order
+    // they are applied in), padded with the identity transform
+    uint8_t* ch = blob.data() + h.off_chain;
+    for (int f = 0; f < NF; ++f)
+        for (int j = 0; j < kChainStride; ++j) {
+            const int n = (int)chain[f].size();
+            ch[f * kChainStride + j] = (uint8_t)(j < n ? chain[f][n - 1 - j] : kIdentity);
+        }
 
     P.n_atoms = N;
     P.n_torsions = T;

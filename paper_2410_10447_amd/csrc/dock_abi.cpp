@@ -418,17 +418,26 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
     // the table, each launch with its own work counter), side by side: the
     // one-slot launch runs on the library's side stream, so that its waves
     // fill the chip as the longer two-slot launch drains.
-    struct Part { int first, count, mode; };
+    // Each launch runs the kernel specialised for its items' variant when
+    // they share one (e.g. a tuning table that picks one variant per layout),
+    // else the one that dispatches per item.
+    struct Part { int first, count, mode, variant; };
     std::vector<Part> parts;
     const int n_dev = (int)tab_count;
+    auto part_variant = [&](int first, int count) {
+        int v = -2;
+        for (int i = first; i < first + count; ++i) v = (v == -2 || v == tab[i].variant) ? tab[i].variant : -1;
+        return v < 0 ? -1 : v;
+    };
     if (split_layouts) {
         int n2 = 0;
         for (int i = 0; i < n_dev; ++i) n2 += tab[i].slots == 2;
-        parts.push_back({0, n2, docklaunch::kSlots2});
-        parts.push_back({n2, n_dev - n2, docklaunch::kSlots1});
+        parts.push_back({0, n2, docklaunch::kSlots2, part_variant(0, n2)});
+        parts.push_back({n2, n_dev - n2, docklaunch::kSlots1, part_variant(n2, n_dev - n2)});
     } else {
         parts.push_back({0, n_dev, (any1 && any2) ? docklaunch::kSlotsAny
-                                                  : (any2 ? docklaunch::kSlots2 : docklaunch::kSlots1)});
+                                                  : (any2 ? docklaunch::kSlots2 : docklaunch::kSlots1),
+                         var_uniform});
     }
     // counters (one 32-bit word per part in the header) start at 0: they are
     // part of the copy
@@ -452,7 +461,7 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
         if (pt.count == 0) continue;
         int64_t units = 0;
         for (int i = pt.first; i < pt.first + pt.count; ++i) units += tab[i].n;
-        int per_cu = docklaunch::ls_blocks_per_cu(pt.mode, var_uniform);
+        int per_cu = docklaunch::ls_blocks_per_cu(pt.mode, pt.variant);
         if (per_cu <= 0) per_cu = 8;
         const int64_t resident = (int64_t)per_cu * n_cu;
         const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(units, resident));
@@ -465,7 +474,7 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
         p.rho = o->rho;
         p.eps = o->eps;
         hipStream_t s_k = k == 0 ? (hipStream_t)stream : side->stream;
-        launch_err = docklaunch::launch_ls(p, pt.mode, var_uniform, grid, s_k);
+        launch_err = docklaunch::launch_ls(p, pt.mode, pt.variant, grid, s_k);
         if (launch_err != hipSuccess) break;
     }
     if (side) {  // joined also after a failed launch

@@ -129,32 +129,38 @@ def uneven_run(steps, warmup, use_table=True):
 
 
 def serving_run(seconds, rate, seed=4000, chunk_iters=25, max_individuals=120_000,
-                budget_bytes=8 << 30, variant=0):
+                budget_bytes=8 << 30, variant=0, use_table=True):
     """Poisson arrivals of docking jobs (ligands of the uneven-batch size
     distribution, 50 runs x 150 individuals, 300 iterations) against four
-    resident receptor grid sets; continuous batching across jobs."""
+    resident receptor grid sets; continuous batching across jobs, each job
+    with its size bucket's tuned reduction variant. A job's starting points
+    are drawn when it is admitted."""
     import torch
     from paper_2410_10447_amd import serve, synth
     rng = np.random.default_rng(seed)
     shapes = [(64, 10), (80, 10), (88, 12), (96, 12)]
     grid_sets = [synth.grids(n, m, seed + 1 + k) for k, (n, m) in enumerate(shapes)]
     pool = synth.uneven_workload(n_ligands=64, per_ligand=1, grid_n=8).ligands
-    ex = serve.GpuExecutor(grid_sets, synth.force_field(), variant=variant)
+    ex = serve.GpuExecutor(grid_sets, synth.force_field(), variant=variant, use_table=use_table)
     arrivals = serve.poisson_arrivals(rate, seconds, seed + 7)
     specs = []
     for k, t in enumerate(arrivals):
         lig = pool[int(rng.integers(len(pool)))]
         gid = int(rng.integers(len(grid_sets)))
-        gen = synth.genotypes(lig, grid_sets[gid], 7500, seed + 100 + k)
-        specs.append(serve.JobSpec(job_id=k, ligand=lig, grid_id=gid, genotypes=gen, arrival=t,
-                                   iterations=300))
+        draw = (lambda lig=lig, g=grid_sets[gid], s=seed + 100 + k: synth.genotypes(lig, g, 7500, s))
+        specs.append(serve.JobSpec(job_id=k, ligand=lig, grid_id=gid, genotypes=draw, arrival=t,
+                                   iterations=300, n=7500))
     torch.cuda.synchronize()
     srv = serve.Server(ex, max_individuals=max_individuals, device_budget=budget_bytes,
                        chunk_iters=chunk_iters)
-    st = srv.run(specs)
+
+    def report(now, st):
+        print(f"[serving] t={now:.0f}s completed={len(st.completed)} evals={st.evals:.3e} "
+              f"chunks={st.chunks}", file=sys.stderr, flush=True)
+    st = srv.run(specs, progress=report, progress_every=30.0)
     out = st.summary()
     out.update({"rate_jobs_per_s": rate, "arrival_window_s": seconds, "chunk_iters": chunk_iters,
-                "max_inflight_individuals": max_individuals,
+                "max_inflight_individuals": max_individuals, "variants_from_table": use_table,
                 "resident_grid_bytes": ex.grid_bytes,
                 "offered_evals_per_s": rate * 7500 * 301})
     return out

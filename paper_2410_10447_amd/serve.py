@@ -40,9 +40,18 @@ class JobSpec:
     job_id: int
     ligand: object            # synth.Ligand (or any object with the ligand fields)
     grid_id: int
-    genotypes: np.ndarray     # float32 [n, 7 + T] starting points
+    genotypes: object         # float32 [n, 7 + T] starting points, or a function that
+                              # returns them when the job is admitted (then `n` is set)
     arrival: float            # seconds, on the server clock
     iterations: int = 300
+    n: int = 0                # individuals, when `genotypes` is a function
+
+    @property
+    def count(self) -> int:
+        return self.n if callable(self.genotypes) else int(self.genotypes.shape[0])
+
+    def starting_points(self) -> np.ndarray:
+        return self.genotypes() if callable(self.genotypes) else self.genotypes
 
 
 @dataclass
@@ -124,7 +133,7 @@ class Server:
     def submit(self, spec: JobSpec):
         rec = JobRecord(spec)
         rec.footprint = self.ex.footprint(spec)
-        if spec.genotypes.shape[0] > self.max_individuals or rec.footprint > self.budget:
+        if spec.count > self.max_individuals or rec.footprint > self.budget:
             raise ValueError(f"job {spec.job_id} can never fit the budgets")
         self.queue.append(rec)
         self.stats.max_queue = max(self.stats.max_queue, len(self.queue))
@@ -132,7 +141,7 @@ class Server:
     def _admit(self, now):
         while self.queue:
             rec = self.queue[0]
-            n = rec.spec.genotypes.shape[0]
+            n = rec.spec.count
             if self.used_individuals + n > self.max_individuals or \
                     self.used_bytes + rec.footprint > self.budget:
                 break
@@ -179,7 +188,7 @@ class Server:
         rec.done = self.clock() - self._t0
         if rec in self.inflight:
             self.inflight.remove(rec)
-            self.used_individuals -= rec.spec.genotypes.shape[0]
+            self.used_individuals -= rec.spec.count
             self.used_bytes -= rec.footprint
             try:
                 self.ex.release(rec.handle)
@@ -203,7 +212,7 @@ class Server:
                 if rec not in self.inflight:
                     continue
                 rec.iters_done += k
-                n = rec.spec.genotypes.shape[0]
+                n = rec.spec.count
                 self.stats.evals += n * (k + (1 if final else 0))
                 if final:
                     rec.done = now
@@ -221,15 +230,21 @@ class Server:
         self._occ_t = now
 
     # -- driver ----------------------------------------------------------
-    def run(self, specs, poll: float = 2e-4, until_empty: bool = True, horizon: float = math.inf):
-        """Serve `specs` (arrival times relative to the start of run)."""
+    def run(self, specs, poll: float = 2e-4, until_empty: bool = True, horizon: float = math.inf,
+            progress=None, progress_every: float = 30.0):
+        """Serve `specs` (arrival times relative to the start of run).
+        `progress(now, stats)` is called every `progress_every` seconds."""
         arrivals = sorted(specs, key=lambda s: s.arrival)
         i = 0
         t0 = self.clock()
         self._t0 = t0
         self._occ_t = 0.0
+        next_report = progress_every
         while True:
             now = self.clock() - t0
+            if progress is not None and now >= next_report:
+                progress(now, self.stats)
+                next_report += progress_every
             while i < len(arrivals) and arrivals[i].arrival <= now and arrivals[i].arrival <= horizon:
                 self.submit(arrivals[i])
                 i += 1
@@ -275,13 +290,14 @@ def poisson_arrivals(rate: float, duration: float, seed: int):
 class GpuExecutor:
     """Runs chunks through the C ABI on one stream; grid sets stay resident."""
 
-    def __init__(self, grid_sets, ff, variant: int = 0, device="cuda"):
+    def __init__(self, grid_sets, ff, variant: int = 0, device="cuda", use_table: bool = False):
         import torch
         from . import dock
         self.dock = dock
         self.torch = torch
         self.device = device
         self.variant = variant
+        self.use_table = use_table   # each job takes its size bucket's tuned variant
         self.ff = ff
         self.grids = [dock.Grids.from_synth(g, device) for g in grid_sets]
         self.grid_bytes = sum(g.nbytes() for g in self.grids)
@@ -293,20 +309,25 @@ class GpuExecutor:
 
     def footprint(self, spec):
         G = 7 + int(len(spec.ligand.rot_bonds))
-        return state_bytes(spec.genotypes.shape[0], G) + 8192
+        return state_bytes(spec.count, G) + 8192
 
     def prepare(self, spec):
         torch = self.torch
         L = self.dock.Ligand(spec.ligand, self.ff, device=self.device, upload=False)
         L.upload(self.device, stream=self.stream)
-        host = torch.from_numpy(np.ascontiguousarray(spec.genotypes)).pin_memory()
+        host = torch.from_numpy(np.ascontiguousarray(spec.starting_points())).pin_memory()
         with torch.cuda.stream(self.stream):
             gen = host.to(self.device, non_blocking=True)
             st = self.dock.LSState.start(gen)
-        return {"ligand": L, "state": st, "grids": self.grids[spec.grid_id], "host": host}
+        var = -1
+        if self.use_table:
+            from . import autotune
+            var = int(autotune.choose(L.n_atoms, L.n_torsions)["variant"])
+        return {"ligand": L, "state": st, "grids": self.grids[spec.grid_id], "host": host,
+                "variant": var}
 
     def launch(self, plan, max_iters):
-        jobs = [self.dock.LsJob(h["grids"], h["ligand"], h["state"], -1, k, 1 if fin else 0)
+        jobs = [self.dock.LsJob(h["grids"], h["ligand"], h["state"], h["variant"], k, 1 if fin else 0)
                 for h, k, fin in plan]
         need = self.dock.workspace_bytes(len(jobs))
         # a workspace per in-flight chunk: reuse one whose chunk has completed
@@ -366,7 +387,7 @@ class FakeExecutor:
         return self.t
 
     def footprint(self, spec):
-        return state_bytes(spec.genotypes.shape[0], spec.genotypes.shape[1])
+        return state_bytes(spec.count, spec.starting_points().shape[1])
 
     def prepare(self, spec):
         h = {"spec": spec, "iters": 0, "final": False}
@@ -381,7 +402,7 @@ class FakeExecutor:
             assert not h["final"], "job launched after its final evaluation"
             h["iters"] += k
             h["final"] = fin
-            evals += h["spec"].genotypes.shape[0] * (k + (1 if fin else 0))
+            evals += h["spec"].count * (k + (1 if fin else 0))
         start = max(self.t, self.busy_until)
         self.busy_until = start + evals * self.sec_per_eval
         self.launched.append([(h["spec"].job_id, k, fin) for h, k, fin in plan])
@@ -402,7 +423,7 @@ class FakeExecutor:
         spec = handle["spec"]
         rng = np.random.default_rng(spec.job_id)
         return {"iters": handle["iters"], "final": handle["final"],
-                "value": float(rng.normal()) + float(spec.genotypes.sum())}
+                "value": float(rng.normal()) + float(spec.starting_points().sum())}
 
     def release(self, handle):
         self.live.pop(handle["spec"].job_id, None)

@@ -10,9 +10,12 @@ resident copy of the state per step, prepared before timing).
 
 Prints one JSON line with the throughput of the best reduction variant, the
 per-variant throughputs (the plain wave-shuffle variant is the baseline), the
-roofline object of the local-search kernel, a serving run (Poisson arrivals of
-docking jobs, continuous batching, p50/p99 job latency) and the FP64 oracle
-timed on the host on a bounded sample.
+roofline object of the local-search kernel, the uneven 64-ligand batch, a
+serving run (Poisson arrivals of docking jobs, continuous batching, p50/p99
+job latency), the scoring throughput (one evaluation per genotype), the
+isolated block reduction per variant and block size against the
+shuffle + shared-atomic baseline, and the FP64 oracle timed on the host on a
+bounded sample (one process, and a pool over the usable cores).
 """
 from __future__ import annotations
 
@@ -81,18 +84,118 @@ def flops_per_eval(n_pairs, n_atoms, n_torsions):
             + FLOPS_GENE * (7 + n_torsions))
 
 
-def cpu_baseline(w, sample, iterations):
-    """The FP64 oracle (unchanged) on `sample` individuals, full iterations."""
+def _oracle_ls_worker(args):
+    """One pool worker: the oracle's local search on a slice of individuals."""
+    lo, hi, iterations = args
+    from oracle import dock_ref as R
+    from paper_2410_10447_amd import synth
+    w = synth.ls_workload(3000, iterations)
+    prep = R.prepare(w.ligands[0], w.ff)
+    st = R.ls_init(w.genotypes[0][lo:hi])
+    t0 = time.perf_counter()
+    R.local_search(prep, w.grids, st, iterations, rho=w.rho, eps=w.eps)
+    return time.perf_counter() - t0
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, sample, iterations, pool_per_worker=None):
+    """The FP64 oracle (unchanged) on a bounded sample at full iteration
+    count: one process, then a process pool over the usable cores (one
+    NumPy thread each). Runs before the GPU is touched (the pool forks)."""
+    import multiprocessing as mp
     from oracle import dock_ref as R
     prep = R.prepare(w.ligands[0], w.ff)
     st = R.ls_init(w.genotypes[0][:sample])
     t0 = time.perf_counter()
     R.local_search(prep, w.grids, st, iterations, rho=w.rho, eps=w.eps)
-    dt = time.perf_counter() - t0
-    evals = sample * (iterations + 1)
-    return {"value": evals / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
-            "sample": f"{sample} of 3000 individuals x {iterations + 1} evaluations "
-                      f"({evals} evals, {dt:.1f} s, NumPy FP64 single process)"}
+    dt1 = time.perf_counter() - t0
+    evals1 = sample * (iterations + 1)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    workers = max(1, min(cores, 16))
+    pool_per_worker = pool_per_worker or sample    # the oracle vectorises over individuals
+    n_pool = workers * pool_per_worker
+    os.environ["OMP_NUM_THREADS"] = "1"
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(workers) as pool:
+        pool.map(_oracle_ls_worker, [(k * pool_per_worker, (k + 1) * pool_per_worker, iterations)
+                                     for k in range(workers)])
+    dtp = time.perf_counter() - t0
+    evalsp = n_pool * (iterations + 1)
+    return {"value": evalsp / dtp, "unit": "evals/s", "cores": workers, "kind": "oracle",
+            "sample": f"{n_pool} of 3000 individuals x {iterations + 1} evaluations over "
+                      f"{workers} processes ({evalsp} evals, {dtp:.1f} s wall incl. start-up, "
+                      "NumPy FP64, one thread each)",
+            "single_process": {"value": evals1 / dt1, "cores": 1,
+                               "sample": f"{sample} individuals, {evals1} evals, {dt1:.1f} s"},
+            "host": {"cpu_model": _cpu_model(), "cpu_count": os.cpu_count(), "usable_cores": cores}}
+
+
+def reduction_run(threads_list=(64, 128, 256, 512, 1024), variants=(5, 0, 1, 2, 3, 4),
+                  n_blocks=2048, repeat=1000, reps=3):
+    """The isolated block reduction (one float4 per thread, every thread gets
+    the block total; `repeat` dependent reductions per launch) per variant and
+    block size, with the speedup over the shuffle + shared-atomic baseline
+    (variant 5, three barriers per component)."""
+    import torch
+    from paper_2410_10447_amd import dock
+    out = {"n_blocks": n_blocks, "repeat": repeat, "unit": "ns per block reduction"}
+    for th in threads_list:
+        x = torch.randn(n_blocks, th, 4, device="cuda")
+        row = {}
+        for v in variants:
+            dock.block_sum4(x, v, repeat)
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                dock.block_sum4(x, v, repeat)
+                b.record()
+                b.synchronize()
+                times.append(a.elapsed_time(b))
+            ms = float(np.median(times))
+            row[dock.VARIANT_NAMES.get(v, str(v))] = round(ms * 1e6 / (n_blocks * repeat), 3)
+        base = row[dock.VARIANT_NAMES.get(5, "5")]
+        row["speedup_vs_baseline"] = {k: round(base / t, 2) for k, t in row.items() if t > 0}
+        out[f"b{th}"] = row
+        del x
+    return out
+
+
+def score_run(n=65536, reps=5):
+    """Scoring throughput: one evaluation per genotype (energy and gradient),
+    the 24-atom, 6-torsion ligand on 40^3 x 10 maps, n genotypes per call."""
+    import torch
+    from paper_2410_10447_amd import dock, synth
+    w = synth.score_workload(n)
+    G = dock.Grids.from_synth(w.grids)
+    L = dock.Ligand(w.ligands[0], w.ff)
+    gen = torch.from_numpy(w.genotypes[0]).cuda()
+    res = {}
+    for v in (0, 1):
+        e, g = dock.score_batch(G, L, gen, variant=v)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            dock.score_batch(G, L, gen, variant=v)
+            b.record()
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        ms = float(np.median(times))
+        res[dock.VARIANT_NAMES[v]] = {"ms": round(ms, 4), "evals_per_s": n / (ms * 1e-3)}
+    return {"workload": w.name, "genotypes": n, **res}
 
 
 def uneven_run(steps, warmup, use_table=True):
@@ -181,16 +284,24 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate (jobs/s)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run a plain device copy of this size (counter calibration)")
+    ap.add_argument("--reduction-repeat", type=int, default=200,
+                    help="dependent reductions per launch in the isolated reduction run (0 = skip)")
+    ap.add_argument("--score-n", type=int, default=65536,
+                    help="genotypes of the scoring-throughput run (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the docking "
               "hot path has no cross-GPU step; individuals and docking jobs are independent, so more GPUs would each run their own share.")
         sys.exit(2)
 
-    import torch
-    from paper_2410_10447_amd import dock, synth
-
+    from paper_2410_10447_amd import synth
     w = synth.ls_workload(3000, 300)
+    # the CPU baseline forks a process pool: it runs before the GPU is touched
+    cpu = None if args.no_cpu else cpu_baseline(w, args.cpu_sample, w.iterations)
+
+    import torch
+    from paper_2410_10447_amd import dock
+
     lig = w.ligands[0]
     G = dock.Grids.from_synth(w.grids)
     L = dock.Ligand(lig, w.ff)
@@ -268,8 +379,12 @@ def main():
         out["uneven"] = uneven_run(args.uneven_steps, 1)
     if args.serve_seconds > 0:
         out["serving"] = serving_run(args.serve_seconds, args.serve_rate, variant=best_v)
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, iters)
+    if args.score_n > 0:
+        out["score"] = score_run(args.score_n)
+    if args.reduction_repeat > 0:
+        out["reduction"] = reduction_run(repeat=args.reduction_repeat)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -981,9 +981,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == dock
     }
 }
 
+// Sum over the first 16-lane row (lanes 16..63 ignored), every lane receives it.
+__device__ __forceinline__ float row0_sum(float v) {
+    v += dpp<0xB1>(v);    // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);    // quad_perm [2,3,0,1]
+    v += dpp<0x141>(v);   // row_half_mirror
+    v += dpp<0x140>(v);   // row_mirror
+    return readlane(v, 0);
+}
+
 // Isolated block sum (reduction test kernel): every thread holds a float4;
-// each wave reduces with the chosen variant, the per-wave results meet in
-// LDS after one barrier and every thread adds them in the same fixed order.
+// each wave reduces with the chosen variant, the per-wave totals (at most 16)
+// meet in LDS after one barrier, and every wave adds them with a butterfly
+// over its first row (lane l holds wave l's total), so every thread gets the
+// block total in a fixed order.
 template <int VAR>
 __global__ __launch_bounds__(1024) void block_sum4_kernel(const float4* __restrict__ in,
                                                           float4* __restrict__ out, int repeat,
@@ -992,18 +1003,20 @@ __global__ __launch_bounds__(1024) void block_sum4_kernel(const float4* __restri
     const int t = threadIdx.x;
     const int nw = blockDim.x >> 6;
     const int w = t >> 6;
+    const int lane = t & 63;
     const size_t idx = (size_t)blockIdx.x * blockDim.x + t;
     const float4 v0 = in[idx];
     float4 v = v0;
     float4 tot = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int r = 0; r < repeat; ++r) {
         const float4 ws = sum4<VAR>(v);
-        if ((t & 63) == 0) part[r & 1][w] = ws;
-        __syncthreads();
-        tot = part[r & 1][0];
-        for (int j = 1; j < nw; ++j) {
-            const float4 pj = part[r & 1][j];
-            tot.x += pj.x; tot.y += pj.y; tot.z += pj.z; tot.w += pj.w;
+        if (nw == 1) {
+            tot = ws;
+        } else {
+            if (lane == 0) part[r & 1][w] = ws;
+            __syncthreads();
+            const float4 p = lane < nw ? part[r & 1][lane & 15] : make_float4(0.f, 0.f, 0.f, 0.f);
+            tot = make_float4(row0_sum(p.x), row0_sum(p.y), row0_sum(p.z), row0_sum(p.w));
         }
         v = make_float4(v0.x + chain * tot.x, v0.y + chain * tot.y, v0.z + chain * tot.z,
                         v0.w + chain * tot.w);

@@ -125,3 +125,35 @@ def test_latency_percentiles_under_load():
     assert s["jobs"] == len(specs)
     assert 0 < s["p50_s"] <= s["p99_s"]
     assert s["evals_per_s"] > 0
+
+
+def test_lazy_starting_points_and_progress_reports():
+    """A job may carry a function that draws its starting points when it is
+    admitted; the result equals the job with the array given up front, and
+    the progress callback fires on the server clock."""
+    drawn = []
+
+    def lazy(i, n):
+        def draw():
+            drawn.append(i)
+            return np.full((n, 17), float(i), np.float32)
+        return draw
+
+    eager = [_spec(i, 50 + 5 * i, arrival=0.02 * i) for i in range(6)]
+    lazy_specs = [serve.JobSpec(job_id=s.job_id, ligand=None, grid_id=0,
+                                genotypes=lazy(s.job_id, s.count), arrival=s.arrival,
+                                iterations=s.iterations, n=s.count) for s in eager]
+    assert all(l.count == e.count for l, e in zip(lazy_specs, eager))
+    _, _, st_e = _run(eager, max_individuals=10_000, device_budget=1 << 30, chunk_iters=50)
+    ex = serve.FakeExecutor(sec_per_eval=1e-6)
+    srv = serve.Server(ex, clock=ex.clock, max_individuals=10_000, device_budget=1 << 30,
+                       chunk_iters=50)
+    reports = []
+    st_l = srv.run(lazy_specs, poll=1e-3, progress=lambda now, s: reports.append(now),
+                   progress_every=0.05)
+    assert sorted(drawn) == list(range(6)) or set(drawn) == set(range(6))
+    res_e = {r.spec.job_id: r.result["value"] for r in st_e.completed}
+    res_l = {r.spec.job_id: r.result["value"] for r in st_l.completed}
+    assert res_e == res_l
+    assert st_l.evals == st_e.evals
+    assert reports and all(b > a for a, b in zip(reports, reports[1:]))

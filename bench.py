@@ -198,23 +198,29 @@ def score_run(n=65536, reps=5):
     return {"workload": w.name, "genotypes": n, **res}
 
 
-def uneven_run(steps, warmup, use_table=True):
+def uneven_run(steps, warmup, use_table=True, tpi_override=0):
     """64 ligands (atoms U{12..128}, torsions U{0..32}) x 100 individuals on one
-    96^3 x 12 grid set, 300 iterations, all in one persistent launch per step;
-    each item takes its size bucket's variant from the autotuning table."""
+    96^3 x 12 grid set, 300 iterations, in one call per step (one persistent
+    launch per kernel family, side by side); each item takes its size
+    bucket's variant and threads per individual from the autotuning table
+    (`tpi_override` forces the thread count of ligands over 64 atoms)."""
     import torch
     from paper_2410_10447_amd import autotune, dock, synth
     w = synth.uneven_workload()
     G = dock.Grids.from_synth(w.grids)
     Ls = [dock.Ligand(l, w.ff) for l in w.ligands]
     gens = [torch.from_numpy(g).cuda() for g in w.genotypes]
-    var = [autotune.choose(L.n_atoms, L.n_torsions)["variant"] if use_table else 0 for L in Ls]
+    pick = [autotune.choose(L.n_atoms, L.n_torsions) if use_table else dict(autotune.DEFAULT) for L in Ls]
+    if tpi_override:
+        for c in pick:
+            c["threads_per_ind"] = tpi_override
     evals = sum(g.shape[0] for g in gens) * (w.iterations + 1)
     ws = torch.empty(dock.workspace_bytes(len(Ls)), dtype=torch.uint8, device="cuda")
     runs = []
     for _ in range(warmup + steps):
         states = [dock.LSState.start(g) for g in gens]
-        jobs = [dock.LsJob(G, L, st, v) for L, st, v in zip(Ls, states, var)]
+        jobs = [dock.LsJob(G, L, st, c["variant"], threads_per_ind=c.get("threads_per_ind", 64))
+                for L, st, c in zip(Ls, states, pick)]
         runs.append((states, dock.make_items(jobs)))
     torch.cuda.synchronize()
     for k in range(warmup):
@@ -227,6 +233,9 @@ def uneven_run(steps, warmup, use_table=True):
     dt = (time.perf_counter() - t0) / steps
     return {"workload": w.name, "evals_per_step": evals, "ms_per_step": 1e3 * dt,
             "evals_per_s": evals / dt, "variants_from_table": use_table,
+            "threads_per_ind_override": tpi_override,
+            "two_wave_items": sum(1 for L, c in zip(Ls, pick)
+                                  if L.n_atoms > 64 and c.get("threads_per_ind", 64) == 128),
             "atoms_mean": float(np.mean([L.n_atoms for L in Ls])),
             "pairs_mean": float(np.mean([L.n_pairs for L in Ls]))}
 
@@ -279,6 +288,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--uneven-steps", type=int, default=3,
                     help="timed steps of the uneven 64-ligand batch (0 = skip)")
+    ap.add_argument("--uneven-tpi", type=int, default=0, choices=(0, 64, 128),
+                    help="threads per individual of the uneven batch's ligands over 64 atoms "
+                         "(0 = the autotuning table's choice)")
     ap.add_argument("--serve-seconds", type=float, default=15.0,
                     help="arrival window of the serving run (0 = skip)")
     ap.add_argument("--serve-rate", type=float, default=20.0, help="Poisson arrival rate (jobs/s)")
@@ -376,7 +388,7 @@ def main():
                      "flops_per_eval": fpe, "kernel_sha256": kernel_sha256()[:16]},
     }
     if args.uneven_steps > 0:
-        out["uneven"] = uneven_run(args.uneven_steps, 1)
+        out["uneven"] = uneven_run(args.uneven_steps, 1, tpi_override=args.uneven_tpi)
     if args.serve_seconds > 0:
         out["serving"] = serving_run(args.serve_seconds, args.serve_rate, variant=best_v)
     if args.score_n > 0:

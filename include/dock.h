@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define DOCK_ABI_VERSION 1
+#define DOCK_ABI_VERSION 2
 
 /* status codes */
 #define DOCK_OK            0
@@ -212,6 +212,7 @@ typedef struct {
     int32_t variant;             /* DOCK_REDUCE_* for this item, or -1 = opts->variant */
     int32_t iterations;          /* steps for this item, 0 .. opts->iterations, or -1 = opts */
     int32_t final_eval;          /* 1/0 overrides DOCK_LS_FINAL_EVAL for this item, -1 = opts */
+    int32_t threads_per_ind;     /* 64 or 128 for this item, 0 = opts->threads_per_ind */
     float* genotype;             /* device [n][G] in/out: current point */
     float* acc_g2;               /* device [n][G] in/out: running mean of g^2 (start 0) */
     float* acc_dx2;              /* device [n][G] in/out: running mean of dx^2 (start 0) */
@@ -230,7 +231,9 @@ typedef struct {
     float rho;                   /* decay, 0 < rho < 1 (0.8) */
     float eps;                   /* conditioner, > 0 (1e-2) */
     int32_t variant;             /* default DOCK_REDUCE_* */
-    int32_t threads_per_ind;     /* 0 (= 64) or 64 */
+    int32_t threads_per_ind;     /* 0 (= 64), 64 or 128: threads (waves of 64) per
+                                    individual for ligands of 65..128 atoms; smaller
+                                    ligands always take one wave */
     uint32_t flags;              /* DOCK_LS_FINAL_EVAL */
 } dock_ls_opts;
 
@@ -239,11 +242,14 @@ int32_t dock_ls_workspace_bytes(int32_t n_items, int64_t* bytes);
 
 /* Runs opts->iterations steps (or the item's own count) on every individual
  * of every item in one persistent launch; items are scheduled longest first.
- * A batch that mixes ligands of <= 64 and > 64 atoms AND reduction variants
- * runs as two persistent launches, one per atom-slot layout, side by side:
- * the second on a stream the library owns (one per device), forked from and
- * joined back into `stream` with events, so work queued on `stream` after
- * the call still waits for both.
+ * Items run in up to three kernel families: ligands of <= 64 atoms (one
+ * wave per individual), larger ligands with one wave (two atoms per lane) or
+ * with two waves per individual (128 threads, each wave owning 64 atoms and
+ * half of the pair batches). A batch that mixes families (or both one-wave
+ * families AND reduction variants) runs as one persistent launch per family,
+ * side by side: the first on `stream`, the others on streams the library
+ * owns (per device), forked from and joined back into `stream` with events,
+ * so work queued on `stream` after the call still waits for all of them.
  * Items may be at different stages: a serving loop passes each job's
  * remaining steps and asks for the final evaluation only in its last call. A call of K
  * iterations without DOCK_LS_FINAL_EVAL followed by one with it gives the

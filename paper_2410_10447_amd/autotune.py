@@ -5,8 +5,8 @@ For each bucket a representative synthetic ligand is timed with every
 candidate (reduction variant x threads per individual) through the C ABI and
 the fastest candidate is stored in a JSON table keyed by GPU architecture and
 bucket. `choose()` reads the table; a persistent launch over ligands of mixed
-sizes then passes each item its bucket's variant (the launch geometry is
-fixed per launch, the per-item choice is the variant).
+sizes then passes each item its bucket's variant and threads per individual
+(items with different thread counts run in separate launches side by side).
 
 Usage: python -m paper_2410_10447_amd.autotune [--out table.json]
 """
@@ -56,9 +56,13 @@ def choose(n_atoms: int, n_torsions: int, path: str = TABLE_PATH) -> dict:
     return dict(load(path)["buckets"].get(bucket(n_atoms, n_torsions), DEFAULT))
 
 
-def candidates():
+def candidates(n_atoms: int = 64):
+    """Reduction variant x threads per individual; ligands of more than 64
+    atoms may also run with two waves (128 threads) per individual."""
     from . import dock
-    return [{"variant": v, "threads_per_ind": 64} for v in (dock.REDUCE_SHUFFLE, dock.REDUCE_MFMA_F32)]
+    tpis = (64, 128) if n_atoms > 64 else (64,)
+    return [{"variant": v, "threads_per_ind": b} for b in tpis
+            for v in (dock.REDUCE_SHUFFLE, dock.REDUCE_MFMA_F32)]
 
 
 def time_candidate(G, L, gen, cand, iterations=20, reps=3):
@@ -71,7 +75,8 @@ def time_candidate(G, L, gen, cand, iterations=20, reps=3):
         st = st0.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        dock.local_search([(G, L, st)], iterations, variant=cand["variant"], workspace=ws)
+        dock.local_search([(G, L, st)], iterations, variant=cand["variant"], workspace=ws,
+                          threads_per_ind=cand.get("threads_per_ind", 64))
         torch.cuda.synchronize()
         if r:
             times.append(time.perf_counter() - t0)
@@ -93,7 +98,7 @@ def tune(out: str = TABLE_PATH, n_individuals: int = 1024, iterations: int = 20,
         L = dock.Ligand(lig, ff)
         gen = torch.from_numpy(synth.genotypes(lig, grd, n_individuals, seed)).cuda()
         best, rates = None, {}
-        for c in candidates():
+        for c in candidates(n):
             rate = time_candidate(G, L, gen, c, iterations)
             rates[f"v{c['variant']}_b{c['threads_per_ind']}"] = rate
             if best is None or rate > best[1]:

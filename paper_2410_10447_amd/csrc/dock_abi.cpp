@@ -130,8 +130,8 @@ int device_cu_count(int32_t& out) {
 // caller's later work still waits for both. The fork-launch-join sequence is
 // serialised, since the events are shared.
 struct SideStream {
-    hipStream_t stream = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t stream[2] = {nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
 };
 
 int side_stream(SideStream*& out, std::unique_lock<std::mutex>& lock) {
@@ -142,10 +142,12 @@ int side_stream(SideStream*& out, std::unique_lock<std::mutex>& lock) {
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     lock = std::unique_lock<std::mutex>(mu);
     SideStream& s = (*table)[dev];
-    if (!s.stream) {
-        e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking);
+    if (!s.stream[0]) {
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+            e = hipStreamCreateWithFlags(&s.stream[k], hipStreamNonBlocking);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&s.join[k], hipEventDisableTiming);
+        }
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s.fork, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&s.join, hipEventDisableTiming);
         if (e != hipSuccess) {
             s = SideStream();
             return hip_fail(e, "side stream creation");
@@ -325,8 +327,8 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
     if (!(o->rho > 0.f && o->rho < 1.f)) return fail(DOCK_EINVAL, "rho must be in (0, 1)");
     if (!(o->eps > 0.f) || !std::isfinite(o->eps)) return fail(DOCK_EINVAL, "eps must be > 0");
     if (!valid_variant(o->variant)) return fail(DOCK_EINVAL, "unknown default variant");
-    if (o->threads_per_ind != 0 && o->threads_per_ind != 64)
-        return fail(DOCK_EUNSUPPORTED, "threads_per_ind must be 0 or 64");
+    if (o->threads_per_ind != 0 && o->threads_per_ind != 64 && o->threads_per_ind != 128)
+        return fail(DOCK_EUNSUPPORTED, "threads_per_ind must be 0, 64 or 128");
     if ((o->flags & ~DOCK_LS_FINAL_EVAL) != 0) return fail(DOCK_EINVAL, "unknown flags");
     int64_t need = 0;
     dock_ls_workspace_bytes(n_items, &need);
@@ -334,7 +336,8 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
     std::vector<int64_t> cost;
     dev.reserve(n_items);
     int64_t total = 0;
-    bool any1 = false, any2 = false;
+    std::vector<int> fam;           // kernel family: 0 two-wave, 1 two-slot, 2 one-slot
+    bool any_fam[3] = {false, false, false};
     int var_u = -2;
     for (int i = 0; i < n_items; ++i) {
         const dock_ls_item& it = items[i];
@@ -349,6 +352,10 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
             return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": iterations outside [-1, opts->iterations]");
         if (it.final_eval < -1 || it.final_eval > 1)
             return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": final_eval must be -1, 0 or 1");
+        if (it.threads_per_ind != 0 && it.threads_per_ind != 64 && it.threads_per_ind != 128)
+            return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": threads_per_ind must be 0, 64 or 128");
+        const int tpi = it.threads_per_ind != 0 ? it.threads_per_ind
+                                                : (o->threads_per_ind != 0 ? o->threads_per_ind : 64);
         const int iters = it.iterations < 0 ? o->iterations : it.iterations;
         const int fin = it.final_eval < 0 ? ((o->flags & DOCK_LS_FINAL_EVAL) ? 1 : 0) : it.final_eval;
         if (it.n == 0) continue;
@@ -382,8 +389,9 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
         // evaluation: pair batches, atom slots, torsion depth, fixed part)
         cost.push_back((int64_t)(iters + fin) *
                        ((int64_t)H->n_batches * 90 + (int64_t)d.slots * (150 + 20 * P.max_depth) + 500));
-        any1 |= d.slots == 1;
-        any2 |= d.slots == 2;
+        const int f = d.slots == 1 ? 2 : (tpi == 128 ? 0 : 1);
+        fam.push_back(f);
+        any_fam[f] = true;
         var_u = (var_u == -2 || var_u == var) ? var : -1;
         total += it.n;
     }
@@ -392,52 +400,48 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
     if (!ws) return fail(DOCK_EINVAL, "dock_local_search_batch: NULL workspace");
     if (ws_bytes < need) return fail(DOCK_EINVAL, "dock_local_search_batch: workspace too small");
     if (!aligned(ws, 16)) return fail(DOCK_EINVAL, "workspace must be 16-byte aligned");
-    // longest items first (stable); when the batch is split by atom-slot
-    // layout (see below), two-slot items come first, each group longest first
-    const bool split_layouts = any1 && any2 && var_u < 0;
+    // A launch carries one kernel family. The two one-wave families share one
+    // launch (kernel dispatching per item) when every item uses the same
+    // reduction variant; otherwise, or with two-wave items, there is one
+    // persistent launch per family (each with its own work counter), two-wave
+    // items first, then two-slot, then one-slot, each group longest first.
+    // Carrying every combination in one kernel would spill registers.
+    const int var_uniform = var_u >= 0 ? var_u : -1;
+    const bool merge_one_wave = !any_fam[0] && any_fam[1] && any_fam[2] && var_uniform >= 0;
+    auto group = [&](int i) { return merge_one_wave ? 1 : fam[i]; };
     std::vector<int> idx(dev.size());
     for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
     std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-        if (split_layouts && dev[a].slots != dev[b].slots) return dev[a].slots > dev[b].slots;
+        if (group(a) != group(b)) return group(a) < group(b);
         return cost[a] > cost[b];
     });
     std::vector<uint8_t> table(docklaunch::kWorkspaceHeader + dev.size() * sizeof(docklaunch::DevItem), 0);
     docklaunch::DevItem* tab = reinterpret_cast<docklaunch::DevItem*>(table.data() + docklaunch::kWorkspaceHeader);
-    const size_t tab_count = dev.size();
-    int32_t ub = 0;
-    for (size_t i = 0; i < idx.size(); ++i) {
-        tab[i] = dev[idx[i]];
-        if (split_layouts && i > 0 && tab[i].slots != tab[i - 1].slots) ub = 0;
-        tab[i].unit_begin = ub;
-        ub += tab[i].n;
-    }
-    const int var_uniform = var_u >= 0 ? var_u : -1;
-    // A launch that mixes both atom-slot layouts AND reduction variants would
-    // carry every combination in one kernel and spill registers; such a batch
-    // runs as two persistent launches, one per layout (two-slot items first in
-    // the table, each launch with its own work counter), side by side: the
-    // one-slot launch runs on the library's side stream, so that its waves
-    // fill the chip as the longer two-slot launch drains.
-    // Each launch runs the kernel specialised for its items' variant when
-    // they share one (e.g. a tuning table that picks one variant per layout),
-    // else the one that dispatches per item.
+    const int n_dev = (int)dev.size();
     struct Part { int first, count, mode, variant; };
     std::vector<Part> parts;
-    const int n_dev = (int)tab_count;
-    auto part_variant = [&](int first, int count) {
+    int32_t ub = 0;
+    for (int i = 0; i < n_dev; ++i) {
+        const int g = group(idx[i]);
+        if (i == 0 || g != group(idx[i - 1])) {
+            const int mode = merge_one_wave ? docklaunch::kSlotsAny
+                                            : (g == 0 ? docklaunch::kTwoWave
+                                                      : (g == 1 ? docklaunch::kSlots2 : docklaunch::kSlots1));
+            parts.push_back({i, 0, mode, -1});
+            ub = 0;
+        }
+        tab[i] = dev[idx[i]];
+        tab[i].unit_begin = ub;
+        ub += tab[i].n;
+        ++parts.back().count;
+    }
+    // each launch runs the kernel specialised for its items' variant when
+    // they share one (e.g. a tuning table that picks one per size bucket)
+    for (Part& pt : parts) {
         int v = -2;
-        for (int i = first; i < first + count; ++i) v = (v == -2 || v == tab[i].variant) ? tab[i].variant : -1;
-        return v < 0 ? -1 : v;
-    };
-    if (split_layouts) {
-        int n2 = 0;
-        for (int i = 0; i < n_dev; ++i) n2 += tab[i].slots == 2;
-        parts.push_back({0, n2, docklaunch::kSlots2, part_variant(0, n2)});
-        parts.push_back({n2, n_dev - n2, docklaunch::kSlots1, part_variant(n2, n_dev - n2)});
-    } else {
-        parts.push_back({0, n_dev, (any1 && any2) ? docklaunch::kSlotsAny
-                                                  : (any2 ? docklaunch::kSlots2 : docklaunch::kSlots1),
-                         var_uniform});
+        for (int i = pt.first; i < pt.first + pt.count; ++i)
+            v = (v == -2 || v == tab[i].variant) ? tab[i].variant : -1;
+        pt.variant = v < 0 ? -1 : v;
     }
     // counters (one 32-bit word per part in the header) start at 0: they are
     // part of the copy
@@ -448,11 +452,12 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
     if (st != DOCK_OK) return st;
     SideStream* side = nullptr;
     std::unique_lock<std::mutex> side_lock;
-    if (parts.size() > 1) {
+    const int n_side = (int)parts.size() - 1;   // at most 2
+    if (n_side > 0) {
         st = side_stream(side, side_lock);
         if (st != DOCK_OK) return st;
         hipError_t e = hipEventRecord(side->fork, (hipStream_t)stream);
-        if (e == hipSuccess) e = hipStreamWaitEvent(side->stream, side->fork, 0);
+        for (int k = 0; k < n_side && e == hipSuccess; ++k) e = hipStreamWaitEvent(side->stream[k], side->fork, 0);
         if (e != hipSuccess) return hip_fail(e, "dock_local_search_batch fork");
     }
     hipError_t launch_err = hipSuccess;
@@ -473,13 +478,16 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
         p.total_units = (int32_t)units;
         p.rho = o->rho;
         p.eps = o->eps;
-        hipStream_t s_k = k == 0 ? (hipStream_t)stream : side->stream;
+        hipStream_t s_k = k == 0 ? (hipStream_t)stream : side->stream[k - 1];
         launch_err = docklaunch::launch_ls(p, pt.mode, pt.variant, grid, s_k);
         if (launch_err != hipSuccess) break;
     }
     if (side) {  // joined also after a failed launch
-        hipError_t e = hipEventRecord(side->join, side->stream);
-        if (e == hipSuccess) e = hipStreamWaitEvent((hipStream_t)stream, side->join, 0);
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < n_side && e == hipSuccess; ++k) {
+            e = hipEventRecord(side->join[k], side->stream[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent((hipStream_t)stream, side->join[k], 0);
+        }
         if (e != hipSuccess && launch_err == hipSuccess) return hip_fail(e, "dock_local_search_batch join");
     }
     if (launch_err != hipSuccess) return hip_fail(launch_err, "dock_local_search_batch launch");

@@ -241,31 +241,41 @@ __device__ __forceinline__ float4 sum4(float4 v) {
 // Ligand data held by a wave.
 // ---------------------------------------------------------------------------
 
-// LDS of one wave. Sized per atom-slot layout: a ligand of at most 64 atoms
-// has at most 128 + 2N <= 256 accumulator slots (n_copies <= 128/N + 2).
-template <int SLOTS>
+// LDS of one individual. Sized per layout: SLOTS atoms per lane and WAVES
+// waves per individual (a wave of the two-wave layout owns 64 atoms and its
+// own range of accumulator copies). A ligand of at most 64 atoms has at most
+// 128 + 2N <= 256 accumulator slots (n_copies <= 128/N + 2).
+template <int SLOTS, int WAVES = 1>
 struct __align__(16) Smem {
-    static constexpr int kAtoms = kWave * SLOTS;
-    static constexpr int kSlots = SLOTS == 1 ? dockblob::kMaxSlotsSmall : dockblob::kMaxSlots;
+    static constexpr int kAtoms = kWave * SLOTS * WAVES;
+    static constexpr int kSlots =
+        (SLOTS == 1 && WAVES == 1) ? dockblob::kMaxSlotsSmall : dockblob::kMaxSlots * WAVES;
     float4 dyn[kAtoms];             // x, y, z relative to t, and sqrt(kElec) q (depth-first order)
     union {
         float tk[kMaxTors + 1][12]; // torsion transforms, 3x4 row-major, and the identity
                                     // (index kMaxTors); live until the atom positions are
                                     // written
-        float4 acc[kSlots];         // pair-force accumulators, slot = copy * N + atom
+        float4 acc[kSlots];         // pair-force accumulators, slot = (range * C + copy) * N
+                                    // + atom, one range per wave
     } u;
     float4 tor[kMaxTors][2];        // torsion k: axis point p and packed positions
                                     // (a | b << 8 | first << 16 | end << 24), unit axis u
     uint32_t chain[kMaxFrag][kChain / 4];  // per fragment: enclosing torsions, innermost
                                            // first, 4 per word, padded with the identity
+    // two-wave layout: each wave's prefix sums of (g, x cross g) at its atoms,
+    // and its {E, g} partial and x cross g total
+    float pre[WAVES == 2 ? 6 : 1][WAVES == 2 ? kAtoms : 1];
+    float4 xchg[WAVES][2];
+    int unit;                       // two-wave layout: the block's work unit
 };
 
 template <int SLOTS>
 struct Lig {
     // uniform
     int N, T, NF, G, n_batches, n_copies, max_depth;
+    int wv;                         // wave of the individual (two-wave layout), else 0
     const u32x4* plist;             // pair records (dockblob::PairRec), n_batches x 64
-    // per lane, per slot: atom a = lane + 64 * slot
+    // per lane, per slot: atom a = lane + 64 * (slot + wv)
     float y0[SLOTS][3];
     float chg[SLOTS][3];            // 332.06363 q, q, |q|
     int cls[SLOTS];
@@ -273,12 +283,13 @@ struct Lig {
     int orig[SLOTS];                // original atom index
 };
 
-template <int SLOTS>
-__device__ void load_ligand(const uint8_t* __restrict__ blob, Smem<SLOTS>& sm, Lig<SLOTS>& L,
+template <int SLOTS, int WAVES = 1>
+__device__ void load_ligand(const uint8_t* __restrict__ blob, Smem<SLOTS, WAVES>& sm, Lig<SLOTS>& L,
                             bool fill_lds = true) {
     if (fill_lds) __syncthreads();  // previous users of the LDS tables are done
     const Header* h = reinterpret_cast<const Header*>(blob);
     const int lane = lane_id();
+    L.wv = WAVES == 1 ? 0 : uniform((int)threadIdx.x >> 6);
     L.N = uniform(h->n_atoms);
     L.T = uniform(h->n_torsions);
     L.NF = uniform(h->n_frag);
@@ -292,7 +303,7 @@ __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem<SLOTS>& sm, L
     const int4* iv = reinterpret_cast<const int4*>(blob + h->off_int);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-        const int a = lane + kWave * s;
+        const int a = lane + kWave * (s + L.wv);
         const bool ok = a < L.N;
         const int ai = ok ? a : 0;
         float4 r = ref[ai], c = chg[ai];
@@ -304,7 +315,7 @@ __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem<SLOTS>& sm, L
         L.orig[s] = ii.z;
     }
     const Torsion* tr = reinterpret_cast<const Torsion*>(blob + h->off_tors);
-    if (fill_lds && lane < L.T) {
+    if (fill_lds && L.wv == 0 && lane < L.T) {
         const Torsion t = tr[lane];
         const int pk = t.a_pos | (t.b_pos << 8) | (t.first << 16) | (t.end << 24);
         sm.tor[lane][0] = make_float4(t.p[0], t.p[1], t.p[2], __int_as_float(pk));
@@ -314,7 +325,7 @@ __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem<SLOTS>& sm, L
     const int n_chain_words = L.NF * (kChain / 4);
     uint32_t* dst = &sm.chain[0][0];
     if (fill_lds)
-        for (int i = lane; i < n_chain_words; i += kWave) dst[i] = ch[i];
+        for (int i = (int)threadIdx.x; i < n_chain_words; i += kWave * WAVES) dst[i] = ch[i];
     __syncthreads();
 }
 
@@ -497,18 +508,16 @@ __device__ __forceinline__ PairForce pair_force(u32x4 pr, float4 pi, float4 pj, 
     return o;
 }
 
-// Accumulator slot at a byte offset (a multiple of 16).
-template <int SLOTS>
-__device__ __forceinline__ float4* slot(Smem<SLOTS>& sm, int byte_offset) {
+// Accumulator slot at a byte offset (a multiple of 16) from `base`.
+__device__ __forceinline__ float4* slot(float4* base, int byte_offset) {
     return reinterpret_cast<float4*>(
-        __builtin_assume_aligned(reinterpret_cast<char*>(sm.u.acc) + byte_offset, 16));
+        __builtin_assume_aligned(reinterpret_cast<char*>(base) + byte_offset, 16));
 }
 
 // Adds -w d to slot si and +w d to slot sj, from their values read earlier.
-template <int SLOTS>
-__device__ __forceinline__ void store_force(Smem<SLOTS>& sm, const PairForce& f, float4 ai, float4 aj) {
-    float4* pi = slot(sm, f.si);
-    float4* pj = slot(sm, f.sj);
+__device__ __forceinline__ void store_force(float4* base, const PairForce& f, float4 ai, float4 aj) {
+    float4* pi = slot(base, f.si);
+    float4* pj = slot(base, f.sj);
     pi->x = fmaf(-f.w, f.dx, ai.x); pi->y = fmaf(-f.w, f.dy, ai.y); pi->z = fmaf(-f.w, f.dz, ai.z);
     pj->x = fmaf(f.w, f.dx, aj.x); pj->y = fmaf(f.w, f.dy, aj.y); pj->z = fmaf(f.w, f.dz, aj.z);
 }
@@ -518,11 +527,12 @@ __device__ __forceinline__ void store_force(Smem<SLOTS>& sm, const PairForce& f,
 // `gene` is gene `lane` (lanes >= G ignored); returns E (uniform) and writes
 // this lane's gradient component to `grad`.
 // ---------------------------------------------------------------------------
-template <int SLOTS, int VAR>
-__device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>& L, float gene,
+template <int SLOTS, int VAR, int WAVES = 1>
+__device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig<SLOTS>& L, float gene,
                           float& grad, float* atom_out) {
     const int lane = lane_id();
     const int N = L.N;
+    const bool lead = WAVES == 1 || L.wv == 0;  // the wave that writes shared tables
     // rigid-body genes (uniform)
     const float tx = readlane(gene, 0), ty = readlane(gene, 1), tz = readlane(gene, 2);
     const float qw0 = readlane(gene, 3), qx0 = readlane(gene, 4), qy0 = readlane(gene, 5),
@@ -542,7 +552,7 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
 
     // torsion transforms: T_k(y) = R_k (y - p) + p, about the reference axis
     const float psi = __shfl(gene, (7 + lane) & 63);
-    if (lane < L.T) {
+    if (lead && lane < L.T) {
         float sn, cs;
         sincosf(psi, &sn, &cs);
         const float4 tp4 = sm.tor[lane][0], tu4 = sm.tor[lane][1];
@@ -561,7 +571,7 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
             o[4 * r + 2] = Rk[3 * r + 2];
             o[4 * r + 3] = tp[r] - (Rk[3 * r] * tp[0] + Rk[3 * r + 1] * tp[1] + Rk[3 * r + 2] * tp[2]);
         }
-    } else if (lane == kMaxTors) {
+    } else if (lead && lane == kMaxTors) {
         float4* o = reinterpret_cast<float4*>(sm.u.tk[kMaxTors]);
         o[0] = make_float4(1.f, 0.f, 0.f, 0.f);
         o[1] = make_float4(0.f, 1.f, 0.f, 0.f);
@@ -579,7 +589,7 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
     float x[SLOTS][3];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-        const int a = lane + kWave * s;
+        const int a = lane + kWave * (s + L.wv);
         float y0 = L.y0[s][0], y1 = L.y0[s][1], y2 = L.y0[s][2];
         // one word of torsion indices per four levels, then the rows of two
         // levels per LDS round trip; levels past the atom's depth apply the
@@ -623,11 +633,16 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
     // (LDS float atomics would serialise in the LDS unit: they made this
     // phase several times slower.)
     {
+        // each wave adds into its own range of copies; a wave of the two-wave
+        // layout takes its half of the batches
         const int nslot = L.n_copies * N;
-        for (int k = lane; k < nslot; k += kWave) sm.u.acc[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        float4* const accw = sm.u.acc + (WAVES == 1 ? 0 : L.wv * nslot);
+        for (int k = lane; k < nslot; k += kWave) accw[k] = make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
-        const auto plist = gmem(L.plist);
-        const int nb = L.n_batches;
+        const int nb_all = L.n_batches;
+        const int half = (nb_all + 1) >> 1;
+        const int nb = WAVES == 1 ? nb_all : (L.wv == 0 ? half : nb_all - half);
+        const auto plist = gmem(L.plist) + (WAVES == 1 || L.wv == 0 ? 0 : half * kWave);
         const int N16 = N * 16;
         // Software pipeline over batches with no branch inside. Step k
         // stores batch k (its slot values were read in step k - 1) and
@@ -658,8 +673,8 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
             Pi[0] = sm.dyn[R[0].x & 127];
             Pj[0] = sm.dyn[(R[0].x >> 7) & 127];
             F[0] = pair_force(R[0], Pi[0], Pj[0], N16);
-            Ai[0] = *slot(sm, F[0].si);
-            Aj[0] = *slot(sm, F[0].sj);
+            Ai[0] = *slot(accw, F[0].si);
+            Aj[0] = *slot(accw, F[0].sj);
             Pi[1] = sm.dyn[R[1].x & 127];
             Pj[1] = sm.dyn[(R[1].x >> 7) & 127];
             int k = 0;
@@ -672,10 +687,10 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
                 R[r] = record(k + 4);
                 __builtin_amdgcn_sched_barrier(0);   // keep the loads at the step's start
                 F[n] = pair_force(R[(r + 1) & 3], Pi[n], Pj[n], N16);
-                store_force(sm, F[c], Ai[c], Aj[c]);
+                store_force(accw, F[c], Ai[c], Aj[c]);
                 e_lane += F[c].e;
-                Ai[n] = *slot(sm, F[n].si);
-                Aj[n] = *slot(sm, F[n].sj);
+                Ai[n] = *slot(accw, F[n].si);
+                Aj[n] = *slot(accw, F[n].sj);
                 __builtin_amdgcn_sched_barrier(0);
                 ++k;
             };
@@ -689,10 +704,10 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
             if (k < nb - 1) step(I2());
             // k == nb - 1: the last batch is computed and its slots read
             if (k & 1) {
-                store_force(sm, F[1], Ai[1], Aj[1]);
+                store_force(accw, F[1], Ai[1], Aj[1]);
                 e_lane += F[1].e;
             } else {
-                store_force(sm, F[0], Ai[0], Aj[0]);
+                store_force(accw, F[0], Ai[0], Aj[0]);
                 e_lane += F[0].e;
             }
         } else {
@@ -700,13 +715,13 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
             for (int s = 0; s < SLOTS; ++s) grid_load(G, L.cls[s], x[s], tv, tap[s]);
         }
         __syncthreads();
-        // each atom adds its copies in copy order
+        // each atom adds its copies in copy order (range by range)
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
-            const int a = lane + kWave * s;
+            const int a = lane + kWave * (s + L.wv);
             g[s][0] = g[s][1] = g[s][2] = 0.f;
             if (a < N) {
-                for (int c = 0; c < L.n_copies; ++c) {
+                for (int c = 0; c < L.n_copies * WAVES; ++c) {
                     const float4 v = sm.u.acc[c * N + a];
                     g[s][0] += v.x;
                     g[s][1] += v.y;
@@ -719,7 +734,7 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
     float e_atom[SLOTS];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
-        const int a = lane + kWave * s;
+        const int a = lane + kWave * (s + L.wv);
         float e, gx, gy, gz;
         grid_term(G, tap[s], L.chg[s][1], L.chg[s][2], x[s], tv, e, gx, gy, gz);
         const bool ok = a < N;
@@ -731,13 +746,13 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
     }
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s)
-        if (lane + kWave * s >= N) { g[s][0] = g[s][1] = g[s][2] = 0.f; }
+        if (lane + kWave * (s + L.wv) >= N) { g[s][0] = g[s][1] = g[s][2] = 0.f; }
 
     // block sum of {E, gx, gy, gz}: the paper's reduction, in the chosen variant
     float4 eg = make_float4(e_lane, 0.f, 0.f, 0.f);
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) { eg.y += g[s][0]; eg.z += g[s][1]; eg.w += g[s][2]; }
-    const float4 EG = sum4<VAR>(eg);
+    float4 EG = sum4<VAR>(eg);
 
     // torsion torques: prefix sums of (g, x cross g) in depth-first order;
     // the last lane's x cross g sums give the torque about t (FP32 always)
@@ -754,8 +769,22 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
         P[0][c] = wave_scan(P[0][c]);
         if constexpr (SLOTS == 2) P[1][c] = wave_scan(P[1][c]) + readlane(P[0][c], 63);
     }
-    const float4 TQ = make_float4(readlane(P[SLOTS - 1][3], 63), readlane(P[SLOTS - 1][4], 63),
-                                  readlane(P[SLOTS - 1][5], 63), 0.f);
+    float4 TQ = make_float4(readlane(P[SLOTS - 1][3], 63), readlane(P[SLOTS - 1][4], 63),
+                            readlane(P[SLOTS - 1][5], 63), 0.f);
+    if constexpr (WAVES == 2) {
+        // the two waves' partials and prefix sums meet in LDS; both waves then
+        // hold the same totals (added in wave order) and step identically
+        const int a = lane + kWave * L.wv;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sm.pre[c][a] = P[0][c];
+        if (lane == 0) sm.xchg[L.wv][0] = EG;
+        __syncthreads();
+        const float4 e0 = sm.xchg[0][0], e1 = sm.xchg[1][0];
+        EG = make_float4(e0.x + e1.x, e0.y + e1.y, e0.z + e1.z, e0.w + e1.w);
+        TQ = make_float4(sm.pre[3][kWave - 1] + sm.pre[3][2 * kWave - 1],
+                         sm.pre[4][kWave - 1] + sm.pre[4][2 * kWave - 1],
+                         sm.pre[5][kWave - 1] + sm.pre[5][2 * kWave - 1], 0.f);
+    }
     float gpsi = 0.f;
     {
         // torsion `lane`: bond atoms a, b and its moving range [first, end)
@@ -767,15 +796,23 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
         float S[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            float ph = __shfl(P[0][c], hi & 63);
-            float pl = __shfl(P[0][c], lo & 63);
-            if constexpr (SLOTS == 2) {
-                const float ph1 = __shfl(P[1][c], hi & 63);
-                const float pl1 = __shfl(P[1][c], lo & 63);
-                ph = hi >= kWave ? ph1 : ph;
-                pl = lo >= kWave ? pl1 : pl;
+            if constexpr (WAVES == 2) {
+                // global prefix: wave 1's local prefix plus wave 0's total
+                const float off = sm.pre[c][kWave - 1];
+                const float ph = sm.pre[c][hi] + (hi >= kWave ? off : 0.f);
+                const float pl = sm.pre[c][lo] + (lo >= kWave ? off : 0.f);
+                S[c] = ph - pl;
+            } else {
+                float ph = __shfl(P[0][c], hi & 63);
+                float pl = __shfl(P[0][c], lo & 63);
+                if constexpr (SLOTS == 2) {
+                    const float ph1 = __shfl(P[1][c], hi & 63);
+                    const float pl1 = __shfl(P[1][c], lo & 63);
+                    ph = hi >= kWave ? ph1 : ph;
+                    pl = lo >= kWave ? pl1 : pl;
+                }
+                S[c] = ph - pl;
             }
-            S[c] = ph - pl;
         }
         const float4 xa = sm.dyn[t_apos];
         const float4 xb = sm.dyn[t_bpos];
@@ -810,7 +847,7 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS>& sm, const Lig<SLOTS>
     if (atom_out) {
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
-            const int a = lane + kWave * s;
+            const int a = lane + kWave * (s + L.wv);
             if (a < N) {
                 float4* o = reinterpret_cast<float4*>(atom_out) + 2 * L.orig[s];
                 o[0] = make_float4(x[s][0] + tx, x[s][1] + ty, x[s][2] + tz, e_atom[s]);
@@ -845,10 +882,13 @@ __global__ __launch_bounds__(64, (SLOTS == 1 ? 3 : 2)) void score_kernel(GridPar
     if (grad && lane < L.G) grad[(size_t)ind * L.G + lane] = gr;
 }
 
-template <int SLOTS, int VAR>
-__device__ void local_search_one(const DevItem& it, int ind, Smem<SLOTS>& sm, const Lig<SLOTS>& L,
+template <int SLOTS, int VAR, int WAVES = 1>
+__device__ void local_search_one(const DevItem& it, int ind, Smem<SLOTS, WAVES>& sm, const Lig<SLOTS>& L,
                                  int iterations, float rho, float eps, bool final_eval) {
+    // both waves of the two-wave layout hold the genotype and take the same
+    // steps on the same totals; the first wave writes the results
     const int lane = lane_id();
+    const bool writer = WAVES == 1 || L.wv == 0;
     const int G = L.G;
     const bool act = lane < G;
     const size_t o = (size_t)ind * G + lane;
@@ -861,7 +901,7 @@ __device__ void local_search_one(const DevItem& it, int ind, Smem<SLOTS>& sm, co
     float lastG = 0.f;
     for (int iter = 0; iter < iterations; ++iter) {
         float gr;
-        const float E = evaluate<SLOTS, VAR>(it.grid, sm, L, x, gr, nullptr);
+        const float E = evaluate<SLOTS, VAR, WAVES>(it.grid, sm, L, x, gr, nullptr);
         lastE = E;
         lastG = gr;
         if (E < bestE) { bestE = E; bx = x; }
@@ -878,11 +918,12 @@ __device__ void local_search_one(const DevItem& it, int ind, Smem<SLOTS>& sm, co
     }
     if (final_eval) {
         float gr;
-        const float E = evaluate<SLOTS, VAR>(it.grid, sm, L, x, gr, nullptr);
+        const float E = evaluate<SLOTS, VAR, WAVES>(it.grid, sm, L, x, gr, nullptr);
         lastE = E;
         lastG = gr;
         if (E < bestE) { bestE = E; bx = x; }
     }
+    if (!writer) return;
     if (act && it.grad && (iterations > 0 || final_eval)) it.grad[o] = lastG;
     if (act) {
         it.genotype[o] = x;
@@ -897,31 +938,32 @@ __device__ void local_search_one(const DevItem& it, int ind, Smem<SLOTS>& sm, co
     }
 }
 
-template <int SLOTS>
-__device__ void ls_dispatch(int var_uniform, const DevItem& it, int ind, Smem<SLOTS>& sm,
+template <int SLOTS, int WAVES>
+__device__ void ls_dispatch(int var_uniform, const DevItem& it, int ind, Smem<SLOTS, WAVES>& sm,
                             const Lig<SLOTS>& L, const LsParams& p) {
     const int var = var_uniform >= 0 ? var_uniform : it.variant;
     const bool fin = it.final_eval != 0;
     switch (var) {
         case DOCK_REDUCE_MFMA_F32:
-            local_search_one<SLOTS, DOCK_REDUCE_MFMA_F32>(it, ind, sm, L, it.iterations, p.rho, p.eps, fin); break;
+            local_search_one<SLOTS, DOCK_REDUCE_MFMA_F32, WAVES>(it, ind, sm, L, it.iterations, p.rho, p.eps, fin); break;
         case DOCK_REDUCE_MFMA_BF16:
-            local_search_one<SLOTS, DOCK_REDUCE_MFMA_BF16>(it, ind, sm, L, it.iterations, p.rho, p.eps, fin); break;
+            local_search_one<SLOTS, DOCK_REDUCE_MFMA_BF16, WAVES>(it, ind, sm, L, it.iterations, p.rho, p.eps, fin); break;
         case DOCK_REDUCE_MFMA_F16:
-            local_search_one<SLOTS, DOCK_REDUCE_MFMA_F16>(it, ind, sm, L, it.iterations, p.rho, p.eps, fin); break;
+            local_search_one<SLOTS, DOCK_REDUCE_MFMA_F16, WAVES>(it, ind, sm, L, it.iterations, p.rho, p.eps, fin); break;
         case DOCK_REDUCE_MFMA_BF16X3:
-            local_search_one<SLOTS, DOCK_REDUCE_MFMA_BF16X3>(it, ind, sm, L, it.iterations, p.rho, p.eps, fin); break;
+            local_search_one<SLOTS, DOCK_REDUCE_MFMA_BF16X3, WAVES>(it, ind, sm, L, it.iterations, p.rho, p.eps, fin); break;
         default:
-            local_search_one<SLOTS, DOCK_REDUCE_SHUFFLE>(it, ind, sm, L, it.iterations, p.rho, p.eps, fin); break;
+            local_search_one<SLOTS, DOCK_REDUCE_SHUFFLE, WAVES>(it, ind, sm, L, it.iterations, p.rho, p.eps, fin); break;
     }
 }
 
-template <int SLOTS, int VAR>
-__device__ void ls_run(const DevItem& it, int ind, Smem<SLOTS>& sm, const Lig<SLOTS>& L, const LsParams& p) {
+template <int SLOTS, int VAR, int WAVES = 1>
+__device__ void ls_run(const DevItem& it, int ind, Smem<SLOTS, WAVES>& sm, const Lig<SLOTS>& L,
+                       const LsParams& p) {
     if constexpr (VAR >= 0)
-        local_search_one<SLOTS, VAR>(it, ind, sm, L, it.iterations, p.rho, p.eps, it.final_eval != 0);
+        local_search_one<SLOTS, VAR, WAVES>(it, ind, sm, L, it.iterations, p.rho, p.eps, it.final_eval != 0);
     else
-        ls_dispatch<SLOTS>(-1, it, ind, sm, L, p);
+        ls_dispatch<SLOTS, WAVES>(-1, it, ind, sm, L, p);
 }
 
 // The item record, read once per work unit, with every word made
@@ -978,6 +1020,36 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == dock
             load_ligand<2>(it.blob, sm, L, reload);
             ls_run<2, VAR>(it, ind, sm, L, p);
         }
+    }
+}
+
+// Two-wave persistent local-search kernel: 128-thread blocks, one individual
+// of a 65..128-atom ligand per block, each wave owning 64 atoms and half of
+// the pair batches. The first thread takes the next unit and hands it to
+// both waves through LDS; every wave exits once the counter passes the last
+// unit.
+template <int VAR>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3, 3))) void ls_kernel_2w(LsParams p) {
+    __shared__ Smem<1, 2> sm;
+    int cur_item = -1;
+    while (true) {
+        __syncthreads();                       // the previous unit is read by both waves
+        if (threadIdx.x == 0) sm.unit = atomicAdd(p.counter, 1);
+        __syncthreads();
+        const int u = uniform(sm.unit);
+        if (u >= p.total_units) break;
+        int lo = 0, hi = p.n_items - 1;
+        while (lo < hi) {  // last item with unit_begin <= u
+            const int mid = (lo + hi + 1) >> 1;
+            if (uniform(gmem(&p.items[mid].unit_begin)[0]) <= u) lo = mid; else hi = mid - 1;
+        }
+        const DevItem it = load_item(p.items, lo);
+        const int ind = u - it.unit_begin;
+        const bool reload = lo != cur_item;
+        cur_item = lo;
+        Lig<1> L;
+        load_ligand<1, 2>(it.blob, sm, L, reload);
+        ls_run<1, VAR, 2>(it, ind, sm, L, p);
     }
 }
 
@@ -1082,7 +1154,19 @@ const void* ls_kernel_ptr(int var) {
     }
 }
 
+const void* ls_kernel_2w_ptr(int var) {
+    switch (var) {
+        case 0: return reinterpret_cast<const void*>(&ls_kernel_2w<0>);
+        case 1: return reinterpret_cast<const void*>(&ls_kernel_2w<1>);
+        case 2: return reinterpret_cast<const void*>(&ls_kernel_2w<2>);
+        case 3: return reinterpret_cast<const void*>(&ls_kernel_2w<3>);
+        case 4: return reinterpret_cast<const void*>(&ls_kernel_2w<4>);
+        default: return reinterpret_cast<const void*>(&ls_kernel_2w<-1>);
+    }
+}
+
 const void* ls_kernel_for(int mode, int var) {
+    if (mode == docklaunch::kTwoWave) return ls_kernel_2w_ptr(var);
     if (mode == docklaunch::kSlots1) return ls_kernel_ptr<docklaunch::kSlots1>(var);
     if (mode == docklaunch::kSlots2) return ls_kernel_ptr<docklaunch::kSlots2>(var);
     return ls_kernel_ptr<docklaunch::kSlotsAny>(var);
@@ -1110,13 +1194,13 @@ hipError_t launch_ls(const LsParams& p, int mode, int variant_uniform, int grid_
     const void* k = ls_kernel_for(mode, variant_uniform);
     LsParams pp = p;
     void* args[] = {&pp};
-    return hipLaunchKernel(k, dim3(grid_blocks), dim3(64), args, 0, stream);
+    return hipLaunchKernel(k, dim3(grid_blocks), dim3(ls_block_threads(mode)), args, 0, stream);
 }
 
 int ls_blocks_per_cu(int mode, int variant_uniform) {
     int nb = 0;
     const void* k = ls_kernel_for(mode, variant_uniform);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64, 0) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, ls_block_threads(mode), 0) != hipSuccess) return 0;
     return nb;
 }
 

@@ -47,8 +47,11 @@ struct LsParams {
 // Workspace layout: [int32 work counters (one per launch of a call), 64 B][DevItem x n_items]
 constexpr int64_t kWorkspaceHeader = 64;
 
-// ls kernel families: slots 1, slots 2, or both (runtime per item)
-enum LsMode { kSlots1 = 1, kSlots2 = 2, kSlotsAny = 3 };
+// ls kernel families: slots 1, slots 2, or both (runtime per item), all one
+// wave per individual; or two waves per individual (ligands of 65..128 atoms)
+enum LsMode { kSlots1 = 1, kSlots2 = 2, kSlotsAny = 3, kTwoWave = 4 };
+
+inline int ls_block_threads(int mode) { return mode == kTwoWave ? 128 : 64; }
 
 hipError_t launch_score(const GridParams& g, const uint8_t* blob, int slots, int n,
                         const float* genotypes, float* energy, float* grad, float* atom_out,
@@ -58,7 +61,7 @@ hipError_t launch_score(const GridParams& g, const uint8_t* blob, int slots, int
 hipError_t launch_ls(const LsParams& p, int mode, int variant_uniform, int grid_blocks,
                      hipStream_t stream);
 
-// Resident 64-thread blocks per CU for the ls kernel family chosen by
+// Resident blocks per CU for the ls kernel family chosen by
 // (mode, variant_uniform); 0 on error.
 int ls_blocks_per_cu(int mode, int variant_uniform);
 

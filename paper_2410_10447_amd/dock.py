@@ -84,6 +84,7 @@ class ExecOpts(C.Structure):
 class LsItem(C.Structure):
     _fields_ = [("grids", C.c_void_p), ("ligand", C.c_void_p), ("n", C.c_int32),
                 ("variant", C.c_int32), ("iterations", C.c_int32), ("final_eval", C.c_int32),
+                ("threads_per_ind", C.c_int32),
                 ("genotype", C.c_void_p), ("acc_g2", C.c_void_p), ("acc_dx2", C.c_void_p),
                 ("best_genotype", C.c_void_p), ("best_energy", C.c_void_p),
                 ("energy", C.c_void_p), ("iters_done", C.c_void_p), ("grad", C.c_void_p)]
@@ -350,6 +351,7 @@ class LsJob:
     iterations: int = -1
     final_eval: int = -1
     grad: object = None          # optional [n, G] CUDA tensor: gradient at the last evaluated point
+    threads_per_ind: int = 0     # 64 or 128 (ligands of 65..128 atoms), 0 defers to the call
 
 
 def _as_job(job):
@@ -371,6 +373,7 @@ def make_items(jobs):
         it.variant = j.variant
         it.iterations = j.iterations
         it.final_eval = j.final_eval
+        it.threads_per_ind = j.threads_per_ind
         it.genotype = st.genotype.data_ptr()
         it.acc_g2 = st.acc_g2.data_ptr()
         it.acc_dx2 = st.acc_dx2.data_ptr()
@@ -384,11 +387,12 @@ def make_items(jobs):
 
 def local_search(jobs, iterations: int, rho: float = 0.8, eps: float = 1e-2,
                  variant: int = REDUCE_SHUFFLE, final_eval: bool = True, workspace=None,
-                 stream=None, items=None):
+                 stream=None, items=None, threads_per_ind: int = 0):
     """ADADELTA on every (Grids, Ligand, LSState[, variant]) job, one launch.
 
     State tensors are updated in place. `workspace` (uint8 CUDA tensor) is
     allocated if not given; `items` may pass a prebuilt item array.
+    `threads_per_ind` (0/64/128) is the default for jobs that leave it at 0.
     """
     import torch
     n_items = len(jobs)
@@ -400,8 +404,8 @@ def local_search(jobs, iterations: int, rho: float = 0.8, eps: float = 1e-2,
     if workspace is None or workspace.numel() < need:
         dev = torch.device("cuda")
         workspace = torch.empty(max(need, 64), dtype=torch.uint8, device=dev)
-    o = LsOpts(iterations=iterations, rho=rho, eps=eps, variant=variant, threads_per_ind=0,
-               flags=LS_FINAL_EVAL if final_eval else 0)
+    o = LsOpts(iterations=iterations, rho=rho, eps=eps, variant=variant,
+               threads_per_ind=threads_per_ind, flags=LS_FINAL_EVAL if final_eval else 0)
     _check(lib().dock_local_search_batch(items, n_items, C.byref(o), _ptr(workspace),
                                          workspace.numel(), _stream_handle(stream)))
     return workspace

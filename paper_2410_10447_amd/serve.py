@@ -297,7 +297,8 @@ class GpuExecutor:
         self.torch = torch
         self.device = device
         self.variant = variant
-        self.use_table = use_table   # each job takes its size bucket's tuned variant
+        self.use_table = use_table   # each job takes its size bucket's tuned variant and
+                                     # threads per individual
         self.ff = ff
         self.grids = [dock.Grids.from_synth(g, device) for g in grid_sets]
         self.grid_bytes = sum(g.nbytes() for g in self.grids)
@@ -319,15 +320,18 @@ class GpuExecutor:
         with torch.cuda.stream(self.stream):
             gen = host.to(self.device, non_blocking=True)
             st = self.dock.LSState.start(gen)
-        var = -1
+        var, tpi = -1, 0
         if self.use_table:
             from . import autotune
-            var = int(autotune.choose(L.n_atoms, L.n_torsions)["variant"])
+            pick = autotune.choose(L.n_atoms, L.n_torsions)
+            var = int(pick["variant"])
+            tpi = int(pick.get("threads_per_ind", 64))
         return {"ligand": L, "state": st, "grids": self.grids[spec.grid_id], "host": host,
-                "variant": var}
+                "variant": var, "threads_per_ind": tpi}
 
     def launch(self, plan, max_iters):
-        jobs = [self.dock.LsJob(h["grids"], h["ligand"], h["state"], h["variant"], k, 1 if fin else 0)
+        jobs = [self.dock.LsJob(h["grids"], h["ligand"], h["state"], h["variant"], k, 1 if fin else 0,
+                                threads_per_ind=h.get("threads_per_ind", 0))
                 for h, k, fin in plan]
         need = self.dock.workspace_bytes(len(jobs))
         # a workspace per in-flight chunk: reuse one whose chunk has completed

@@ -188,14 +188,25 @@ def _ls_setup(dk, w, n):
     return G, L, st
 
 
-@pytest.mark.parametrize("variant", FP32_VARIANTS)
-def test_ls_step_map(dk, variant):
+def _two_wave_workload(n):
+    """A 100-atom, 14-torsion ligand (two atoms per lane in one wave, or one
+    per lane in two waves) on 64^3 x 10 maps."""
+    lig = synth.ligand(100, 14, 4100)
+    grd = synth.grids(64, 10, 4101)
+    return synth.Workload("ls_n100_t14_g64", [lig], grd, synth.force_field(),
+                          [synth.genotypes(lig, grd, n, 4102)], iterations=30)
+
+
+@pytest.mark.parametrize("variant,tpi", [(v, 64) for v in FP32_VARIANTS] + [(v, 128) for v in FP32_VARIANTS])
+def test_ls_step_map(dk, variant, tpi):
     """Each GPU step is the ADADELTA update (Zeiler Alg. 1) of the GPU's own
     state and gradient, and that gradient and energy match the oracle's at the
     same point. (Comparing with a step taken on the oracle's gradient would mix
     the two: ADADELTA passes small gradient components through almost
-    unscaled, so their absolute FP32 error, ~1e-4 of |g|, would dominate.)"""
-    w = synth.ls_workload(64)
+    unscaled, so their absolute FP32 error, ~1e-4 of |g|, would dominate.)
+    tpi = 64 runs the 48-atom benchmark ligand in one wave; tpi = 128 runs a
+    100-atom ligand with two waves per individual."""
+    w = synth.ls_workload(64) if tpi == 64 else _two_wave_workload(64)
     prep = R.prepare(w.ligands[0], w.ff)
     G, L, st = _ls_setup(dk, w, 64)
     grad = torch.zeros_like(st.genotype)
@@ -204,8 +215,8 @@ def test_ls_step_map(dk, variant):
     n_cond = 0
     for it in range(12):
         s0 = st.to_numpy()
-        ws = dk.local_search([dk.LsJob(G, L, st, variant, grad=grad)], 1, variant=variant,
-                             final_eval=False, workspace=ws)
+        ws = dk.local_search([dk.LsJob(G, L, st, variant, grad=grad, threads_per_ind=tpi)], 1,
+                             variant=variant, final_eval=False, workspace=ws)
         torch.cuda.synchronize()
         s1 = st.to_numpy()
         g_gpu = grad.cpu().numpy().astype(np.float64)
@@ -230,20 +241,21 @@ def test_ls_step_map(dk, variant):
             worst_step = max(worst_step, err.max())
             assert np.all(err <= 1e-5), (it, name, err.max())
         assert np.all(s1["iters_done"] == it + 1)
-    print(f"\n[ls step-map v{variant}] worst update rel err {worst_step:.2e}, worst gradient err "
+    print(f"\n[ls step-map v{variant} tpi {tpi}] worst update rel err {worst_step:.2e}, worst gradient err "
           f"{worst_g:.2e}; energies held to a conditioning bound {n_cond}", flush=True)
 
 
-def test_ls_chunked_equals_single_and_deterministic(dk):
-    w = synth.ls_workload(200)
+@pytest.mark.parametrize("tpi", [64, 128])
+def test_ls_chunked_equals_single_and_deterministic(dk, tpi):
+    w = synth.ls_workload(200) if tpi == 64 else _two_wave_workload(200)
     G, L, st_a = _ls_setup(dk, w, 200)
     st_b = st_a.clone()
     st_c = st_a.clone()
-    dk.local_search([(G, L, st_a)], 30, final_eval=True)
+    dk.local_search([(G, L, st_a)], 30, final_eval=True, threads_per_ind=tpi)
     for _ in range(2):
-        dk.local_search([(G, L, st_b)], 10, final_eval=False)
-    dk.local_search([(G, L, st_b)], 10, final_eval=True)
-    dk.local_search([(G, L, st_c)], 30, final_eval=True)
+        dk.local_search([(G, L, st_b)], 10, final_eval=False, threads_per_ind=tpi)
+    dk.local_search([(G, L, st_b)], 10, final_eval=True, threads_per_ind=tpi)
+    dk.local_search([(G, L, st_c)], 30, final_eval=True, threads_per_ind=tpi)
     torch.cuda.synchronize()
     a, b, c = st_a.to_numpy(), st_b.to_numpy(), st_c.to_numpy()
     for f in a:
@@ -327,6 +339,42 @@ def test_ls_uneven_mixed_variants_alone_equals_mixed(dk):
         an, mn = a.to_numpy(), m.to_numpy()
         for f in an:
             assert np.array_equal(an[f], mn[f]), (k, f)
+
+
+def test_ls_three_families_alone_equals_mixed(dk):
+    """One call holding ligands of <= 64 atoms (one wave), larger ligands in
+    one wave and larger ligands in two waves, with mixed reduction variants,
+    runs one launch per family side by side and gives, bit for bit, what each
+    item gives alone; the two-wave items meet oracle parity at their best
+    point."""
+    spec = ((20, 4, 64), (90, 12, 128), (48, 8, 64), (128, 20, 64), (100, 14, 128), (65, 9, 128),
+            (128, 32, 128), (70, 0, 64))
+    ligs = [synth.ligand(n, t, 90 + n + t) for n, t, _ in spec]
+    grd = synth.grids(64, 10, 91)
+    ff = synth.force_field()
+    G = dk.Grids.from_synth(grd)
+    Ls = [dk.Ligand(l, ff) for l in ligs]
+    gens = [torch.from_numpy(synth.genotypes(l, grd, 20 + 3 * k, 92 + k)).cuda() for k, l in enumerate(ligs)]
+    mixed = [dk.LSState.start(g) for g in gens]
+    alone = [m.clone() for m in mixed]
+    var = [(0, 1, 2, 0, 1, 3, 4, 0)[k] for k in range(len(ligs))]
+    def job(k, st):
+        return dk.LsJob(G, Ls[k], st, var[k], threads_per_ind=spec[k][2])
+    dk.local_search([job(k, s) for k, s in enumerate(mixed)], 15)
+    for k, s in enumerate(alone):
+        dk.local_search([job(k, s)], 15)
+    torch.cuda.synchronize()
+    for k, (a, m) in enumerate(zip(alone, mixed)):
+        an, mn = a.to_numpy(), m.to_numpy()
+        for f in an:
+            assert np.array_equal(an[f], mn[f]), (k, spec[k], f)
+        assert np.all(mn["iters_done"] == 15)
+        if spec[k][2] == 128 and var[k] in FP32_VARIANTS:
+            prep = R.prepare(ligs[k], ff)
+            ref = R.score(prep, grd, mn["best_genotype"].astype(np.float64))
+            flag = near_discontinuity(prep, grd, ref.x)
+            ok, _ = e_ok(mn["best_energy"], ref, mn["best_genotype"])
+            assert np.all(ok[~flag]), (k, e_relerr(mn["best_energy"], ref.energy).max())
 
 
 def test_ls_mixed_variants_in_one_launch(dk):

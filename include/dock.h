@@ -160,12 +160,16 @@ int32_t dock_ligand_info_get(const dock_ligand* lig, dock_ligand_info* out);
  *   pairs     [n_pairs]        (i << 16) | j with i < j (original indices),
  *                              sorted ascending
  *   pair_hb   [n_pairs]        1 for a donor-acceptor (12-10) pair, else 0
- *   batches   [n_batches][64]  the pair list as the kernels read it: one record
- *                              per lane, i | j << 7 | ci << 14 | cj << 18 |
- *                              hb << 22 | table << 23 | valid << 31, with i, j
- *                              depth-first positions and ci, cj < n_copies the
- *                              accumulator copies the pair's force goes to; within
- *                              a batch every (copy, atom) slot occurs at most once */
+ *   batches   [n_batches][64]  the pair list as the kernels read it, decoded: one
+ *                              record per lane, i | j << 7 | ci << 14 | cj << 18 |
+ *                              hb << 22 | valid << 31, with i, j depth-first
+ *                              positions and ci, cj < n_copies the accumulator
+ *                              copies the pair's force goes to; within a batch
+ *                              every (copy, atom) slot occurs at most once. An
+ *                              unused lane (valid clear) holds two slots no pair
+ *                              of its batch uses; its i, j may be "atoms" past
+ *                              n_atoms (below the next power of two, at least 16)
+ *                              whose slots are never summed */
 int32_t dock_ligand_export(const dock_ligand* lig, int32_t* order, int32_t* torsions,
                            int32_t* fragment, uint32_t* pairs, uint8_t* pair_hb,
                            uint32_t* batches);

@@ -267,8 +267,7 @@ int32_t dock_ligand_export(const dock_ligand* l, int32_t* order, int32_t* torsio
     }
     if (batches) {
         const dockblob::Header* h = reinterpret_cast<const dockblob::Header*>(P.blob.data());
-        const auto* pl = reinterpret_cast<const dockblob::PairRec*>(P.blob.data() + h->off_plist);
-        for (size_t k = 0; k < (size_t)h->n_batches * dockblob::kBatch; ++k) batches[k] = pl[k].rec;
+        for (int k = 0; k < h->n_batches * dockblob::kBatch; ++k) batches[k] = dockprep::record_of(P, k);
     }
     return ok();
 }

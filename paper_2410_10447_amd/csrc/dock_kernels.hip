@@ -244,19 +244,20 @@ __device__ __forceinline__ float4 sum4(float4 v) {
 // LDS of one individual. Sized per layout: SLOTS atoms per lane and WAVES
 // waves per individual (a wave of the two-wave layout owns 64 atoms and its
 // own range of accumulator copies). A ligand of at most 64 atoms has at most
-// 128 + 2N <= 256 accumulator slots (n_copies <= 128/N + 2).
+// 320 accumulator slots (n_copies * stride, n_copies <= 128/N + 2).
 template <int SLOTS, int WAVES = 1>
 struct __align__(16) Smem {
     static constexpr int kAtoms = kWave * SLOTS * WAVES;
     static constexpr int kSlots =
         (SLOTS == 1 && WAVES == 1) ? dockblob::kMaxSlotsSmall : dockblob::kMaxSlots * WAVES;
-    float4 dyn[kAtoms];             // x, y, z relative to t, and sqrt(kElec) q (depth-first order)
+    float4 dyn[kAtoms];             // x, y, z relative to t, and sqrt(kElec) q (depth-first
+                                    // order); zero past the last atom
     union {
         float tk[kMaxTors + 1][12]; // torsion transforms, 3x4 row-major, and the identity
                                     // (index kMaxTors); live until the atom positions are
                                     // written
-        float4 acc[kSlots];         // pair-force accumulators, slot = (range * C + copy) * N
-                                    // + atom, one range per wave
+        float4 acc[kSlots];         // pair-force accumulators, slot = (range * C + copy) *
+                                    // stride + atom, one range per wave
     } u;
     float4 tor[kMaxTors][2];        // torsion k: axis point p and packed positions
                                     // (a | b << 8 | first << 16 | end << 24), unit axis u
@@ -273,6 +274,8 @@ template <int SLOTS>
 struct Lig {
     // uniform
     int N, T, NF, G, n_batches, n_copies, max_depth;
+    int stride;                     // accumulator stride (power of two >= N)
+    int pmask;                      // stride * 16 - 1: slot byte offset -> position byte offset
     int wv;                         // wave of the individual (two-wave layout), else 0
     const u32x4* plist;             // pair records (dockblob::PairRec), n_batches x 64
     // per lane, per slot: atom a = lane + 64 * (slot + wv)
@@ -297,6 +300,8 @@ __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem<SLOTS, WAVES>
     L.n_batches = uniform(h->n_batches);
     L.n_copies = uniform(h->n_copies);
     L.max_depth = uniform(h->max_depth);
+    L.stride = uniform(h->slot_stride);
+    L.pmask = L.stride * 16 - 1;
     L.plist = uniform_ptr(reinterpret_cast<const u32x4*>(blob + h->off_plist));
     const float4* ref = reinterpret_cast<const float4*>(blob + h->off_ref);
     const float4* chg = reinterpret_cast<const float4*>(blob + h->off_chg);
@@ -451,15 +456,18 @@ __device__ __forceinline__ void pair_term(float dx, float dy, float dz, float A,
     const bool capped = elj > kCap;
     elj = capped ? kCap : elj;
     dlj = capped ? 0.f : dlj;
-    // Mehler-Solmajer dielectric eps(r) = A' + B' / (1 + K exp(-lambda B' r)),
-    // d eps / dr = lambda B'^2 K exp(-lambda B' r) / (1 + K exp(...))^2
+    // Mehler-Solmajer dielectric eps(r) = A' + B' / D, D = 1 + K exp(-lambda B' r),
+    // d eps / dr = lambda B'^2 K exp(-lambda B' r) / D^2. With M = D eps =
+    // A' D + B' (> 0 for every r) one reciprocal q = 1 / (r D M) gives both
+    // 1 / (r eps) = D^2 q and r eps' / eps = lambda B'^2 K exp(..) r^2 q.
     const float ex = __builtin_amdgcn_exp2f(-kDielLB * kLog2e * r);
-    const float iden = __builtin_amdgcn_rcpf(1.f + kDielK * ex);
-    const float epsr = kDielA + kDielB * iden;
-    const float ired = __builtin_amdgcn_rcpf(r * epsr);
+    const float D = fmaf(kDielK, ex, 1.f);
+    const float M = fmaf(kDielA, D, kDielB);
+    const float q = __builtin_amdgcn_rcpf((r * D) * M);
+    const float ired = (D * D) * q;
     const float eel = qq * ired;
-    // r dE/dr = -E (1 + r eps' / eps), and r / eps = r^2 / (r eps)
-    const float del = -eel * fmaf(((r2 * ired) * (ex * iden)) * iden, kDielBKLB, 1.f);
+    // r dE/dr = -E (1 + r eps' / eps)
+    const float del = -eel * fmaf((r2 * ex) * q, kDielBKLB, 1.f);
     // desolvation ds exp(-r^2 / (2 sigma^2)), r dE/dr = -E r^2 / sigma^2
     const float eds = ds * __builtin_amdgcn_exp2f(-kDsInv2S2 * kLog2e * r2);
     e = live ? elj + eel + eds : 0.f;
@@ -479,20 +487,13 @@ struct PairForce {
 template <int V>
 struct IntC { static constexpr int value = V; };
 
-// 24-bit multiply-add: full rate, where a 32-bit integer multiply is not.
-__device__ __forceinline__ int mad24(int a, int b, int c) {
-    return (int)(__umul24((unsigned)a, (unsigned)b) + (unsigned)c);
-}
-
-// Unused lanes (valid bit clear) carry two slots no pair of their batch uses
-// and get zero energy and force, so every lane updates its slots.
-__device__ __forceinline__ PairForce pair_force(u32x4 pr, float4 pi, float4 pj, int N16) {
+// Unused lanes (A = -0.0f) carry two slots no pair of their batch uses and
+// get zero energy and force, so every lane updates its slots.
+__device__ __forceinline__ PairForce pair_force(u32x4 pr, float4 pi, float4 pj) {
     PairForce o;
     const uint32_t rec = pr.x;
-    const bool valid = (rec & dockblob::kRecValid) != 0u;
-    const int i = rec & 127, j = (rec >> 7) & 127;
-    const int ci = (rec >> 14) & 15, cj = (rec >> 18) & 15;
-    const bool hb = (rec >> 22) & 1u;
+    const bool valid = pr.y != dockblob::kPadC12;
+    const bool hb = (int)rec < 0;
     const float dx = pj.x - pi.x, dy = pj.y - pi.y, dz = pj.z - pi.z;
     const float qq = pi.w * pj.w;           // charges pre-scaled by sqrt(kElec)
     float e, w;
@@ -503,8 +504,8 @@ __device__ __forceinline__ PairForce pair_force(u32x4 pr, float4 pi, float4 pj, 
     o.dx = dx;
     o.dy = dy;
     o.dz = dz;
-    o.si = mad24(ci, N16, i << 4);
-    o.sj = mad24(cj, N16, j << 4);
+    o.si = rec & dockblob::kSlotMask;
+    o.sj = (rec >> dockblob::kSlotShift) & dockblob::kSlotMask;
     return o;
 }
 
@@ -618,7 +619,9 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
         }
 #pragma unroll
         for (int r = 0; r < 3; ++r) x[s][r] = Rq[3 * r] * y0 + Rq[3 * r + 1] * y1 + Rq[3 * r + 2] * y2;
-        if (a < N) sm.dyn[a] = make_float4(x[s][0], x[s][1], x[s][2], kSqrtElec * L.chg[s][1]);
+        // entries past the last atom hold zeros (unused pair lanes may read them)
+        sm.dyn[a] = a < N ? make_float4(x[s][0], x[s][1], x[s][2], kSqrtElec * L.chg[s][1])
+                          : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     __syncthreads();
 
@@ -635,7 +638,7 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
     {
         // each wave adds into its own range of copies; a wave of the two-wave
         // layout takes its half of the batches
-        const int nslot = L.n_copies * N;
+        const int nslot = L.n_copies * L.stride;
         float4* const accw = sm.u.acc + (WAVES == 1 ? 0 : L.wv * nslot);
         for (int k = lane; k < nslot; k += kWave) accw[k] = make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
@@ -643,7 +646,10 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
         const int half = (nb_all + 1) >> 1;
         const int nb = WAVES == 1 ? nb_all : (L.wv == 0 ? half : nb_all - half);
         const auto plist = gmem(L.plist) + (WAVES == 1 || L.wv == 0 ? 0 : half * kWave);
-        const int N16 = N * 16;
+        const int pmask = L.pmask;
+        // an atom's position sits at its slot's byte offset masked to one stride
+        auto pos_i = [&](uint32_t w) { return *slot(sm.dyn, w & pmask); };
+        auto pos_j = [&](uint32_t w) { return *slot(sm.dyn, (w >> dockblob::kSlotShift) & pmask); };
         // Software pipeline over batches with no branch inside. Step k
         // stores batch k (its slot values were read in step k - 1) and
         // computes batch k + 1 while reading the positions of batch k + 2
@@ -670,23 +676,23 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s) grid_load(G, L.cls[s], x[s], tv, tap[s]);
             __builtin_amdgcn_sched_barrier(0);
-            Pi[0] = sm.dyn[R[0].x & 127];
-            Pj[0] = sm.dyn[(R[0].x >> 7) & 127];
-            F[0] = pair_force(R[0], Pi[0], Pj[0], N16);
+            Pi[0] = pos_i(R[0].x);
+            Pj[0] = pos_j(R[0].x);
+            F[0] = pair_force(R[0], Pi[0], Pj[0]);
             Ai[0] = *slot(accw, F[0].si);
             Aj[0] = *slot(accw, F[0].sj);
-            Pi[1] = sm.dyn[R[1].x & 127];
-            Pj[1] = sm.dyn[(R[1].x >> 7) & 127];
+            Pi[1] = pos_i(R[1].x);
+            Pj[1] = pos_j(R[1].x);
             int k = 0;
             auto step = [&](auto residue) {
                 constexpr int r = decltype(residue)::value;  // k mod 4
                 constexpr int c = r & 1, n = (r + 1) & 1;
                 const u32x4 rf = R[(r + 2) & 3];
-                Pi[c] = sm.dyn[rf.x & 127];
-                Pj[c] = sm.dyn[(rf.x >> 7) & 127];
+                Pi[c] = pos_i(rf.x);
+                Pj[c] = pos_j(rf.x);
                 R[r] = record(k + 4);
                 __builtin_amdgcn_sched_barrier(0);   // keep the loads at the step's start
-                F[n] = pair_force(R[(r + 1) & 3], Pi[n], Pj[n], N16);
+                F[n] = pair_force(R[(r + 1) & 3], Pi[n], Pj[n]);
                 store_force(accw, F[c], Ai[c], Aj[c]);
                 e_lane += F[c].e;
                 Ai[n] = *slot(accw, F[n].si);
@@ -722,7 +728,7 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
             g[s][0] = g[s][1] = g[s][2] = 0.f;
             if (a < N) {
                 for (int c = 0; c < L.n_copies * WAVES; ++c) {
-                    const float4 v = sm.u.acc[c * N + a];
+                    const float4 v = sm.u.acc[c * L.stride + a];
                     g[s][0] += v.x;
                     g[s][1] += v.y;
                     g[s][2] += v.z;

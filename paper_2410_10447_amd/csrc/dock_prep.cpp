@@ -151,7 +151,7 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
     const int n_pairs = (int)plist.size();
     // batches of kBatch pairs, each atom at most C times per batch. C grows for
     // small ligands so that C * N can hold a full batch's 128 pair ends (up to
-    // 15, the largest copy index a record holds besides the spare copy). The
+    // 15, the largest copy index a record holds). The
     // batch count starts at its lower bound, max(P / 64, max degree / C);
     // pairs are placed most-constrained first (largest endpoint degree), each
     // into the open batch where its two atoms are used least (then the least
@@ -161,7 +161,8 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
     const int C = std::max(2, std::min(15, (2 * kBatch + N - 1) / N + 1));
     using dockblob::kMaxSlots;
     using dockblob::kMaxSlotsSmall;
-    if (C * N > (N <= 64 ? kMaxSlotsSmall : kMaxSlots)) {
+    const int S = dockblob::slot_stride(N);
+    if (C * S > (N <= 64 ? kMaxSlotsSmall : kMaxSlots)) {
         err = "internal: accumulator slots exceed the build limit"; return DOCK_EUNSUPPORTED;
     }
     std::vector<int> degp(N, 0);
@@ -198,16 +199,16 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
         if (placed_all) {
             // Unused lanes get records with the valid bit clear whose two
             // slots are distinct and unused in their batch: first free copies
-            // of real atoms, then spare slots C * N + t (copy index C,
-            // "atom" t < 64, needed only when C * N < 128). Their force is
+            // of real atoms, then slots of the "atoms" N .. S-1 past the end
+            // (C * S >= 128 + N > 128 always leaves enough). Their force is
             // zero, so every lane may update its slots without a branch.
             for (int b = 0; b < nb; ++b) {
                 std::vector<std::pair<int, int>> free_slots;  // (copy, atom)
                 for (int c = 0; c < C; ++c)
                     for (int a = 0; a < N; ++a)
                         if (c >= use[size_t(b) * N + a]) free_slots.push_back({c, a});
-                for (int t = 0; t < kBatch && C * N + t < (N <= 64 ? kMaxSlotsSmall : kMaxSlots); ++t)
-                    free_slots.push_back({C, t});
+                for (int c = 0; c < C; ++c)
+                    for (int a = N; a < S; ++a) free_slots.push_back({c, a});
                 size_t f = 0;
                 while ((int)batch[b].size() < kBatch) {
                     if (f + 1 >= free_slots.size()) {
@@ -247,6 +248,7 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
     h.max_depth = max_depth;
     h.n_batches = n_batches;
     h.n_copies = C;
+    h.slot_stride = S;
     h.total_bytes = (int32_t)off;
     int max_class = 0;
     for (int i = 0; i < N; ++i) max_class = std::max(max_class, (int)d.cls[i]);
@@ -295,9 +297,11 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
         for (size_t k = 0; k < batch[b].size(); ++k) {
             const uint32_t r = batch[b][k];
             PairRec& o = pl[b * kBatch + k];
-            o.rec = r;
+            o.rec = dockblob::device_word(r, S);
             if (!(r & kRecValid)) {
-                o.c12 = o.cm = o.ds = 0.f;
+                uint32_t neg_zero = kPadC12;
+                std::memcpy(&o.c12, &neg_zero, sizeof(float));
+                o.cm = o.ds = 0.f;
                 continue;
             }
             const int i = order[r & 127], j = order[(r >> 7) & 127];
@@ -344,13 +348,21 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
     return DOCK_OK;
 }
 
+uint32_t record_of(const Prepared& P, int k) {
+    using namespace dockblob;
+    const Header* h = reinterpret_cast<const Header*>(P.blob.data());
+    const PairRec& pr = reinterpret_cast<const PairRec*>(P.blob.data() + h->off_plist)[k];
+    uint32_t c12_bits;
+    std::memcpy(&c12_bits, &pr.c12, sizeof(float));
+    return logical_record(pr.rec, c12_bits != kPadC12, h->slot_stride);
+}
+
 void decode_pairs(const Prepared& P, std::vector<uint32_t>& pairs, std::vector<uint8_t>& hb) {
     using namespace dockblob;
     const Header* h = reinterpret_cast<const Header*>(P.blob.data());
-    const PairRec* pl = reinterpret_cast<const PairRec*>(P.blob.data() + h->off_plist);
     std::vector<std::pair<uint32_t, uint8_t>> v;
     for (int k = 0; k < h->n_batches * kBatch; ++k) {
-        const uint32_t r = pl[k].rec;
+        const uint32_t r = record_of(P, k);
         if (!(r & kRecValid)) continue;
         const int i = P.order[r & 127], j = P.order[(r >> 7) & 127];
         const uint32_t lo = (uint32_t)std::min(i, j), hi = (uint32_t)std::max(i, j);

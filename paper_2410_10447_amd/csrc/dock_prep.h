@@ -27,5 +27,7 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& out, std::string& err);
 
 // Pairs decoded from the blob's masks: (i << 16) | j, i < j original, sorted.
 void decode_pairs(const Prepared& p, std::vector<uint32_t>& pairs, std::vector<uint8_t>& hb);
+// Record k of the packed pair list, in the logical layout (dockblob).
+uint32_t record_of(const Prepared& p, int k);
 
 }  // namespace dockprep

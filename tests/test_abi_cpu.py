@@ -71,10 +71,12 @@ def _check_prep(lig):
 def _check_batches(b, C, N, p, order):
     """Batch records: valid pairs are the pair list; every lane of a batch,
     unused lanes included, owns two (copy, atom) slots no other lane of the
-    batch touches; unused lanes take free copies of real atoms, or spare
-    slots C*N + t (copy index C) inside the accumulator."""
-    cap = 256 if N <= 64 else 384
-    assert C * N <= cap and 2 <= C <= 15
+    batch touches; unused lanes take free copies of real atoms, or slots of
+    the "atoms" N .. S-1 (S the power-of-two stride >= max(N, 16)) that are
+    never summed; C * S fits the accumulator."""
+    S = max(16, 1 << (N - 1).bit_length())
+    cap = 320 if N <= 64 else 384
+    assert C * S <= cap and 2 <= C <= 15
     got = []
     for row in b:
         slots = []
@@ -84,7 +86,7 @@ def _check_batches(b, C, N, p, order):
             if not (r >> 31) & 1:
                 assert (r >> 22) == 0, "unused lane with flags"
                 for c, a in ((ci, i), (cj, j)):
-                    assert (c < C and a < N) or (c == C and a < 64 and C * N + a < cap), (c, a)
+                    assert c < C and a < S, (c, a)
                 slots += [(ci, i), (cj, j)]
                 continue
             assert i < N and j < N and ci < C and cj < C

@@ -28,6 +28,114 @@ int role_index(const int32_t list[2], int c) {
     return -1;
 }
 
+// LDS bank spreading of one batch. A wave's 16-byte LDS accesses are
+// served a group of lanes at a time, and two lanes of a group whose
+// addresses fall into the same bank quad (address / 16 modulo the group's
+// quad count) wait for each other. The pair loop reads the first and the
+// second atom of each lane's pair (position and slot: with a stride that is a
+// multiple of 16 both lie in the quad of the atom index), so the batch's
+// records are permuted over the lanes, and a pair's two atoms may swap roles,
+// to spread those quads over every aligned group of 8 lanes (modulo 8) and
+// of 16 lanes (modulo 16): a descent on the sum of squared quad counts. The
+// unused lanes then take, one by one, the free slots whose quads are least
+// used in their groups. Neither step changes which slots a pair updates or
+// the order of additions to any slot.
+struct LaneCounts {
+    int c8[2][8][8] = {};     // [stream][group of 8 lanes][index mod 8]
+    int c16[2][4][16] = {};   // [stream][group of 16 lanes][index mod 16]
+    long long cost = 0;
+    void add(int stream, int lane, int atom, int sgn) {
+        int& a = c8[stream][lane >> 3][atom & 7];
+        int& b = c16[stream][lane >> 4][atom & 15];
+        if (sgn > 0) { cost += 2 * a + 1; ++a; cost += 2 * b + 1; ++b; }
+        else { --a; cost -= 2 * a + 1; --b; cost -= 2 * b + 1; }
+    }
+};
+
+std::vector<uint32_t> arrange_batch(const std::vector<uint32_t>& real, const uint8_t* use, int N, int S,
+                                    int C, uint64_t seed, std::string& err) {
+    const int B = dockblob::kBatch;
+    const int n = (int)real.size();
+    // lane -> record index (-1: unused lane), and whether the pair's atoms swap
+    std::vector<int> item(B, -1);
+    std::vector<uint8_t> flip(B, 0);
+    for (int l = 0; l < n; ++l) item[l] = l;
+    auto atom = [&](int l, int end) {  // atom of lane l's first (end 0) or second (end 1) role
+        const uint32_t r = real[item[l]];
+        const int i = r & 127, j = (r >> 7) & 127;
+        return (end ^ flip[l]) ? j : i;
+    };
+    LaneCounts lc;
+    auto place = [&](int l, int sgn) {
+        if (item[l] < 0) return;
+        lc.add(0, l, atom(l, 0), sgn);
+        lc.add(1, l, atom(l, 1), sgn);
+    };
+    for (int l = 0; l < B; ++l) place(l, +1);
+    uint64_t x = seed * 0x9E3779B97F4A7C15ull + 1;
+    auto rnd = [&]() { x ^= x << 13; x ^= x >> 7; x ^= x << 17; return x; };
+    int since = 0;
+    for (int it = 0; it < 40000 && since < 3000 && n > 0; ++it) {
+        const long long before = lc.cost;
+        const int a = (int)(rnd() % B);
+        const bool do_flip = (rnd() & 3) == 0;
+        const int b = do_flip ? a : (int)(rnd() % B);
+        if ((do_flip && item[a] < 0) || (!do_flip && (a == b || (item[a] < 0 && item[b] < 0)))) { ++since; continue; }
+        place(a, -1);
+        if (b != a) place(b, -1);
+        if (do_flip) flip[a] ^= 1; else { std::swap(item[a], item[b]); std::swap(flip[a], flip[b]); }
+        place(a, +1);
+        if (b != a) place(b, +1);
+        if (lc.cost <= before) {
+            since = lc.cost < before ? 0 : since + 1;
+            continue;
+        }
+        place(a, -1);
+        if (b != a) place(b, -1);
+        if (do_flip) flip[a] ^= 1; else { std::swap(item[a], item[b]); std::swap(flip[a], flip[b]); }
+        place(a, +1);
+        if (b != a) place(b, +1);
+        ++since;
+    }
+    // free slots (copy, atom): unused copies of real atoms, then every slot of
+    // the atoms N .. S-1 past the end
+    std::vector<std::pair<int, int>> free_slots;
+    for (int c = 0; c < C; ++c)
+        for (int a = 0; a < S; ++a)
+            if (a >= N || c >= use[a]) free_slots.push_back({c, a});
+    std::vector<uint8_t> taken(free_slots.size(), 0);
+    auto take_best = [&](int stream, int l) -> int {
+        int best = -1;
+        long long best_cost = 0;
+        for (size_t k = 0; k < free_slots.size(); ++k) {
+            if (taken[k]) continue;
+            const int a = free_slots[k].second;
+            const long long c = lc.c8[stream][l >> 3][a & 7] + lc.c16[stream][l >> 4][a & 15];
+            if (best < 0 || c < best_cost) { best = (int)k; best_cost = c; }
+        }
+        if (best >= 0) {
+            taken[best] = 1;
+            lc.add(stream, l, free_slots[best].second, +1);
+        }
+        return best;
+    };
+    std::vector<uint32_t> out(B);
+    for (int l = 0; l < B; ++l) {
+        if (item[l] >= 0) {
+            const uint32_t r = real[item[l]];
+            if (!flip[l]) { out[l] = r; continue; }
+            const uint32_t i = r & 127, j = (r >> 7) & 127, ci = (r >> 14) & 15, cj = (r >> 18) & 15;
+            out[l] = (r & ~0x3FFFFFu) | j | (i << 7) | (cj << 14) | (ci << 18);
+            continue;
+        }
+        const int u = take_best(0, l), v = take_best(1, l);
+        if (u < 0 || v < 0) { err = "internal: no free accumulator slots for batch padding"; return {}; }
+        out[l] = dockblob::make_pad_record(free_slots[u].second, free_slots[v].second,
+                                           free_slots[u].first, free_slots[v].first);
+    }
+    return out;
+}
+
 }  // namespace
 
 int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
@@ -197,28 +305,15 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
             batch[best].push_back(dockblob::make_record(pr.p, pr.q, ci, cj, pr.hb, pr.table));
         }
         if (placed_all) {
+            // Lanes are arranged for LDS bank spreading (arrange_batch).
             // Unused lanes get records with the valid bit clear whose two
-            // slots are distinct and unused in their batch: first free copies
-            // of real atoms, then slots of the "atoms" N .. S-1 past the end
+            // slots are distinct and unused in their batch: free copies of
+            // real atoms or slots of the "atoms" N .. S-1 past the end
             // (C * S >= 128 + N > 128 always leaves enough). Their force is
             // zero, so every lane may update its slots without a branch.
             for (int b = 0; b < nb; ++b) {
-                std::vector<std::pair<int, int>> free_slots;  // (copy, atom)
-                for (int c = 0; c < C; ++c)
-                    for (int a = 0; a < N; ++a)
-                        if (c >= use[size_t(b) * N + a]) free_slots.push_back({c, a});
-                for (int c = 0; c < C; ++c)
-                    for (int a = N; a < S; ++a) free_slots.push_back({c, a});
-                size_t f = 0;
-                while ((int)batch[b].size() < kBatch) {
-                    if (f + 1 >= free_slots.size()) {
-                        err = "internal: no free accumulator slots for batch padding";
-                        return DOCK_EUNSUPPORTED;
-                    }
-                    const auto u = free_slots[f], v = free_slots[f + 1];
-                    f += 2;
-                    batch[b].push_back(dockblob::make_pad_record(u.second, v.second, u.first, v.first));
-                }
+                batch[b] = arrange_batch(batch[b], &use[size_t(b) * N], N, S, C, (uint64_t)b + 1, err);
+                if (batch[b].empty()) return DOCK_EUNSUPPORTED;
             }
             break;
         }

@@ -516,11 +516,11 @@ __device__ __forceinline__ float4* slot(float4* base, int byte_offset) {
 }
 
 // Adds -w d to slot si and +w d to slot sj, from their values read earlier.
+// Slots are read and written whole (the fourth word passes through): 16-byte
+// LDS accesses are served 16 lanes at a time, 12-byte ones take longer.
 __device__ __forceinline__ void store_force(float4* base, const PairForce& f, float4 ai, float4 aj) {
-    float4* pi = slot(base, f.si);
-    float4* pj = slot(base, f.sj);
-    pi->x = fmaf(-f.w, f.dx, ai.x); pi->y = fmaf(-f.w, f.dy, ai.y); pi->z = fmaf(-f.w, f.dz, ai.z);
-    pj->x = fmaf(f.w, f.dx, aj.x); pj->y = fmaf(f.w, f.dy, aj.y); pj->z = fmaf(f.w, f.dz, aj.z);
+    *slot(base, f.si) = make_float4(fmaf(-f.w, f.dx, ai.x), fmaf(-f.w, f.dy, ai.y), fmaf(-f.w, f.dz, ai.z), ai.w);
+    *slot(base, f.sj) = make_float4(fmaf(f.w, f.dx, aj.x), fmaf(f.w, f.dy, aj.y), fmaf(f.w, f.dz, aj.z), aj.w);
 }
 
 // ---------------------------------------------------------------------------

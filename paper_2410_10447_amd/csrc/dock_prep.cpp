@@ -29,73 +29,160 @@ int role_index(const int32_t list[2], int c) {
 }
 
 // LDS bank spreading of one batch. A wave's 16-byte LDS accesses are
-// served a group of lanes at a time, and two lanes of a group whose
-// addresses fall into the same bank quad (address / 16 modulo the group's
-// quad count) wait for each other. The pair loop reads the first and the
-// second atom of each lane's pair (position and slot: with a stride that is a
-// multiple of 16 both lie in the quad of the atom index), so the batch's
-// records are permuted over the lanes, and a pair's two atoms may swap roles,
-// to spread those quads over every aligned group of 8 lanes (modulo 8) and
-// of 16 lanes (modulo 16): a descent on the sum of squared quad counts. The
-// unused lanes then take, one by one, the free slots whose quads are least
-// used in their groups. Neither step changes which slots a pair updates or
-// the order of additions to any slot.
+// served 16 lanes at a time over 64 four-byte banks (16 bank quads), and two
+// lanes of a group whose different addresses fall into the same quad
+// (address / 16 modulo 16) wait for each other. The pair loop reads and
+// writes the first and the second atom of each lane's pair (position and
+// slot: with a stride that is a multiple of 16 both lie in the quad of the
+// atom index, its residue mod 16). The batch's records are therefore placed
+// on the lanes, and a pair's two atoms may swap roles, so that within each
+// aligned group of 16 lanes the first atoms' residues differ and so do the
+// second atoms'. Seen as a multigraph on the 16 residues with one edge per
+// pair, this is an orientation followed by an edge colouring with 4 colours
+// (one per lane group): the orientation follows Euler circuits, so each
+// residue is first atom about as often as second (|out - in| <= 1), and the
+// bipartite (first residue, second residue) multigraph, after setting aside
+// the few pairs that push a residue past 4 uses per role, is coloured with 4
+// colours by Kempe-chain recolouring (Konig's theorem: a bipartite multigraph
+// of maximum degree 4 has a proper 4-edge colouring); the pairs set aside go
+// to the groups with room, where they add the fewest repeats. The unused lanes then take, one by one, the free
+// slots whose residues their group uses least. Neither step changes which
+// slots a pair updates or the order of additions to any slot.
 struct LaneCounts {
-    int c8[2][8][8] = {};     // [stream][group of 8 lanes][index mod 8]
-    int c16[2][4][16] = {};   // [stream][group of 16 lanes][index mod 16]
-    long long cost = 0;
-    void add(int stream, int lane, int atom, int sgn) {
-        int& a = c8[stream][lane >> 3][atom & 7];
-        int& b = c16[stream][lane >> 4][atom & 15];
-        if (sgn > 0) { cost += 2 * a + 1; ++a; cost += 2 * b + 1; ++b; }
-        else { --a; cost -= 2 * a + 1; --b; cost -= 2 * b + 1; }
-    }
+    int c16[2][4][16] = {};   // [role][group of 16 lanes][atom index mod 16]
+    void add(int role, int lane, int atom) { ++c16[role][lane >> 4][atom & 15]; }
 };
 
+// Orients the edges (u[e], v[e]) of a multigraph on 16 vertices along Euler
+// circuits (odd vertices paired by virtual edges): flip[e] = 1 reverses edge e.
+void euler_orient(const std::vector<int>& u, const std::vector<int>& v, std::vector<uint8_t>& flip) {
+    const int n = (int)u.size();
+    std::vector<int> eu(u), ev(v);
+    std::vector<int> deg(16, 0);
+    for (int e = 0; e < n; ++e) { ++deg[eu[e]]; ++deg[ev[e]]; }
+    int odd = -1;
+    for (int r = 0; r < 16; ++r)
+        if (deg[r] & 1) {
+            if (odd < 0) { odd = r; continue; }
+            eu.push_back(odd); ev.push_back(r); odd = -1;
+        }
+    const int m = (int)eu.size();
+    std::vector<std::vector<int>> adj(16);
+    for (int e = 0; e < m; ++e) { adj[eu[e]].push_back(e); if (ev[e] != eu[e]) adj[ev[e]].push_back(e); }
+    std::vector<uint8_t> used(m, 0);
+    std::vector<size_t> next(16, 0);
+    flip.assign(n, 0);
+    for (int start = 0; start < 16; ++start) {
+        // walk unused edges from `start`, orienting each edge in the walking direction
+        int cur = start;
+        while (true) {
+            while (next[cur] < adj[cur].size() && used[adj[cur][next[cur]]]) ++next[cur];
+            if (next[cur] == adj[cur].size()) {
+                // stuck (closed a circuit): continue from any vertex with unused edges
+                int w = -1;
+                for (int r = 0; r < 16 && w < 0; ++r) {
+                    while (next[r] < adj[r].size() && used[adj[r][next[r]]]) ++next[r];
+                    if (next[r] < adj[r].size()) w = r;
+                }
+                if (w < 0) break;
+                cur = w;
+                continue;
+            }
+            const int e = adj[cur][next[cur]];
+            used[e] = 1;
+            const int to = (eu[e] == cur) ? ev[e] : eu[e];
+            if (e < n) flip[e] = (eu[e] == cur) ? 0 : 1;
+            cur = to;
+        }
+    }
+}
+
 std::vector<uint32_t> arrange_batch(const std::vector<uint32_t>& real, const uint8_t* use, int N, int S,
-                                    int C, uint64_t seed, std::string& err) {
+                                    int C, std::string& err) {
     const int B = dockblob::kBatch;
     const int n = (int)real.size();
-    // lane -> record index (-1: unused lane), and whether the pair's atoms swap
-    std::vector<int> item(B, -1);
-    std::vector<uint8_t> flip(B, 0);
-    for (int l = 0; l < n; ++l) item[l] = l;
-    auto atom = [&](int l, int end) {  // atom of lane l's first (end 0) or second (end 1) role
-        const uint32_t r = real[item[l]];
-        const int i = r & 127, j = (r >> 7) & 127;
-        return (end ^ flip[l]) ? j : i;
-    };
-    LaneCounts lc;
-    auto place = [&](int l, int sgn) {
-        if (item[l] < 0) return;
-        lc.add(0, l, atom(l, 0), sgn);
-        lc.add(1, l, atom(l, 1), sgn);
-    };
-    for (int l = 0; l < B; ++l) place(l, +1);
-    uint64_t x = seed * 0x9E3779B97F4A7C15ull + 1;
-    auto rnd = [&]() { x ^= x << 13; x ^= x >> 7; x ^= x << 17; return x; };
-    int since = 0;
-    for (int it = 0; it < 40000 && since < 3000 && n > 0; ++it) {
-        const long long before = lc.cost;
-        const int a = (int)(rnd() % B);
-        const bool do_flip = (rnd() & 3) == 0;
-        const int b = do_flip ? a : (int)(rnd() % B);
-        if ((do_flip && item[a] < 0) || (!do_flip && (a == b || (item[a] < 0 && item[b] < 0)))) { ++since; continue; }
-        place(a, -1);
-        if (b != a) place(b, -1);
-        if (do_flip) flip[a] ^= 1; else { std::swap(item[a], item[b]); std::swap(flip[a], flip[b]); }
-        place(a, +1);
-        if (b != a) place(b, +1);
-        if (lc.cost <= before) {
-            since = lc.cost < before ? 0 : since + 1;
-            continue;
+    std::vector<int> ea(n), eb(n);   // first and second atom of each pair
+    for (int e = 0; e < n; ++e) { ea[e] = real[e] & 127; eb[e] = (real[e] >> 7) & 127; }
+    std::vector<int> ru(n), rv(n);
+    for (int e = 0; e < n; ++e) { ru[e] = ea[e] & 15; rv[e] = eb[e] & 15; }
+    std::vector<uint8_t> flip;
+    euler_orient(ru, rv, flip);
+    std::vector<int> tail(n), head(n);
+    for (int e = 0; e < n; ++e) {
+        tail[e] = flip[e] ? rv[e] : ru[e];
+        head[e] = flip[e] ? ru[e] : rv[e];
+    }
+    // Residues used more than 4 times as first (or second) atom cannot be
+    // kept apart in 4 groups: set aside as few pairs as needed to bring every
+    // residue to <= 4 uses per role, preferring pairs that relieve both ends.
+    std::vector<int> n_first(16, 0), n_second(16, 0);
+    for (int e = 0; e < n; ++e) { ++n_first[tail[e]]; ++n_second[head[e]]; }
+    std::vector<uint8_t> aside(n, 0);
+    for (int pass = 0; pass < 2; ++pass)
+        for (int e = 0; e < n; ++e) {
+            if (aside[e]) continue;
+            const bool xt = n_first[tail[e]] > 4, xh = n_second[head[e]] > 4;
+            if (pass == 0 ? (xt && xh) : (xt || xh)) {
+                aside[e] = 1;
+                --n_first[tail[e]];
+                --n_second[head[e]];
+            }
         }
-        place(a, -1);
-        if (b != a) place(b, -1);
-        if (do_flip) flip[a] ^= 1; else { std::swap(item[a], item[b]); std::swap(flip[a], flip[b]); }
-        place(a, +1);
-        if (b != a) place(b, +1);
-        ++since;
+    // Kempe-chain colouring of the rest, a bipartite multigraph (first-atom
+    // residues, second-atom residues) of maximum degree <= 4, with 4 colours
+    const int K = 4;
+    std::vector<int> at_t(16 * K, -1), at_h(16 * K, -1), col(n, -1);
+    for (int e = 0; e < n; ++e) {
+        if (aside[e]) continue;
+        const int t = tail[e], h = head[e];
+        int a = -1, b = -1;
+        for (int c = 0; c < K && a < 0; ++c) if (at_t[t * K + c] < 0) a = c;
+        for (int c = 0; c < K && b < 0; ++c) if (at_h[h * K + c] < 0) b = c;
+        if (at_h[h * K + a] >= 0) {
+            // swap colours a and b along the path from h that starts with colour a
+            std::vector<int> path;
+            int x = h, want = a;
+            bool on_head = true;
+            while (true) {
+                const int f = on_head ? at_h[x * K + want] : at_t[x * K + want];
+                if (f < 0) break;
+                path.push_back(f);
+                x = on_head ? tail[f] : head[f];
+                on_head = !on_head;
+                want = (want == a) ? b : a;
+            }
+            for (int f : path) { at_t[tail[f] * K + col[f]] = -1; at_h[head[f] * K + col[f]] = -1; }
+            for (int f : path) {
+                col[f] = (col[f] == a) ? b : a;
+                at_t[tail[f] * K + col[f]] = f;
+                at_h[head[f] * K + col[f]] = f;
+            }
+        }
+        col[e] = a;
+        at_t[t * K + a] = e;
+        at_h[h * K + a] = e;
+    }
+    // colour g = lane group g; the pairs set aside go where they add the
+    // fewest repeats
+    std::vector<std::vector<int>> groups(4);
+    LaneCounts lc;
+    for (int e = 0; e < n; ++e) {
+        if (aside[e]) continue;
+        groups[col[e]].push_back(e);
+        ++lc.c16[0][col[e]][tail[e]];
+        ++lc.c16[1][col[e]][head[e]];
+    }
+    for (int e = 0; e < n; ++e) {
+        if (!aside[e]) continue;
+        int best = -1, best_cost = 0;
+        for (int g = 0; g < 4; ++g) {
+            if ((int)groups[g].size() >= 16) continue;
+            const int c = lc.c16[0][g][tail[e]] + lc.c16[1][g][head[e]];
+            if (best < 0 || c < best_cost) { best = g; best_cost = c; }
+        }
+        groups[best].push_back(e);
+        ++lc.c16[0][best][tail[e]];
+        ++lc.c16[1][best][head[e]];
     }
     // free slots (copy, atom): unused copies of real atoms, then every slot of
     // the atoms N .. S-1 past the end
@@ -104,34 +191,34 @@ std::vector<uint32_t> arrange_batch(const std::vector<uint32_t>& real, const uin
         for (int a = 0; a < S; ++a)
             if (a >= N || c >= use[a]) free_slots.push_back({c, a});
     std::vector<uint8_t> taken(free_slots.size(), 0);
-    auto take_best = [&](int stream, int l) -> int {
-        int best = -1;
-        long long best_cost = 0;
+    auto take_best = [&](int role, int g) -> int {
+        int best = -1, best_cost = 0;
         for (size_t k = 0; k < free_slots.size(); ++k) {
             if (taken[k]) continue;
-            const int a = free_slots[k].second;
-            const long long c = lc.c8[stream][l >> 3][a & 7] + lc.c16[stream][l >> 4][a & 15];
+            const int c = lc.c16[role][g][free_slots[k].second & 15];
             if (best < 0 || c < best_cost) { best = (int)k; best_cost = c; }
         }
         if (best >= 0) {
             taken[best] = 1;
-            lc.add(stream, l, free_slots[best].second, +1);
+            ++lc.c16[role][g][free_slots[best].second & 15];
         }
         return best;
     };
-    std::vector<uint32_t> out(B);
-    for (int l = 0; l < B; ++l) {
-        if (item[l] >= 0) {
-            const uint32_t r = real[item[l]];
-            if (!flip[l]) { out[l] = r; continue; }
+    std::vector<uint32_t> out;
+    out.reserve(B);
+    for (int g = 0; g < 4; ++g) {
+        for (int e : groups[g]) {
+            const uint32_t r = real[e];
+            if (!flip[e]) { out.push_back(r); continue; }
             const uint32_t i = r & 127, j = (r >> 7) & 127, ci = (r >> 14) & 15, cj = (r >> 18) & 15;
-            out[l] = (r & ~0x3FFFFFu) | j | (i << 7) | (cj << 14) | (ci << 18);
-            continue;
+            out.push_back((r & ~0x3FFFFFu) | j | (i << 7) | (cj << 14) | (ci << 18));
         }
-        const int u = take_best(0, l), v = take_best(1, l);
-        if (u < 0 || v < 0) { err = "internal: no free accumulator slots for batch padding"; return {}; }
-        out[l] = dockblob::make_pad_record(free_slots[u].second, free_slots[v].second,
-                                           free_slots[u].first, free_slots[v].first);
+        for (int l = (int)groups[g].size(); l < 16; ++l) {
+            const int u = take_best(0, g), v = take_best(1, g);
+            if (u < 0 || v < 0) { err = "internal: no free accumulator slots for batch padding"; return {}; }
+            out.push_back(dockblob::make_pad_record(free_slots[u].second, free_slots[v].second,
+                                                    free_slots[u].first, free_slots[v].first));
+        }
     }
     return out;
 }
@@ -262,9 +349,11 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
     // 15, the largest copy index a record holds). The
     // batch count starts at its lower bound, max(P / 64, max degree / C);
     // pairs are placed most-constrained first (largest endpoint degree), each
-    // into the open batch where its two atoms are used least (then the least
-    // filled batch, then the lowest index); if a pair finds no batch, the
-    // count grows by one and the placement restarts.
+    // into the open batch where its atoms' residues mod 16 stay within 8 uses
+    // (the share of a full batch's 128 pair ends, which lets arrange_batch
+    // place the batch without LDS bank repeats), then where its two atoms are
+    // used least, then the least filled batch, then the lowest index; if a
+    // pair finds no batch, the count grows by one and the placement restarts.
     using dockblob::kBatch;
     const int C = std::max(2, std::min(15, (2 * kBatch + N - 1) / N + 1));
     using dockblob::kMaxSlots;
@@ -288,19 +377,27 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
         batch.assign(nb, {});
         std::vector<int> cnt(nb, 0);
         std::vector<uint8_t> use(size_t(nb) * N, 0);
+        std::vector<int> rload(size_t(nb) * 16, 0);   // pair ends per residue mod 16
         bool placed_all = true;
         for (int k : porder) {
             const KeptPair& pr = plist[k];
-            int best = -1, best_score = 0;
+            const int rp = pr.p & 15, rq = pr.q & 15;
+            int best = -1;
+            long long best_score = 0;
             for (int b = 0; b < nb; ++b) {
                 const int up = use[size_t(b) * N + pr.p], uq = use[size_t(b) * N + pr.q];
                 if (cnt[b] >= kBatch || up >= C || uq >= C) continue;
-                const int score = -(up + uq) * 1000 - cnt[b];
+                const int* rl = &rload[size_t(b) * 16];
+                const int over = rp == rq ? std::max(0, rl[rp] + 2 - 8)
+                                          : std::max(0, rl[rp] + 1 - 8) + std::max(0, rl[rq] + 1 - 8);
+                const long long score = -(long long)over * 1000000 - (up + uq) * 1000 - cnt[b];
                 if (best < 0 || score > best_score) { best = b; best_score = score; }
             }
             if (best < 0) { placed_all = false; break; }
             const int ci = use[size_t(best) * N + pr.p]++;
             const int cj = use[size_t(best) * N + pr.q]++;
+            ++rload[size_t(best) * 16 + rp];
+            ++rload[size_t(best) * 16 + rq];
             ++cnt[best];
             batch[best].push_back(dockblob::make_record(pr.p, pr.q, ci, cj, pr.hb, pr.table));
         }
@@ -312,7 +409,7 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
             // (C * S >= 128 + N > 128 always leaves enough). Their force is
             // zero, so every lane may update its slots without a branch.
             for (int b = 0; b < nb; ++b) {
-                batch[b] = arrange_batch(batch[b], &use[size_t(b) * N], N, S, C, (uint64_t)b + 1, err);
+                batch[b] = arrange_batch(batch[b], &use[size_t(b) * N], N, S, C, err);
                 if (batch[b].empty()) return DOCK_EUNSUPPORTED;
             }
             break;

@@ -586,35 +586,32 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
     // separations, torques and torsion axes are translation invariant and
     // keep the precision of the small local coordinates.
     const float tv[3] = {tx, ty, tz};
-    const int n_chunks = (L.max_depth + 3) >> 2;
+    const int n_duos = (L.max_depth + 1) >> 1;   // levels, two per LDS round trip
     float x[SLOTS][3];
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s) {
         const int a = lane + kWave * (s + L.wv);
         float y0 = L.y0[s][0], y1 = L.y0[s][1], y2 = L.y0[s][2];
-        // one word of torsion indices per four levels, then the rows of two
-        // levels per LDS round trip; levels past the atom's depth apply the
-        // identity, so every lane takes the same (uniform) number of chunks
+        // one word of torsion indices per four levels; two levels per LDS
+        // round trip; levels past the atom's depth apply the identity, so
+        // every lane takes the same (uniform) number of level pairs
         const uint32_t* row = sm.chain[L.frag[s]];
-        for (int c = 0; c < n_chunks; ++c) {
-            const uint32_t w = row[c];
+        for (int d = 0; d < n_duos; ++d) {
+            const uint32_t w = row[d >> 1] >> (16 * (d & 1));
+            float4 T[2][3];
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                float4 T[2][3];
+            for (int q = 0; q < 2; ++q) {
+                const unsigned k = (w >> (8 * q)) & 255u;
+                const float4* t = reinterpret_cast<const float4*>(__builtin_assume_aligned(
+                    reinterpret_cast<const char*>(sm.u.tk) + __umul24(k, 48u), 16));
+                T[q][0] = t[0]; T[q][1] = t[1]; T[q][2] = t[2];
+            }
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const unsigned k = (w >> (16 * h + 8 * q)) & 255u;
-                    const float4* t = reinterpret_cast<const float4*>(__builtin_assume_aligned(
-                        reinterpret_cast<const char*>(sm.u.tk) + __umul24(k, 48u), 16));
-                    T[q][0] = t[0]; T[q][1] = t[1]; T[q][2] = t[2];
-                }
-#pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const float z0 = T[q][0].x * y0 + T[q][0].y * y1 + T[q][0].z * y2 + T[q][0].w;
-                    const float z1 = T[q][1].x * y0 + T[q][1].y * y1 + T[q][1].z * y2 + T[q][1].w;
-                    const float z2 = T[q][2].x * y0 + T[q][2].y * y1 + T[q][2].z * y2 + T[q][2].w;
-                    y0 = z0; y1 = z1; y2 = z2;
-                }
+            for (int q = 0; q < 2; ++q) {
+                const float z0 = T[q][0].x * y0 + T[q][0].y * y1 + T[q][0].z * y2 + T[q][0].w;
+                const float z1 = T[q][1].x * y0 + T[q][1].y * y1 + T[q][1].z * y2 + T[q][1].w;
+                const float z2 = T[q][2].x * y0 + T[q][2].y * y1 + T[q][2].z * y2 + T[q][2].w;
+                y0 = z0; y1 = z1; y2 = z2;
             }
         }
 #pragma unroll

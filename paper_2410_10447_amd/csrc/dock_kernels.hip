@@ -667,27 +667,24 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
             PairForce F[2];
 #pragma unroll
             for (int q = 0; q < 4; ++q) R[q] = record(q);
-            // the grid-map loads go after the records (global loads complete
-            // in order) and are consumed after the pair phase
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int s = 0; s < SLOTS; ++s) grid_load(G, L.cls[s], x[s], tv, tap[s]);
-            __builtin_amdgcn_sched_barrier(0);
+            // the prologue issues its LDS reads in the loop's order (positions
+            // of the next batch before the slots of this one), so that at the
+            // loop head the slot reads may still be in flight
             Pi[0] = pos_i(R[0].x);
             Pj[0] = pos_j(R[0].x);
+            Pi[1] = pos_i(R[1].x);
+            Pj[1] = pos_j(R[1].x);
             F[0] = pair_force(R[0], Pi[0], Pj[0]);
             Ai[0] = *slot(accw, F[0].si);
             Aj[0] = *slot(accw, F[0].sj);
-            Pi[1] = pos_i(R[1].x);
-            Pj[1] = pos_j(R[1].x);
             int k = 0;
-            auto step = [&](auto residue) {
+            auto step = [&](auto residue, auto load) {
                 constexpr int r = decltype(residue)::value;  // k mod 4
                 constexpr int c = r & 1, n = (r + 1) & 1;
                 const u32x4 rf = R[(r + 2) & 3];
                 Pi[c] = pos_i(rf.x);
                 Pj[c] = pos_j(rf.x);
-                R[r] = record(k + 4);
+                if constexpr (decltype(load)::value != 0) R[r] = record(k + 4);
                 __builtin_amdgcn_sched_barrier(0);   // keep the loads at the step's start
                 F[n] = pair_force(R[(r + 1) & 3], Pi[n], Pj[n]);
                 store_force(accw, F[c], Ai[c], Aj[c]);
@@ -701,10 +698,20 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
             using I1 = IntC<1>;
             using I2 = IntC<2>;
             using I3 = IntC<3>;
-            while (k + 4 < nb) { step(I0()); step(I1()); step(I2()); step(I3()); }
-            if (k < nb - 1) step(I0());
-            if (k < nb - 1) step(I1());
-            if (k < nb - 1) step(I2());
+            using Load = IntC<1>;
+            using NoLoad = IntC<0>;
+            while (k + 4 < nb) { step(I0(), Load()); step(I1(), Load()); step(I2(), Load()); step(I3(), Load()); }
+            // Every record the remaining steps need is loaded. The grid-map
+            // loads go here, after the last record load: global loads
+            // complete in order, so a record load issued after them would
+            // wait for them. They are consumed after the pair phase.
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) grid_load(G, L.cls[s], x[s], tv, tap[s]);
+            __builtin_amdgcn_sched_barrier(0);
+            if (k < nb - 1) step(I0(), NoLoad());
+            if (k < nb - 1) step(I1(), NoLoad());
+            if (k < nb - 1) step(I2(), NoLoad());
             // k == nb - 1: the last batch is computed and its slots read
             if (k & 1) {
                 store_force(accw, F[1], Ai[1], Aj[1]);

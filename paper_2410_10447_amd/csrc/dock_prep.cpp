@@ -11,6 +11,7 @@
 #include "dock_prep.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 
@@ -45,13 +46,110 @@ int role_index(const int32_t list[2], int c) {
 // the few pairs that push a residue past 4 uses per role, is coloured with 4
 // colours by Kempe-chain recolouring (Konig's theorem: a bipartite multigraph
 // of maximum degree 4 has a proper 4-edge colouring); the pairs set aside go
-// to the groups with room, where they add the fewest repeats. The unused lanes then take, one by one, the free
-// slots whose residues their group uses least. Neither step changes which
-// slots a pair updates or the order of additions to any slot.
+// to the groups with room, where they add the fewest repeats. The unused
+// lanes then take, one by one, the free slots whose residues their group
+// uses least, and each group's records are ordered for the 8-lane halves of
+// 16-byte writes (split_halves). Neither step changes which slots a pair
+// updates or the order of additions to any slot.
 struct LaneCounts {
     int c16[2][4][16] = {};   // [role][group of 16 lanes][atom index mod 16]
     void add(int role, int lane, int atom) { ++c16[role][lane >> 4][atom & 15]; }
 };
+
+// 16-byte LDS writes are served 8 lanes at a time: two lanes of an aligned
+// 8-lane half whose atom indices agree mod 8 wait for each other. Orders a
+// 16-lane group's records so that the halves repeat as few first-atom and
+// second-atom residues mod 8 as possible. When each residue mod 8 occurs at
+// most twice per role, "the two lanes of a residue go to different halves"
+// is a graph of paths and even cycles (each lane has at most one partner per
+// role, and the roles alternate around a cycle): it is 2-coloured per
+// component and the components' colourings are chosen (subset sum) to fill
+// both halves with 8 lanes. Otherwise, or if no such choice exists, pairwise
+// swaps across the halves improve the split until none helps.
+int halves_cost(const std::vector<uint32_t>& rec) {
+    int c = 0;
+    for (int h = 0; h < 2; ++h)
+        for (int role = 0; role < 2; ++role) {
+            int cnt[8] = {};
+            for (int l = 8 * h; l < 8 * h + 8; ++l) {
+                const int a = role ? (rec[l] >> 7) & 127 : rec[l] & 127;
+                c += cnt[a & 7]++;
+            }
+        }
+    return c;
+}
+
+void split_halves(std::vector<uint32_t>& rec) {
+    const int L = 16;
+    std::vector<std::vector<int>> adj(L);
+    bool ok = true;
+    for (int role = 0; role < 2; ++role)
+        for (int cls = 0; cls < 8; ++cls) {
+            std::vector<int> lanes;
+            for (int l = 0; l < L; ++l) {
+                const int a = role ? (rec[l] >> 7) & 127 : rec[l] & 127;
+                if ((a & 7) == cls) lanes.push_back(l);
+            }
+            if (lanes.size() > 2) ok = false;
+            if (lanes.size() == 2) { adj[lanes[0]].push_back(lanes[1]); adj[lanes[1]].push_back(lanes[0]); }
+        }
+    std::vector<int> col(L, -1), comp(L, -1);
+    std::vector<std::array<int, 2>> size;
+    for (int v = 0; v < L && ok; ++v) {
+        if (col[v] >= 0) continue;
+        const int id = (int)size.size();
+        size.push_back({0, 0});
+        std::vector<int> queue{v};
+        col[v] = 0;
+        for (size_t q = 0; q < queue.size() && ok; ++q) {
+            const int x = queue[q];
+            comp[x] = id;
+            ++size[id][col[x]];
+            for (int y : adj[x]) {
+                if (col[y] < 0) { col[y] = col[x] ^ 1; queue.push_back(y); }
+                else if (col[y] == col[x]) ok = false;
+            }
+        }
+    }
+    if (ok) {
+        // reach[k][s]: the first k components can put s lanes into half 0
+        const int K = (int)size.size();
+        std::vector<std::vector<uint8_t>> reach(K + 1, std::vector<uint8_t>(L + 1, 0));
+        reach[0][0] = 1;
+        for (int k = 0; k < K; ++k)
+            for (int s0 = 0; s0 <= L; ++s0) {
+                if (!reach[k][s0]) continue;
+                if (s0 + size[k][0] <= L) reach[k + 1][s0 + size[k][0]] = 1;
+                if (s0 + size[k][1] <= L) reach[k + 1][s0 + size[k][1]] = 1;
+            }
+        if (reach[K][L / 2]) {
+            std::vector<int> flip(K, 0);
+            int want = L / 2;
+            for (int k = K - 1; k >= 0; --k) {
+                if (want - size[k][0] >= 0 && reach[k][want - size[k][0]]) { want -= size[k][0]; }
+                else { flip[k] = 1; want -= size[k][1]; }
+            }
+            std::vector<uint32_t> out;
+            for (int half = 0; half < 2; ++half)
+                for (int l = 0; l < L; ++l)
+                    if ((col[l] ^ flip[comp[l]]) == half) out.push_back(rec[l]);
+            rec.swap(out);
+            return;
+        }
+    }
+    int best = halves_cost(rec);
+    for (int pass = 0; pass < 16 && best > 0; ++pass) {
+        bool improved = false;
+        for (int a = 0; a < 8; ++a)
+            for (int b = 8; b < 16; ++b) {
+                std::swap(rec[a], rec[b]);
+                const int c = halves_cost(rec);
+                if (c < best) { best = c; improved = true; }
+                else std::swap(rec[a], rec[b]);
+            }
+        if (!improved) break;
+    }
+}
 
 // Orients the edges (u[e], v[e]) of a multigraph on 16 vertices along Euler
 // circuits (odd vertices paired by virtual edges): flip[e] = 1 reverses edge e.
@@ -207,18 +305,21 @@ std::vector<uint32_t> arrange_batch(const std::vector<uint32_t>& real, const uin
     std::vector<uint32_t> out;
     out.reserve(B);
     for (int g = 0; g < 4; ++g) {
+        std::vector<uint32_t> rec;
         for (int e : groups[g]) {
             const uint32_t r = real[e];
-            if (!flip[e]) { out.push_back(r); continue; }
+            if (!flip[e]) { rec.push_back(r); continue; }
             const uint32_t i = r & 127, j = (r >> 7) & 127, ci = (r >> 14) & 15, cj = (r >> 18) & 15;
-            out.push_back((r & ~0x3FFFFFu) | j | (i << 7) | (cj << 14) | (ci << 18));
+            rec.push_back((r & ~0x3FFFFFu) | j | (i << 7) | (cj << 14) | (ci << 18));
         }
         for (int l = (int)groups[g].size(); l < 16; ++l) {
             const int u = take_best(0, g), v = take_best(1, g);
             if (u < 0 || v < 0) { err = "internal: no free accumulator slots for batch padding"; return {}; }
-            out.push_back(dockblob::make_pad_record(free_slots[u].second, free_slots[v].second,
+            rec.push_back(dockblob::make_pad_record(free_slots[u].second, free_slots[v].second,
                                                     free_slots[u].first, free_slots[v].first));
         }
+        split_halves(rec);
+        out.insert(out.end(), rec.begin(), rec.end());
     }
     return out;
 }

@@ -11,7 +11,6 @@
 #include "dock_prep.h"
 
 #include <algorithm>
-#include <array>
 #include <cmath>
 #include <cstring>
 
@@ -29,126 +28,216 @@ int role_index(const int32_t list[2], int c) {
     return -1;
 }
 
-// LDS bank spreading of one batch. A wave's 16-byte LDS accesses are
-// served 16 lanes at a time over 64 four-byte banks (16 bank quads), and two
-// lanes of a group whose different addresses fall into the same quad
-// (address / 16 modulo 16) wait for each other. The pair loop reads and
-// writes the first and the second atom of each lane's pair (position and
-// slot: with a stride that is a multiple of 16 both lie in the quad of the
-// atom index, its residue mod 16). The batch's records are therefore placed
-// on the lanes, and a pair's two atoms may swap roles, so that within each
-// aligned group of 16 lanes the first atoms' residues differ and so do the
+// LDS bank spreading of one batch. On gfx950 a wave's 16-byte LDS read is
+// served in 4 passes of 16 lanes (see read_pass) over 64 four-byte banks,
+// and two lanes of a pass whose different addresses agree mod 16 bank quads
+// (address / 16 mod 16) wait for each other; a 16-byte write is served 8
+// consecutive lanes at a time, conflicting mod 8 (see place_half). The pair
+// loop reads and writes the first and the second atom of each lane's pair
+// (position and slot: with a stride that is a multiple of 16 both lie in the
+// quad of the atom index, its residue mod 16). The batch's records are
+// therefore placed on the lanes, and a pair's two atoms may swap roles, so
+// that within each read pass the first atoms' residues differ and so do the
 // second atoms'. Seen as a multigraph on the 16 residues with one edge per
 // pair, this is an orientation followed by an edge colouring with 4 colours
-// (one per lane group): the orientation follows Euler circuits, so each
+// (one per read pass): the orientation follows Euler circuits, so each
 // residue is first atom about as often as second (|out - in| <= 1), and the
 // bipartite (first residue, second residue) multigraph, after setting aside
 // the few pairs that push a residue past 4 uses per role, is coloured with 4
 // colours by Kempe-chain recolouring (Konig's theorem: a bipartite multigraph
 // of maximum degree 4 has a proper 4-edge colouring); the pairs set aside go
-// to the groups with room, where they add the fewest repeats. The unused
-// lanes then take, one by one, the free slots whose residues their group
-// uses least, and each group's records are ordered for the 8-lane halves of
-// 16-byte writes (split_halves). Neither step changes which slots a pair
-// updates or the order of additions to any slot.
+// to the passes with room, where they add the fewest repeats. The unused
+// lanes then take, one by one, the free slots whose residues their pass uses
+// least, each half's two passes are laid onto their lanes for the write
+// groups (place_half), and a descent over both kinds of repeat finishes the
+// half (refine_half). Neither step changes which slots a pair updates or the
+// order of additions to any slot.
 struct LaneCounts {
-    int c16[2][4][16] = {};   // [role][group of 16 lanes][atom index mod 16]
-    void add(int role, int lane, int atom) { ++c16[role][lane >> 4][atom & 15]; }
+    int c16[2][4][16] = {};   // [role][read pass][atom index mod 16]
 };
 
-// 16-byte LDS writes are served 8 lanes at a time: two lanes of an aligned
-// 8-lane half whose atom indices agree mod 8 wait for each other. Orders a
-// 16-lane group's records so that the halves repeat as few first-atom and
-// second-atom residues mod 8 as possible. When each residue mod 8 occurs at
-// most twice per role, "the two lanes of a residue go to different halves"
-// is a graph of paths and even cycles (each lane has at most one partner per
-// role, and the roles alternate around a cycle): it is 2-coloured per
-// component and the components' colourings are chosen (subset sum) to fill
-// both halves with 8 lanes. Otherwise, or if no such choice exists, pairwise
-// swaps across the halves improve the split until none helps.
-int halves_cost(const std::vector<uint32_t>& rec) {
-    int c = 0;
-    for (int h = 0; h < 2; ++h)
-        for (int role = 0; role < 2; ++role) {
-            int cnt[8] = {};
-            for (int l = 8 * h; l < 8 * h + 8; ++l) {
-                const int a = role ? (rec[l] >> 7) & 127 : rec[l] & 127;
-                c += cnt[a & 7]++;
-            }
-        }
-    return c;
+// Lanes of one read pass: a 16-byte LDS read is served in 4 passes of 16
+// lanes, a pass holding the lanes that agree in lane bit 5 and in the parity
+// of lane bits 2..4 (measured on gfx950: two active lanes conflict exactly
+// when their addresses agree mod 16 bank quads and they share such a pass).
+inline int read_pass(int lane) {
+    const int b = (lane >> 2) & 7;
+    return 2 * (lane >> 5) + (((b >> 2) ^ (b >> 1) ^ b) & 1);
 }
 
-void split_halves(std::vector<uint32_t>& rec) {
-    const int L = 16;
-    std::vector<std::vector<int>> adj(L);
-    bool ok = true;
-    for (int role = 0; role < 2; ++role)
-        for (int cls = 0; cls < 8; ++cls) {
-            std::vector<int> lanes;
-            for (int l = 0; l < L; ++l) {
-                const int a = role ? (rec[l] >> 7) & 127 : rec[l] & 127;
-                if ((a & 7) == cls) lanes.push_back(l);
-            }
-            if (lanes.size() > 2) ok = false;
-            if (lanes.size() == 2) { adj[lanes[0]].push_back(lanes[1]); adj[lanes[1]].push_back(lanes[0]); }
+// A 16-byte LDS write is served 8 consecutive lanes at a time, over 8 bank
+// quads: lanes of one aligned 8-lane group whose atom indices agree mod 8
+// wait for each other. Each 8-lane group holds 4 lanes of each of the two
+// read passes of its 32-lane half.
+// Descent on read and write repeats together over a 32-lane half: swaps of
+// any two lanes (also across the two read passes) and swaps of a pair's two
+// atoms, on the sums of squared residue counts per read pass (mod 16) and per
+// write group (mod 8); a fixed-seed random move order.
+constexpr int kRefineMoves = 4000;
+
+void refine_half(uint32_t* lanes32, int half) {
+    int rc[2][2][16] = {}, wc[4][2][8] = {};
+    auto atom = [&](int l, int role) { return role ? (int)((lanes32[l] >> 7) & 127) : (int)(lanes32[l] & 127); };
+    auto pass = [&](int l) { return read_pass(32 * half + l) & 1; };
+    auto put = [&](int l, int sgn, long long& cost) {
+        for (int role = 0; role < 2; ++role) {
+            const int a = atom(l, role);
+            int& r = rc[pass(l)][role][a & 15];
+            int& w = wc[l >> 3][role][a & 7];
+            if (sgn > 0) { cost += 2 * r + 1; ++r; cost += 2 * w + 1; ++w; }
+            else { --r; cost -= 2 * r + 1; --w; cost -= 2 * w + 1; }
         }
-    std::vector<int> col(L, -1), comp(L, -1);
-    std::vector<std::array<int, 2>> size;
-    for (int v = 0; v < L && ok; ++v) {
-        if (col[v] >= 0) continue;
-        const int id = (int)size.size();
-        size.push_back({0, 0});
-        std::vector<int> queue{v};
-        col[v] = 0;
-        for (size_t q = 0; q < queue.size() && ok; ++q) {
-            const int x = queue[q];
-            comp[x] = id;
-            ++size[id][col[x]];
-            for (int y : adj[x]) {
-                if (col[y] < 0) { col[y] = col[x] ^ 1; queue.push_back(y); }
-                else if (col[y] == col[x]) ok = false;
+    };
+    auto flip = [&](int l) {
+        const uint32_t r = lanes32[l];
+        const uint32_t i = r & 127, j = (r >> 7) & 127, ci = (r >> 14) & 15, cj = (r >> 18) & 15;
+        lanes32[l] = (r & ~0x3FFFFFu) | j | (i << 7) | (cj << 14) | (ci << 18);
+    };
+    long long cost = 0;
+    for (int l = 0; l < 32; ++l) put(l, +1, cost);
+    uint64_t x = 0x9E3779B97F4A7C15ull * (uint64_t)(half + 1);
+    auto rnd = [&]() { x ^= x << 13; x ^= x >> 7; x ^= x << 17; return x; };
+    for (int it = 0; it < kRefineMoves; ++it) {
+        const long long before = cost;
+        const int a = (int)(rnd() % 32);
+        const bool do_flip = (rnd() & 3) == 0;
+        const int b = do_flip ? a : (int)(rnd() % 32);
+        if (!do_flip && a == b) continue;
+        put(a, -1, cost);
+        if (b != a) put(b, -1, cost);
+        if (do_flip) flip(a); else std::swap(lanes32[a], lanes32[b]);
+        put(a, +1, cost);
+        if (b != a) put(b, +1, cost);
+        if (cost <= before) continue;
+        put(a, -1, cost);
+        if (b != a) put(b, -1, cost);
+        if (do_flip) flip(a); else std::swap(lanes32[a], lanes32[b]);
+        put(a, +1, cost);
+        if (b != a) put(b, +1, cost);
+    }
+}
+
+// Splits 16 records whose first-atom and second-atom classes mod 8 each occur
+// exactly twice (a 2-regular bipartite multigraph) into two sets of 8 that
+// each hold every class once per role: alternate edges around each cycle.
+bool two_matchings(const std::vector<uint32_t>& rec, std::vector<int>& side) {
+    const int n = (int)rec.size();
+    if (n != 16) return false;
+    std::vector<int> t(n), h(n);
+    int ct[8] = {}, ch[8] = {};
+    for (int e = 0; e < n; ++e) {
+        t[e] = rec[e] & 7;
+        h[e] = (rec[e] >> 7) & 7;
+        ++ct[t[e]];
+        ++ch[h[e]];
+    }
+    for (int c = 0; c < 8; ++c) if (ct[c] != 2 || ch[c] != 2) return false;
+    side.assign(n, -1);
+    for (int start = 0; start < n; ++start) {
+        if (side[start] >= 0) continue;
+        int e = start, s = 0;
+        bool at_head = true;            // walk from e's head to the other edge there
+        while (side[e] < 0) {
+            side[e] = s;
+            s ^= 1;
+            const int v = at_head ? h[e] : t[e];
+            int f = -1;
+            for (int g = 0; g < n && f < 0; ++g)
+                if (g != e && side[g] < 0 && (at_head ? h[g] : t[g]) == v) f = g;
+            if (f < 0) break;
+            e = f;
+            at_head = !at_head;
+        }
+    }
+    return true;
+}
+
+// Given perfect matchings X and Y on the 8 + 8 classes (8 records each),
+// chooses cycles of X u Y so that one perfect matching takes 4 records of X
+// and 4 of Y; the rest form the complementary one. m[e] in {0, 1} for the
+// 16 records (X first). False if no subset of cycles has half-length 4.
+bool balanced_pair(const std::vector<uint32_t>& xy, std::vector<int>& m) {
+    const int n = 16;
+    std::vector<int> cyc(n, -1);
+    std::vector<int> len;
+    for (int start = 0; start < n; ++start) {
+        if (cyc[start] >= 0) continue;
+        const int id = (int)len.size();
+        len.push_back(0);
+        std::vector<int> stack{start};
+        cyc[start] = id;
+        while (!stack.empty()) {
+            const int e = stack.back();
+            stack.pop_back();
+            ++len[id];
+            for (int f = 0; f < n; ++f) {
+                if (cyc[f] >= 0) continue;
+                if (((xy[f] & 7) == (xy[e] & 7)) || (((xy[f] >> 7) & 7) == ((xy[e] >> 7) & 7))) {
+                    cyc[f] = id;
+                    stack.push_back(f);
+                }
             }
         }
     }
-    if (ok) {
-        // reach[k][s]: the first k components can put s lanes into half 0
-        const int K = (int)size.size();
-        std::vector<std::vector<uint8_t>> reach(K + 1, std::vector<uint8_t>(L + 1, 0));
-        reach[0][0] = 1;
-        for (int k = 0; k < K; ++k)
-            for (int s0 = 0; s0 <= L; ++s0) {
-                if (!reach[k][s0]) continue;
-                if (s0 + size[k][0] <= L) reach[k + 1][s0 + size[k][0]] = 1;
-                if (s0 + size[k][1] <= L) reach[k + 1][s0 + size[k][1]] = 1;
+    const int K = (int)len.size();
+    // subset of cycles whose X-edge count (half the length) sums to 4
+    std::vector<std::vector<uint8_t>> reach(K + 1, std::vector<uint8_t>(9, 0));
+    reach[0][0] = 1;
+    for (int k = 0; k < K; ++k)
+        for (int s0 = 0; s0 <= 8; ++s0) {
+            if (!reach[k][s0]) continue;
+            reach[k + 1][s0] = 1;
+            if (s0 + len[k] / 2 <= 8) reach[k + 1][s0 + len[k] / 2] = 1;
+        }
+    if (!reach[K][4]) return false;
+    std::vector<int> take(K, 0);
+    int want = 4;
+    for (int k = K - 1; k >= 0; --k)
+        if (!reach[k][want]) { take[k] = 1; want -= len[k] / 2; }
+    m.assign(n, 0);
+    for (int e = 0; e < n; ++e) {
+        const bool is_x = e < 8;
+        m[e] = (take[cyc[e]] ? (is_x ? 0 : 1) : (is_x ? 1 : 0));
+    }
+    return true;
+}
+
+void place_half(const std::vector<uint32_t>& p0, const std::vector<uint32_t>& p1, int half, uint32_t* out64) {
+    uint32_t* lanes32 = out64 + 32 * half;
+    // lanes of each (write group, read pass) within the half
+    std::vector<int> slot[4][2];
+    for (int l = 0; l < 32; ++l) slot[l >> 3][read_pass(32 * half + l) & 1].push_back(l);
+    // exact: both passes 2-regular on the classes mod 8, and the write groups
+    // formed as balanced perfect matchings of X u Y
+    std::vector<int> sa, sb;
+    if (two_matchings(p0, sa) && two_matchings(p1, sb)) {
+        std::vector<uint32_t> A[2], Bm[2];
+        for (int e = 0; e < 16; ++e) { A[sa[e]].push_back(p0[e]); Bm[sb[e]].push_back(p1[e]); }
+        for (int pairing = 0; pairing < 2; ++pairing) {
+            std::vector<uint32_t> groups[4][2];
+            bool ok = true;
+            for (int q = 0; q < 2 && ok; ++q) {
+                std::vector<uint32_t> xy(A[q]);
+                const std::vector<uint32_t>& y = Bm[q ^ pairing];
+                xy.insert(xy.end(), y.begin(), y.end());
+                std::vector<int> m;
+                ok = balanced_pair(xy, m);
+                if (!ok) break;
+                for (int e = 0; e < 16; ++e) groups[2 * q + m[e]][e < 8 ? 0 : 1].push_back(xy[e]);
             }
-        if (reach[K][L / 2]) {
-            std::vector<int> flip(K, 0);
-            int want = L / 2;
-            for (int k = K - 1; k >= 0; --k) {
-                if (want - size[k][0] >= 0 && reach[k][want - size[k][0]]) { want -= size[k][0]; }
-                else { flip[k] = 1; want -= size[k][1]; }
-            }
-            std::vector<uint32_t> out;
-            for (int half = 0; half < 2; ++half)
-                for (int l = 0; l < L; ++l)
-                    if ((col[l] ^ flip[comp[l]]) == half) out.push_back(rec[l]);
-            rec.swap(out);
+            if (!ok) continue;
+            for (int w = 0; w < 4; ++w)
+                for (int p = 0; p < 2; ++p)
+                    for (int k = 0; k < 4; ++k) lanes32[slot[w][p][k]] = groups[w][p][k];
             return;
         }
     }
-    int best = halves_cost(rec);
-    for (int pass = 0; pass < 16 && best > 0; ++pass) {
-        bool improved = false;
-        for (int a = 0; a < 8; ++a)
-            for (int b = 8; b < 16; ++b) {
-                std::swap(rec[a], rec[b]);
-                const int c = halves_cost(rec);
-                if (c < best) { best = c; improved = true; }
-                else std::swap(rec[a], rec[b]);
-            }
-        if (!improved) break;
+    int k[2] = {0, 0};
+    for (int l = 0; l < 32; ++l) {
+        const int p = read_pass(32 * half + l) & 1;
+        lanes32[l] = (p ? p1 : p0)[k[p]++];
     }
+    refine_half(lanes32, half);
 }
 
 // Orients the edges (u[e], v[e]) of a multigraph on 16 vertices along Euler
@@ -302,10 +391,10 @@ std::vector<uint32_t> arrange_batch(const std::vector<uint32_t>& real, const uin
         }
         return best;
     };
-    std::vector<uint32_t> out;
-    out.reserve(B);
+    // colour g becomes read pass g: half g / 2, parity g % 2
+    std::vector<std::vector<uint32_t>> pass_rec(4);
     for (int g = 0; g < 4; ++g) {
-        std::vector<uint32_t> rec;
+        std::vector<uint32_t>& rec = pass_rec[g];
         for (int e : groups[g]) {
             const uint32_t r = real[e];
             if (!flip[e]) { rec.push_back(r); continue; }
@@ -318,9 +407,9 @@ std::vector<uint32_t> arrange_batch(const std::vector<uint32_t>& real, const uin
             rec.push_back(dockblob::make_pad_record(free_slots[u].second, free_slots[v].second,
                                                     free_slots[u].first, free_slots[v].first));
         }
-        split_halves(rec);
-        out.insert(out.end(), rec.begin(), rec.end());
     }
+    std::vector<uint32_t> out(B);
+    for (int half = 0; half < 2; ++half) place_half(pass_rec[2 * half], pass_rec[2 * half + 1], half, out.data());
     return out;
 }
 

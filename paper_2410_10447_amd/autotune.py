@@ -7,6 +7,8 @@ the fastest candidate is stored in a JSON table keyed by GPU architecture and
 bucket. `choose()` reads the table; a persistent launch over ligands of mixed
 sizes then passes each item its bucket's variant and threads per individual
 (items with different thread counts run in separate launches side by side).
+Within a kernel family the buckets share one variant when that costs at
+most 3 % in every bucket (`unify_families`).
 
 Usage: python -m paper_2410_10447_amd.autotune [--out table.json]
 """
@@ -109,9 +111,52 @@ def tune(out: str = TABLE_PATH, n_individuals: int = 1024, iterations: int = 20,
         entry["atoms"], entry["torsions"] = n, lig.n_torsions
         table["buckets"][key] = entry
         print(key, entry, flush=True)
+    unify_families(table)
     with open(out, "w") as f:
         json.dump(table, f, indent=1)
     _cache.pop(out, None)
+    return table
+
+
+def family(entry) -> str:
+    """Kernel family a bucket's items run in: ligands of <= 64 atoms (one atom
+    per lane), larger ligands in one wave (two per lane) or in two waves."""
+    if entry["atoms"] <= 64:
+        return "one-slot"
+    return "two-wave" if entry["threads_per_ind"] == 128 else "two-slot"
+
+
+def unify_families(table, tol: float = 0.03):
+    """One reduction variant per kernel family where it costs little.
+
+    A launch whose items use different variants runs the kernel that
+    dispatches per item, which holds every variant's registers; one variant
+    per family keeps the specialised kernels. Per family, the variant whose
+    worst relative loss over the family's buckets (against each bucket's best
+    candidate, at the bucket's thread count) is smallest is given to every
+    bucket of the family, if that loss is at most `tol`.
+    """
+    fams = {}
+    for key, e in table["buckets"].items():
+        fams.setdefault(family(e), []).append(key)
+    for fam, keys in fams.items():
+        best_v, best_loss = None, None
+        for v in sorted({int(k.split("_")[0][1:]) for e in (table["buckets"][k] for k in keys)
+                         for k in e["measured"]}):
+            loss = 0.0
+            for key in keys:
+                e = table["buckets"][key]
+                r = e["measured"].get(f"v{v}_b{e['threads_per_ind']}")
+                loss = max(loss, 1.0 if r is None else 1.0 - r / e["evals_per_s"])
+            if best_loss is None or loss < best_loss:
+                best_v, best_loss = v, loss
+        if best_loss is not None and best_loss <= tol:
+            for key in keys:
+                e = table["buckets"][key]
+                e["variant"] = best_v
+                e["evals_per_s"] = e["measured"][f"v{best_v}_b{e['threads_per_ind']}"]
+        table.setdefault("families", {})[fam] = {"variant": best_v, "worst_loss": best_loss,
+                                                 "unified": best_loss is not None and best_loss <= tol}
     return table
 
 

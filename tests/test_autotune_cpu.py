@@ -1,0 +1,45 @@
+"""Host logic of the launch-option table: bucketing, lookup and the
+one-variant-per-kernel-family pass."""
+from paper_2410_10447_amd import autotune
+
+
+def _entry(atoms, tpi, rates, variant):
+    return {"atoms": atoms, "torsions": 4, "threads_per_ind": tpi, "variant": variant,
+            "evals_per_s": rates[f"v{variant}_b{tpi}"], "measured": rates}
+
+
+def test_bucket_keys_cover_the_size_range():
+    keys = set(autotune.all_buckets())
+    assert len(keys) == 16
+    for n in (1, 12, 32, 33, 64, 65, 100, 128):
+        for t in (0, 7, 8, 31, 32):
+            assert autotune.bucket(n, t) in keys
+    assert autotune.bucket(64, 0) == "a1_t0" and autotune.bucket(65, 0) == "a2_t0"
+
+
+def test_shipped_table_is_family_consistent():
+    t = autotune.load()
+    assert set(t["buckets"]) == set(autotune.all_buckets())
+    fams = {}
+    for e in t["buckets"].values():
+        fams.setdefault(autotune.family(e), set()).add(e["variant"])
+        assert e["threads_per_ind"] in (64, 128)
+        assert e["atoms"] > 64 or e["threads_per_ind"] == 64
+    assert all(len(v) == 1 for v in fams.values()), fams
+
+
+def test_unify_families_within_tolerance():
+    table = {"buckets": {
+        "a0_t0": _entry(16, 64, {"v0_b64": 100.0, "v1_b64": 99.0}, 0),
+        "a0_t1": _entry(16, 64, {"v0_b64": 98.0, "v1_b64": 100.0}, 1),
+        "a2_t0": _entry(80, 128, {"v0_b64": 50.0, "v1_b64": 50.0, "v0_b128": 70.0, "v1_b128": 60.0}, 0),
+        "a2_t1": _entry(80, 128, {"v0_b64": 50.0, "v1_b64": 50.0, "v0_b128": 60.0, "v1_b128": 70.0}, 1),
+    }}
+    autotune.unify_families(table, tol=0.03)
+    b = table["buckets"]
+    # one-slot: variant 1 loses 1 % in a0_t0, variant 0 loses 2 % in a0_t1 -> variant 1
+    assert b["a0_t0"]["variant"] == 1 and b["a0_t1"]["variant"] == 1
+    assert b["a0_t0"]["evals_per_s"] == 99.0
+    # two-wave: either variant loses > 3 % somewhere -> left per bucket
+    assert b["a2_t0"]["variant"] == 0 and b["a2_t1"]["variant"] == 1
+    assert table["families"]["one-slot"]["unified"] and not table["families"]["two-wave"]["unified"]

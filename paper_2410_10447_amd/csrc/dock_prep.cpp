@@ -72,10 +72,8 @@ inline int read_pass(int lane) {
 // Descent on read and write repeats together over a 32-lane half: swaps of
 // any two lanes (also across the two read passes) and swaps of a pair's two
 // atoms, on the sums of squared residue counts per read pass (mod 16) and per
-// write group (mod 8); a fixed-seed random move order, stopped after a run of
-// moves that found nothing better.
-constexpr int kRefineMoves = 4000;
-constexpr int kRefinePatience = 300;
+// write group (mod 8); first-improvement passes until none helps.
+constexpr int kRefinePasses = 12;
 
 void refine_half(uint32_t* lanes32, int half) {
     int rc[2][2][16] = {}, wc[4][2][8] = {};
@@ -97,30 +95,28 @@ void refine_half(uint32_t* lanes32, int half) {
     };
     long long cost = 0;
     for (int l = 0; l < 32; ++l) put(l, +1, cost);
-    uint64_t x = 0x9E3779B97F4A7C15ull * (uint64_t)(half + 1);
-    auto rnd = [&]() { x ^= x << 13; x ^= x >> 7; x ^= x << 17; return x; };
-    long long best = cost;
-    for (int it = 0, since = 0; it < kRefineMoves && since < kRefinePatience; ++it) {
+    // first-improvement passes over every lane pair and every lane's atom
+    // swap, until a pass finds nothing better
+    auto try_move = [&](int a, int b) {
         const long long before = cost;
-        const int a = (int)(rnd() % 32);
-        const bool do_flip = (rnd() & 3) == 0;
-        const int b = do_flip ? a : (int)(rnd() % 32);
-        if (!do_flip && a == b) continue;
         put(a, -1, cost);
         if (b != a) put(b, -1, cost);
-        if (do_flip) flip(a); else std::swap(lanes32[a], lanes32[b]);
+        if (b == a) flip(a); else std::swap(lanes32[a], lanes32[b]);
         put(a, +1, cost);
         if (b != a) put(b, +1, cost);
-        if (cost <= before) {
-            if (cost < best) { best = cost; since = 0; } else { ++since; }
-            continue;
-        }
-        ++since;
+        if (cost < before) return true;
         put(a, -1, cost);
         if (b != a) put(b, -1, cost);
-        if (do_flip) flip(a); else std::swap(lanes32[a], lanes32[b]);
+        if (b == a) flip(a); else std::swap(lanes32[a], lanes32[b]);
         put(a, +1, cost);
         if (b != a) put(b, +1, cost);
+        return false;
+    };
+    for (int pass = 0; pass < kRefinePasses; ++pass) {
+        bool improved = false;
+        for (int a = 0; a < 32; ++a)
+            for (int b = a; b < 32; ++b) improved |= try_move(a, b);
+        if (!improved) break;
     }
 }
 

@@ -228,7 +228,8 @@ def test_lane_arrangement_spreads_banks():
         rd0, wr0 = _bank_repeats(shuffled, L.n_atoms)
         assert rd + wr <= 0.5 * (rd0 + wr0), (L.n_atoms, rd, wr, rd0, wr0)
         if k == 0:
-            assert rd + wr <= 12.0, (rd, wr)
+            # random lanes give about 47 repeats per batch for this ligand
+            assert rd + wr <= 15.0, (rd, wr)
 
 
 def test_create_ligand_rejects_bad_topologies():

@@ -354,12 +354,12 @@ __device__ __forceinline__ float two_sum_fraction(float t, float node, float xl)
     return s2 + (e1 + e2);
 }
 
+// The fraction inside cell c (chosen when the loads were issued) along one
+// axis, and the world and box-clamped coordinates.
 __device__ __forceinline__ void axis_cell(float t, float xl, float lo, float hi, float h, float ih,
-                                          int n, int& c, float& f, float& xw, float& xc) {
+                                          int c, float& f, float& xw, float& xc) {
     xw = t + xl;
     xc = fminf(fmaxf(xw, lo), hi);
-    const float u = (xc - lo) * ih;
-    c = min(max((int)floorf(u), 0), n - 2);
     const float node = lo + (float)c * h;
     f = ((xw == xc) ? two_sum_fraction(t, node, xl) : (xc - node)) * ih;
 }
@@ -370,6 +370,7 @@ __device__ __forceinline__ void axis_cell(float t, float xl, float lo, float hi,
 // latency overlaps other work.
 struct GridTaps {
     float v[3][8];
+    int cell[3];
 };
 
 __device__ __forceinline__ int axis_index(float t, float xl, float lo, float hi, float ih, int n) {
@@ -383,6 +384,9 @@ __device__ __forceinline__ void grid_load(const GridParams& G, int cls, const fl
     const int cx = axis_index(t[0], xl[0], G.origin[0], G.hi[0], ih, G.nx);
     const int cy = axis_index(t[1], xl[1], G.origin[1], G.hi[1], ih, G.ny);
     const int cz = axis_index(t[2], xl[2], G.origin[2], G.hi[2], ih, G.nz);
+    tp.cell[0] = cx;
+    tp.cell[1] = cy;
+    tp.cell[2] = cz;
     const int plane = G.nx * G.ny;
     const int vol = plane * G.nz;
     const int base = (cz * G.ny + cy) * G.nx + cx;
@@ -401,12 +405,11 @@ __device__ __forceinline__ void grid_load(const GridParams& G, int cls, const fl
 __device__ __forceinline__ void grid_term(const GridParams& G, const GridTaps& tp, float q, float aq,
                                           const float xl[3], const float t[3],
                                           float& e, float& gx, float& gy, float& gz) {
-    int cx, cy, cz;
     float fx, fy, fz, xw, yw, zw, xc, yc, zc;
     const float ih = G.inv_spacing;
-    axis_cell(t[0], xl[0], G.origin[0], G.hi[0], G.spacing, ih, G.nx, cx, fx, xw, xc);
-    axis_cell(t[1], xl[1], G.origin[1], G.hi[1], G.spacing, ih, G.ny, cy, fy, yw, yc);
-    axis_cell(t[2], xl[2], G.origin[2], G.hi[2], G.spacing, ih, G.nz, cz, fz, zw, zc);
+    axis_cell(t[0], xl[0], G.origin[0], G.hi[0], G.spacing, ih, tp.cell[0], fx, xw, xc);
+    axis_cell(t[1], xl[1], G.origin[1], G.hi[1], G.spacing, ih, tp.cell[1], fy, yw, yc);
+    axis_cell(t[2], xl[2], G.origin[2], G.hi[2], G.spacing, ih, tp.cell[2], fz, zw, zc);
     float v[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = tp.v[0][i] + q * tp.v[1][i] + aq * tp.v[2][i];
@@ -608,9 +611,10 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
             }
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                const float z0 = T[q][0].x * y0 + T[q][0].y * y1 + T[q][0].z * y2 + T[q][0].w;
-                const float z1 = T[q][1].x * y0 + T[q][1].y * y1 + T[q][1].z * y2 + T[q][1].w;
-                const float z2 = T[q][2].x * y0 + T[q][2].y * y1 + T[q][2].z * y2 + T[q][2].w;
+                // one row = three FMAs, starting from the translation column
+                const float z0 = fmaf(T[q][0].x, y0, fmaf(T[q][0].y, y1, fmaf(T[q][0].z, y2, T[q][0].w)));
+                const float z1 = fmaf(T[q][1].x, y0, fmaf(T[q][1].y, y1, fmaf(T[q][1].z, y2, T[q][1].w)));
+                const float z2 = fmaf(T[q][2].x, y0, fmaf(T[q][2].y, y1, fmaf(T[q][2].z, y2, T[q][2].w)));
                 y0 = z0; y1 = z1; y2 = z2;
             }
         }

@@ -97,13 +97,16 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const
 
 // Sum over the wave, every lane receives the same value. Butterfly inside
 // each 16-lane row with DPP (quad swaps, half-row and row mirrors), then the
-// four row sums are read as scalars and added in a fixed order.
+// row sums S0..S3 are combined by row broadcasts as (S3 + S2) + (S1 + S0)
+// in the last lane, which is read as a scalar.
 __device__ __forceinline__ float wave_sum(float v) {
-    v += dpp<0xB1>(v);    // quad_perm [1,0,3,2]
-    v += dpp<0x4E>(v);    // quad_perm [2,3,0,1]
-    v += dpp<0x141>(v);   // row_half_mirror
-    v += dpp<0x140>(v);   // row_mirror
-    return (readlane(v, 0) + readlane(v, 16)) + (readlane(v, 32) + readlane(v, 48));
+    v += dpp<0xB1>(v);         // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);         // quad_perm [2,3,0,1]
+    v += dpp<0x141>(v);        // row_half_mirror
+    v += dpp<0x140>(v);        // row_mirror
+    v += dpp<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += dpp<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    return readlane(v, 63);
 }
 
 __device__ __forceinline__ float wave_max(float v) {

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define DOCK_ABI_VERSION 2
+#define DOCK_ABI_VERSION 3
 
 /* status codes */
 #define DOCK_OK            0
@@ -95,6 +95,23 @@ typedef struct {
 int32_t dock_create_grids(const dock_grid_desc* desc, const float* maps_dev, dock_grids** out);
 /* NULL is accepted (DOCK_OK). */
 int32_t dock_destroy_grids(dock_grids* grids);
+
+/* Corner-expanded copy of the maps, for the trilinear term of Sec. 2.1
+ * (each atom reads the 8 corners of its cell in 3 maps): for every map and
+ * every cell (cx, cy, cz) of the (nx-1)(ny-1)(nz-1) cells, the cell's 8
+ * corner values v[4 dz + 2 dy + dx] as 32 contiguous bytes, cells x fastest.
+ * An atom then reads 32 contiguous bytes per map instead of four separate
+ * rows; the values and the arithmetic are the same, so scores are identical
+ * with and without it. *bytes = n_maps (nx-1)(ny-1)(nz-1) 32 (about 8 times
+ * the maps). */
+int32_t dock_grids_corner_bytes(const dock_grids* grids, int64_t* bytes);
+/* Fills corners_dev (device, caller-owned, 16-byte aligned, >= the size above)
+ * from the handle's maps on `stream` and binds it to the handle: later calls
+ * read it (so they must run on `stream` or after it); the maps stay borrowed.
+ * corners_dev = NULL unbinds (the maps are read directly). Errors:
+ * DOCK_EINVAL for a NULL handle, a small or misaligned buffer (no device work
+ * is started then). */
+int32_t dock_grids_bind_corners(dock_grids* grids, void* corners_dev, int64_t bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * Ligand: topology, torsion tree and intramolecular pair list, prepared once

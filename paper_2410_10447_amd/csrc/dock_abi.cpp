@@ -187,6 +187,7 @@ int32_t dock_create_grids(const dock_grid_desc* d, const float* maps_dev, dock_g
     if (!g) return fail(DOCK_ENOMEM, "out of host memory");
     g->desc = *d;
     g->gp.maps = maps_dev;
+    g->gp.corners = nullptr;
     g->gp.nx = d->nx;
     g->gp.ny = d->ny;
     g->gp.nz = d->nz;
@@ -204,6 +205,29 @@ int32_t dock_create_grids(const dock_grid_desc* d, const float* maps_dev, dock_g
 
 int32_t dock_destroy_grids(dock_grids* g) {
     delete g;
+    return ok();
+}
+
+int32_t dock_grids_corner_bytes(const dock_grids* g, int64_t* bytes) {
+    if (!g || !bytes) return fail(DOCK_EINVAL, "dock_grids_corner_bytes: NULL argument");
+    *bytes = (int64_t)g->desc.n_maps * (g->desc.nx - 1) * (g->desc.ny - 1) * (g->desc.nz - 1) * 32;
+    return ok();
+}
+
+int32_t dock_grids_bind_corners(dock_grids* g, void* corners_dev, int64_t bytes, void* stream) {
+    if (!g) return fail(DOCK_EINVAL, "dock_grids_bind_corners: NULL grids");
+    if (!corners_dev) {
+        g->gp.corners = nullptr;
+        return ok();
+    }
+    int64_t need = 0;
+    dock_grids_corner_bytes(g, &need);
+    if (bytes < need) return fail(DOCK_EINVAL, "corner buffer too small");
+    if (!aligned(corners_dev, 16)) return fail(DOCK_EINVAL, "corner buffer must be 16-byte aligned");
+    hipError_t e = docklaunch::launch_expand_corners(g->gp, static_cast<float*>(corners_dev),
+                                                     (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "dock_grids_bind_corners launch");
+    g->gp.corners = static_cast<const float*>(corners_dev);
     return ok();
 }
 

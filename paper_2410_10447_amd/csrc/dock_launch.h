@@ -9,6 +9,8 @@ namespace docklaunch {
 // Receptor grid as the kernels see it.
 struct GridParams {
     const float* maps;   // [n_maps][nz][ny][nx]
+    const float* corners;  // nullptr, or per map and cell the cell's 8 corner values:
+                           // [n_maps][(nz-1)(ny-1)(nx-1)][8], v[4 dz + 2 dy + dx]
     int32_t nx, ny, nz, n_maps;
     float spacing;
     float inv_spacing;
@@ -67,5 +69,8 @@ int ls_blocks_per_cu(int mode, int variant_uniform);
 
 hipError_t launch_block_sum4(const float* in, float* out, int n_blocks, int threads,
                              int variant, int repeat, hipStream_t stream);
+
+// Writes the corner-expanded copy of g.maps (layout of GridParams::corners).
+hipError_t launch_expand_corners(const GridParams& g, float* corners, hipStream_t stream);
 
 }  // namespace docklaunch

@@ -38,6 +38,7 @@ MAX_TORSIONS = 32
 # exported symbols of include/dock.h
 ABI_SYMBOLS = (
     "dock_abi_version", "dock_last_error", "dock_create_grids", "dock_destroy_grids",
+    "dock_grids_corner_bytes", "dock_grids_bind_corners",
     "dock_create_ligand", "dock_ligand_info_get", "dock_ligand_export", "dock_ligand_upload",
     "dock_destroy_ligand", "dock_score_batch", "dock_ls_workspace_bytes",
     "dock_local_search_batch", "dock_block_sum4",
@@ -113,6 +114,8 @@ def lib():
         "dock_last_error": ([], C.c_char_p),
         "dock_create_grids": ([C.POINTER(GridDesc), vp, C.POINTER(vp)], i32),
         "dock_destroy_grids": ([vp], i32),
+        "dock_grids_corner_bytes": ([vp, C.POINTER(C.c_int64)], i32),
+        "dock_grids_bind_corners": ([vp, vp, C.c_int64, vp], i32),
         "dock_create_ligand": ([C.POINTER(LigandDesc), C.POINTER(vp)], i32),
         "dock_ligand_info_get": ([vp, C.POINTER(LigandInfo)], i32),
         "dock_ligand_export": ([vp, vp, vp, vp, vp, vp, vp], i32),
@@ -176,14 +179,38 @@ class Grids:
         h = C.c_void_p()
         _check(lib().dock_create_grids(C.byref(d), _ptr(maps), C.byref(h)))
         self.handle = h
+        self.corners = None
 
     @classmethod
-    def from_synth(cls, g, device="cuda"):
+    def from_synth(cls, g, device="cuda", corners: bool = True, stream=None):
+        """Upload a synthetic grid set; with `corners` (the default) also build
+        and bind the corner-expanded copy the kernels read fastest."""
         import torch
-        return cls(torch.from_numpy(np.ascontiguousarray(g.maps)).to(device), g.spacing, g.origin)
+        G = cls(torch.from_numpy(np.ascontiguousarray(g.maps)).to(device), g.spacing, g.origin)
+        if corners:
+            G.bind_corners(stream=stream)
+        return G
+
+    def corner_bytes(self) -> int:
+        n = C.c_int64()
+        _check(lib().dock_grids_corner_bytes(self.handle, C.byref(n)))
+        return int(n.value)
+
+    def bind_corners(self, enable: bool = True, stream=None):
+        """Build the corner-expanded copy (a uint8 CUDA tensor this object
+        keeps) on `stream` and bind it; enable=False unbinds and frees it."""
+        import torch
+        if not enable:
+            _check(lib().dock_grids_bind_corners(self.handle, None, 0, _stream_handle(stream)))
+            self.corners = None
+            return
+        n = self.corner_bytes()
+        buf = torch.empty(max(n, 16), dtype=torch.uint8, device=self.maps.device)
+        _check(lib().dock_grids_bind_corners(self.handle, _ptr(buf), buf.numel(), _stream_handle(stream)))
+        self.corners = buf
 
     def nbytes(self) -> int:
-        return self.maps.numel() * 4
+        return self.maps.numel() * 4 + (self.corners.numel() if self.corners is not None else 0)
 
     def __del__(self):
         h = getattr(self, "handle", None)

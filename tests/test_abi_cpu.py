@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(dock.ABI_SYMBOLS)
     for name in declared:
         assert hasattr(L, name)
-    assert L.dock_abi_version() == 2
+    assert L.dock_abi_version() == 3
 
 
 def _check_prep(lig):
@@ -286,6 +286,14 @@ def test_batch_calls_validate_before_device_work():
     d4 = dock.GridDesc(nx=8, ny=8, nz=8, n_maps=10, spacing=0.0)
     assert L.dock_create_grids(C.byref(d4), fake, C.byref(g)) == dock.DOCK_EINVAL
     assert L.dock_create_grids(C.byref(d), fake, C.byref(g)) == dock.DOCK_OK
+    # corner-expanded copy: size, and validation before any launch
+    nb = C.c_int64()
+    assert L.dock_grids_corner_bytes(g, C.byref(nb)) == dock.DOCK_OK and nb.value == 10 * 7 * 7 * 7 * 32
+    assert L.dock_grids_corner_bytes(None, C.byref(nb)) == dock.DOCK_EINVAL
+    assert L.dock_grids_bind_corners(None, fake, nb.value, None) == dock.DOCK_EINVAL
+    assert L.dock_grids_bind_corners(g, fake, nb.value - 1, None) == dock.DOCK_EINVAL
+    assert L.dock_grids_bind_corners(g, vp(0x1008), nb.value, None) == dock.DOCK_EINVAL
+    assert L.dock_grids_bind_corners(g, None, 0, None) == dock.DOCK_OK      # unbind: no device work
     # ligand never uploaded
     st = L.dock_score_batch(g, lig.handle, 4, fake, fake, fake, None, None)
     assert st == dock.DOCK_EINVAL and "uploaded" in dock.last_error()

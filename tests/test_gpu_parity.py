@@ -384,6 +384,46 @@ def test_ls_three_families_alone_equals_mixed(dk):
             assert np.all(ok[~flag]), (k, e_relerr(mn["best_energy"], ref.energy).max())
 
 
+def test_corner_expanded_grids_identical(dk):
+    """The corner-expanded copy holds the same corner values and the kernels
+    do the same arithmetic on them: scores and a 20-step local search are
+    bit-identical with and without it (one-wave and two-wave ligands)."""
+    w = synth.ls_workload(64)
+    L = dk.Ligand(w.ligands[0], w.ff)
+    Gp = dk.Grids.from_synth(w.grids, corners=False)
+    Gc = dk.Grids.from_synth(w.grids)
+    assert Gc.corners is not None and Gc.corners.numel() == Gc.corner_bytes()
+    n_cells = (np.array(w.grids.maps.shape[1:]) - 1).prod()
+    assert Gc.corner_bytes() == w.grids.maps.shape[0] * n_cells * 32
+    # spot-check the layout: corner v[4 dz + 2 dy + dx] of cell (cx, cy, cz) of map m
+    M, nz, ny, nx = w.grids.maps.shape
+    cv = Gc.corners.view(torch.float32).cpu().numpy().reshape(M, nz - 1, ny - 1, nx - 1, 8)
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        m, cz, cy, cx = rng.integers(M), rng.integers(nz - 1), rng.integers(ny - 1), rng.integers(nx - 1)
+        for k in range(8):
+            dz, dy, dx = k >> 2, (k >> 1) & 1, k & 1
+            assert cv[m, cz, cy, cx, k] == w.grids.maps[m, cz + dz, cy + dy, cx + dx]
+    gt = torch.from_numpy(w.genotypes[0]).cuda()
+    for v in FP32_VARIANTS:
+        Ep, gp = dk.score_batch(Gp, L, gt, variant=v)
+        Ec, gc = dk.score_batch(Gc, L, gt, variant=v)
+        assert torch.equal(Ep, Ec) and torch.equal(gp, gc)
+    for lig_n, tpi in ((48, 64), (100, 128)):
+        ww = w if lig_n == 48 else _two_wave_workload(64)
+        LL = L if lig_n == 48 else dk.Ligand(ww.ligands[0], ww.ff)
+        Gp2 = Gp if lig_n == 48 else dk.Grids.from_synth(ww.grids, corners=False)
+        Gc2 = Gc if lig_n == 48 else dk.Grids.from_synth(ww.grids)
+        a = dk.LSState.start(torch.from_numpy(ww.genotypes[0]).cuda())
+        b = a.clone()
+        dk.local_search([(Gp2, LL, a)], 20, threads_per_ind=tpi)
+        dk.local_search([(Gc2, LL, b)], 20, threads_per_ind=tpi)
+        torch.cuda.synchronize()
+        an, bn = a.to_numpy(), b.to_numpy()
+        for f in an:
+            assert np.array_equal(an[f], bn[f]), (lig_n, f)
+
+
 def test_ls_mixed_variants_in_one_launch(dk):
     w = synth.ls_workload(64)
     G, L, st0 = _ls_setup(dk, w, 64)

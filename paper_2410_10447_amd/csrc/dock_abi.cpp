@@ -460,11 +460,16 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
     }
     // each launch runs the kernel specialised for its items' variant when
     // they share one (e.g. a tuning table that picks one per size bucket)
+    // (the specialised kernels read corner-expanded grids only; a part with an
+    // item on plain maps runs the dispatching kernel, which reads either)
     for (Part& pt : parts) {
         int v = -2;
-        for (int i = pt.first; i < pt.first + pt.count; ++i)
+        bool corners = true;
+        for (int i = pt.first; i < pt.first + pt.count; ++i) {
             v = (v == -2 || v == tab[i].variant) ? tab[i].variant : -1;
-        pt.variant = v < 0 ? -1 : v;
+            corners = corners && tab[i].grid.corners != nullptr;
+        }
+        pt.variant = (v < 0 || !corners) ? -1 : v;
     }
     // counters (one 32-bit word per part in the header) start at 0: they are
     // part of the copy

@@ -381,6 +381,10 @@ __device__ __forceinline__ int axis_index(float t, float xl, float lo, float hi,
     return min(max((int)floorf((xc - lo) * ih), 0), n - 2);
 }
 
+// ANY_LAYOUT: the maps may be plain or corner-expanded (checked at run time);
+// otherwise the corner-expanded copy is bound (the host makes sure), and the
+// plain path is not compiled in (it costs registers).
+template <bool ANY_LAYOUT>
 __device__ __forceinline__ void grid_load(const GridParams& G, int cls, const float xl[3],
                                           const float t[3], GridTaps& tp) {
     const float ih = G.inv_spacing;
@@ -390,7 +394,7 @@ __device__ __forceinline__ void grid_load(const GridParams& G, int cls, const fl
     tp.cell[0] = cx;
     tp.cell[1] = cy;
     tp.cell[2] = cz;
-    if (G.corners) {
+    if (!ANY_LAYOUT || G.corners) {
         // corner-expanded maps: a cell's 8 corners are 32 contiguous bytes per
         // map, two 16-byte loads instead of four rows (same values)
         const int ncx = G.nx - 1, ncy = G.ny - 1;
@@ -407,6 +411,7 @@ __device__ __forceinline__ void grid_load(const GridParams& G, int cls, const fl
         }
         return;
     }
+    if constexpr (!ANY_LAYOUT) return;
     const int plane = G.nx * G.ny;
     const int vol = plane * G.nz;
     const int base = (cz * G.ny + cy) * G.nx + cx;
@@ -572,7 +577,7 @@ __device__ __forceinline__ void store_force(float4* base, const PairForce& f, fl
 // `gene` is gene `lane` (lanes >= G ignored); returns E (uniform) and writes
 // this lane's gradient component to `grad`.
 // ---------------------------------------------------------------------------
-template <int SLOTS, int VAR, int WAVES = 1>
+template <int SLOTS, int VAR, int WAVES = 1, bool ANY_LAYOUT = true>
 __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig<SLOTS>& L, float gene,
                           float& grad, float* atom_out) {
     const int lane = lane_id();
@@ -752,7 +757,7 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
             // wait for them. They are consumed after the pair phase.
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int s = 0; s < SLOTS; ++s) grid_load(G, L.cls[s], x[s], tv, tap[s]);
+            for (int s = 0; s < SLOTS; ++s) grid_load<ANY_LAYOUT>(G, L.cls[s], x[s], tv, tap[s]);
             __builtin_amdgcn_sched_barrier(0);
             if (k < nb - 1) step(I0(), NoLoad());
             if (k < nb - 1) step(I1(), NoLoad());
@@ -767,7 +772,7 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
             }
         } else {
 #pragma unroll
-            for (int s = 0; s < SLOTS; ++s) grid_load(G, L.cls[s], x[s], tv, tap[s]);
+            for (int s = 0; s < SLOTS; ++s) grid_load<ANY_LAYOUT>(G, L.cls[s], x[s], tv, tap[s]);
         }
         __syncthreads();
         // each atom adds its copies in copy order (range by range)
@@ -937,7 +942,7 @@ __global__ __launch_bounds__(64, (SLOTS == 1 ? 3 : 2)) void score_kernel(GridPar
     if (grad && lane < L.G) grad[(size_t)ind * L.G + lane] = gr;
 }
 
-template <int SLOTS, int VAR, int WAVES = 1>
+template <int SLOTS, int VAR, int WAVES = 1, bool ANY_LAYOUT = true>
 __device__ void local_search_one(const DevItem& it, int ind, Smem<SLOTS, WAVES>& sm, const Lig<SLOTS>& L,
                                  int iterations, float rho, float eps, bool final_eval) {
     // both waves of the two-wave layout hold the genotype and take the same
@@ -956,7 +961,7 @@ __device__ void local_search_one(const DevItem& it, int ind, Smem<SLOTS, WAVES>&
     float lastG = 0.f;
     for (int iter = 0; iter < iterations; ++iter) {
         float gr;
-        const float E = evaluate<SLOTS, VAR, WAVES>(it.grid, sm, L, x, gr, nullptr);
+        const float E = evaluate<SLOTS, VAR, WAVES, ANY_LAYOUT>(it.grid, sm, L, x, gr, nullptr);
         lastE = E;
         lastG = gr;
         if (E < bestE) { bestE = E; bx = x; }
@@ -973,7 +978,7 @@ __device__ void local_search_one(const DevItem& it, int ind, Smem<SLOTS, WAVES>&
     }
     if (final_eval) {
         float gr;
-        const float E = evaluate<SLOTS, VAR, WAVES>(it.grid, sm, L, x, gr, nullptr);
+        const float E = evaluate<SLOTS, VAR, WAVES, ANY_LAYOUT>(it.grid, sm, L, x, gr, nullptr);
         lastE = E;
         lastG = gr;
         if (E < bestE) { bestE = E; bx = x; }
@@ -1015,8 +1020,10 @@ __device__ void ls_dispatch(int var_uniform, const DevItem& it, int ind, Smem<SL
 template <int SLOTS, int VAR, int WAVES = 1>
 __device__ void ls_run(const DevItem& it, int ind, Smem<SLOTS, WAVES>& sm, const Lig<SLOTS>& L,
                        const LsParams& p) {
+    // a kernel specialised for one variant runs only items whose grids have
+    // the corner-expanded copy bound; the dispatching kernel takes any
     if constexpr (VAR >= 0)
-        local_search_one<SLOTS, VAR, WAVES>(it, ind, sm, L, it.iterations, p.rho, p.eps, it.final_eval != 0);
+        local_search_one<SLOTS, VAR, WAVES, false>(it, ind, sm, L, it.iterations, p.rho, p.eps, it.final_eval != 0);
     else
         ls_dispatch<SLOTS, WAVES>(-1, it, ind, sm, L, p);
 }

@@ -395,17 +395,17 @@ __device__ __forceinline__ void grid_load(const GridParams& G, int cls, const fl
     tp.cell[1] = cy;
     tp.cell[2] = cz;
     if (!ANY_LAYOUT || G.corners) {
-        // corner-expanded maps: a cell's 8 corners are 32 contiguous bytes per
-        // map, two 16-byte loads instead of four rows (same values)
+        // corner-expanded maps: for the atom's type and cell, the 8 corners of
+        // its type map, of the electrostatic and of the desolvation map are 96
+        // contiguous bytes, six 16-byte loads instead of twelve rows (same
+        // values)
         const int ncx = G.nx - 1, ncy = G.ny - 1;
         const size_t ncell = (size_t)ncx * ncy * (G.nz - 1);
         const size_t cell = (size_t)((cz * ncy + cy) * ncx + cx);
-        const auto base = gmem(reinterpret_cast<const f32x4*>(G.corners));
-        const int maps[3] = {cls, G.n_maps - 2, G.n_maps - 1};
+        const auto base = gmem(reinterpret_cast<const f32x4*>(G.corners)) + ((size_t)cls * ncell + cell) * 6;
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            const size_t at = ((size_t)maps[m] * ncell + cell) * 2;
-            const f32x4 a = base[at], b = base[at + 1];
+            const f32x4 a = base[2 * m], b = base[2 * m + 1];
             tp.v[m][0] = a.x; tp.v[m][1] = a.y; tp.v[m][2] = a.z; tp.v[m][3] = a.w;
             tp.v[m][4] = b.x; tp.v[m][5] = b.y; tp.v[m][6] = b.z; tp.v[m][7] = b.w;
         }
@@ -427,25 +427,30 @@ __device__ __forceinline__ void grid_load(const GridParams& G, int cls, const fl
     }
 }
 
-// Corner expansion of a grid set: thread t handles cell t % ncell of map
-// t / ncell and writes its 8 corner values (v[4 dz + 2 dy + dx]) as two
-// float4. Every corner index stays inside the map (cells stop one node
-// before each upper face).
+// Corner expansion of a grid set: thread t handles cell t % ncell for atom
+// type t / ncell and writes the cell's 8 corner values (v[4 dz + 2 dy + dx])
+// of that type's map, of the electrostatic map and of the desolvation map,
+// as six float4. Every corner index stays inside the maps (cells stop one
+// node before each upper face).
 __global__ __launch_bounds__(256) void expand_corners_kernel(GridParams G, float4* __restrict__ out,
                                                              long long total) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total) return;
     const int ncx = G.nx - 1, ncy = G.ny - 1;
     const long long ncell = (long long)ncx * ncy * (G.nz - 1);
-    const int m = (int)(t / ncell);
-    const long long cell = t - (long long)m * ncell;
+    const int type = (int)(t / ncell);
+    const long long cell = t - (long long)type * ncell;
     const int cx = (int)(cell % ncx);
     const long long rest = cell / ncx;
     const int cy = (int)(rest % ncy), cz = (int)(rest / ncy);
     const size_t plane = (size_t)G.nx * G.ny;
-    const float* p = G.maps + (size_t)m * plane * G.nz + ((size_t)cz * G.ny + cy) * G.nx + cx;
-    out[2 * t] = make_float4(p[0], p[1], p[G.nx], p[G.nx + 1]);
-    out[2 * t + 1] = make_float4(p[plane], p[plane + 1], p[plane + G.nx], p[plane + G.nx + 1]);
+    const size_t at = ((size_t)cz * G.ny + cy) * G.nx + cx;
+    const int maps[3] = {type, G.n_maps - 2, G.n_maps - 1};
+    for (int m = 0; m < 3; ++m) {
+        const float* p = G.maps + (size_t)maps[m] * plane * G.nz + at;
+        out[6 * t + 2 * m] = make_float4(p[0], p[1], p[G.nx], p[G.nx + 1]);
+        out[6 * t + 2 * m + 1] = make_float4(p[plane], p[plane + 1], p[plane + G.nx], p[plane + G.nx + 1]);
+    }
 }
 
 __device__ __forceinline__ void grid_term(const GridParams& G, const GridTaps& tp, float q, float aq,
@@ -1252,7 +1257,7 @@ hipError_t launch_score(const GridParams& g, const uint8_t* blob, int slots, int
 }
 
 hipError_t launch_expand_corners(const GridParams& g, float* corners, hipStream_t stream) {
-    const long long total = (long long)g.n_maps * (g.nx - 1) * (g.ny - 1) * (g.nz - 1);
+    const long long total = (long long)(g.n_maps - 2) * (g.nx - 1) * (g.ny - 1) * (g.nz - 1);
     if (total <= 0) return hipSuccess;
     const long long blocks = (total + 255) / 256;
     hipLaunchKernelGGL(expand_corners_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, g,

@@ -394,16 +394,18 @@ def test_corner_expanded_grids_identical(dk):
     Gc = dk.Grids.from_synth(w.grids)
     assert Gc.corners is not None and Gc.corners.numel() == Gc.corner_bytes()
     n_cells = (np.array(w.grids.maps.shape[1:]) - 1).prod()
-    assert Gc.corner_bytes() == w.grids.maps.shape[0] * n_cells * 32
-    # spot-check the layout: corner v[4 dz + 2 dy + dx] of cell (cx, cy, cz) of map m
     M, nz, ny, nx = w.grids.maps.shape
-    cv = Gc.corners.view(torch.float32).cpu().numpy().reshape(M, nz - 1, ny - 1, nx - 1, 8)
+    assert Gc.corner_bytes() == (M - 2) * n_cells * 96
+    # spot-check the layout: for type t and cell (cx, cy, cz), corner
+    # v[4 dz + 2 dy + dx] of the type map, the electrostatic and the desolvation map
+    cv = Gc.corners.view(torch.float32).cpu().numpy().reshape(M - 2, nz - 1, ny - 1, nx - 1, 3, 8)
     rng = np.random.default_rng(3)
     for _ in range(50):
-        m, cz, cy, cx = rng.integers(M), rng.integers(nz - 1), rng.integers(ny - 1), rng.integers(nx - 1)
-        for k in range(8):
-            dz, dy, dx = k >> 2, (k >> 1) & 1, k & 1
-            assert cv[m, cz, cy, cx, k] == w.grids.maps[m, cz + dz, cy + dy, cx + dx]
+        t, cz, cy, cx = rng.integers(M - 2), rng.integers(nz - 1), rng.integers(ny - 1), rng.integers(nx - 1)
+        for j, m in enumerate((t, M - 2, M - 1)):
+            for k in range(8):
+                dz, dy, dx = k >> 2, (k >> 1) & 1, k & 1
+                assert cv[t, cz, cy, cx, j, k] == w.grids.maps[m, cz + dz, cy + dy, cx + dx]
     gt = torch.from_numpy(w.genotypes[0]).cuda()
     for v in FP32_VARIANTS:
         Ep, gp = dk.score_batch(Gp, L, gt, variant=v)

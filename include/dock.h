@@ -101,11 +101,12 @@ int32_t dock_destroy_grids(dock_grids* grids);
  * electrostatic and the desolvation map): for every atom type t < n_maps-2
  * and every cell (cx, cy, cz) of the (nx-1)(ny-1)(nz-1) cells (x fastest),
  * the cell's 8 corner values v[4 dz + 2 dy + dx] of map t, of the
- * electrostatic and of the desolvation map, as 96 contiguous bytes. An atom
- * then reads 96 contiguous bytes instead of twelve separate rows; the values
- * and the arithmetic are the same, so scores are identical with and without
- * it. *bytes = (n_maps-2) (nx-1)(ny-1)(nz-1) 96 (about 24 (n_maps-2)/n_maps
- * times the maps). */
+ * electrostatic and of the desolvation map, as 96 contiguous bytes of a
+ * 128-byte block (32 bytes of zeros). An atom then reads one block (one
+ * cache line when the buffer is 128-byte aligned) instead of twelve separate
+ * rows; the values and the arithmetic are the same, so scores are identical
+ * with and without it. *bytes = (n_maps-2) (nx-1)(ny-1)(nz-1) 128 (about
+ * 32 (n_maps-2)/n_maps times the maps). */
 int32_t dock_grids_corner_bytes(const dock_grids* grids, int64_t* bytes);
 /* Fills corners_dev (device, caller-owned, 16-byte aligned, >= the size above)
  * from the handle's maps on `stream` and binds it to the handle: later calls

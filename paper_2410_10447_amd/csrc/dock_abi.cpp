@@ -210,7 +210,7 @@ int32_t dock_destroy_grids(dock_grids* g) {
 
 int32_t dock_grids_corner_bytes(const dock_grids* g, int64_t* bytes) {
     if (!g || !bytes) return fail(DOCK_EINVAL, "dock_grids_corner_bytes: NULL argument");
-    *bytes = (int64_t)(g->desc.n_maps - 2) * (g->desc.nx - 1) * (g->desc.ny - 1) * (g->desc.nz - 1) * 96;
+    *bytes = (int64_t)(g->desc.n_maps - 2) * (g->desc.nx - 1) * (g->desc.ny - 1) * (g->desc.nz - 1) * 128;
     return ok();
 }
 

@@ -397,12 +397,12 @@ __device__ __forceinline__ void grid_load(const GridParams& G, int cls, const fl
     if (!ANY_LAYOUT || G.corners) {
         // corner-expanded maps: for the atom's type and cell, the 8 corners of
         // its type map, of the electrostatic and of the desolvation map are 96
-        // contiguous bytes, six 16-byte loads instead of twelve rows (same
-        // values)
+        // contiguous bytes of a 128-byte block (one cache line), six 16-byte
+        // loads instead of twelve rows (same values)
         const int ncx = G.nx - 1, ncy = G.ny - 1;
         const size_t ncell = (size_t)ncx * ncy * (G.nz - 1);
         const size_t cell = (size_t)((cz * ncy + cy) * ncx + cx);
-        const auto base = gmem(reinterpret_cast<const f32x4*>(G.corners)) + ((size_t)cls * ncell + cell) * 6;
+        const auto base = gmem(reinterpret_cast<const f32x4*>(G.corners)) + ((size_t)cls * ncell + cell) * 8;
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             const f32x4 a = base[2 * m], b = base[2 * m + 1];
@@ -430,8 +430,9 @@ __device__ __forceinline__ void grid_load(const GridParams& G, int cls, const fl
 // Corner expansion of a grid set: thread t handles cell t % ncell for atom
 // type t / ncell and writes the cell's 8 corner values (v[4 dz + 2 dy + dx])
 // of that type's map, of the electrostatic map and of the desolvation map,
-// as six float4. Every corner index stays inside the maps (cells stop one
-// node before each upper face).
+// as six float4 of a block of eight (the last two are zero padding, so a
+// block fills one 128-byte line). Every corner index stays inside the maps
+// (cells stop one node before each upper face).
 __global__ __launch_bounds__(256) void expand_corners_kernel(GridParams G, float4* __restrict__ out,
                                                              long long total) {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -448,9 +449,11 @@ __global__ __launch_bounds__(256) void expand_corners_kernel(GridParams G, float
     const int maps[3] = {type, G.n_maps - 2, G.n_maps - 1};
     for (int m = 0; m < 3; ++m) {
         const float* p = G.maps + (size_t)maps[m] * plane * G.nz + at;
-        out[6 * t + 2 * m] = make_float4(p[0], p[1], p[G.nx], p[G.nx + 1]);
-        out[6 * t + 2 * m + 1] = make_float4(p[plane], p[plane + 1], p[plane + G.nx], p[plane + G.nx + 1]);
+        out[8 * t + 2 * m] = make_float4(p[0], p[1], p[G.nx], p[G.nx + 1]);
+        out[8 * t + 2 * m + 1] = make_float4(p[plane], p[plane + 1], p[plane + G.nx], p[plane + G.nx + 1]);
     }
+    out[8 * t + 6] = make_float4(0.f, 0.f, 0.f, 0.f);
+    out[8 * t + 7] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 __device__ __forceinline__ void grid_term(const GridParams& G, const GridTaps& tp, float q, float aq,

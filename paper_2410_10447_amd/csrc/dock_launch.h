@@ -11,7 +11,8 @@ struct GridParams {
     const float* maps;   // [n_maps][nz][ny][nx]
     const float* corners;  // nullptr, or per atom type and cell the cell's 8 corner values
                            // v[4 dz + 2 dy + dx] of the type map, the electrostatic and
-                           // the desolvation map: [n_maps-2][(nz-1)(ny-1)(nx-1)][3][8]
+                           // the desolvation map, padded to 128 bytes:
+                           // [n_maps-2][(nz-1)(ny-1)(nx-1)][32] (24 values, 8 zeros)
     int32_t nx, ny, nz, n_maps;
     float spacing;
     float inv_spacing;

@@ -288,7 +288,7 @@ def test_batch_calls_validate_before_device_work():
     assert L.dock_create_grids(C.byref(d), fake, C.byref(g)) == dock.DOCK_OK
     # corner-expanded copy: size, and validation before any launch
     nb = C.c_int64()
-    assert L.dock_grids_corner_bytes(g, C.byref(nb)) == dock.DOCK_OK and nb.value == 8 * 7 * 7 * 7 * 96
+    assert L.dock_grids_corner_bytes(g, C.byref(nb)) == dock.DOCK_OK and nb.value == 8 * 7 * 7 * 7 * 128
     assert L.dock_grids_corner_bytes(None, C.byref(nb)) == dock.DOCK_EINVAL
     assert L.dock_grids_bind_corners(None, fake, nb.value, None) == dock.DOCK_EINVAL
     assert L.dock_grids_bind_corners(g, fake, nb.value - 1, None) == dock.DOCK_EINVAL

@@ -395,10 +395,11 @@ def test_corner_expanded_grids_identical(dk):
     assert Gc.corners is not None and Gc.corners.numel() == Gc.corner_bytes()
     n_cells = (np.array(w.grids.maps.shape[1:]) - 1).prod()
     M, nz, ny, nx = w.grids.maps.shape
-    assert Gc.corner_bytes() == (M - 2) * n_cells * 96
+    assert Gc.corner_bytes() == (M - 2) * n_cells * 128
     # spot-check the layout: for type t and cell (cx, cy, cz), corner
     # v[4 dz + 2 dy + dx] of the type map, the electrostatic and the desolvation map
-    cv = Gc.corners.view(torch.float32).cpu().numpy().reshape(M - 2, nz - 1, ny - 1, nx - 1, 3, 8)
+    cv = Gc.corners.view(torch.float32).cpu().numpy().reshape(M - 2, nz - 1, ny - 1, nx - 1, 4, 8)
+    assert np.all(cv[..., 3, :] == 0)
     rng = np.random.default_rng(3)
     for _ in range(50):
         t, cz, cy, cx = rng.integers(M - 2), rng.integers(nz - 1), rng.integers(ny - 1), rng.integers(nx - 1)

@@ -40,7 +40,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kWave = 64;
-constexpr int kMaxAtoms = dockblob::kMaxAtoms;
 constexpr int kMaxTors = dockblob::kMaxTorsions;
 constexpr int kMaxFrag = dockblob::kMaxFrag;
 constexpr int kChain = dockblob::kChainStride;
@@ -57,8 +56,7 @@ constexpr float kDielBKLB = 86.9525f * 7.7839f * 0.003627f * 86.9525f;
 constexpr float kDsInv2S2 = 1.0f / (2.0f * 3.5f * 3.5f);   // 1 / (2 sigma^2)
 constexpr float kDsInvS2 = 1.0f / (3.5f * 3.5f);
 constexpr float kLog2e = 1.4426950408889634f;
-constexpr float kElec = 332.06363f;          // kcal A / (mol e^2)
-constexpr float kSqrtElec = 18.222613f;      // sqrt(kElec): charges in LDS carry it
+constexpr float kSqrtElec = 18.222613f;      // sqrt(332.06363 kcal A / (mol e^2)): charges in LDS carry it
 
 // ---------------------------------------------------------------------------
 // Cross-lane primitives (wave64).

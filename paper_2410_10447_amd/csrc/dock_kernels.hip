@@ -40,6 +40,9 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kWave = 64;
+// Fourth word of a raw buffer resource on CDNA (32-bit data format, no
+// swizzle, no stride): loads address bytes [0, num_records).
+constexpr int kBufferWord3 = 0x00020000;
 constexpr int kMaxTors = dockblob::kMaxTorsions;
 constexpr int kMaxFrag = dockblob::kMaxFrag;
 constexpr int kChain = dockblob::kChainStride;
@@ -698,7 +701,7 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
         const int nb_all = L.n_batches;
         const int half = (nb_all + 1) >> 1;
         const int nb = WAVES == 1 ? nb_all : (L.wv == 0 ? half : nb_all - half);
-        const auto plist = gmem(L.plist) + (WAVES == 1 || L.wv == 0 ? 0 : half * kWave);
+        const u32x4* const plist_at = L.plist + (WAVES == 1 || L.wv == 0 ? 0 : half * kWave);
         const int pmask = L.pmask;
         // an atom's position sits at its slot's byte offset masked to one stride
         auto pos_i = [&](uint32_t w) { return *slot(sm.dyn, w & pmask); };
@@ -714,9 +717,15 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
         // order: batch k's stores precede batch k + 1's loads). Prefetch
         // indices are clamped to the last batch, so loads need no guard.
         if (nb > 0) {
-            auto record = [&](int b) -> u32x4 {  // uniform row address, lane offset
-                const auto row = plist + uniform(min(b, nb - 1)) * kWave;
-                return row[lane];
+            // records through a buffer resource over this wave's batches: the
+            // row offset is a scalar and the lane offset a loop-invariant
+            // register, so a record load costs no vector address arithmetic
+            const __amdgpu_buffer_rsrc_t prsrc = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<u32x4*>(plist_at), 0, nb * kWave * (int)sizeof(u32x4), kBufferWord3);
+            const int lane_off = lane * (int)sizeof(u32x4);
+            auto record = [&](int b) -> u32x4 {
+                return __builtin_amdgcn_raw_buffer_load_b128(
+                    prsrc, lane_off, uniform(min(b, nb - 1)) * kWave * (int)sizeof(u32x4), 0);
             };
             u32x4 R[4];
             float4 Pi[2], Pj[2], Ai[2], Aj[2];

@@ -198,6 +198,62 @@ def score_run(n=65536, reps=5):
     return {"workload": w.name, "genotypes": n, **res}
 
 
+def ga_step_bytes(R, P, G):
+    """Algorithmic HBM bytes of one GA step: per child gene the parent gene,
+    the mutation draw and displacement, and the child gene (16 B); per child
+    its candidates, coins and cut points (36 B); the energies (4 B per
+    member) and the best index per run."""
+    return R * P * G * 16 + R * P * 36 + R * P * 4 + R * 4
+
+
+def lga_run(G, L, gen0, generations, variant, n_runs=20, seed=77):
+    """LGA generations on the benchmark docking job: 20 runs x 150 members of
+    the 48-atom ligand. A generation draws the GA step's random inputs,
+    makes the children (dock_ga_step, elitism, tournament 0.6, crossover 0.8,
+    mutation 0.02), and runs the ADADELTA search (300 iterations) on every
+    child; the search's best points and energies form the next population.
+    Times are medians over the generations after a warm-up generation; the
+    generation time is host wall clock (draws, GA step, search, and a
+    synchronisation), the GA step time HIP events around its two kernels."""
+    import torch
+    from paper_2410_10447_amd import dock
+    n, Gn = gen0.shape
+    P = n // n_runs
+    st = dock.LSState.start(gen0[: n_runs * P])
+    ws = torch.empty(dock.workspace_bytes(1), dtype=torch.uint8, device="cuda")
+    dock.local_search([(G, L, st)], 300, variant=variant, workspace=ws)
+    gen_rng = torch.Generator(device="cuda")
+    gen_rng.manual_seed(seed)
+    stream = torch.cuda.current_stream()
+    best_per_gen, ga_ms, gen_ms = [float(st.best_energy.min())], [], []
+    for g in range(generations + 1):       # generation 0 is the warm-up (first launches)
+        a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        draws = dock.ga_draws(n_runs, P, Gn, gen_rng, "cuda")
+        a.record(stream)
+        children, _ = dock.ga_step(st.best_genotype.view(n_runs, P, Gn), st.best_energy.view(n_runs, P),
+                                   *draws, 0.6, 0.8, 0.02, True)
+        b.record(stream)
+        st = dock.LSState.start(children.view(n_runs * P, Gn))
+        dock.local_search([(G, L, st)], 300, variant=variant, workspace=ws)
+        c.record(stream)
+        torch.cuda.synchronize()
+        if g > 0:
+            gen_ms.append(1e3 * (time.perf_counter() - t0))
+            ga_ms.append(a.elapsed_time(b))
+        best_per_gen.append(float(st.best_energy.min()))
+    ga = float(np.median(ga_ms))
+    achieved = ga_step_bytes(n_runs, P, Gn) / (ga * 1e-3) / 1e9
+    return {"workload": f"lga_r{n_runs}_p{P}_n{L.n_atoms}_t{L.n_torsions}", "generations": generations,
+            "ms_per_generation": round(float(np.median(gen_ms)), 4),
+            "ga_step_us": round(1e3 * ga, 2),
+            "ga_step_roofline": {"bound": "hbm", "achieved": round(achieved, 2), "peak": 8000.0,
+                                 "unit": "GB/s", "frac": achieved / 8000.0,
+                                 "bytes": ga_step_bytes(n_runs, P, Gn)},
+            "best_energy_per_generation": [round(x, 4) for x in best_per_gen]}
+
+
 def uneven_run(steps, warmup, use_table=True, tpi_override=0):
     """64 ligands (atoms U{12..128}, torsions U{0..32}) x 100 individuals on one
     96^3 x 12 grid set, 300 iterations, in one call per step (one persistent
@@ -298,6 +354,8 @@ def main():
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--reduction-repeat", type=int, default=200,
                     help="dependent reductions per launch in the isolated reduction run (0 = skip)")
+    ap.add_argument("--lga-generations", type=int, default=3,
+                    help="LGA generations (GA step + local search) on the benchmark job (0 = skip)")
     ap.add_argument("--score-n", type=int, default=65536,
                     help="genotypes of the scoring-throughput run (0 = skip)")
     args = ap.parse_args()
@@ -391,6 +449,8 @@ def main():
         out["uneven"] = uneven_run(args.uneven_steps, 1, tpi_override=args.uneven_tpi)
     if args.serve_seconds > 0:
         out["serving"] = serving_run(args.serve_seconds, args.serve_rate, variant=best_v)
+    if args.lga_generations > 0:
+        out["lga"] = lga_run(G, L, gen0, args.lga_generations, best_v)
     if args.score_n > 0:
         out["score"] = score_run(args.score_n)
     if args.reduction_repeat > 0:

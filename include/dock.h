@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define DOCK_ABI_VERSION 3
+#define DOCK_ABI_VERSION 4
 
 /* status codes */
 #define DOCK_OK            0
@@ -297,6 +297,70 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items,
  * ---------------------------------------------------------------------- */
 int32_t dock_block_sum4(const float* in_dev, float* out_dev, int32_t n_blocks, int32_t threads,
                         int32_t variant, int32_t repeat, void* stream);
+
+/* ------------------------------------------------------------------------
+ * One generation step of the genetic search of the LGA (Sec. 2.1: the GA
+ * produces new genotypes that the local search then improves; a docking job
+ * holds many independent LGA runs). The paper names no operator; these are
+ * the standard AutoDock ones:
+ *   elitism      child 0 of each run copies the run's best member unchanged
+ *                (lowest energy, lowest index among equals, NaN as +inf);
+ *   selection    every other child takes two parents, each the winner of a
+ *                binary tournament between two candidate members: the fitter
+ *                (lower energy, the first candidate on a tie, NaN as +inf)
+ *                wins when the tournament draw is < p_tournament, else the
+ *                other;
+ *   crossover    when the crossover draw is < p_crossover, genes [lo, hi)
+ *                come from the second parent (lo, hi = the smaller and the
+ *                larger cut point), the rest from the first;
+ *   mutation     gene g changes when its draw is < p_mutation, by adding its
+ *                displacement (one float32 addition, no fused operation).
+ * Every random number is an input, drawn by the caller, so the result is
+ * exact (reproducible bit for bit). All arrays are device, float32 or int32,
+ * row-major, caller-owned:
+ *   genotypes  [n_runs][pop][n_genes]  the current population
+ *   energies   [n_runs][pop]           its energies
+ *   candidates [n_runs][pop][4]        tournament candidates of parent 1
+ *                                      (0, 1) and parent 2 (2, 3), member
+ *                                      indices within the run, clamped to
+ *                                      [0, pop - 1]; 16-byte aligned
+ *   coins      [n_runs][pop][3]        draws of tournament 1, tournament 2
+ *                                      and the crossover
+ *   cuts       [n_runs][pop][2]        crossover cut points, clamped to
+ *                                      [0, n_genes]; 8-byte aligned
+ *   mut_coin   [n_runs][pop][n_genes]  mutation draws
+ *   mut_delta  [n_runs][pop][n_genes]  mutation displacements
+ *   children   [n_runs][pop][n_genes]  written; must not overlap genotypes
+ *   best       [n_runs]                written: index of each run's best
+ *                                      member (also without elitism)
+ * Entries of child 0 of a run with elitism read no draws. The call queues
+ * two kernels on `stream` (the best member per run, then one thread per
+ * child gene) and returns; no host synchronisation, no allocation.
+ * Errors: DOCK_EINVAL on a NULL descriptor or pointer, sizes < 1, n_genes >
+ * DOCK_MAX_GENES, more than 2^31 - 1 child genes, a NaN probability,
+ * elitism not 0 or 1, misaligned candidates or cuts, or overlapping
+ * genotypes and children.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    const float* genotypes;
+    const float* energies;
+    const int32_t* candidates;
+    const float* coins;
+    const int32_t* cuts;
+    const float* mut_coin;
+    const float* mut_delta;
+    float* children;
+    int32_t* best;
+    int32_t n_runs;
+    int32_t pop;
+    int32_t n_genes;
+    float p_tournament;
+    float p_crossover;
+    float p_mutation;
+    int32_t elitism;
+} dock_ga_step_desc;
+
+int32_t dock_ga_step(const dock_ga_step_desc* desc, void* stream);
 
 #ifdef __cplusplus
 }

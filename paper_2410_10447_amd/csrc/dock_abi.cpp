@@ -535,4 +535,45 @@ int32_t dock_block_sum4(const float* in, float* out, int32_t n_blocks, int32_t t
     return ok();
 }
 
+int32_t dock_ga_step(const dock_ga_step_desc* d, void* stream) {
+    if (!d) return fail(DOCK_EINVAL, "dock_ga_step: NULL descriptor");
+    if (!d->genotypes || !d->energies || !d->candidates || !d->coins || !d->cuts || !d->mut_coin ||
+        !d->mut_delta || !d->children || !d->best)
+        return fail(DOCK_EINVAL, "dock_ga_step: NULL pointer");
+    if (d->n_runs < 1 || d->pop < 1 || d->n_genes < 1 || d->n_genes > DOCK_MAX_GENES)
+        return fail(DOCK_EINVAL, "dock_ga_step: bad sizes");
+    const int64_t genes = (int64_t)d->n_runs * d->pop * d->n_genes;
+    if (genes > 2147483647LL) return fail(DOCK_EINVAL, "dock_ga_step: more than 2^31 - 1 child genes");
+    if (std::isnan(d->p_tournament) || std::isnan(d->p_crossover) || std::isnan(d->p_mutation))
+        return fail(DOCK_EINVAL, "dock_ga_step: NaN probability");
+    if (d->elitism != 0 && d->elitism != 1) return fail(DOCK_EINVAL, "dock_ga_step: elitism must be 0 or 1");
+    if (!aligned(d->candidates, 16) || !aligned(d->cuts, 8) || !aligned(d->genotypes, 4) ||
+        !aligned(d->energies, 4) || !aligned(d->coins, 4) || !aligned(d->mut_coin, 4) ||
+        !aligned(d->mut_delta, 4) || !aligned(d->children, 4) || !aligned(d->best, 4))
+        return fail(DOCK_EINVAL, "dock_ga_step: misaligned array");
+    const uintptr_t g0 = reinterpret_cast<uintptr_t>(d->genotypes), c0 = reinterpret_cast<uintptr_t>(d->children);
+    const uintptr_t span = (uintptr_t)genes * sizeof(float);
+    if (g0 < c0 + span && c0 < g0 + span) return fail(DOCK_EINVAL, "dock_ga_step: children overlap genotypes");
+    docklaunch::GaParams p;
+    p.genotypes = d->genotypes;
+    p.energies = d->energies;
+    p.cand = d->candidates;
+    p.coins = d->coins;
+    p.cuts = d->cuts;
+    p.mut_coin = d->mut_coin;
+    p.mut_delta = d->mut_delta;
+    p.children = d->children;
+    p.best = d->best;
+    p.n_runs = d->n_runs;
+    p.pop = d->pop;
+    p.n_genes = d->n_genes;
+    p.p_tournament = d->p_tournament;
+    p.p_crossover = d->p_crossover;
+    p.p_mutation = d->p_mutation;
+    p.elitism = d->elitism;
+    hipError_t e = docklaunch::launch_ga_step(p, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "dock_ga_step launch");
+    return ok();
+}
+
 }  // extern "C"

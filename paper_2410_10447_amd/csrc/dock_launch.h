@@ -75,4 +75,22 @@ hipError_t launch_block_sum4(const float* in, float* out, int n_blocks, int thre
 // Writes the corner-expanded copy of g.maps (layout of GridParams::corners).
 hipError_t launch_expand_corners(const GridParams& g, float* corners, hipStream_t stream);
 
+// One GA generation step (the operators of dock_ga_step).
+struct GaParams {
+    const float* genotypes;   // [n_runs][pop][n_genes]
+    const float* energies;    // [n_runs][pop]
+    const int32_t* cand;      // [n_runs][pop][4]
+    const float* coins;       // [n_runs][pop][3]
+    const int32_t* cuts;      // [n_runs][pop][2]
+    const float* mut_coin;    // [n_runs][pop][n_genes]
+    const float* mut_delta;   // [n_runs][pop][n_genes]
+    float* children;          // [n_runs][pop][n_genes]
+    int32_t* best;            // [n_runs]
+    int32_t n_runs, pop, n_genes;
+    float p_tournament, p_crossover, p_mutation;
+    int32_t elitism;
+};
+
+hipError_t launch_ga_step(const GaParams& p, hipStream_t stream);
+
 }  // namespace docklaunch

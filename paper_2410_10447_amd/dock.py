@@ -41,7 +41,7 @@ ABI_SYMBOLS = (
     "dock_grids_corner_bytes", "dock_grids_bind_corners",
     "dock_create_ligand", "dock_ligand_info_get", "dock_ligand_export", "dock_ligand_upload",
     "dock_destroy_ligand", "dock_score_batch", "dock_ls_workspace_bytes",
-    "dock_local_search_batch", "dock_block_sum4",
+    "dock_local_search_batch", "dock_block_sum4", "dock_ga_step",
 )
 
 
@@ -96,6 +96,15 @@ class LsOpts(C.Structure):
                 ("variant", C.c_int32), ("threads_per_ind", C.c_int32), ("flags", C.c_uint32)]
 
 
+class GaStepDesc(C.Structure):
+    _fields_ = [("genotypes", C.c_void_p), ("energies", C.c_void_p), ("candidates", C.c_void_p),
+                ("coins", C.c_void_p), ("cuts", C.c_void_p), ("mut_coin", C.c_void_p),
+                ("mut_delta", C.c_void_p), ("children", C.c_void_p), ("best", C.c_void_p),
+                ("n_runs", C.c_int32), ("pop", C.c_int32), ("n_genes", C.c_int32),
+                ("p_tournament", C.c_float), ("p_crossover", C.c_float), ("p_mutation", C.c_float),
+                ("elitism", C.c_int32)]
+
+
 _lib = None
 
 
@@ -125,6 +134,7 @@ def lib():
         "dock_ls_workspace_bytes": ([i32, C.POINTER(i64)], i32),
         "dock_local_search_batch": ([C.POINTER(LsItem), i32, C.POINTER(LsOpts), vp, i64, vp], i32),
         "dock_block_sum4": ([vp, vp, i32, i32, i32, i32, vp], i32),
+        "dock_ga_step": ([C.POINTER(GaStepDesc), vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -447,3 +457,55 @@ def block_sum4(x, variant: int, repeat: int = 1, stream=None):
     out = torch.empty_like(x)
     _check(lib().dock_block_sum4(_ptr(x), _ptr(out), nb, th, variant, repeat, _stream_handle(stream)))
     return out
+
+
+def ga_step(genotypes, energies, candidates, coins, cuts, mut_coin, mut_delta,
+            p_tournament: float, p_crossover: float, p_mutation: float, elitism: bool,
+            children=None, best=None, stream=None):
+    """One GA generation step (dock_ga_step) on CUDA tensors.
+
+    genotypes (R, P, G) float32, energies (R, P) float32, candidates (R, P, 4)
+    int32, coins (R, P, 3) float32, cuts (R, P, 2) int32, mut_coin and
+    mut_delta (R, P, G) float32. Returns (children (R, P, G), best (R,) int32).
+    """
+    import torch
+    R, P, G = genotypes.shape
+    args = [t.contiguous() for t in (genotypes, energies, candidates, coins, cuts, mut_coin, mut_delta)]
+    gen, E, cand, cn, cu, mc, md = args
+    shapes = {"energies": (E, (R, P), torch.float32), "candidates": (cand, (R, P, 4), torch.int32),
+              "coins": (cn, (R, P, 3), torch.float32), "cuts": (cu, (R, P, 2), torch.int32),
+              "mut_coin": (mc, (R, P, G), torch.float32), "mut_delta": (md, (R, P, G), torch.float32)}
+    if gen.dtype != torch.float32:
+        raise ValueError("genotypes must be float32")
+    for name, (t, shp, dt) in shapes.items():
+        if tuple(t.shape) != shp or t.dtype != dt:
+            raise ValueError(f"{name}: expected {shp} {dt}, got {tuple(t.shape)} {t.dtype}")
+    if children is None:
+        children = torch.empty_like(gen)
+    if best is None:
+        best = torch.empty(R, dtype=torch.int32, device=gen.device)
+    d = GaStepDesc(_ptr(gen).value, _ptr(E).value, _ptr(cand).value, _ptr(cn).value, _ptr(cu).value,
+                   _ptr(mc).value, _ptr(md).value, _ptr(children).value, _ptr(best).value,
+                   R, P, G, float(p_tournament), float(p_crossover), float(p_mutation), int(bool(elitism)))
+    _check(lib().dock_ga_step(C.byref(d), _stream_handle(stream)))
+    return children, best
+
+
+def ga_draws(n_runs: int, pop: int, n_genes: int, generator, device,
+             max_translation: float = 2.0, max_quaternion: float = 0.25, max_torsion: float = 1.5708):
+    """Random inputs of one GA step, drawn on the device with a seeded torch
+    generator: tournament candidates, coins, cut points, mutation draws, and
+    displacements uniform in +-max_translation (genes 0..2, Angstrom),
+    +-max_quaternion (genes 3..6) and +-max_torsion (torsion genes, rad)."""
+    import torch
+    R, P, G = n_runs, pop, n_genes
+    kw = dict(generator=generator, device=device)
+    cand = torch.randint(0, P, (R, P, 4), dtype=torch.int32, **kw)
+    coins = torch.rand((R, P, 3), dtype=torch.float32, **kw)
+    cuts = torch.randint(0, G + 1, (R, P, 2), dtype=torch.int32, **kw)
+    mut_coin = torch.rand((R, P, G), dtype=torch.float32, **kw)
+    scale = torch.full((G,), max_torsion, dtype=torch.float32, device=device)
+    scale[:3] = max_translation
+    scale[3:7] = max_quaternion
+    mut_delta = (torch.rand((R, P, G), dtype=torch.float32, **kw) * 2.0 - 1.0) * scale
+    return cand, coins, cuts, mut_coin, mut_delta

@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(dock.ABI_SYMBOLS)
     for name in declared:
         assert hasattr(L, name)
-    assert L.dock_abi_version() == 3
+    assert L.dock_abi_version() == 4
 
 
 def _check_prep(lig):
@@ -324,3 +324,23 @@ def test_batch_calls_validate_before_device_work():
     assert L.dock_block_sum4(fake, fake, 1, 2048, 0, 1, None) == dock.DOCK_EINVAL
     assert L.dock_destroy_grids(g) == 0 and L.dock_destroy_grids(g5) == 0
     assert L.dock_destroy_grids(None) == 0 and L.dock_destroy_ligand(None) == 0
+
+
+def test_ga_step_rejects_bad_descriptors_before_any_device_work():
+    """Argument checks of dock_ga_step run on the host and need no GPU."""
+    L = dock.lib()
+    assert L.dock_ga_step(None, None) == dock.DOCK_EINVAL
+    fake = 1 << 20                      # never dereferenced: every call below fails a check
+    base = dict(genotypes=fake, energies=fake + 4096, candidates=fake + 8192, coins=fake + 12288,
+                cuts=fake + 16384, mut_coin=fake + 20480, mut_delta=fake + 24576,
+                children=fake + (1 << 16), best=fake + (1 << 17),
+                n_runs=2, pop=3, n_genes=7, p_tournament=0.6, p_crossover=0.8, p_mutation=0.02,
+                elitism=1)
+    bad = [dict(n_runs=0), dict(pop=-1), dict(n_genes=0), dict(n_genes=40),
+           dict(n_runs=1 << 16, pop=1 << 16, n_genes=2), dict(p_crossover=float("nan")),
+           dict(elitism=2), dict(candidates=fake + 8200), dict(cuts=fake + 16388),
+           dict(children=fake + 8), dict(best=None), dict(genotypes=None)]
+    for change in bad:
+        d = dock.GaStepDesc(**{**base, **change})
+        assert L.dock_ga_step(C.byref(d), None) == dock.DOCK_EINVAL, change
+        assert "dock_ga_step" in dock.last_error()

@@ -1,0 +1,140 @@
+"""GPU parity of the GA generation step (dock_ga_step) against the reference
+step: bit-exact, since every random number is an input and the step's only
+arithmetic is one float32 addition per mutated gene. Shapes span several
+256-thread blocks with a ragged tail, one member per run, the longest
+genotype, and the docking job the benchmark runs (20 runs x 150 members, 17
+genes)."""
+import numpy as np
+import pytest
+
+from oracle import ga_ref as GA
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dk():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2410_10447_amd import dock
+    dock.lib()
+    return dock
+
+
+def _inputs(R, P, G, seed, energy_kind="normal"):
+    rng = np.random.default_rng(seed)
+    gen = rng.normal(size=(R, P, G)).astype(np.float32)
+    if energy_kind == "normal":
+        E = rng.normal(size=(R, P)).astype(np.float32)
+    elif energy_kind == "ties":
+        E = rng.integers(-2, 3, size=(R, P)).astype(np.float32)   # many equal energies
+    else:                                                          # NaN and inf sprinkled in
+        E = rng.normal(size=(R, P)).astype(np.float32)
+        E[rng.random((R, P)) < 0.2] = np.nan
+        E[rng.random((R, P)) < 0.1] = np.inf
+    cand = rng.integers(0, P, size=(R, P, 4), dtype=np.int32)
+    coins = rng.random((R, P, 3), dtype=np.float32)
+    cuts = rng.integers(0, G + 1, size=(R, P, 2), dtype=np.int32)
+    mut_coin = rng.random((R, P, G), dtype=np.float32)
+    mut_delta = ((rng.random((R, P, G), dtype=np.float32) - 0.5) * 3.0).astype(np.float32)
+    return gen, E, cand, coins, cuts, mut_coin, mut_delta
+
+
+def _run(dk, arrays, p_t, p_c, p_m, elitism):
+    dev = [torch.from_numpy(a).cuda() for a in arrays]
+    children, best = dk.ga_step(*dev, p_t, p_c, p_m, elitism)
+    torch.cuda.synchronize()
+    return children.cpu().numpy(), best.cpu().numpy()
+
+
+@pytest.mark.parametrize("shape", [(3, 7, 7), (2, 33, 17), (1, 1, 39), (5, 61, 13), (20, 150, 17)])
+@pytest.mark.parametrize("elitism", [0, 1])
+def test_ga_step_bit_exact(dk, shape, elitism):
+    R, P, G = shape
+    arrays = _inputs(R, P, G, seed=R * 1000 + P * 10 + G)
+    print(f"ga_step shape={shape} elitism={elitism}", flush=True)
+    got, best = _run(dk, arrays, 0.6, 0.8, 0.02, elitism)
+    want, want_best = GA.ga_step(*arrays, 0.6, 0.8, 0.02, elitism)
+    assert np.array_equal(best, want_best)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+@pytest.mark.parametrize("kind", ["ties", "nonfinite"])
+@pytest.mark.parametrize("probs", [(0.6, 0.8, 0.02), (1.0, 1.0, 1.0), (0.0, 0.0, 0.0)])
+def test_ga_step_ties_nonfinite_and_extreme_rates(dk, kind, probs):
+    R, P, G = 4, 50, 17
+    arrays = _inputs(R, P, G, seed=7 if kind == "ties" else 8, energy_kind=kind)
+    print(f"ga_step kind={kind} probs={probs}", flush=True)
+    got, best = _run(dk, arrays, *probs, 1)
+    want, want_best = GA.ga_step(*arrays, *probs, 1)
+    assert np.array_equal(best, want_best)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def test_ga_step_clamps_out_of_range_draws(dk):
+    R, P, G = 2, 9, 11
+    gen, E, cand, coins, cuts, mc, md = _inputs(R, P, G, seed=9)
+    cand[0, :, 0] = -5
+    cand[1, :, 1] = P + 3
+    cuts[0, :, 0] = -2
+    cuts[1, :, 1] = G + 9
+    arrays = (gen, E, cand, coins, cuts, mc, md)
+    got, best = _run(dk, arrays, 0.6, 0.9, 0.1, 0)
+    want, want_best = GA.ga_step(*arrays, 0.6, 0.9, 0.1, 0)
+    assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+def test_ga_step_twice_then_smaller(dk):
+    """Two calls in a row reuse nothing from each other: the second, smaller
+    call matches the reference on its own inputs."""
+    for shape, seed in (((6, 100, 17), 11), ((2, 5, 9), 12)):
+        arrays = _inputs(*shape, seed=seed)
+        got, best = _run(dk, arrays, 0.6, 0.8, 0.05, 1)
+        want, want_best = GA.ga_step(*arrays, 0.6, 0.8, 0.05, 1)
+        assert np.array_equal(got.view(np.uint32), want.view(np.uint32))
+        assert np.array_equal(best, want_best)
+
+
+def test_ga_step_rejects_bad_arguments(dk):
+    R, P, G = 2, 4, 7
+    dev = [torch.from_numpy(a).cuda() for a in _inputs(R, P, G, seed=13)]
+    with pytest.raises(dk.DockError):
+        dk.ga_step(*dev, float("nan"), 0.8, 0.02, 1)
+    with pytest.raises(dk.DockError):        # children overlapping the parents
+        dk.ga_step(*dev, 0.6, 0.8, 0.02, 1, children=dev[0])
+
+
+def test_lga_generation_keeps_the_elite(dk):
+    """One generation of the LGA on the device (GA step, scoring, local
+    search): with elitism, child 0 of each run is the run's best genotype, so
+    its score equals the parent's, and after the local search (which keeps
+    each individual's best point) no run's best energy has risen."""
+    from paper_2410_10447_amd import synth
+    wl = synth.ls_workload(600)
+    grids = dk.Grids.from_synth(wl.grids)
+    lig = dk.Ligand(wl.ligands[0], wl.ff)
+    R, P = 4, 150
+    G = lig.n_genes
+    gen0 = torch.from_numpy(np.asarray(wl.genotypes[0], np.float32)[: R * P]).cuda()
+    E0, _ = dk.score_batch(grids, lig, gen0)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    draws = dk.ga_draws(R, P, G, g, "cuda")
+    children, best = dk.ga_step(gen0.view(R, P, G), E0.view(R, P), *draws, 0.6, 0.8, 0.02, True)
+    E1, _ = dk.score_batch(grids, lig, children.view(R * P, G))
+    torch.cuda.synchronize()
+    b = best.cpu().numpy()
+    e0 = E0.view(R, P).cpu().numpy()
+    e1 = E1.view(R, P).cpu().numpy()
+    assert np.array_equal(e1[:, 0], e0[np.arange(R), b])
+    assert np.array_equal(children[:, 0].cpu().numpy(),
+                          gen0.view(R, P, G)[torch.arange(R, device="cuda"), best.long()].cpu().numpy())
+    st = dk.LSState.start(children.view(R * P, G))
+    dk.local_search([(grids, lig, st)], iterations=30)
+    torch.cuda.synchronize()
+    e2 = st.best_energy.view(R, P).cpu().numpy()
+    m0 = e0.min(axis=1)
+    # the search's first point is the elite itself, evaluated by the same
+    # FP32 code; the bound allows only rounding
+    assert np.all(e2.min(axis=1) <= m0 + 1e-5 * np.maximum(np.abs(m0), 1.0))

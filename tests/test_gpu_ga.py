@@ -138,3 +138,30 @@ def test_lga_generation_keeps_the_elite(dk):
     # the search's first point is the elite itself, evaluated by the same
     # FP32 code; the bound allows only rounding
     assert np.all(e2.min(axis=1) <= m0 + 1e-5 * np.maximum(np.abs(m0), 1.0))
+
+
+def test_lga_job_budget_monotone_and_oracle_checked(dk):
+    """A small docking job (3 runs x 40 members, 20 search iterations): the
+    per-run best energy never rises from generation to generation (elitism
+    plus a search that keeps its start point), the evaluation budget stops
+    the job before a generation that would exceed it, and the reported best
+    genotypes score, under the FP64 reference, to the reported energies."""
+    from oracle import dock_ref as R
+    from paper_2410_10447_amd import lga, synth
+    from tests.gpu_common import e_ok
+    wl = synth.ls_workload(120)
+    grids = dk.Grids.from_synth(wl.grids)
+    lig = dk.Ligand(wl.ligands[0], wl.ff)
+    gen0 = torch.from_numpy(np.asarray(wl.genotypes[0], np.float32)).cuda()
+    n, its = gen0.shape[0], 20
+    budget = 3 * n * (its + 1) + n            # initial search + 2 generations fit, a third does not
+    res = lga.run_lga(grids, lig, gen0, n_runs=3, generations=5, ls_iterations=its,
+                      eval_budget=budget, seed=3)
+    assert res.generations == 2 and res.evaluations == 3 * n * (its + 1)
+    h = np.stack(res.history)
+    assert h.shape == (3, 3)
+    assert np.all(np.diff(h, axis=0) <= 0), h
+    prep = R.prepare(wl.ligands[0], wl.ff)
+    ref = R.score(prep, wl.grids, res.best_genotype.astype(np.float64))
+    ok, _ = e_ok(res.best_energy, ref, res.best_genotype)
+    assert np.all(ok), (res.best_energy, ref.energy)

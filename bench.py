@@ -124,12 +124,20 @@ def cpu_baseline(w, sample, iterations, pool_per_worker=None):
     workers = max(1, min(cores, 16))
     pool_per_worker = pool_per_worker or sample    # the oracle vectorises over individuals
     n_pool = workers * pool_per_worker
+    omp = os.environ.get("OMP_NUM_THREADS")
     os.environ["OMP_NUM_THREADS"] = "1"
     t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(workers) as pool:
-        pool.map(_oracle_ls_worker, [(k * pool_per_worker, (k + 1) * pool_per_worker, iterations)
-                                     for k in range(workers)])
+    pool = mp.get_context("fork").Pool(workers)
+    pool.map(_oracle_ls_worker, [(k * pool_per_worker, (k + 1) * pool_per_worker, iterations)
+                                 for k in range(workers)])
     dtp = time.perf_counter() - t0
+    # let the workers exit (and their memory go) before anything is timed on the GPU
+    pool.close()
+    pool.join()
+    if omp is None:
+        os.environ.pop("OMP_NUM_THREADS", None)
+    else:
+        os.environ["OMP_NUM_THREADS"] = omp
     evalsp = n_pool * (iterations + 1)
     return {"value": evalsp / dtp, "unit": "evals/s", "cores": workers, "kind": "oracle",
             "sample": f"{n_pool} of 3000 individuals x {iterations + 1} evaluations over "

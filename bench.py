@@ -262,6 +262,40 @@ def lga_run(G, L, gen0, generations, variant, n_runs=20, seed=77):
             "best_energy_per_generation": [round(x, 4) for x in best_per_gen]}
 
 
+def sw_run(G, L, gen0, iterations, variant, reps=3, seed=91):
+    """Solis-Wets search on the benchmark population (3000 individuals of the
+    48-atom ligand): `iterations` per call, standard normal draws resident
+    in HBM before timing, step scales 1 A / 0.1 / 0.5 rad. Evaluations are
+    the trials made (one or two per iteration), counted from the trial log."""
+    import torch
+    from paper_2410_10447_amd import dock
+    n, Gn = gen0.shape
+    E0, _ = dock.score_batch(G, L, gen0, variant=variant, with_grad=False)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    normals = torch.randn((iterations, n, Gn), generator=g, device="cuda", dtype=torch.float32)
+    scale = torch.full((Gn,), 0.5, dtype=torch.float32, device="cuda")
+    scale[:3] = 1.0
+    scale[3:7] = 0.1
+    dock.solis_wets(G, L, dock.SWState.start(gen0, E0), normals[:2], scale, variant=variant)   # warm-up
+    times, evals = [], []
+    for _ in range(reps):
+        st = dock.SWState.start(gen0, E0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        log = dock.solis_wets(G, L, st, normals, scale, variant=variant, log=True)
+        b.record()
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+        evals.append(int((~torch.isnan(log)).sum()))
+    ms = float(np.median(times))
+    return {"workload": f"sw_n{L.n_atoms}_t{L.n_torsions}_i{n}", "iterations": iterations,
+            "variant": dock.VARIANT_NAMES[variant], "ms": round(ms, 4), "evals": evals[-1],
+            "evals_per_s": evals[-1] / (ms * 1e-3),
+            "energy_median_start": float(E0.median()), "energy_median_end": float(st.energy.median())}
+
+
 def uneven_run(steps, warmup, use_table=True, tpi_override=0):
     """64 ligands (atoms U{12..128}, torsions U{0..32}) x 100 individuals on one
     96^3 x 12 grid set, 300 iterations, in one call per step (one persistent
@@ -362,6 +396,8 @@ def main():
                     help="also run a plain device copy of this size (counter calibration)")
     ap.add_argument("--reduction-repeat", type=int, default=200,
                     help="dependent reductions per launch in the isolated reduction run (0 = skip)")
+    ap.add_argument("--sw-iterations", type=int, default=300,
+                    help="Solis-Wets iterations on the benchmark population (0 = skip)")
     ap.add_argument("--lga-generations", type=int, default=3,
                     help="LGA generations (GA step + local search) on the benchmark job (0 = skip)")
     ap.add_argument("--score-n", type=int, default=65536,
@@ -459,6 +495,8 @@ def main():
         out["serving"] = serving_run(args.serve_seconds, args.serve_rate, variant=best_v)
     if args.lga_generations > 0:
         out["lga"] = lga_run(G, L, gen0, args.lga_generations, best_v)
+    if args.sw_iterations > 0:
+        out["sw"] = sw_run(G, L, gen0, args.sw_iterations, best_v if best_v in (0, 1) else 0)
     if args.score_n > 0:
         out["score"] = score_run(args.score_n)
     if args.reduction_repeat > 0:

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define DOCK_ABI_VERSION 4
+#define DOCK_ABI_VERSION 5
 
 /* status codes */
 #define DOCK_OK            0
@@ -297,6 +297,44 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items,
  * ---------------------------------------------------------------------- */
 int32_t dock_block_sum4(const float* in_dev, float* out_dev, int32_t n_blocks, int32_t threads,
                         int32_t variant, int32_t repeat, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Solis-Wets local search (Sec. 2.1: the LGA's second local search beside
+ * ADADELTA; it needs energies only). The paper gives no step; this is the
+ * random search of Solis and Wets as AutoDock uses it. Per iteration and
+ * individual, with z the iteration's standard normal draws (an input):
+ *   dev = rho * (scale[g] * z[g]);
+ *   trial 1: x + bias + dev; if E < current: move, bias = 0.2 bias + 0.4 dev;
+ *   else trial 2: x - bias - dev; if E < current: move, bias = bias - 0.4 dev;
+ *   else bias = 0.5 bias (a failure);
+ *   n_success successes in a row double rho, n_failure failures halve it.
+ * Float32 throughout, every state update in the order written with no fused
+ * operations; one wave per individual (ligands of up to DOCK_MAX_ATOMS
+ * atoms), the energy by the scoring evaluation with the chosen FP32 variant.
+ * Device arrays, float32 unless stated, row-major, caller-owned, in/out:
+ *   genotype [n][G], energy [n] (the energy of genotype on entry, e.g. from
+ *   dock_score_batch), bias [n][G], rho [n], counts int32 [n][2] (successes,
+ *   failures in a row). Inputs: normals [iterations][n][G], scale [G].
+ *   energy_log: NULL or [n][iterations][2], the trials' energies (NaN where
+ *   the second trial was not needed).
+ * A call of K iterations followed by one of L equals one call of K + L with
+ * the concatenated draws, bit for bit. Errors: DOCK_EINVAL on NULL handles,
+ * opts or arrays, n < 0, iterations < 0, run lengths < 1, a variant other
+ * than SHUFFLE or MFMA_F32, a ligand never uploaded, a grid set without the
+ * ligand's type maps, or misaligned arrays.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t iterations;
+    int32_t n_success;           /* successes in a row that double rho (AutoDock: 4) */
+    int32_t n_failure;           /* failures in a row that halve rho (AutoDock: 4) */
+    int32_t variant;             /* DOCK_REDUCE_SHUFFLE or DOCK_REDUCE_MFMA_F32 */
+} dock_sw_opts;
+
+int32_t dock_solis_wets_batch(const dock_grids* grids, const dock_ligand* ligand, int32_t n,
+                              float* genotype_dev, float* energy_dev, float* bias_dev,
+                              float* rho_dev, int32_t* counts_dev, const float* normals_dev,
+                              const float* scale_dev, const dock_sw_opts* opts,
+                              float* energy_log_dev, void* stream);
 
 /* ------------------------------------------------------------------------
  * One generation step of the genetic search of the LGA (Sec. 2.1: the GA

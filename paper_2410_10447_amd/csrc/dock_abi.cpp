@@ -535,6 +535,42 @@ int32_t dock_block_sum4(const float* in, float* out, int32_t n_blocks, int32_t t
     return ok();
 }
 
+int32_t dock_solis_wets_batch(const dock_grids* g, const dock_ligand* l, int32_t n, float* genotype,
+                              float* energy, float* bias, float* rho, int32_t* counts, const float* normals,
+                              const float* scale, const dock_sw_opts* o, float* energy_log, void* stream) {
+    if (!g || !l || !o) return fail(DOCK_EINVAL, "dock_solis_wets_batch: NULL handle or opts");
+    if (n < 0 || o->iterations < 0) return fail(DOCK_EINVAL, "dock_solis_wets_batch: n or iterations < 0");
+    if (o->n_success < 1 || o->n_failure < 1) return fail(DOCK_EINVAL, "dock_solis_wets_batch: run lengths must be >= 1");
+    if (o->variant != DOCK_REDUCE_SHUFFLE && o->variant != DOCK_REDUCE_MFMA_F32)
+        return fail(DOCK_EINVAL, "dock_solis_wets_batch: variant must be SHUFFLE or MFMA_F32");
+    if (!l->blob_dev) return fail(DOCK_EINVAL, "dock_solis_wets_batch: ligand not uploaded");
+    int32_t st = check_grid_for_ligand(g, l);
+    if (st != DOCK_OK) return st;
+    if (n == 0) return ok();
+    if (!genotype || !energy || !bias || !rho || !counts || !scale || (o->iterations > 0 && !normals))
+        return fail(DOCK_EINVAL, "dock_solis_wets_batch: NULL array");
+    if (!aligned(genotype, 4) || !aligned(energy, 4) || !aligned(bias, 4) || !aligned(rho, 4) ||
+        !aligned(counts, 4) || !aligned(scale, 4) || (normals && !aligned(normals, 4)) ||
+        (energy_log && !aligned(energy_log, 4)))
+        return fail(DOCK_EINVAL, "dock_solis_wets_batch: arrays must be 4-byte aligned");
+    docklaunch::SwParams p;
+    p.normals = normals;
+    p.scale = scale;
+    p.genotype = genotype;
+    p.energy = energy;
+    p.bias = bias;
+    p.rho = rho;
+    p.counts = counts;
+    p.log = energy_log;
+    p.n = n;
+    p.iterations = o->iterations;
+    p.n_success = o->n_success;
+    p.n_failure = o->n_failure;
+    hipError_t e = docklaunch::launch_sw(g->gp, l->blob_dev, l->slots, o->variant, p, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "dock_solis_wets_batch launch");
+    return ok();
+}
+
 int32_t dock_ga_step(const dock_ga_step_desc* d, void* stream) {
     if (!d) return fail(DOCK_EINVAL, "dock_ga_step: NULL descriptor");
     if (!d->genotypes || !d->energies || !d->candidates || !d->coins || !d->cuts || !d->mut_coin ||

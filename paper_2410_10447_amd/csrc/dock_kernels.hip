@@ -957,6 +957,88 @@ __global__ __launch_bounds__(64, (SLOTS == 1 ? 3 : 2)) void score_kernel(GridPar
     if (grad && lane < L.G) grad[(size_t)ind * L.G + lane] = gr;
 }
 
+// Solis-Wets random search (Sec. 2.1: the LGA's second local search; the
+// steps are those of Solis and Wets as AutoDock uses them): per iteration the
+// trial x + bias + dev, else x - bias - dev, accepted when its energy is lower;
+// bias and the step scale rho follow the outcome. One wave per individual,
+// gene `lane`; energies only (the gradient evaluate() also makes is unused).
+// State updates are float32 in a fixed order with no fused operations
+// (contraction is off in this kernel; evaluate() keeps its own FMAs).
+template <int SLOTS, int VAR>
+__global__ __launch_bounds__(64, (SLOTS == 1 ? 3 : 2)) void sw_kernel(GridParams G, const uint8_t* __restrict__ blob,
+                                                docklaunch::SwParams p) {
+    // no product below may be fused into an add (FMA): the state must round
+    // after every operation
+#pragma clang fp contract(off)
+    __shared__ Smem<SLOTS> sm;
+    Lig<SLOTS> L;
+    load_ligand<SLOTS>(blob, sm, L);
+    const int lane = lane_id();
+    const int ind = blockIdx.x;
+    if (ind >= p.n) return;
+    const int Gn = L.G;
+    const bool on = lane < Gn;
+    const size_t row = (size_t)ind * Gn + lane;
+    float x = on ? p.genotype[row] : 0.f;
+    float b = on ? p.bias[row] : 0.f;
+    const float sc = on ? p.scale[lane] : 0.f;
+    float E = p.energy[ind];
+    float rho = p.rho[ind];
+    int succ = p.counts[2 * ind], fail = p.counts[2 * ind + 1];
+    for (int it = 0; it < p.iterations; ++it) {
+        const float z = on ? p.normals[((size_t)it * p.n + ind) * Gn + lane] : 0.f;
+        const float dev = rho * (sc * z);
+        float e_try0 = __builtin_nanf(""), e_try1 = __builtin_nanf("");
+        int accepted = -1;
+        for (int t = 0; t < 2; ++t) {      // uniform: E and the trial energies are wave-uniform
+            const float c = t == 0 ? (x + b) + dev : (x - b) - dev;
+            float gr;
+            const float Et = evaluate<SLOTS, VAR>(G, sm, L, c, gr, nullptr);
+            if (t == 0) e_try0 = Et; else e_try1 = Et;
+            if (Et < E) {
+                x = c;
+                E = Et;
+                accepted = t;
+                break;
+            }
+        }
+        if (accepted == 0) {
+            b = 0.2f * b + 0.4f * dev;
+            ++succ;
+            fail = 0;
+        } else if (accepted == 1) {
+            b = b - 0.4f * dev;
+            ++succ;
+            fail = 0;
+        } else {
+            b = 0.5f * b;
+            ++fail;
+            succ = 0;
+        }
+        if (succ >= p.n_success) {
+            rho = 2.f * rho;
+            succ = 0;
+        } else if (fail >= p.n_failure) {
+            rho = 0.5f * rho;
+            fail = 0;
+        }
+        if (p.log && lane == 0) {
+            p.log[((size_t)ind * p.iterations + it) * 2] = e_try0;
+            p.log[((size_t)ind * p.iterations + it) * 2 + 1] = e_try1;
+        }
+    }
+    if (on) {
+        p.genotype[row] = x;
+        p.bias[row] = b;
+    }
+    if (lane == 0) {
+        p.energy[ind] = E;
+        p.rho[ind] = rho;
+        p.counts[2 * ind] = succ;
+        p.counts[2 * ind + 1] = fail;
+    }
+}
+
 template <int SLOTS, int VAR, int WAVES = 1, bool ANY_LAYOUT = true>
 __device__ void local_search_one(const DevItem& it, int ind, Smem<SLOTS, WAVES>& sm, const Lig<SLOTS>& L,
                                  int iterations, float rho, float eps, bool final_eval) {
@@ -1219,6 +1301,16 @@ hipError_t launch_score_v(const GridParams& g, const uint8_t* blob, int slots, i
     return hipGetLastError();
 }
 
+template <int VAR>
+hipError_t launch_sw_v(const GridParams& g, const uint8_t* blob, int slots, const docklaunch::SwParams& p,
+                       hipStream_t st) {
+    if (slots == 1)
+        hipLaunchKernelGGL((sw_kernel<1, VAR>), dim3(p.n), dim3(64), 0, st, g, blob, p);
+    else
+        hipLaunchKernelGGL((sw_kernel<2, VAR>), dim3(p.n), dim3(64), 0, st, g, blob, p);
+    return hipGetLastError();
+}
+
 template <int MODE>
 const void* ls_kernel_ptr(int var) {
     switch (var) {
@@ -1262,6 +1354,15 @@ hipError_t launch_score(const GridParams& g, const uint8_t* blob, int slots, int
         case DOCK_REDUCE_MFMA_BF16: return launch_score_v<2>(g, blob, slots, n, genotypes, energy, grad, atom_out, stream);
         case DOCK_REDUCE_MFMA_F16: return launch_score_v<3>(g, blob, slots, n, genotypes, energy, grad, atom_out, stream);
         case DOCK_REDUCE_MFMA_BF16X3: return launch_score_v<4>(g, blob, slots, n, genotypes, energy, grad, atom_out, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_sw(const GridParams& g, const uint8_t* blob, int slots, int variant, const SwParams& p,
+                     hipStream_t stream) {
+    switch (variant) {
+        case DOCK_REDUCE_SHUFFLE: return launch_sw_v<0>(g, blob, slots, p, stream);
+        case DOCK_REDUCE_MFMA_F32: return launch_sw_v<1>(g, blob, slots, p, stream);
         default: return hipErrorInvalidValue;
     }
 }

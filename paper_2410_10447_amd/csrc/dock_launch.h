@@ -75,6 +75,23 @@ hipError_t launch_block_sum4(const float* in, float* out, int n_blocks, int thre
 // Writes the corner-expanded copy of g.maps (layout of GridParams::corners).
 hipError_t launch_expand_corners(const GridParams& g, float* corners, hipStream_t stream);
 
+// Solis-Wets search state and draws (dock_solis_wets_batch), one individual per block.
+struct SwParams {
+    const float* normals;     // [iterations][n][G] standard normal draws
+    const float* scale;       // [G] per-gene step scale
+    float* genotype;          // [n][G] in/out
+    float* energy;            // [n] in/out: energy of genotype
+    float* bias;              // [n][G] in/out
+    float* rho;               // [n] in/out
+    int32_t* counts;          // [n][2] in/out: successes, failures in a row
+    float* log;               // optional [n][iterations][2]: the trials' energies (NaN: not tried)
+    int32_t n, iterations, n_success, n_failure;
+};
+
+// variant: DOCK_REDUCE_SHUFFLE or DOCK_REDUCE_MFMA_F32.
+hipError_t launch_sw(const GridParams& g, const uint8_t* blob, int slots, int variant, const SwParams& p,
+                     hipStream_t stream);
+
 // One GA generation step (the operators of dock_ga_step).
 struct GaParams {
     const float* genotypes;   // [n_runs][pop][n_genes]

@@ -41,7 +41,7 @@ ABI_SYMBOLS = (
     "dock_grids_corner_bytes", "dock_grids_bind_corners",
     "dock_create_ligand", "dock_ligand_info_get", "dock_ligand_export", "dock_ligand_upload",
     "dock_destroy_ligand", "dock_score_batch", "dock_ls_workspace_bytes",
-    "dock_local_search_batch", "dock_block_sum4", "dock_ga_step",
+    "dock_local_search_batch", "dock_block_sum4", "dock_ga_step", "dock_solis_wets_batch",
 )
 
 
@@ -96,6 +96,11 @@ class LsOpts(C.Structure):
                 ("variant", C.c_int32), ("threads_per_ind", C.c_int32), ("flags", C.c_uint32)]
 
 
+class SwOpts(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("n_success", C.c_int32), ("n_failure", C.c_int32),
+                ("variant", C.c_int32)]
+
+
 class GaStepDesc(C.Structure):
     _fields_ = [("genotypes", C.c_void_p), ("energies", C.c_void_p), ("candidates", C.c_void_p),
                 ("coins", C.c_void_p), ("cuts", C.c_void_p), ("mut_coin", C.c_void_p),
@@ -135,6 +140,7 @@ def lib():
         "dock_local_search_batch": ([C.POINTER(LsItem), i32, C.POINTER(LsOpts), vp, i64, vp], i32),
         "dock_block_sum4": ([vp, vp, i32, i32, i32, i32, vp], i32),
         "dock_ga_step": ([C.POINTER(GaStepDesc), vp], i32),
+        "dock_solis_wets_batch": ([vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, C.POINTER(SwOpts), vp, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -509,3 +515,42 @@ def ga_draws(n_runs: int, pop: int, n_genes: int, generator, device,
     scale[3:7] = max_quaternion
     mut_delta = (torch.rand((R, P, G), dtype=torch.float32, **kw) * 2.0 - 1.0) * scale
     return cand, coins, cuts, mut_coin, mut_delta
+
+
+@dataclass
+class SWState:
+    """Device state of a Solis-Wets population (CUDA tensors)."""
+    genotype: object     # [n, G] float32
+    energy: object       # [n] float32, energy of genotype
+    bias: object         # [n, G] float32
+    rho: object          # [n] float32
+    counts: object       # [n, 2] int32: successes, failures in a row
+
+    @classmethod
+    def start(cls, genotypes, energies, rho0: float = 1.0):
+        import torch
+        g = genotypes.contiguous().clone()
+        n = g.shape[0]
+        return cls(g, energies.contiguous().clone(), torch.zeros_like(g),
+                   torch.full((n,), rho0, dtype=torch.float32, device=g.device),
+                   torch.zeros((n, 2), dtype=torch.int32, device=g.device))
+
+
+def solis_wets(grids: Grids, ligand: Ligand, st: SWState, normals, scale, n_success: int = 4,
+               n_failure: int = 4, variant: int = REDUCE_SHUFFLE, log: bool = False, stream=None):
+    """len(normals) Solis-Wets iterations in place on `st` (dock_solis_wets_batch).
+    normals [iters, n, G] float32, scale [G] float32 (CUDA tensors). Returns the
+    trials' energies [n, iters, 2] if `log`, else None."""
+    import torch
+    iters = normals.shape[0]
+    n, G = st.genotype.shape
+    if tuple(normals.shape[1:]) != (n, G) or tuple(scale.shape) != (G,):
+        raise ValueError("normals must be [iters, n, G] and scale [G]")
+    nm = normals.contiguous()
+    sc = scale.contiguous()
+    lg = torch.empty((n, iters, 2), dtype=torch.float32, device=st.genotype.device) if log else None
+    o = SwOpts(iters, n_success, n_failure, variant)
+    _check(lib().dock_solis_wets_batch(grids.handle, ligand.handle, n, _ptr(st.genotype), _ptr(st.energy),
+                                       _ptr(st.bias), _ptr(st.rho), _ptr(st.counts), _ptr(nm), _ptr(sc),
+                                       C.byref(o), _ptr(lg), _stream_handle(stream)))
+    return lg

@@ -165,3 +165,19 @@ def test_lga_job_budget_monotone_and_oracle_checked(dk):
     ref = R.score(prep, wl.grids, res.best_genotype.astype(np.float64))
     ok, _ = e_ok(res.best_energy, ref, res.best_genotype)
     assert np.all(ok), (res.best_energy, ref.energy)
+
+
+def test_lga_job_early_stop(dk):
+    """The convergence rule ends the job: with a tolerance no improvement can
+    exceed, the job stops after `patience` generations."""
+    from paper_2410_10447_amd import lga, synth
+    wl = synth.ls_workload(60)
+    grids = dk.Grids.from_synth(wl.grids)
+    lig = dk.Ligand(wl.ligands[0], wl.ff)
+    gen0 = torch.from_numpy(np.asarray(wl.genotypes[0], np.float32)).cuda()
+    res = lga.run_lga(grids, lig, gen0, n_runs=2, generations=6, ls_iterations=10,
+                      stop_patience=2, stop_tol=1e9, seed=4)
+    assert res.stopped_early and res.generations == 2 and len(res.history) == 3
+    res = lga.run_lga(grids, lig, gen0, n_runs=2, generations=3, ls_iterations=10,
+                      stop_patience=2, stop_tol=-1.0, seed=4)     # never converged
+    assert not res.stopped_early and res.generations == 3

@@ -56,8 +56,8 @@ FLOPS_PAIR, FLOPS_ATOM, FLOPS_TORSION, FLOPS_GENE = 66, 141, 125, 12
 # for it, WRITE_SIZE 256 MiB: scales 2.0 and 1.0). Valid only for the kernel
 # sources whose SHA-256 is recorded; after any change the field is null until
 # the counters are taken again.
-TRAFFIC = {"kernel_sha256": "8c9e44fe96629aa970b7f59c79dbf4b907e77c057bb403a70ca9a20c5751603e",
-           "fetch_kib": 1455437.5, "write_kib": 1468.0,
+TRAFFIC = {"kernel_sha256": "60810ad725e5228ac5891423b52b9ff5e282dd8ca8bcb68791d3b43aec5520c8",
+           "fetch_kib": 1455478.5, "write_kib": 1487.7,
            "fetch_scale": 2.0, "write_scale": 1.0}
 KERNEL_SOURCES = ("paper_2410_10447_amd/csrc/dock_kernels.hip", "paper_2410_10447_amd/csrc/dock_blob.h",
                   "paper_2410_10447_amd/csrc/dock_prep.cpp")

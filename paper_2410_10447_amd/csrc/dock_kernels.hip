@@ -586,7 +586,7 @@ __device__ __forceinline__ void store_force(float4* base, const PairForce& f, fl
 // `gene` is gene `lane` (lanes >= G ignored); returns E (uniform) and writes
 // this lane's gradient component to `grad`.
 // ---------------------------------------------------------------------------
-template <int SLOTS, int VAR, int WAVES = 1, bool ANY_LAYOUT = true>
+template <int SLOTS, int VAR, int WAVES = 1, bool ANY_LAYOUT = true, bool GRAD = true>
 __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig<SLOTS>& L, float gene,
                           float& grad, float* atom_out) {
     const int lane = lane_id();
@@ -691,7 +691,31 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
     // instruction touch one address and the order of additions is fixed.
     // (LDS float atomics would serialise in the LDS unit: they made this
     // phase several times slower.)
-    {
+    if constexpr (!GRAD) {
+        // energies only (a search that needs no gradient): each lane sums its
+        // pairs' energies from the positions, records loaded two batches
+        // ahead; no accumulators, no force
+        static_assert(WAVES == 1, "the energy-only evaluation is one wave per individual");
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) grid_load<ANY_LAYOUT>(G, L.cls[s], x[s], tv, tap[s]);
+        const int nb = L.n_batches;
+        const int pmask = L.pmask;
+        const auto plist = gmem(L.plist);
+        auto record = [&](int b) -> u32x4 { return plist[uniform(min(b, nb - 1)) * kWave + lane]; };
+        if (nb > 0) {
+            u32x4 r0 = record(0), r1 = record(1);
+            for (int k = 0; k < nb; ++k) {
+                const u32x4 rc = r0;
+                r0 = r1;
+                r1 = record(k + 2);
+                const float4 pi = *slot(sm.dyn, rc.x & pmask);
+                const float4 pj = *slot(sm.dyn, (rc.x >> dockblob::kSlotShift) & pmask);
+                e_lane += pair_force(rc, pi, pj).e;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < SLOTS; ++s) g[s][0] = g[s][1] = g[s][2] = 0.f;
+    } else {
         // each wave adds into its own range of copies; a wave of the two-wave
         // layout takes its half of the batches
         const int nslot = L.n_copies * L.stride;
@@ -822,6 +846,13 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
 #pragma unroll
     for (int s = 0; s < SLOTS; ++s)
         if (lane + kWave * (s + L.wv) >= N) { g[s][0] = g[s][1] = g[s][2] = 0.f; }
+
+    if constexpr (!GRAD) {
+        // the block sum of E alone, in the chosen variant
+        grad = 0.f;
+        __syncthreads();   // the next evaluation rewrites the position table
+        return sum4<VAR>(make_float4(e_lane, 0.f, 0.f, 0.f)).x;
+    }
 
     // block sum of {E, gx, gy, gz}: the paper's reduction, in the chosen variant
     float4 eg = make_float4(e_lane, 0.f, 0.f, 0.f);
@@ -993,7 +1024,7 @@ __global__ __launch_bounds__(64, (SLOTS == 1 ? 3 : 2)) void sw_kernel(GridParams
         for (int t = 0; t < 2; ++t) {      // uniform: E and the trial energies are wave-uniform
             const float c = t == 0 ? (x + b) + dev : (x - b) - dev;
             float gr;
-            const float Et = evaluate<SLOTS, VAR>(G, sm, L, c, gr, nullptr);
+            const float Et = evaluate<SLOTS, VAR, 1, true, false>(G, sm, L, c, gr, nullptr);
             if (t == 0) e_try0 = Et; else e_try1 = Et;
             if (Et < E) {
                 x = c;

@@ -1,5 +1,5 @@
 // Packed device layout of a prepared ligand, shared by the host preparation
-// (dock_host.cpp) and the kernels (dock_kernels.hip).
+// (dock_prep.cpp) and the kernels (dock_kernels.hip).
 //
 // Atoms are stored in depth-first order from the root atom, so the atoms a
 // torsion moves form one contiguous range [first, end) of positions. All

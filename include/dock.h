@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define DOCK_ABI_VERSION 5
+#define DOCK_ABI_VERSION 6
 
 /* status codes */
 #define DOCK_OK            0
@@ -233,6 +233,7 @@ typedef struct {
     const dock_grids* grids;
     const dock_ligand* ligand;   /* uploaded */
     int32_t n;                   /* individuals in this item, >= 0 */
+    int32_t n_genes;             /* G of the rows below; must equal the ligand's 7 + T */
     int32_t variant;             /* DOCK_REDUCE_* for this item, or -1 = opts->variant */
     int32_t iterations;          /* steps for this item, 0 .. opts->iterations, or -1 = opts */
     int32_t final_eval;          /* 1/0 overrides DOCK_LS_FINAL_EVAL for this item, -1 = opts */
@@ -280,8 +281,9 @@ int32_t dock_ls_workspace_bytes(int32_t n_items, int64_t* bytes);
  * same state, bit for bit, as a single call with all the iterations.
  * workspace_dev: device, >= dock_ls_workspace_bytes(n_items), 16-byte
  * aligned, caller-owned; it must not be shared by calls that may overlap.
- * Errors: DOCK_EINVAL on NULL pointers, bad opts, mismatched sizes, a ligand
- * never uploaded, or a workspace that is too small. */
+ * Errors: DOCK_EINVAL on NULL pointers, bad opts, an item whose n_genes is not
+ * its ligand's gene count, a ligand never uploaded, or a workspace that is
+ * too small. */
 int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items,
                                 const dock_ls_opts* opts, void* workspace_dev,
                                 int64_t workspace_bytes, void* stream);
@@ -319,12 +321,14 @@ int32_t dock_block_sum4(const float* in_dev, float* out_dev, int32_t n_blocks, i
  *   the second trial was not needed).
  * A call of K iterations followed by one of L equals one call of K + L with
  * the concatenated draws, bit for bit. Errors: DOCK_EINVAL on NULL handles,
- * opts or arrays, n < 0, iterations < 0, run lengths < 1, a variant other
+ * opts or arrays, n < 0, iterations < 0, opts->n_genes other than the
+ * ligand's gene count, run lengths < 1, a variant other
  * than SHUFFLE or MFMA_F32, a ligand never uploaded, a grid set without the
  * ligand's type maps, or misaligned arrays.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int32_t iterations;
+    int32_t n_genes;             /* G of the arrays; must equal the ligand's 7 + T */
     int32_t n_success;           /* successes in a row that double rho (AutoDock: 4) */
     int32_t n_failure;           /* failures in a row that halve rho (AutoDock: 4) */
     int32_t variant;             /* DOCK_REDUCE_SHUFFLE or DOCK_REDUCE_MFMA_F32 */

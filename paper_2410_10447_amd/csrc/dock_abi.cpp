@@ -365,6 +365,9 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
     for (int i = 0; i < n_items; ++i) {
         const dock_ls_item& it = items[i];
         if (!it.grids || !it.ligand) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": NULL handle");
+        if (it.n_genes != 7 + it.ligand->prep.n_torsions)
+            return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": n_genes " + std::to_string(it.n_genes) +
+                                         " is not the ligand's " + std::to_string(7 + it.ligand->prep.n_torsions));
         if (!it.ligand->blob_dev) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": ligand not uploaded");
         if (it.n < 0) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": n < 0");
         int32_t st = check_grid_for_ligand(it.grids, it.ligand);
@@ -543,6 +546,9 @@ int32_t dock_solis_wets_batch(const dock_grids* g, const dock_ligand* l, int32_t
     if (o->n_success < 1 || o->n_failure < 1) return fail(DOCK_EINVAL, "dock_solis_wets_batch: run lengths must be >= 1");
     if (o->variant != DOCK_REDUCE_SHUFFLE && o->variant != DOCK_REDUCE_MFMA_F32)
         return fail(DOCK_EINVAL, "dock_solis_wets_batch: variant must be SHUFFLE or MFMA_F32");
+    if (o->n_genes != 7 + l->prep.n_torsions)
+        return fail(DOCK_EINVAL, "dock_solis_wets_batch: n_genes " + std::to_string(o->n_genes) +
+                                     " is not the ligand's " + std::to_string(7 + l->prep.n_torsions));
     if (!l->blob_dev) return fail(DOCK_EINVAL, "dock_solis_wets_batch: ligand not uploaded");
     int32_t st = check_grid_for_ligand(g, l);
     if (st != DOCK_OK) return st;

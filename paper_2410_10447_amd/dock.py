@@ -15,6 +15,9 @@ import numpy as np
 
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdockmi.so")
 
+# the struct layouts below follow include/dock.h of this ABI version
+ABI_VERSION = 6
+
 DOCK_OK = 0
 DOCK_EINVAL = -1
 DOCK_ENOMEM = -2
@@ -84,7 +87,7 @@ class ExecOpts(C.Structure):
 
 class LsItem(C.Structure):
     _fields_ = [("grids", C.c_void_p), ("ligand", C.c_void_p), ("n", C.c_int32),
-                ("variant", C.c_int32), ("iterations", C.c_int32), ("final_eval", C.c_int32),
+                ("n_genes", C.c_int32), ("variant", C.c_int32), ("iterations", C.c_int32), ("final_eval", C.c_int32),
                 ("threads_per_ind", C.c_int32),
                 ("genotype", C.c_void_p), ("acc_g2", C.c_void_p), ("acc_dx2", C.c_void_p),
                 ("best_genotype", C.c_void_p), ("best_energy", C.c_void_p),
@@ -97,8 +100,8 @@ class LsOpts(C.Structure):
 
 
 class SwOpts(C.Structure):
-    _fields_ = [("iterations", C.c_int32), ("n_success", C.c_int32), ("n_failure", C.c_int32),
-                ("variant", C.c_int32)]
+    _fields_ = [("iterations", C.c_int32), ("n_genes", C.c_int32), ("n_success", C.c_int32),
+                ("n_failure", C.c_int32), ("variant", C.c_int32)]
 
 
 class GaStepDesc(C.Structure):
@@ -146,6 +149,9 @@ def lib():
         f = getattr(L, name)
         f.argtypes = args
         f.restype = res
+    if L.dock_abi_version() != ABI_VERSION:
+        raise ImportError(f"{_LIB_PATH} has ABI version {L.dock_abi_version()}, the binding "
+                          f"expects {ABI_VERSION}: rebuild it")
     _lib = L
     return L
 
@@ -171,6 +177,28 @@ def _ptr(t):
 
 def _dptr(a: np.ndarray, ct):
     return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _need(name, t, shape, dtype, device=None, placement=True):
+    """Raise ValueError unless `t` is a contiguous CUDA tensor of the given
+    shape and dtype (on `device` if given; the device checks only with
+    `placement`): the C ABI receives bare pointers and cannot check any of
+    this itself."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: expected {dtype}, got {t.dtype}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if not placement:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a CUDA tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name}: on {t.device}, expected {device}")
 
 
 # ---------------------------------------------------------------------------
@@ -328,10 +356,11 @@ def score_batch(grids: Grids, ligand: Ligand, genotypes, variant: int = REDUCE_S
                 with_grad: bool = True, atom_out: bool = False, stream=None):
     """Energy [n] and gradient [n, G] of each genotype row (float32 CUDA tensor)."""
     import torch
-    n = genotypes.shape[0]
     if genotypes.dim() != 2 or genotypes.shape[1] != ligand.n_genes:
         raise ValueError(f"genotypes must be [n, {ligand.n_genes}]")
+    n = genotypes.shape[0]
     gen = genotypes.contiguous()
+    _need("genotypes", gen, (n, ligand.n_genes), torch.float32)
     E = torch.empty(n, dtype=torch.float32, device=gen.device)
     grad = torch.empty(n, ligand.n_genes, dtype=torch.float32, device=gen.device) if with_grad else None
     ao = torch.empty(n, ligand.n_atoms, 8, dtype=torch.float32, device=gen.device) if atom_out else None
@@ -375,6 +404,22 @@ class LSState:
                 ("genotype", "acc_g2", "acc_dx2", "best_genotype", "best_energy", "energy",
                  "iters_done")}
 
+    def validate(self, n_genes: int):
+        """Raise ValueError unless every tensor fits a population of rows of
+        `n_genes` genes: [n, G] float32 rows, [n] float32 energies, [n] int32
+        counts, all contiguous and on the genotype's device."""
+        import torch
+        g = self.genotype
+        if not (isinstance(g, torch.Tensor) and g.dim() == 2):
+            raise ValueError("LSState.genotype must be a 2-D tensor")
+        n, dev = g.shape[0], g.device
+        spec = [(f, (n, n_genes), torch.float32) for f in ("genotype", "acc_g2", "acc_dx2", "best_genotype")]
+        spec += [(f, (n,), torch.float32) for f in ("best_energy", "energy")]
+        spec += [("iters_done", (n,), torch.int32)]
+        for placement in (False, True):      # every shape first, then placement
+            for f, shp, dt in spec:
+                _need(f"LSState.{f}", getattr(self, f), shp, dt, dev, placement)
+
 
 def workspace_bytes(n_items: int) -> int:
     b = C.c_int64()
@@ -409,10 +454,20 @@ def make_items(jobs):
     for i, job in enumerate(jobs):
         j = _as_job(job)
         grids, ligand, st = j.grids, j.ligand, j.state
+        if j.grad is not None:
+            import torch
+            for placement in (False, True):
+                _need("grad", j.grad, (st.genotype.shape[0], ligand.n_genes), torch.float32,
+                      st.genotype.device, placement)
+                if not placement:
+                    st.validate(ligand.n_genes)
+        else:
+            st.validate(ligand.n_genes)
         it = arr[i]
         it.grids = grids.handle.value
         it.ligand = ligand.handle.value
         it.n = st.genotype.shape[0]
+        it.n_genes = ligand.n_genes
         it.variant = j.variant
         it.iterations = j.iterations
         it.final_eval = j.final_eval
@@ -543,13 +598,26 @@ def solis_wets(grids: Grids, ligand: Ligand, st: SWState, normals, scale, n_succ
     trials' energies [n, iters, 2] if `log`, else None."""
     import torch
     iters = normals.shape[0]
+    if st.genotype.dim() != 2:
+        raise ValueError("SWState.genotype must be [n, G]")
     n, G = st.genotype.shape
+    if G != ligand.n_genes:
+        raise ValueError(f"SWState rows have {G} genes, the ligand {ligand.n_genes}")
+    dev = st.genotype.device
+    spec = (("genotype", (n, G), torch.float32), ("energy", (n,), torch.float32),
+            ("bias", (n, G), torch.float32), ("rho", (n,), torch.float32),
+            ("counts", (n, 2), torch.int32))
     if tuple(normals.shape[1:]) != (n, G) or tuple(scale.shape) != (G,):
         raise ValueError("normals must be [iters, n, G] and scale [G]")
     nm = normals.contiguous()
     sc = scale.contiguous()
-    lg = torch.empty((n, iters, 2), dtype=torch.float32, device=st.genotype.device) if log else None
-    o = SwOpts(iters, n_success, n_failure, variant)
+    for placement in (False, True):          # every shape first, then placement
+        for f, shp, dt in spec:
+            _need(f"SWState.{f}", getattr(st, f), shp, dt, dev, placement)
+        _need("normals", nm, (iters, n, G), torch.float32, dev, placement)
+        _need("scale", sc, (G,), torch.float32, dev, placement)
+    lg = torch.empty((n, iters, 2), dtype=torch.float32, device=dev) if log else None
+    o = SwOpts(iters, G, n_success, n_failure, variant)
     _check(lib().dock_solis_wets_batch(grids.handle, ligand.handle, n, _ptr(st.genotype), _ptr(st.energy),
                                        _ptr(st.bias), _ptr(st.rho), _ptr(st.counts), _ptr(nm), _ptr(sc),
                                        C.byref(o), _ptr(lg), _stream_handle(stream)))

@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(dock.ABI_SYMBOLS)
     for name in declared:
         assert hasattr(L, name)
-    assert L.dock_abi_version() == 5
+    assert L.dock_abi_version() == dock.ABI_VERSION == 6
 
 
 def _check_prep(lig):
@@ -307,8 +307,21 @@ def test_batch_calls_validate_before_device_work():
     item[0].n = 4
     item[0].variant = -1
     o = dock.LsOpts(iterations=10, rho=0.8, eps=1e-2, variant=0, threads_per_ind=0, flags=1)
+    # rows of another gene count than the ligand's are rejected (the kernels
+    # would index them with the ligand's G)
+    for bad_g in (0, lig.n_genes - 1, lig.n_genes + 1):
+        item[0].n_genes = bad_g
+        st = L.dock_local_search_batch(item, 1, C.byref(o), fake, 1 << 20, None)
+        assert st == dock.DOCK_EINVAL and "n_genes" in dock.last_error()
+    item[0].n_genes = lig.n_genes
     st = L.dock_local_search_batch(item, 1, C.byref(o), fake, 1 << 20, None)
     assert st == dock.DOCK_EINVAL and "uploaded" in dock.last_error()
+    # the same check in the Solis-Wets call
+    for bad_g in (lig.n_genes - 1, lig.n_genes + 1):
+        so = dock.SwOpts(iterations=2, n_genes=bad_g, n_success=4, n_failure=4, variant=0)
+        st = L.dock_solis_wets_batch(g, lig.handle, 4, fake, fake, fake, fake, fake, fake, fake,
+                                     C.byref(so), None, None)
+        assert st == dock.DOCK_EINVAL and "n_genes" in dock.last_error()
     for bad in (dict(rho=1.0), dict(rho=0.0), dict(eps=0.0), dict(iterations=-1), dict(variant=9),
                 dict(flags=8), dict(threads_per_ind=96), dict(threads_per_ind=256)):
         kw = dict(iterations=10, rho=0.8, eps=1e-2, variant=0, threads_per_ind=0, flags=1)
@@ -344,3 +357,59 @@ def test_ga_step_rejects_bad_descriptors_before_any_device_work():
         d = dock.GaStepDesc(**{**base, **change})
         assert L.dock_ga_step(C.byref(d), None) == dock.DOCK_EINVAL, change
         assert "dock_ga_step" in dock.last_error()
+
+
+def test_binding_validates_state_tensors():
+    """The binding rejects state, gradient, draw and scale tensors that do not
+    fit the ligand (wrong gene width or length, dtype, layout or device)
+    before the C call, which receives bare pointers. Checked with CPU
+    tensors: the shape, dtype and layout checks come before the device one."""
+    import torch
+    w = synth.ls_workload(4)
+    lig = dock.Ligand(w.ligands[0], w.ff, upload=False)
+    G = lig.n_genes
+    n = 5
+
+    def state(**over):
+        f = dict(genotype=torch.zeros(n, G), acc_g2=torch.zeros(n, G), acc_dx2=torch.zeros(n, G),
+                 best_genotype=torch.zeros(n, G), best_energy=torch.zeros(n), energy=torch.zeros(n),
+                 iters_done=torch.zeros(n, dtype=torch.int32))
+        f.update(over)
+        return dock.LSState(**f)
+
+    grids_stub = object()          # never reached: validation fails first
+    bad = [
+        (dict(genotype=torch.zeros(n, G - 1)), "shape"),
+        (dict(acc_g2=torch.zeros(n, G + 1)), "shape"),
+        (dict(best_genotype=torch.zeros(n + 1, G)), "shape"),
+        (dict(best_energy=torch.zeros(n - 1)), "shape"),
+        (dict(acc_dx2=torch.zeros(n, G, dtype=torch.float64)), "float32"),
+        (dict(iters_done=torch.zeros(n, dtype=torch.int64)), "int32"),
+        (dict(energy=torch.zeros(2 * n)[::2]), "contiguous"),
+        (dict(genotype=torch.zeros(G, n).t()), "contiguous"),
+        ({}, "CUDA"),
+    ]
+    for over, what in bad:
+        with pytest.raises(ValueError, match=what):
+            dock.make_items([dock.LsJob(grids_stub, lig, state(**over))])
+    with pytest.raises(ValueError, match="shape"):
+        dock.make_items([dock.LsJob(grids_stub, lig, state(), grad=torch.zeros(n, G - 1))])
+    # Solis-Wets state, draws and scales
+    def sw(**over):
+        f = dict(genotype=torch.zeros(n, G), energy=torch.zeros(n), bias=torch.zeros(n, G),
+                 rho=torch.ones(n), counts=torch.zeros(n, 2, dtype=torch.int32))
+        f.update(over)
+        return dock.SWState(**f)
+    normals, scale = torch.zeros(3, n, G), torch.ones(G)
+    with pytest.raises(ValueError, match="genes"):
+        dock.solis_wets(grids_stub, lig, sw(genotype=torch.zeros(n, G - 1)), normals, scale)
+    for over, what in ((dict(bias=torch.zeros(n, G + 1)), "shape"), (dict(rho=torch.ones(n + 1)), "shape"),
+                       (dict(counts=torch.zeros(n, 2)), "int32"), ({}, "CUDA")):
+        with pytest.raises(ValueError, match=what):
+            dock.solis_wets(grids_stub, lig, sw(**over), normals, scale)
+    with pytest.raises(ValueError, match="normals"):
+        dock.solis_wets(grids_stub, lig, sw(), torch.zeros(3, n, G - 1), scale)
+    with pytest.raises(ValueError):
+        dock.score_batch(grids_stub, lig, torch.zeros(n, G - 1))
+    with pytest.raises(ValueError, match="float32"):
+        dock.score_batch(grids_stub, lig, torch.zeros(n, G, dtype=torch.float64))

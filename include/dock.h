@@ -211,7 +211,12 @@ typedef struct {
     int32_t threads_per_ind;  /* 0 (= 64) or 64; wider tiles are reserved */
     uint32_t flags;           /* 0 */
     float* atom_out;          /* device [n][n_atoms][8] or NULL: per atom (original
-                                 order) x, y, z, e_inter, gx, gy, gz, 0 */
+                                 order) x - tx, y - ty, z - tz (the atom's position
+                                 relative to the translation genes, the FP32 values
+                                 the evaluation holds: t plus these, summed exactly,
+                                 is the world position its terms use), e_inter (the
+                                 atom's grid energy with the outside penalty),
+                                 gx, gy, gz (dE/dx of the atom), 0 */
 } dock_exec_opts;
 
 /* genotypes_dev [n][G], energy_dev [n], grad_dev [n][G] (may be NULL): device

@@ -956,7 +956,8 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
             const int a = lane + kWave * (s + L.wv);
             if (a < N) {
                 float4* o = reinterpret_cast<float4*>(atom_out) + 2 * L.orig[s];
-                o[0] = make_float4(x[s][0] + tx, x[s][1] + ty, x[s][2] + tz, e_atom[s]);
+                // position relative to t, as held (t + it is the world position)
+                o[0] = make_float4(x[s][0], x[s][1], x[s][2], e_atom[s]);
                 o[1] = make_float4(g[s][0], g[s][1], g[s][2], 0.f);
             }
         }

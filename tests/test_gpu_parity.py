@@ -1,10 +1,10 @@
 """GPU parity of the HIP path against the FP64 oracle, through the C ABI.
 
 Tolerances (FP32 path, per individual): |dE|/max(|E|,1) <= 1e-5 and
-||dg||/max(||g||,1) <= 1e-4. Individuals whose pose lies within rounding
-reach of a kink of the piecewise-smooth score (grid-cell face, box face, the
-1e5 cap, the r^2 clamp) are held to a looser bound and counted; they must be
-rare.
+||dg||/max(||g||,1) <= 1e-4, with the oracle evaluated at the kernel's own
+atom positions and the pose checked separately (tests/gpu_common.py states
+the comparison, the conditioning exception and its cap, and the kink
+exemption of the gradient and its cap; every count is printed).
 """
 import math
 
@@ -14,13 +14,17 @@ import pytest
 from oracle import dock_ref as R
 from oracle import reduce_ref as RR
 from paper_2410_10447_amd import synth
-from tests.gpu_common import E_TOL, G_TOL, e_ok, e_relerr, g_relerr, near_discontinuity
+from tests.gpu_common import check, check_reported, gpu_points
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 FP32_VARIANTS = [0, 1]          # shuffle, FP32 MFMA
 SPLIT_VARIANTS = [2, 3, 4]      # BF16 2-term, FP16 2-term, BF16 3-term
+
+# 300-step best-energy distribution against the oracle's (3000 individuals)
+DIST_TOL = 0.01
+DIST_KS = 0.05
 
 
 @pytest.fixture(scope="module")
@@ -74,78 +78,45 @@ def _score_case(dk, w, variant, n=None):
     G = dk.Grids.from_synth(w.grids)
     L = dk.Ligand(lig, w.ff)
     gen = w.genotypes[0] if n is None else w.genotypes[0][:n]
-    gt = torch.from_numpy(gen).cuda()
-    E, g, ao = dk.score_batch(G, L, gt, variant=variant, atom_out=True)
-    torch.cuda.synchronize()
-    ref = R.score(prep, w.grids, gen.astype(np.float64))
-    return prep, ref, E.cpu().numpy(), g.cpu().numpy(), ao.cpu().numpy()
-
-
-def _report(tag, ee, ge, flag):
-    print(f"\n[{tag}] n={len(ee)} flagged={flag.sum()} E err p50={np.median(ee):.2e} "
-          f"max={ee.max():.2e} (unflagged {ee[~flag].max() if (~flag).any() else 0:.2e}); "
-          f"g err p50={np.median(ge):.2e} max={ge.max():.2e} "
-          f"(unflagged {ge[~flag].max() if (~flag).any() else 0:.2e})", flush=True)
+    E, g, ao = gpu_points(dk, G, L, gen, variant)
+    return prep, gen, E, g, ao
 
 
 @pytest.mark.parametrize("variant", FP32_VARIANTS)
 def test_score_parity_small_ligand(dk, variant):
+    """The 24-atom, 6-torsion ligand at 256 random genotypes on 40^3 x 10 maps."""
     w = synth.score_workload(256)
-    prep, ref, E, g, ao = _score_case(dk, w, variant)
-    ee, ge = e_relerr(E, ref.energy), g_relerr(g, ref.grad)
-    flag = near_discontinuity(prep, w.grids, ref.x)
-    _report(f"score c0 v{variant}", ee, ge, flag)
-    # per-atom positions and gradients
-    print(f"[score c0 v{variant}] max pose error {np.abs(ao[:, :, 0:3] - ref.x).max():.2e} A", flush=True)
-    assert np.abs(ao[:, :, 0:3] - ref.x).max() < 1e-4
-    assert flag.mean() < 0.05
-    assert np.all(ee[~flag] <= E_TOL)
-    assert np.all(ge[~flag] <= G_TOL)
-    assert np.all(ee[flag] <= 1e-3) and np.all(ge[flag] <= 1e-2)
+    prep, gen, E, g, ao = _score_case(dk, w, variant)
+    check(f"score c0 v{variant}", prep, w.grids, gen, E, g, ao, variant)
 
 
 @pytest.mark.parametrize("variant", FP32_VARIANTS)
 def test_score_parity_ls_ligand(dk, variant):
+    """The 48-atom, 10-torsion ligand at 512 random genotypes on 64^3 x 10 maps."""
     w = synth.ls_workload(512)
-    prep, ref, E, g, ao = _score_case(dk, w, variant)
-    ee, ge = e_relerr(E, ref.energy), g_relerr(g, ref.grad)
-    flag = near_discontinuity(prep, w.grids, ref.x)
-    _report(f"score c1-ligand v{variant}", ee, ge, flag)
-    print(f"[score c1-ligand v{variant}] max pose error {np.abs(ao[:, :, 0:3] - ref.x).max():.2e} A",
-          flush=True)
-    ok, cond = e_ok(E, ref, w.genotypes[0])
-    print(f"[score c1-ligand v{variant}] strict E bound missed by {cond.sum()} (conditioning bound holds)",
-          flush=True)
-    assert flag.mean() < 0.05
-    assert np.all(ok[~flag])
-    assert np.all(ge[~flag] <= G_TOL)
+    prep, gen, E, g, ao = _score_case(dk, w, variant)
+    check(f"score c1-ligand v{variant}", prep, w.grids, gen, E, g, ao, variant)
 
 
 @pytest.mark.parametrize("variant", SPLIT_VARIANTS)
 def test_score_split_variants_error_report(dk, variant):
-    """Half-width MFMA reductions: error against FP64, stated per individual."""
+    """Half-width MFMA reductions: error against FP64, stated per individual.
+    2-term BF16 is held to its own split bound (2^-16 of the terms'
+    magnitudes), the FP32-level splits (FP16 2-term, BF16 3-term) to the
+    FP32 path's bounds."""
     w = synth.ls_workload(512)
-    prep, ref, E, g, ao = _score_case(dk, w, variant)
-    ee, ge = e_relerr(E, ref.energy), g_relerr(g, ref.grad)
-    flag = near_discontinuity(prep, w.grids, ref.x)
-    _report(f"score split v{variant}", ee, ge, flag)
-    if variant == 2:
-        # 2-term BF16 carries 2^-16 per element
-        assert np.all(ee[~flag] <= 1e-4)
-    else:
-        # the others reach FP32 level, so they are held to the FP32 path's
-        # bound: strict, or the conditioning bound that FP32 partials imply
-        ok, cond = e_ok(E, ref, w.genotypes[0])
-        print(f"[score split v{variant}] strict E bound missed by {cond.sum()} (conditioning bound holds)",
-              flush=True)
-        assert np.all(ok[~flag])
-    assert np.all(ge[~flag] <= G_TOL)
+    prep, gen, E, g, ao = _score_case(dk, w, variant)
+    rep = check(f"score split v{variant}", prep, w.grids, gen, E, g, ao, variant)
+    print(f"[score split v{variant}] individuals over 1e-5 in E: {int((rep.e_err > 1e-5).sum())} of {rep.n}; "
+          f"over 1e-4 in g: {int((rep.g_err > 1e-4).sum())}", flush=True)
 
 
 @pytest.mark.parametrize("n_atoms,n_tors,seed", [(1, 0, 1), (2, 0, 2), (5, 1, 3), (63, 12, 4),
                                                  (64, 20, 5), (65, 20, 6), (100, 32, 7),
                                                  (128, 32, 8)])
 def test_score_parity_sizes(dk, n_atoms, n_tors, seed):
+    """Ligand sizes across both atom-slot layouts on 48^3 maps: large ligands
+    often reach out of the box (those atoms are checked like the others)."""
     if n_atoms == 1:
         from tests.helpers import ligand_from_bonds
         lig = ligand_from_bonds(np.zeros((0, 2), np.int32), [], seed=seed)
@@ -154,25 +125,89 @@ def test_score_parity_sizes(dk, n_atoms, n_tors, seed):
     grd = synth.grids(48, 10, seed + 100)
     gen = synth.genotypes(lig, grd, 96, seed + 200)
     w = synth.Workload("sizes", [lig], grd, synth.force_field(), [gen])
-    prep, ref, E, g, ao = _score_case(dk, w, 0)
-    ee, ge = e_relerr(E, ref.energy), g_relerr(g, ref.grad)
-    flag = near_discontinuity(prep, w.grids, ref.x)
-    _report(f"score N={n_atoms} T={lig.n_torsions}", ee, ge, flag)
-    assert np.all(ee[~flag] <= E_TOL)
-    assert np.all(ge[~flag] <= G_TOL)
+    prep, gen, E, g, ao = _score_case(dk, w, 0)
+    x = R.pose(prep, gen.astype(np.float64))
+    lo = np.asarray(grd.origin)
+    hi = lo + (np.array(grd.dims) - 1) * grd.spacing
+    out = np.any((x < lo) | (x > hi), axis=(1, 2))
+    print(f"\n[score N={n_atoms}] individuals with an atom outside the box: {int(out.sum())} of {len(out)}",
+          flush=True)
+    check(f"score N={n_atoms} T={lig.n_torsions}", prep, grd, gen, E, g, ao, 0)
 
 
-def test_score_outside_box_and_unnormalised_quaternion(dk):
+def _outside_genotypes(lig, grd, n_per_case, seed):
+    """Genotypes that put the whole ligand, or about half of it, outside the
+    box through each of the six faces, at random orientations and torsions."""
+    rng = np.random.default_rng(seed)
+    lo = np.asarray(grd.origin, np.float64)
+    hi = lo + (np.array(grd.dims) - 1) * grd.spacing
+    rad = synth.ligand_radius(lig)
+    rows, tags = [], []
+    for axis in range(3):
+        for side in (0, 1):
+            face = hi[axis] if side else lo[axis]
+            sgn = 1.0 if side else -1.0
+            for whole in (True, False):
+                base = synth.genotypes(lig, grd, n_per_case, int(rng.integers(1 << 30)))
+                base = base.astype(np.float64)
+                shift = rad + 0.5 + rng.uniform(0.0, 3.0, n_per_case) if whole else \
+                    rng.uniform(-0.5, 0.5, n_per_case)
+                base[:, axis] = face + sgn * shift
+                rows.append(base)
+                tags += [(axis, side, whole)] * n_per_case
+    return np.concatenate(rows).astype(np.float32), tags
+
+
+@pytest.mark.parametrize("n_atoms,n_tors", [(24, 6), (100, 14)])
+@pytest.mark.parametrize("variant", FP32_VARIANTS)
+def test_score_outside_box(dk, n_atoms, n_tors, variant):
+    """Atoms outside the grid box (interpolation at the clamped point, no
+    gradient along clamped axes, K_out d^2 penalty): the whole ligand and
+    about half of it outside, through each face, element-wise against the
+    oracle; and per atom, the outside atoms' energies and gradients."""
+    lig = synth.score_workload(4).ligands[0] if n_atoms == 24 else synth.ligand(n_atoms, n_tors, 4100)
+    grd = synth.grids(40, 10, 501)
+    ff = synth.force_field()
+    gen, tags = _outside_genotypes(lig, grd, 8, 502 + n_atoms)
+    w = synth.Workload("outside", [lig], grd, ff, [gen])
+    prep, gen, E, g, ao = _score_case(dk, w, variant)
+    rep = check(f"score outside N={n_atoms} v{variant}", prep, grd, gen, E, g, ao, variant)
+    x = rep.ref.x
+    lo = np.asarray(grd.origin)
+    hi = lo + (np.array(grd.dims) - 1) * grd.spacing
+    outside = np.any((x < lo) | (x > hi), axis=2)                   # [n, N]
+    whole = np.array([t[2] for t in tags])
+    assert np.all(outside[whole]), "a whole-outside genotype left an atom inside"
+    part = outside[~whole]
+    assert part.any(axis=1).mean() > 0.75 and (~part).any(axis=1).mean() > 0.75, \
+        "the partial cases must straddle the face"
+    # per atom, outside atoms: grid energy (with the penalty) and gradient
+    from tests.gpu_common import oracle_at
+    ref = oracle_at(prep, grd, gen, x)
+    e_at = ao[:, :, 3].astype(np.float64)
+    g_at = ao[:, :, 4:7].astype(np.float64)
+    # atom_out rows are in original atom order, as the oracle's
+    e_err = np.abs(e_at - ref.e_inter) / np.maximum(np.abs(ref.e_inter), 1.0)
+    g_err = np.linalg.norm(g_at - ref.atom_grad, axis=-1) / np.maximum(
+        np.linalg.norm(ref.atom_grad, axis=-1), 1.0)
+    print(f"[score outside N={n_atoms} v{variant}] outside atoms {int(outside.sum())}: per-atom E err max "
+          f"{e_err[outside].max():.2e}, g err max {g_err[outside].max():.2e}", flush=True)
+    assert np.all(e_err[outside] <= 1e-5) and np.all(g_err[outside] <= 1e-4)
+
+
+def test_score_unnormalised_quaternion(dk):
+    """Quaternions scaled by 0.2 .. 5 give the pose of the unit quaternion
+    and a gradient orthogonal to q."""
     w = synth.score_workload(64)
     gen = w.genotypes[0].copy()
-    gen[:16, 0] += 9.0                          # far outside the 40^3 box on x
     gen[16:32, 3:7] *= np.linspace(0.2, 5.0, 16, dtype=np.float32)[:, None]
     w.genotypes[0] = gen
-    prep, ref, E, g, ao = _score_case(dk, w, 0)
-    ee, ge = e_relerr(E, ref.energy), g_relerr(g, ref.grad)
-    flag = near_discontinuity(prep, w.grids, ref.x)
-    _report("score outside/unnormalised", ee, ge, flag)
-    assert np.all(ee[~flag] <= E_TOL) and np.all(ge[~flag] <= G_TOL)
+    prep, gen, E, g, ao = _score_case(dk, w, 0)
+    check("score unnormalised q", prep, w.grids, gen, E, g, ao, 0)
+    q = gen[:, 3:7].astype(np.float64)
+    dot = np.abs(np.sum(q * g[:, 3:7], axis=1)) / (np.linalg.norm(q, axis=1) * np.maximum(
+        np.linalg.norm(g[:, 3:7], axis=1), 1.0))
+    assert dot.max() < 1e-5
 
 
 def test_score_empty_batch(dk):
@@ -204,22 +239,27 @@ def _two_wave_workload(n):
                           [synth.genotypes(lig, grd, n, 4102)], iterations=30)
 
 
-@pytest.mark.parametrize("variant,tpi", [(v, 64) for v in FP32_VARIANTS] + [(v, 128) for v in FP32_VARIANTS])
+@pytest.mark.parametrize("variant,tpi", [(v, 64) for v in FP32_VARIANTS] + [(v, 128) for v in FP32_VARIANTS]
+                         + [(v, 64) for v in SPLIT_VARIANTS])
 def test_ls_step_map(dk, variant, tpi):
     """Each GPU step is the ADADELTA update (Zeiler Alg. 1) of the GPU's own
     state and gradient, and that gradient and energy match the oracle's at the
-    same point. (Comparing with a step taken on the oracle's gradient would mix
+    kernel's own positions of the same point (taken from a scoring evaluation
+    of the point; with one wave per individual it gives the same energy bit
+    for bit). (Comparing with a step taken on the oracle's gradient would mix
     the two: ADADELTA passes small gradient components through almost
     unscaled, so their absolute FP32 error, ~1e-4 of |g|, would dominate.)
     tpi = 64 runs the 48-atom benchmark ligand in one wave; tpi = 128 runs a
-    100-atom ligand with two waves per individual."""
+    100-atom ligand with two waves per individual. The split reductions
+    (BF16 2-term, FP16 2-term, BF16 3-term) are held to their bounds."""
+    from tests.gpu_common import assert_reports
     w = synth.ls_workload(64) if tpi == 64 else _two_wave_workload(64)
     prep = R.prepare(w.ligands[0], w.ff)
     G, L, st = _ls_setup(dk, w, 64)
     grad = torch.zeros_like(st.genotype)
     ws = None
-    worst_step = worst_g = 0.0
-    n_cond = 0
+    worst_step = 0.0
+    reps, same = [], 0
     for it in range(12):
         s0 = st.to_numpy()
         ws = dk.local_search([dk.LsJob(G, L, st, variant, grad=grad, threads_per_ind=tpi)], 1,
@@ -227,15 +267,12 @@ def test_ls_step_map(dk, variant, tpi):
         torch.cuda.synchronize()
         s1 = st.to_numpy()
         g_gpu = grad.cpu().numpy().astype(np.float64)
-        x = s0["genotype"].astype(np.float64)
-        ref = R.score(prep, w.grids, x)
-        flag = near_discontinuity(prep, w.grids, ref.x)
-        ok, cond = e_ok(s1["energy"], ref, x)
-        n_cond += cond[~flag].sum()
-        assert np.all(ok[~flag]), (it, e_relerr(s1["energy"], ref.energy)[~ok].max())
-        ge = g_relerr(g_gpu, ref.grad)
-        worst_g = max(worst_g, ge[~flag].max())
-        assert np.all(ge[~flag] <= G_TOL), (it, ge[~flag].max())
+        x = s0["genotype"]
+        E_s, _, ao = gpu_points(dk, G, L, x, variant)
+        same += int(np.sum(E_s.view(np.uint32) == s1["energy"].view(np.uint32)))
+        reps.append(check(f"ls step {it} v{variant} tpi {tpi}", prep, w.grids, x, s1["energy"], g_gpu, ao,
+                          variant, assert_ok=False))
+        x = x.astype(np.float64)
         xn, ag, ad = R.adadelta_step(x, g_gpu, s0["acc_g2"].astype(np.float64),
                                      s0["acc_dx2"].astype(np.float64), 0.8, 1e-2)
         # accumulators are sums of non-negative terms (relative error is
@@ -248,8 +285,11 @@ def test_ls_step_map(dk, variant, tpi):
             worst_step = max(worst_step, err.max())
             assert np.all(err <= 1e-5), (it, name, err.max())
         assert np.all(s1["iters_done"] == it + 1)
-    print(f"\n[ls step-map v{variant} tpi {tpi}] worst update rel err {worst_step:.2e}, worst gradient err "
-          f"{worst_g:.2e}; energies held to a conditioning bound {n_cond}", flush=True)
+    print(f"\n[ls step-map v{variant} tpi {tpi}] worst update rel err {worst_step:.2e}; search energies equal "
+          f"to a rescoring bit for bit: {same} of {12 * 64}", flush=True)
+    assert_reports(f"ls step-map v{variant} tpi {tpi}", reps)
+    if tpi == 64:
+        assert same == 12 * 64
 
 
 @pytest.mark.parametrize("tpi", [64, 128])
@@ -282,25 +322,11 @@ def test_ls_full_size_sampled(dk):
     s = st.to_numpy()
     assert np.all(s["iters_done"] == 300)
     assert np.all(np.isfinite(s["best_energy"]))
-    start = R.score(prep, w.grids, w.genotypes[0][:3000:25].astype(np.float64)).energy
     idx = np.arange(0, 3000, 25)
-    ref = R.score(prep, w.grids, s["best_genotype"][idx].astype(np.float64))
-    flag = near_discontinuity(prep, w.grids, ref.x)
-    ee = e_relerr(s["best_energy"][idx], ref.energy)
-    ok, cond = e_ok(s["best_energy"][idx], ref, s["best_genotype"][idx])
-    kappa = ref.e_abs / np.maximum(np.abs(ref.energy), 1.0)
-    print(f"\n[ls full] best E median {np.median(s['best_energy']):.3f} "
-          f"start median {np.median(start):.1f}; sampled E err max {ee[~flag].max():.2e}; "
-          f"kappa median {np.median(kappa):.1f} max {kappa.max():.1f}; "
-          f"held to the magnitude bound {cond[~flag].sum()} of {(~flag).sum()}", flush=True)
-    assert np.all(ok[~flag])
+    start = R.score(prep, w.grids, w.genotypes[0][idx].astype(np.float64)).energy
+    check_reported("ls full sampled best points", dk, G, L, prep, w.grids, s["best_genotype"][idx],
+                   s["best_energy"][idx])
     assert np.all(s["best_energy"][idx] <= start + 1e-3 * np.abs(start))
-    # distribution against the oracle's own 300-step search on a subsample
-    sub = np.arange(0, 3000, 100)
-    ost = R.ls_init(w.genotypes[0][sub])
-    R.local_search(prep, w.grids, ost, 300)
-    gm, om = np.median(s["best_energy"][sub]), np.median(ost.best_energy)
-    print(f"[ls full] median best E gpu {gm:.4f} oracle {om:.4f}", flush=True)
 
 
 def test_ls_uneven_batch_alone_equals_mixed(dk):
@@ -315,15 +341,16 @@ def test_ls_uneven_batch_alone_equals_mixed(dk):
     for L, s in zip(Ls, alone):
         dk.local_search([(G, L, s)], 20)
     torch.cuda.synchronize()
+    reps = []
     for k, (a, m) in enumerate(zip(alone, mixed)):
         an, mn = a.to_numpy(), m.to_numpy()
         for f in an:
             assert np.array_equal(an[f], mn[f]), (k, f)
         prep = R.prepare(w.ligands[k], w.ff)
-        ref = R.score(prep, w.grids, mn["best_genotype"].astype(np.float64))
-        flag = near_discontinuity(prep, w.grids, ref.x)
-        ok, cond = e_ok(mn["best_energy"], ref, mn["best_genotype"])
-        assert np.all(ok[~flag]), (k, e_relerr(mn["best_energy"], ref.energy).max())
+        reps.append(check_reported(f"uneven item {k} best points", dk, G, Ls[k], prep, w.grids,
+                                   mn["best_genotype"], mn["best_energy"], assert_ok=False))
+    from tests.gpu_common import assert_reports
+    assert_reports("uneven items best points", reps)
 
 
 def test_ls_uneven_mixed_variants_alone_equals_mixed(dk):
@@ -371,17 +398,19 @@ def test_ls_three_families_alone_equals_mixed(dk):
     for k, s in enumerate(alone):
         dk.local_search([job(k, s)], 15)
     torch.cuda.synchronize()
+    reps = []
     for k, (a, m) in enumerate(zip(alone, mixed)):
         an, mn = a.to_numpy(), m.to_numpy()
         for f in an:
             assert np.array_equal(an[f], mn[f]), (k, spec[k], f)
         assert np.all(mn["iters_done"] == 15)
-        if spec[k][2] == 128 and var[k] in FP32_VARIANTS:
+        if spec[k][2] == 128:
             prep = R.prepare(ligs[k], ff)
-            ref = R.score(prep, grd, mn["best_genotype"].astype(np.float64))
-            flag = near_discontinuity(prep, grd, ref.x)
-            ok, _ = e_ok(mn["best_energy"], ref, mn["best_genotype"])
-            assert np.all(ok[~flag]), (k, e_relerr(mn["best_energy"], ref.energy).max())
+            reps.append(check_reported(f"two-wave item {k} best points", dk, G, Ls[k], prep, grd,
+                                       mn["best_genotype"], mn["best_energy"], variant=var[k],
+                                       exact_rescore=False, assert_ok=False))
+    from tests.gpu_common import assert_reports
+    assert_reports("two-wave items best points", reps)
 
 
 def test_corner_expanded_grids_identical(dk):
@@ -440,3 +469,72 @@ def test_ls_mixed_variants_in_one_launch(dk):
         an, bn = a.to_numpy(), b.to_numpy()
         for f in an:
             assert np.array_equal(an[f], bn[f]), f
+
+
+def _oracle_best_fixture():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ls_oracle_best_n48_t10_i3000.txt")
+    return np.loadtxt(path, comments="#")
+
+
+@pytest.mark.parametrize("variant", FP32_VARIANTS)
+def test_ls_best_energy_distribution_vs_oracle(dk, variant):
+    """300-step searches are chaotic, so individual best energies of the FP32
+    kernel and the FP64 oracle part ways; their distributions over the 3000
+    individuals of the benchmark workload must agree (the paper validates its
+    reduction the same way, by the best energies of many runs against the
+    reference code, Sec. 5.1). The oracle's best energies are a committed
+    fixture written by tests/golden/make_ls_oracle_best.py. Bounds: median
+    and mean of the best energy within DIST_TOL relative, and the two
+    empirical distributions within a two-sample Kolmogorov-Smirnov distance
+    of DIST_KS."""
+    w = synth.ls_workload(3000)
+    G, L, st = _ls_setup(dk, w, 3000)
+    dk.local_search([(G, L, st)], 300, variant=variant, final_eval=True)
+    torch.cuda.synchronize()
+    gpu = st.best_energy.cpu().numpy().astype(np.float64)
+    ora = _oracle_best_fixture()
+    assert ora.shape == (3000,)
+    med_g, med_o = np.median(gpu), np.median(ora)
+    mean_g, mean_o = gpu.mean(), ora.mean()
+    # paired view: how many individuals reach the same best energy
+    rel = np.abs(gpu - ora) / np.maximum(np.abs(ora), 1.0)
+    grid = np.sort(np.concatenate([gpu, ora]))
+    ks = np.max(np.abs(np.searchsorted(np.sort(gpu), grid, side="right")
+                       - np.searchsorted(np.sort(ora), grid, side="right"))) / 3000.0
+    print(f"\n[ls distribution v{variant}] median gpu {med_g:.4f} oracle {med_o:.4f} "
+          f"(rel {abs(med_g - med_o) / abs(med_o):.2e}); mean gpu {mean_g:.4f} oracle {mean_o:.4f} "
+          f"(rel {abs(mean_g - mean_o) / abs(mean_o):.2e}); KS {ks:.4f}; same best E within 1e-5: "
+          f"{int((rel <= 1e-5).sum())}, within 1e-3: {int((rel <= 1e-3).sum())} of 3000", flush=True)
+    assert abs(med_g - med_o) <= DIST_TOL * abs(med_o)
+    assert abs(mean_g - mean_o) <= DIST_TOL * abs(mean_o)
+    assert ks <= DIST_KS
+
+
+def test_ls_uneven_full_size_sampled(dk):
+    """The uneven batch at full size (64 ligands of 12-128 atoms and 0-32
+    torsions, 100 individuals each, one 96^3 x 12 grid set, 300 iterations,
+    variants and thread counts from the tuning table) in one call: four best
+    points of every ligand against the oracle at the kernel's positions."""
+    from paper_2410_10447_amd import autotune
+    from tests.gpu_common import assert_reports
+    w = synth.uneven_workload()
+    G = dk.Grids.from_synth(w.grids)
+    Ls = [dk.Ligand(l, w.ff) for l in w.ligands]
+    states = [dk.LSState.start(torch.from_numpy(g).cuda()) for g in w.genotypes]
+    picks = [autotune.choose(L.n_atoms, L.n_torsions) for L in Ls]
+    jobs = [dk.LsJob(G, L, st, c["variant"], threads_per_ind=c.get("threads_per_ind", 64))
+            for L, st, c in zip(Ls, states, picks)]
+    dk.local_search(jobs, w.iterations)
+    torch.cuda.synchronize()
+    reps = []
+    idx = np.arange(0, 100, 25)
+    for k, (lig, L, st, c) in enumerate(zip(w.ligands, Ls, states, picks)):
+        s = st.to_numpy()
+        assert np.all(s["iters_done"] == w.iterations)
+        prep = R.prepare(lig, w.ff)
+        one_wave = L.n_atoms <= 64 or c.get("threads_per_ind", 64) == 64
+        reps.append(check_reported(f"uneven full ligand {k} N={L.n_atoms} T={L.n_torsions}", dk, G, L, prep,
+                                   w.grids, s["best_genotype"][idx], s["best_energy"][idx],
+                                   variant=c["variant"], exact_rescore=one_wave, assert_ok=False))
+    assert_reports("uneven full size, 4 best points per ligand", reps)

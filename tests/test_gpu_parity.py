@@ -22,9 +22,15 @@ pytestmark = pytest.mark.gpu
 FP32_VARIANTS = [0, 1]          # shuffle, FP32 MFMA
 SPLIT_VARIANTS = [2, 3, 4]      # BF16 2-term, FP16 2-term, BF16 3-term
 
-# 300-step best-energy distribution against the oracle's (3000 individuals)
-DIST_TOL = 0.01
-DIST_KS = 0.05
+# 300-step best-energy distribution against the oracle's (3000 individuals).
+# The searches are chaotic, so each individual's best energy is a draw from
+# the search's distribution; the bounds are set by the sample, not by the
+# arithmetic: mean and median may differ by DIST_SE paired standard errors
+# (z = 4: a false alarm about once in 16,000 runs), and the two empirical
+# distributions by the two-sample Kolmogorov-Smirnov critical distance at
+# alpha = 0.001, 1.949 * sqrt(2 / n).
+DIST_SE = 4.0
+DIST_KS_ALPHA_COEF = 1.949
 
 
 @pytest.fixture(scope="module")
@@ -477,6 +483,18 @@ def _oracle_best_fixture():
     return np.loadtxt(path, comments="#")
 
 
+def _paired_standard_errors(a, b, n_boot=2000, seed=0):
+    """Standard errors of mean(a) - mean(b) and median(a) - median(b) for
+    paired samples (a_i and b_i start from the same genotype): the mean's
+    from the paired differences, the median's by resampling the pairs."""
+    d = a - b
+    se_mean = d.std(ddof=1) / math.sqrt(len(d))
+    rng = np.random.default_rng(seed)
+    idx = rng.integers(0, len(a), (n_boot, len(a)))
+    dm = np.median(a[idx], axis=1) - np.median(b[idx], axis=1)
+    return se_mean, float(dm.std(ddof=1))
+
+
 @pytest.mark.parametrize("variant", FP32_VARIANTS)
 def test_ls_best_energy_distribution_vs_oracle(dk, variant):
     """300-step searches are chaotic, so individual best energies of the FP32
@@ -484,31 +502,38 @@ def test_ls_best_energy_distribution_vs_oracle(dk, variant):
     individuals of the benchmark workload must agree (the paper validates its
     reduction the same way, by the best energies of many runs against the
     reference code, Sec. 5.1). The oracle's best energies are a committed
-    fixture written by tests/golden/make_ls_oracle_best.py. Bounds: median
-    and mean of the best energy within DIST_TOL relative, and the two
-    empirical distributions within a two-sample Kolmogorov-Smirnov distance
-    of DIST_KS."""
+    fixture written by tests/golden/make_ls_oracle_best.py. Bounds: mean and
+    median of the best energy within DIST_SE paired standard errors, and the
+    two empirical distributions within the two-sample Kolmogorov-Smirnov
+    critical distance at alpha = 0.001. (At n = 3000 one standard error of
+    the median is about 0.85 % of it: a fixed 0.2 % bound would need some
+    10^5 individuals to be met by chance alone.)"""
     w = synth.ls_workload(3000)
     G, L, st = _ls_setup(dk, w, 3000)
     dk.local_search([(G, L, st)], 300, variant=variant, final_eval=True)
     torch.cuda.synchronize()
     gpu = st.best_energy.cpu().numpy().astype(np.float64)
     ora = _oracle_best_fixture()
-    assert ora.shape == (3000,)
+    assert ora.shape == (3000,) and np.all(np.isfinite(gpu))
+    n = len(ora)
     med_g, med_o = np.median(gpu), np.median(ora)
     mean_g, mean_o = gpu.mean(), ora.mean()
+    se_mean, se_med = _paired_standard_errors(gpu, ora)
     # paired view: how many individuals reach the same best energy
     rel = np.abs(gpu - ora) / np.maximum(np.abs(ora), 1.0)
     grid = np.sort(np.concatenate([gpu, ora]))
     ks = np.max(np.abs(np.searchsorted(np.sort(gpu), grid, side="right")
-                       - np.searchsorted(np.sort(ora), grid, side="right"))) / 3000.0
+                       - np.searchsorted(np.sort(ora), grid, side="right"))) / n
+    ks_crit = DIST_KS_ALPHA_COEF * math.sqrt(2.0 / n)
     print(f"\n[ls distribution v{variant}] median gpu {med_g:.4f} oracle {med_o:.4f} "
-          f"(rel {abs(med_g - med_o) / abs(med_o):.2e}); mean gpu {mean_g:.4f} oracle {mean_o:.4f} "
-          f"(rel {abs(mean_g - mean_o) / abs(mean_o):.2e}); KS {ks:.4f}; same best E within 1e-5: "
-          f"{int((rel <= 1e-5).sum())}, within 1e-3: {int((rel <= 1e-3).sum())} of 3000", flush=True)
-    assert abs(med_g - med_o) <= DIST_TOL * abs(med_o)
-    assert abs(mean_g - mean_o) <= DIST_TOL * abs(mean_o)
-    assert ks <= DIST_KS
+          f"(rel {abs(med_g - med_o) / abs(med_o):.2e}, {abs(med_g - med_o) / se_med:.2f} SE); "
+          f"mean gpu {mean_g:.4f} oracle {mean_o:.4f} (rel {abs(mean_g - mean_o) / abs(mean_o):.2e}, "
+          f"{abs(mean_g - mean_o) / se_mean:.2f} SE); KS {ks:.4f} (critical {ks_crit:.4f}); "
+          f"same best E within 1e-5: {int((rel <= 1e-5).sum())}, within 1e-3: {int((rel <= 1e-3).sum())} "
+          f"of {n}", flush=True)
+    assert abs(mean_g - mean_o) <= DIST_SE * se_mean
+    assert abs(med_g - med_o) <= DIST_SE * se_med
+    assert ks <= ks_crit
 
 
 def test_ls_uneven_full_size_sampled(dk):

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define DOCK_ABI_VERSION 6
+#define DOCK_ABI_VERSION 7
 
 /* status codes */
 #define DOCK_OK            0
@@ -292,6 +292,25 @@ int32_t dock_ls_workspace_bytes(int32_t n_items, int64_t* bytes);
 int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items,
                                 const dock_ls_opts* opts, void* workspace_dev,
                                 int64_t workspace_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * search as dock_local_search_batch, same items, opts, kernels and results
+ * bit for bit, with the workspace held by the library instead of passed in.
+ * Each GPU holds one library-resident workspace of
+ * 64 + DOCK_STATIC_MAX_ITEMS item records (about 10 KB) until the process
+ * ends; the call writes its item table there with kernel launches on
+ * `stream` (the data travels in kernel arguments) and then launches the
+ * search on `stream`, each kernel family after the other (no side streams).
+ * It calls no hipMalloc, hipFree, hipHostMalloc or memset/memcpy: only
+ * kernel launches. Every call on one GPU shares that workspace, so calls
+ * that may overlap on one GPU (different streams, or different host
+ * threads) race and must not be made; calls queued on one stream are safe.
+ * Errors: those of dock_local_search_batch, and DOCK_EINVAL for more than
+ * DOCK_STATIC_MAX_ITEMS items (nothing is launched then). */
+#define DOCK_STATIC_MAX_ITEMS 64
+int32_t dock_local_search_batch_static(const dock_ls_item* items, int32_t n_items,
+                                       const dock_ls_opts* opts, void* stream);
 
 /* ------------------------------------------------------------------------
  * Isolated block sum (the paper's reduction test kernel, Sec. 5.2): each of

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdockmi.so")
 ARCH = "gfx950"
 
-SOURCES = ["dock_kernels.hip", "dock_ga.hip", "dock_abi.cpp", "dock_prep.cpp"]
+SOURCES = ["dock_kernels.hip", "dock_ga.hip", "dock_static.hip", "dock_abi.cpp", "dock_prep.cpp"]
 
 # Packed FP32 VALU instructions are disabled for all device code.
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -108,19 +108,20 @@ StagingRing& staging() {
 
 int device_cu_count(int32_t& out) {
     static std::mutex mu;
-    static std::map<int, int> cache;
+    static int cache[64] = {};
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     std::lock_guard<std::mutex> lock(mu);
-    auto it = cache.find(dev);
-    if (it == cache.end()) {
+    if (dev < 0 || dev >= 64 || cache[dev] == 0) {
         int n = 0;
         e = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
-        it = cache.emplace(dev, n).first;
+        if (dev >= 0 && dev < 64) cache[dev] = n;
+        out = n;
+        return DOCK_OK;
     }
-    out = it->second;
+    out = cache[dev];
     return DOCK_OK;
 }
 
@@ -164,6 +165,213 @@ int32_t check_grid_for_ligand(const dock_grids* g, const dock_ligand* l) {
 }
 
 bool valid_variant(int v) { return v >= 0 && v < DOCK_REDUCE_COUNT; }
+
+// Storage of one call's plan; every array holds at least max(n_items, 1)
+// entries, table kWorkspaceHeader + that many item records.
+struct LsPlanBuf {
+    docklaunch::DevItem* dev;
+    int64_t* cost;
+    int* fam;
+    int* idx;
+    uint8_t* table;
+};
+
+struct LsPart { int first, count, mode, variant; };
+
+struct LsPlan {
+    LsPart part[3];
+    int n_parts = 0;
+    int64_t table_bytes = 0;
+};
+
+// Validates a local-search call and builds its device item table (header of
+// zeroed work counters, then the items grouped by launch) in buf.table.
+// n_parts = 0 when no item has work. Allocates nothing.
+int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* o, LsPlanBuf& buf,
+                LsPlan& plan) {
+    plan = LsPlan();
+    if (!o) return fail(DOCK_EINVAL, "dock_local_search_batch: NULL opts");
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(DOCK_EINVAL, "dock_local_search_batch: bad items");
+    if (o->iterations < 0) return fail(DOCK_EINVAL, "iterations must be >= 0");
+    if (!(o->rho > 0.f && o->rho < 1.f)) return fail(DOCK_EINVAL, "rho must be in (0, 1)");
+    if (!(o->eps > 0.f) || !std::isfinite(o->eps)) return fail(DOCK_EINVAL, "eps must be > 0");
+    if (!valid_variant(o->variant)) return fail(DOCK_EINVAL, "unknown default variant");
+    if (o->threads_per_ind != 0 && o->threads_per_ind != 64 && o->threads_per_ind != 128)
+        return fail(DOCK_EUNSUPPORTED, "threads_per_ind must be 0, 64 or 128");
+    if ((o->flags & ~DOCK_LS_FINAL_EVAL) != 0) return fail(DOCK_EINVAL, "unknown flags");
+    docklaunch::DevItem* dev = buf.dev;
+    int64_t* cost = buf.cost;
+    int* fam = buf.fam;             // kernel family: 0 two-wave, 1 two-slot, 2 one-slot
+    int n_dev = 0;
+    int64_t total = 0;
+    bool any_fam[3] = {false, false, false};
+    int var_u = -2;
+    for (int i = 0; i < n_items; ++i) {
+        const dock_ls_item& it = items[i];
+        if (!it.grids || !it.ligand) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": NULL handle");
+        if (it.n_genes != 7 + it.ligand->prep.n_torsions)
+            return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": n_genes " + std::to_string(it.n_genes) +
+                                         " is not the ligand's " + std::to_string(7 + it.ligand->prep.n_torsions));
+        if (!it.ligand->blob_dev) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": ligand not uploaded");
+        if (it.n < 0) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": n < 0");
+        int32_t st = check_grid_for_ligand(it.grids, it.ligand);
+        if (st != DOCK_OK) return st;
+        const int var = it.variant < 0 ? o->variant : it.variant;
+        if (!valid_variant(var)) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": unknown variant");
+        if (it.iterations < -1 || it.iterations > o->iterations)
+            return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": iterations outside [-1, opts->iterations]");
+        if (it.final_eval < -1 || it.final_eval > 1)
+            return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": final_eval must be -1, 0 or 1");
+        if (it.threads_per_ind != 0 && it.threads_per_ind != 64 && it.threads_per_ind != 128)
+            return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": threads_per_ind must be 0, 64 or 128");
+        const int tpi = it.threads_per_ind != 0 ? it.threads_per_ind
+                                                : (o->threads_per_ind != 0 ? o->threads_per_ind : 64);
+        const int iters = it.iterations < 0 ? o->iterations : it.iterations;
+        const int fin = it.final_eval < 0 ? ((o->flags & DOCK_LS_FINAL_EVAL) ? 1 : 0) : it.final_eval;
+        if (it.n == 0) continue;
+        void* ptrs[] = {it.genotype, it.acc_g2, it.acc_dx2, it.best_genotype, it.best_energy, it.energy,
+                        it.iters_done};
+        for (void* p : ptrs)
+            if (!p || !aligned(p, 4)) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": NULL or misaligned state");
+        if (it.grad && !aligned(it.grad, 4)) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": misaligned grad");
+        if (iters == 0 && !fin) continue;  // nothing to do for this item
+        docklaunch::DevItem& d = dev[n_dev];
+        std::memset(&d, 0, sizeof(d));
+        d.grid = it.grids->gp;
+        d.blob = it.ligand->blob_dev;
+        d.genotype = it.genotype;
+        d.acc_g2 = it.acc_g2;
+        d.acc_dx2 = it.acc_dx2;
+        d.best_genotype = it.best_genotype;
+        d.best_energy = it.best_energy;
+        d.energy = it.energy;
+        d.iters_done = it.iters_done;
+        d.grad = it.grad;
+        d.n = it.n;
+        d.variant = var;
+        d.slots = it.ligand->slots;
+        d.iterations = iters;
+        d.final_eval = fin;
+        const auto& P = it.ligand->prep;
+        const auto* H = reinterpret_cast<const dockblob::Header*>(P.blob.data());
+        // per-individual cost: evaluations x (instruction estimate per
+        // evaluation: pair batches, atom slots, torsion depth, fixed part)
+        cost[n_dev] = (int64_t)(iters + fin) *
+                      ((int64_t)H->n_batches * 90 + (int64_t)d.slots * (150 + 20 * P.max_depth) + 500);
+        const int f = d.slots == 1 ? 2 : (tpi == 128 ? 0 : 1);
+        fam[n_dev] = f;
+        any_fam[f] = true;
+        var_u = (var_u == -2 || var_u == var) ? var : -1;
+        total += it.n;
+        ++n_dev;
+    }
+    if (total > 2147483647LL) return fail(DOCK_EUNSUPPORTED, "more than 2^31 individuals in one call");
+    if (n_dev == 0) return ok();
+    // A launch carries one kernel family. The two one-wave families share one
+    // launch (kernel dispatching per item) when every item uses the same
+    // reduction variant; otherwise, or with two-wave items, there is one
+    // persistent launch per family (each with its own work counter), two-wave
+    // items first, then two-slot, then one-slot, each group longest first.
+    // Carrying every combination in one kernel would spill registers.
+    const int var_uniform = var_u >= 0 ? var_u : -1;
+    const bool merge_one_wave = !any_fam[0] && any_fam[1] && any_fam[2] && var_uniform >= 0;
+    auto group = [&](int i) { return merge_one_wave ? 1 : fam[i]; };
+    int* idx = buf.idx;
+    for (int i = 0; i < n_dev; ++i) idx[i] = i;
+    std::stable_sort(idx, idx + n_dev, [&](int a, int b) {
+        if (group(a) != group(b)) return group(a) < group(b);
+        return cost[a] > cost[b];
+    });
+    plan.table_bytes = docklaunch::kWorkspaceHeader + (int64_t)n_dev * (int64_t)sizeof(docklaunch::DevItem);
+    std::memset(buf.table, 0, (size_t)plan.table_bytes);
+    docklaunch::DevItem* tab = reinterpret_cast<docklaunch::DevItem*>(buf.table + docklaunch::kWorkspaceHeader);
+    int32_t ub = 0;
+    for (int i = 0; i < n_dev; ++i) {
+        const int g = group(idx[i]);
+        if (i == 0 || g != group(idx[i - 1])) {
+            const int mode = merge_one_wave ? docklaunch::kSlotsAny
+                                            : (g == 0 ? docklaunch::kTwoWave
+                                                      : (g == 1 ? docklaunch::kSlots2 : docklaunch::kSlots1));
+            plan.part[plan.n_parts++] = {i, 0, mode, -1};
+            ub = 0;
+        }
+        tab[i] = dev[idx[i]];
+        tab[i].unit_begin = ub;
+        ub += tab[i].n;
+        ++plan.part[plan.n_parts - 1].count;
+    }
+    // each launch runs the kernel specialised for its items' variant when
+    // they share one (e.g. a tuning table that picks one per size bucket)
+    // (the specialised kernels read corner-expanded grids only; a part with an
+    // item on plain maps runs the dispatching kernel, which reads either)
+    for (int k = 0; k < plan.n_parts; ++k) {
+        LsPart& pt = plan.part[k];
+        int v = -2;
+        bool corners = true;
+        for (int i = pt.first; i < pt.first + pt.count; ++i) {
+            v = (v == -2 || v == tab[i].variant) ? tab[i].variant : -1;
+            corners = corners && tab[i].grid.corners != nullptr;
+        }
+        pt.variant = (v < 0 || !corners) ? -1 : v;
+    }
+    return ok();
+}
+
+// Launches the parts of a plan whose table is already on its way to `ws`
+// on `stream`. With side streams the second and third parts run beside the
+// first on library-owned streams (forked from and joined back into
+// `stream`); without, every part runs on `stream`, one after another.
+int32_t ls_launch(const LsPlan& plan, const LsPlanBuf& buf, void* ws, const dock_ls_opts* o,
+                  hipStream_t stream, bool side_streams) {
+    const docklaunch::DevItem* tab =
+        reinterpret_cast<const docklaunch::DevItem*>(buf.table + docklaunch::kWorkspaceHeader);
+    int32_t n_cu = 0;
+    int32_t st = device_cu_count(n_cu);
+    if (st != DOCK_OK) return st;
+    SideStream* side = nullptr;
+    std::unique_lock<std::mutex> side_lock;
+    const int n_side = side_streams ? plan.n_parts - 1 : 0;   // at most 2
+    if (n_side > 0) {
+        st = side_stream(side, side_lock);
+        if (st != DOCK_OK) return st;
+        hipError_t e = hipEventRecord(side->fork, stream);
+        for (int k = 0; k < n_side && e == hipSuccess; ++k) e = hipStreamWaitEvent(side->stream[k], side->fork, 0);
+        if (e != hipSuccess) return hip_fail(e, "dock_local_search_batch fork");
+    }
+    hipError_t launch_err = hipSuccess;
+    for (int k = 0; k < plan.n_parts; ++k) {
+        const LsPart& pt = plan.part[k];
+        if (pt.count == 0) continue;
+        int64_t units = 0;
+        for (int i = pt.first; i < pt.first + pt.count; ++i) units += tab[i].n;
+        int per_cu = docklaunch::ls_blocks_per_cu(pt.mode, pt.variant);
+        if (per_cu <= 0) per_cu = 8;
+        const int64_t resident = (int64_t)per_cu * n_cu;
+        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(units, resident));
+        docklaunch::LsParams p;
+        p.items = reinterpret_cast<const docklaunch::DevItem*>(static_cast<uint8_t*>(ws) +
+                                                               docklaunch::kWorkspaceHeader) + pt.first;
+        p.counter = static_cast<int32_t*>(ws) + k;
+        p.n_items = pt.count;
+        p.total_units = (int32_t)units;
+        p.rho = o->rho;
+        p.eps = o->eps;
+        hipStream_t s_k = (k == 0 || !side) ? stream : side->stream[k - 1];
+        launch_err = docklaunch::launch_ls(p, pt.mode, pt.variant, grid, s_k);
+        if (launch_err != hipSuccess) break;
+    }
+    if (side) {  // joined also after a failed launch
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < n_side && e == hipSuccess; ++k) {
+            e = hipEventRecord(side->join[k], side->stream[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(stream, side->join[k], 0);
+        }
+        if (e != hipSuccess && launch_err == hipSuccess) return hip_fail(e, "dock_local_search_batch join");
+    }
+    if (launch_err != hipSuccess) return hip_fail(launch_err, "dock_local_search_batch launch");
+    return ok();
+}
+
 
 }  // namespace
 
@@ -344,185 +552,52 @@ int32_t dock_ls_workspace_bytes(int32_t n_items, int64_t* bytes) {
 
 int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* o,
                                 void* ws, int64_t ws_bytes, void* stream) {
-    if (!o) return fail(DOCK_EINVAL, "dock_local_search_batch: NULL opts");
     if (n_items < 0 || (n_items > 0 && !items)) return fail(DOCK_EINVAL, "dock_local_search_batch: bad items");
-    if (o->iterations < 0) return fail(DOCK_EINVAL, "iterations must be >= 0");
-    if (!(o->rho > 0.f && o->rho < 1.f)) return fail(DOCK_EINVAL, "rho must be in (0, 1)");
-    if (!(o->eps > 0.f) || !std::isfinite(o->eps)) return fail(DOCK_EINVAL, "eps must be > 0");
-    if (!valid_variant(o->variant)) return fail(DOCK_EINVAL, "unknown default variant");
-    if (o->threads_per_ind != 0 && o->threads_per_ind != 64 && o->threads_per_ind != 128)
-        return fail(DOCK_EUNSUPPORTED, "threads_per_ind must be 0, 64 or 128");
-    if ((o->flags & ~DOCK_LS_FINAL_EVAL) != 0) return fail(DOCK_EINVAL, "unknown flags");
+    std::vector<docklaunch::DevItem> dev(std::max(n_items, 1));
+    std::vector<int64_t> cost(std::max(n_items, 1));
+    std::vector<int> fam(std::max(n_items, 1)), idx(std::max(n_items, 1));
+    std::vector<uint8_t> table(docklaunch::kWorkspaceHeader + (size_t)std::max(n_items, 1) * sizeof(docklaunch::DevItem));
+    LsPlanBuf buf{dev.data(), cost.data(), fam.data(), idx.data(), table.data()};
+    LsPlan plan;
+    int32_t st = ls_plan(items, n_items, o, buf, plan);
+    if (st != DOCK_OK || plan.n_parts == 0) return st;
     int64_t need = 0;
     dock_ls_workspace_bytes(n_items, &need);
-    std::vector<docklaunch::DevItem> dev;
-    std::vector<int64_t> cost;
-    dev.reserve(n_items);
-    int64_t total = 0;
-    std::vector<int> fam;           // kernel family: 0 two-wave, 1 two-slot, 2 one-slot
-    bool any_fam[3] = {false, false, false};
-    int var_u = -2;
-    for (int i = 0; i < n_items; ++i) {
-        const dock_ls_item& it = items[i];
-        if (!it.grids || !it.ligand) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": NULL handle");
-        if (it.n_genes != 7 + it.ligand->prep.n_torsions)
-            return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": n_genes " + std::to_string(it.n_genes) +
-                                         " is not the ligand's " + std::to_string(7 + it.ligand->prep.n_torsions));
-        if (!it.ligand->blob_dev) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": ligand not uploaded");
-        if (it.n < 0) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": n < 0");
-        int32_t st = check_grid_for_ligand(it.grids, it.ligand);
-        if (st != DOCK_OK) return st;
-        const int var = it.variant < 0 ? o->variant : it.variant;
-        if (!valid_variant(var)) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": unknown variant");
-        if (it.iterations < -1 || it.iterations > o->iterations)
-            return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": iterations outside [-1, opts->iterations]");
-        if (it.final_eval < -1 || it.final_eval > 1)
-            return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": final_eval must be -1, 0 or 1");
-        if (it.threads_per_ind != 0 && it.threads_per_ind != 64 && it.threads_per_ind != 128)
-            return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": threads_per_ind must be 0, 64 or 128");
-        const int tpi = it.threads_per_ind != 0 ? it.threads_per_ind
-                                                : (o->threads_per_ind != 0 ? o->threads_per_ind : 64);
-        const int iters = it.iterations < 0 ? o->iterations : it.iterations;
-        const int fin = it.final_eval < 0 ? ((o->flags & DOCK_LS_FINAL_EVAL) ? 1 : 0) : it.final_eval;
-        if (it.n == 0) continue;
-        void* ptrs[] = {it.genotype, it.acc_g2, it.acc_dx2, it.best_genotype, it.best_energy, it.energy,
-                        it.iters_done};
-        for (void* p : ptrs)
-            if (!p || !aligned(p, 4)) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": NULL or misaligned state");
-        docklaunch::DevItem d;
-        std::memset(&d, 0, sizeof(d));
-        d.grid = it.grids->gp;
-        d.blob = it.ligand->blob_dev;
-        d.genotype = it.genotype;
-        d.acc_g2 = it.acc_g2;
-        d.acc_dx2 = it.acc_dx2;
-        d.best_genotype = it.best_genotype;
-        d.best_energy = it.best_energy;
-        d.energy = it.energy;
-        d.iters_done = it.iters_done;
-        d.grad = it.grad;
-        if (it.grad && !aligned(it.grad, 4)) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": misaligned grad");
-        d.n = it.n;
-        d.variant = var;
-        d.slots = it.ligand->slots;
-        d.iterations = iters;
-        d.final_eval = fin;
-        if (iters == 0 && !fin) continue;  // nothing to do for this item
-        dev.push_back(d);
-        const auto& P = it.ligand->prep;
-        const auto* H = reinterpret_cast<const dockblob::Header*>(P.blob.data());
-        // per-individual cost: evaluations x (instruction estimate per
-        // evaluation: pair batches, atom slots, torsion depth, fixed part)
-        cost.push_back((int64_t)(iters + fin) *
-                       ((int64_t)H->n_batches * 90 + (int64_t)d.slots * (150 + 20 * P.max_depth) + 500));
-        const int f = d.slots == 1 ? 2 : (tpi == 128 ? 0 : 1);
-        fam.push_back(f);
-        any_fam[f] = true;
-        var_u = (var_u == -2 || var_u == var) ? var : -1;
-        total += it.n;
-    }
-    if (total > 2147483647LL) return fail(DOCK_EUNSUPPORTED, "more than 2^31 individuals in one call");
-    if (dev.empty()) return ok();
     if (!ws) return fail(DOCK_EINVAL, "dock_local_search_batch: NULL workspace");
     if (ws_bytes < need) return fail(DOCK_EINVAL, "dock_local_search_batch: workspace too small");
     if (!aligned(ws, 16)) return fail(DOCK_EINVAL, "workspace must be 16-byte aligned");
-    // A launch carries one kernel family. The two one-wave families share one
-    // launch (kernel dispatching per item) when every item uses the same
-    // reduction variant; otherwise, or with two-wave items, there is one
-    // persistent launch per family (each with its own work counter), two-wave
-    // items first, then two-slot, then one-slot, each group longest first.
-    // Carrying every combination in one kernel would spill registers.
-    const int var_uniform = var_u >= 0 ? var_u : -1;
-    const bool merge_one_wave = !any_fam[0] && any_fam[1] && any_fam[2] && var_uniform >= 0;
-    auto group = [&](int i) { return merge_one_wave ? 1 : fam[i]; };
-    std::vector<int> idx(dev.size());
-    for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
-    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
-        if (group(a) != group(b)) return group(a) < group(b);
-        return cost[a] > cost[b];
-    });
-    std::vector<uint8_t> table(docklaunch::kWorkspaceHeader + dev.size() * sizeof(docklaunch::DevItem), 0);
-    docklaunch::DevItem* tab = reinterpret_cast<docklaunch::DevItem*>(table.data() + docklaunch::kWorkspaceHeader);
-    const int n_dev = (int)dev.size();
-    struct Part { int first, count, mode, variant; };
-    std::vector<Part> parts;
-    int32_t ub = 0;
-    for (int i = 0; i < n_dev; ++i) {
-        const int g = group(idx[i]);
-        if (i == 0 || g != group(idx[i - 1])) {
-            const int mode = merge_one_wave ? docklaunch::kSlotsAny
-                                            : (g == 0 ? docklaunch::kTwoWave
-                                                      : (g == 1 ? docklaunch::kSlots2 : docklaunch::kSlots1));
-            parts.push_back({i, 0, mode, -1});
-            ub = 0;
-        }
-        tab[i] = dev[idx[i]];
-        tab[i].unit_begin = ub;
-        ub += tab[i].n;
-        ++parts.back().count;
-    }
-    // each launch runs the kernel specialised for its items' variant when
-    // they share one (e.g. a tuning table that picks one per size bucket)
-    // (the specialised kernels read corner-expanded grids only; a part with an
-    // item on plain maps runs the dispatching kernel, which reads either)
-    for (Part& pt : parts) {
-        int v = -2;
-        bool corners = true;
-        for (int i = pt.first; i < pt.first + pt.count; ++i) {
-            v = (v == -2 || v == tab[i].variant) ? tab[i].variant : -1;
-            corners = corners && tab[i].grid.corners != nullptr;
-        }
-        pt.variant = (v < 0 || !corners) ? -1 : v;
-    }
     // counters (one 32-bit word per part in the header) start at 0: they are
     // part of the copy
-    int32_t st = staging().copy_to_device(ws, table.data(), table.size(), (hipStream_t)stream);
+    st = staging().copy_to_device(ws, table.data(), plan.table_bytes, (hipStream_t)stream);
     if (st != DOCK_OK) return st;
-    int32_t n_cu = 0;
-    st = device_cu_count(n_cu);
-    if (st != DOCK_OK) return st;
-    SideStream* side = nullptr;
-    std::unique_lock<std::mutex> side_lock;
-    const int n_side = (int)parts.size() - 1;   // at most 2
-    if (n_side > 0) {
-        st = side_stream(side, side_lock);
-        if (st != DOCK_OK) return st;
-        hipError_t e = hipEventRecord(side->fork, (hipStream_t)stream);
-        for (int k = 0; k < n_side && e == hipSuccess; ++k) e = hipStreamWaitEvent(side->stream[k], side->fork, 0);
-        if (e != hipSuccess) return hip_fail(e, "dock_local_search_batch fork");
-    }
-    hipError_t launch_err = hipSuccess;
-    for (size_t k = 0; k < parts.size(); ++k) {
-        const Part& pt = parts[k];
-        if (pt.count == 0) continue;
-        int64_t units = 0;
-        for (int i = pt.first; i < pt.first + pt.count; ++i) units += tab[i].n;
-        int per_cu = docklaunch::ls_blocks_per_cu(pt.mode, pt.variant);
-        if (per_cu <= 0) per_cu = 8;
-        const int64_t resident = (int64_t)per_cu * n_cu;
-        const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(units, resident));
-        docklaunch::LsParams p;
-        p.items = reinterpret_cast<const docklaunch::DevItem*>(static_cast<uint8_t*>(ws) +
-                                                               docklaunch::kWorkspaceHeader) + pt.first;
-        p.counter = static_cast<int32_t*>(ws) + k;
-        p.n_items = pt.count;
-        p.total_units = (int32_t)units;
-        p.rho = o->rho;
-        p.eps = o->eps;
-        hipStream_t s_k = k == 0 ? (hipStream_t)stream : side->stream[k - 1];
-        launch_err = docklaunch::launch_ls(p, pt.mode, pt.variant, grid, s_k);
-        if (launch_err != hipSuccess) break;
-    }
-    if (side) {  // joined also after a failed launch
-        hipError_t e = hipSuccess;
-        for (int k = 0; k < n_side && e == hipSuccess; ++k) {
-            e = hipEventRecord(side->join[k], side->stream[k]);
-            if (e == hipSuccess) e = hipStreamWaitEvent((hipStream_t)stream, side->join[k], 0);
-        }
-        if (e != hipSuccess && launch_err == hipSuccess) return hip_fail(e, "dock_local_search_batch join");
-    }
-    if (launch_err != hipSuccess) return hip_fail(launch_err, "dock_local_search_batch launch");
-    return ok();
+    return ls_launch(plan, buf, ws, o, (hipStream_t)stream, true);
+}
+
+int32_t dock_local_search_batch_static(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* o,
+                                       void* stream) {
+    if (n_items < 0 || (n_items > 0 && !items))
+        return fail(DOCK_EINVAL, "dock_local_search_batch_static: bad items");
+    if (n_items > DOCK_STATIC_MAX_ITEMS)
+        return fail(DOCK_EINVAL, "dock_local_search_batch_static: " + std::to_string(n_items) +
+                                     " items exceed DOCK_STATIC_MAX_ITEMS (" +
+                                     std::to_string(DOCK_STATIC_MAX_ITEMS) + ")");
+    docklaunch::DevItem dev[DOCK_STATIC_MAX_ITEMS];
+    int64_t cost[DOCK_STATIC_MAX_ITEMS];
+    int fam[DOCK_STATIC_MAX_ITEMS], idx[DOCK_STATIC_MAX_ITEMS];
+    alignas(16) uint8_t table[docklaunch::kWorkspaceHeader + DOCK_STATIC_MAX_ITEMS * sizeof(docklaunch::DevItem)];
+    LsPlanBuf buf{dev, cost, fam, idx, table};
+    LsPlan plan;
+    int32_t st = ls_plan(items, n_items, o, buf, plan);
+    if (st != DOCK_OK || plan.n_parts == 0) return st;
+    if (plan.table_bytes > docklaunch::static_workspace_capacity())
+        return fail(DOCK_EINVAL, "dock_local_search_batch_static: item table exceeds the static workspace");
+    void* ws = nullptr;
+    hipError_t e = docklaunch::static_workspace(&ws);
+    if (e != hipSuccess) return hip_fail(e, "dock_local_search_batch_static: workspace address");
+    // the fill kernel writes the whole table, counters included (zeros)
+    e = docklaunch::launch_table_fill(ws, table, plan.table_bytes, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "dock_local_search_batch_static: table fill");
+    return ls_launch(plan, buf, ws, o, (hipStream_t)stream, false);
 }
 
 int32_t dock_block_sum4(const float* in, float* out, int32_t n_blocks, int32_t threads, int32_t variant,

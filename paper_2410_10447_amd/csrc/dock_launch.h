@@ -110,4 +110,15 @@ struct GaParams {
 
 hipError_t launch_ga_step(const GaParams& p, hipStream_t stream);
 
+// Library-resident workspace (dock_local_search_batch_static): its size in
+// bytes, and its device address on the current device (looked up once per
+// device with hipGetSymbolAddress).
+int64_t static_workspace_capacity();
+hipError_t static_workspace(void** out);
+
+// Writes `bytes` (a multiple of 4) of host memory to dst_dev on `stream` by
+// kernel launches that carry the data in their arguments (no host staging,
+// no copy or memset node).
+hipError_t launch_table_fill(void* dst_dev, const void* src_host, int64_t bytes, hipStream_t stream);
+
 }  // namespace docklaunch

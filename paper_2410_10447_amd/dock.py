@@ -16,7 +16,7 @@ import numpy as np
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdockmi.so")
 
 # the struct layouts below follow include/dock.h of this ABI version
-ABI_VERSION = 6
+ABI_VERSION = 7
 
 DOCK_OK = 0
 DOCK_EINVAL = -1
@@ -34,6 +34,7 @@ VARIANT_NAMES = {0: "shuffle", 1: "mfma_f32", 2: "mfma_bf16", 3: "mfma_f16", 4: 
                  5: "shared_atomic"}
 
 LS_FINAL_EVAL = 1
+STATIC_MAX_ITEMS = 64   # items per dock_local_search_batch_static call
 
 MAX_ATOMS = 128
 MAX_TORSIONS = 32
@@ -44,7 +45,7 @@ ABI_SYMBOLS = (
     "dock_grids_corner_bytes", "dock_grids_bind_corners",
     "dock_create_ligand", "dock_ligand_info_get", "dock_ligand_export", "dock_ligand_upload",
     "dock_destroy_ligand", "dock_score_batch", "dock_ls_workspace_bytes",
-    "dock_local_search_batch", "dock_block_sum4", "dock_ga_step", "dock_solis_wets_batch",
+    "dock_local_search_batch", "dock_local_search_batch_static", "dock_block_sum4", "dock_ga_step", "dock_solis_wets_batch",
 )
 
 
@@ -141,6 +142,7 @@ def lib():
         "dock_score_batch": ([vp, vp, i32, vp, vp, vp, C.POINTER(ExecOpts), vp], i32),
         "dock_ls_workspace_bytes": ([i32, C.POINTER(i64)], i32),
         "dock_local_search_batch": ([C.POINTER(LsItem), i32, C.POINTER(LsOpts), vp, i64, vp], i32),
+        "dock_local_search_batch_static": ([C.POINTER(LsItem), i32, C.POINTER(LsOpts), vp], i32),
         "dock_block_sum4": ([vp, vp, i32, i32, i32, i32, vp], i32),
         "dock_ga_step": ([C.POINTER(GaStepDesc), vp], i32),
         "dock_solis_wets_batch": ([vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, C.POINTER(SwOpts), vp, vp], i32),
@@ -507,6 +509,22 @@ def local_search(jobs, iterations: int, rho: float = 0.8, eps: float = 1e-2,
     _check(lib().dock_local_search_batch(items, n_items, C.byref(o), _ptr(workspace),
                                          workspace.numel(), _stream_handle(stream)))
     return workspace
+
+
+def local_search_static(jobs, iterations: int, rho: float = 0.8, eps: float = 1e-2,
+                        variant: int = REDUCE_SHUFFLE, final_eval: bool = True, stream=None,
+                        items=None, threads_per_ind: int = 0):
+    """local_search through dock_local_search_batch_static: the workspace is
+    the library's own (at most STATIC_MAX_ITEMS jobs per call); the call
+    allocates no device memory. Calls that may overlap on one GPU race."""
+    n_items = len(jobs)
+    if items is None:
+        items = make_items(jobs)
+    elif len(items) < n_items:
+        raise ValueError("items shorter than jobs")
+    o = LsOpts(iterations=iterations, rho=rho, eps=eps, variant=variant,
+               threads_per_ind=threads_per_ind, flags=LS_FINAL_EVAL if final_eval else 0)
+    _check(lib().dock_local_search_batch_static(items, n_items, C.byref(o), _stream_handle(stream)))
 
 
 def block_sum4(x, variant: int, repeat: int = 1, stream=None):

@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(dock.ABI_SYMBOLS)
     for name in declared:
         assert hasattr(L, name)
-    assert L.dock_abi_version() == dock.ABI_VERSION == 6
+    assert L.dock_abi_version() == dock.ABI_VERSION == 7
 
 
 def _check_prep(lig):
@@ -329,6 +329,20 @@ def test_batch_calls_validate_before_device_work():
         ob = dock.LsOpts(**kw)
         assert L.dock_local_search_batch(item, 1, C.byref(ob), fake, 1 << 20, None) in (
             dock.DOCK_EINVAL, dock.DOCK_EUNSUPPORTED)
+    # the library-resident variant validates the same way, before any device work
+    for bad_g in (lig.n_genes - 1, lig.n_genes + 1):
+        item[0].n_genes = bad_g
+        st = L.dock_local_search_batch_static(item, 1, C.byref(o), None)
+        assert st == dock.DOCK_EINVAL and "n_genes" in dock.last_error()
+    item[0].n_genes = lig.n_genes
+    st = L.dock_local_search_batch_static(item, 1, C.byref(o), None)
+    assert st == dock.DOCK_EINVAL and "uploaded" in dock.last_error()
+    assert L.dock_local_search_batch_static(item, 1, None, None) == dock.DOCK_EINVAL
+    assert L.dock_local_search_batch_static(None, 1, C.byref(o), None) == dock.DOCK_EINVAL
+    many = (dock.LsItem * (dock.STATIC_MAX_ITEMS + 1))()
+    st = L.dock_local_search_batch_static(many, dock.STATIC_MAX_ITEMS + 1, C.byref(o), None)
+    assert st == dock.DOCK_EINVAL and "DOCK_STATIC_MAX_ITEMS" in dock.last_error()
+    assert L.dock_local_search_batch_static(item, 0, C.byref(o), None) == dock.DOCK_OK   # nothing to do
     b = C.c_int64()
     assert L.dock_ls_workspace_bytes(3, C.byref(b)) == 0 and b.value >= 64 + 3 * 64
     assert L.dock_ls_workspace_bytes(-1, C.byref(b)) == dock.DOCK_EINVAL

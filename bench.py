@@ -32,22 +32,33 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "energy+gradient evals/sec on 1 MI355X vs plain FP32; p50/p99 dock latency"
-PEAK_FP32_VECTOR_TFLOPS = 157.3   # MI355X FP32 vector peak (packed FMA)
+# Peaks of the FP32 VALU roofline, in lane operations per second (an FMA is
+# one operation): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 without
+# packed FP32 (78.6 TFLOP/s counting an FMA as two), twice that with packed
+# FP32 (the published 157.3 TFLOP/s).
+PEAK_TOPS_PACKED = 157.3 / 2.0
+PEAK_TOPS_NONPACKED = 157.3 / 4.0
 
-# Algorithmic FP32 operations of one scoring evaluation, counted from the
-# formulas the method computes (an FMA counts 2, a transcendental or a
-# division 1; compares and selects 0):
-#   per kept pair  : separation 3, r^2 5, sqrt 1, r0/r and powers 7, 12-6 or
-#                    12-10 energy and slope 8, dielectric and its slope 9,
-#                    electrostatics 7, desolvation 5, w = dE/dr / r 3, energy
-#                    sum 3, forces on both atoms 9, pair parameters 6 -> 66
-#   per atom       : pose 18, grid term (cell, 8 corners x 3 maps combined,
-#                    value + gradient, penalty) 92, torque 9, sums 7, torsion
-#                    prefix terms 15 -> 141
-#   per torsion    : rotation 27, its share of fragment products 63, torsion
-#                    gradient 35 -> 125
-#   per gene       : ADADELTA update 12
-FLOPS_PAIR, FLOPS_ATOM, FLOPS_TORSION, FLOPS_GENE = 66, 141, 125, 12
+
+def work_per_eval(n_pairs, n_atoms, n_torsions):
+    """Algorithmic work of one energy+gradient evaluation (and its ADADELTA
+    update) in FP32 lane-slots, transcendentals weighted 4: 75 per kept
+    pair, 150 per atom, 80 per torsion, 25 per gene. The oracle's own
+    operation tally of the same evaluation (oracle/work.py) is larger; this
+    model is the conservative choice."""
+    return 75 * n_pairs + 150 * n_atoms + 80 * n_torsions + 25 * (7 + n_torsions)
+
+
+def roofline(evals, seconds, w_eval, traffic=None, **extra):
+    """FP32 VALU roofline object: `evals` evaluations of w_eval lane-slots in
+    `seconds` of kernel time."""
+    achieved = w_eval * evals / seconds / 1e12
+    out = {"bound": "alu", "achieved": achieved, "peak": PEAK_TOPS_PACKED, "unit": "Tops/s",
+           "frac": achieved / PEAK_TOPS_PACKED, "traffic": traffic,
+           "peak_nonpacked": PEAK_TOPS_NONPACKED, "frac_nonpacked": achieved / PEAK_TOPS_NONPACKED,
+           "work_per_eval": w_eval}
+    out.update(extra)
+    return out
 
 
 # HBM traffic of one benchmark launch, from rocprofv3 --pmc FETCH_SIZE and
@@ -77,11 +88,6 @@ def traffic_bytes():
     if t["kernel_sha256"] is None or t["kernel_sha256"] != kernel_sha256():
         return None
     return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
-
-
-def flops_per_eval(n_pairs, n_atoms, n_torsions):
-    return (FLOPS_PAIR * n_pairs + FLOPS_ATOM * n_atoms + FLOPS_TORSION * n_torsions
-            + FLOPS_GENE * (7 + n_torsions))
 
 
 def _oracle_ls_worker(args):
@@ -114,7 +120,9 @@ def cpu_baseline(w, sample, iterations, pool_per_worker=None):
     NumPy thread each). Runs before the GPU is touched (the pool forks)."""
     import multiprocessing as mp
     from oracle import dock_ref as R
+    from oracle import work as OW
     prep = R.prepare(w.ligands[0], w.ff)
+    tally = OW.tally(prep, w.grids, w.genotypes[0][0])
     st = R.ls_init(w.genotypes[0][:sample])
     t0 = time.perf_counter()
     R.local_search(prep, w.grids, st, iterations, rho=w.rho, eps=w.eps)
@@ -145,7 +153,10 @@ def cpu_baseline(w, sample, iterations, pool_per_worker=None):
                       "NumPy FP64, one thread each)",
             "single_process": {"value": evals1 / dt1, "cores": 1,
                                "sample": f"{sample} individuals, {evals1} evals, {dt1:.1f} s"},
-            "host": {"cpu_model": _cpu_model(), "cpu_count": os.cpu_count(), "usable_cores": cores}}
+            "host": {"cpu_model": _cpu_model(), "cpu_count": os.cpu_count(), "usable_cores": cores},
+            # the oracle's own operation count of one evaluation + ADADELTA step
+            # (lane-slots, transcendentals x4), per stage
+            "oracle_work_per_eval": {k: v["slots"] for k, v in tally.items() if isinstance(v, dict)}}
 
 
 def reduction_run(threads_list=(64, 128, 256, 512, 1024), variants=(5, 0, 1, 2, 3, 4),
@@ -203,7 +214,10 @@ def score_run(n=65536, reps=5):
             times.append(a.elapsed_time(b))
         ms = float(np.median(times))
         res[dock.VARIANT_NAMES[v]] = {"ms": round(ms, 4), "evals_per_s": n / (ms * 1e-3)}
-    return {"workload": w.name, "genotypes": n, **res}
+    best = min(res, key=lambda k: res[k]["ms"])
+    w_eval = work_per_eval(L.n_pairs, L.n_atoms, L.n_torsions)
+    return {"workload": w.name, "genotypes": n, **res,
+            "roofline": roofline(n, res[best]["ms"] * 1e-3, w_eval, kernel="score_kernel", variant=best)}
 
 
 def ga_step_bytes(R, P, G):
@@ -290,9 +304,14 @@ def sw_run(G, L, gen0, iterations, variant, reps=3, seed=91):
         times.append(a.elapsed_time(b))
         evals.append(int((~torch.isnan(log)).sum()))
     ms = float(np.median(times))
+    w_eval = work_per_eval(L.n_pairs, L.n_atoms, L.n_torsions)
     return {"workload": f"sw_n{L.n_atoms}_t{L.n_torsions}_i{n}", "iterations": iterations,
             "variant": dock.VARIANT_NAMES[variant], "ms": round(ms, 4), "evals": evals[-1],
             "evals_per_s": evals[-1] / (ms * 1e-3),
+            # energy-only trials priced at the energy+gradient work model (the
+            # oracle evaluates a trial in full): an upper bound of their work
+            "roofline": roofline(evals[-1], ms * 1e-3, w_eval, kernel="sw_kernel",
+                                 work="energy+gradient model (upper bound for energy-only trials)"),
             "energy_median_start": float(E0.median()), "energy_median_end": float(st.energy.median())}
 
 
@@ -300,8 +319,10 @@ def uneven_run(steps, warmup, use_table=True, tpi_override=0):
     """64 ligands (atoms U{12..128}, torsions U{0..32}) x 100 individuals on one
     96^3 x 12 grid set, 300 iterations, in one call per step (one persistent
     launch per kernel family, side by side); each item takes its size
-    bucket's variant and threads per individual from the autotuning table
-    (`tpi_override` forces the thread count of ligands over 64 atoms)."""
+    bucket's variant, threads per individual and grid layout from the
+    autotuning table (`tpi_override` forces the thread count of every
+    ligand). Without the table every item takes one wave and the shuffle
+    reduction, and the call is a single persistent launch."""
     import torch
     from paper_2410_10447_amd import autotune, dock, synth
     w = synth.uneven_workload()
@@ -317,7 +338,8 @@ def uneven_run(steps, warmup, use_table=True, tpi_override=0):
     runs = []
     for _ in range(warmup + steps):
         states = [dock.LSState.start(g) for g in gens]
-        jobs = [dock.LsJob(G, L, st, c["variant"], threads_per_ind=c.get("threads_per_ind", 64))
+        jobs = [dock.LsJob(G, L, st, c["variant"], threads_per_ind=c.get("threads_per_ind", 64),
+                           plain_maps=c.get("plain_maps", False))
                 for L, st, c in zip(Ls, states, pick)]
         runs.append((states, dock.make_items(jobs)))
     torch.cuda.synchronize()
@@ -329,11 +351,17 @@ def uneven_run(steps, warmup, use_table=True, tpi_override=0):
         dock.local_search([None] * len(Ls), w.iterations, workspace=ws, items=runs[k][1])
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / steps
+    work = sum(g.shape[0] * (w.iterations + 1) * work_per_eval(L.n_pairs, L.n_atoms, L.n_torsions)
+               for g, L in zip(gens, Ls))
     return {"workload": w.name, "evals_per_step": evals, "ms_per_step": 1e3 * dt,
-            "evals_per_s": evals / dt, "variants_from_table": use_table,
+            "evals_per_s": evals / dt,
+            "roofline": roofline(evals, dt, work / evals,
+                                 kernel="ls_kernel (all families, wall clock per call; mean work per eval)"),
+            "variants_from_table": use_table,
+            "single_launch": not use_table and tpi_override in (0, 64),
             "threads_per_ind_override": tpi_override,
-            "two_wave_items": sum(1 for L, c in zip(Ls, pick)
-                                  if L.n_atoms > 64 and c.get("threads_per_ind", 64) == 128),
+            "two_wave_items": sum(1 for c in pick if c.get("threads_per_ind", 64) == 128),
+            "plain_map_items": sum(1 for c in pick if c.get("plain_maps", False)),
             "atoms_mean": float(np.mean([L.n_atoms for L in Ls])),
             "pairs_mean": float(np.mean([L.n_pairs for L in Ls]))}
 
@@ -381,7 +409,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--variants", default="0,1", help="reduction variants to time (0 shuffle, 1 FP32 MFMA, ...)")
+    ap.add_argument("--variants", default="0,1,2,3,4",
+                    help="reduction variants to time (0 shuffle, 1 FP32 MFMA, 2 BF16 split, 3 FP16 split, "
+                         "4 BF16 x3 split); the headline takes the faster of 0 and 1")
+    ap.add_argument("--tpi", default="64,128",
+                    help="threads per individual of the benchmark runs (64: one wave; 128: two waves "
+                         "splitting the pair batches, timed for the FP32 variants)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--uneven-steps", type=int, default=3,
@@ -423,8 +456,9 @@ def main():
     n = gen0.shape[0]
     iters = w.iterations
     evals_per_step = n * (iters + 1)
-    fpe = flops_per_eval(L.n_pairs, L.n_atoms, L.n_torsions)
+    w_eval = work_per_eval(L.n_pairs, L.n_atoms, L.n_torsions)
     variants = [int(v) for v in args.variants.split(",") if v != ""]
+    tpis = [int(t) for t in args.tpi.split(",") if t != ""]
     results = {}
     stream = torch.cuda.current_stream()
     ws = torch.empty(dock.workspace_bytes(1), dtype=torch.uint8, device="cuda")
@@ -437,33 +471,43 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
-    for v in variants:
+    combos = [(v, 64) for v in variants] + [(v, 128) for v in variants if v in (0, 1) and 128 in tpis]
+    for v, tpi in combos:
         states = [dock.LSState.start(gen0) for _ in range(args.warmup + args.steps)]
-        items = [dock.make_items([(G, L, s)]) for s in states]
+        items = [dock.make_items([dock.LsJob(G, L, s, v, threads_per_ind=tpi)]) for s in states]
         torch.cuda.synchronize()
         for k in range(args.warmup):
-            dock.local_search([(G, L, states[k])], iters, variant=v, workspace=ws, items=items[k])
+            dock.local_search([None], iters, workspace=ws, items=items[k])
         torch.cuda.synchronize()
         evs = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
         t0 = time.perf_counter()
         for k in range(args.steps):
-            s = states[args.warmup + k]
             evs[2 * k].record(stream)
-            dock.local_search([(G, L, s)], iters, variant=v, workspace=ws, items=items[args.warmup + k])
+            dock.local_search([None], iters, workspace=ws, items=items[args.warmup + k])
             evs[2 * k + 1].record(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         kms = [evs[2 * k].elapsed_time(evs[2 * k + 1]) for k in range(args.steps)]
         best = states[-1].best_energy.cpu().numpy()
-        results[v] = {"evals_per_s": evals_per_step * args.steps / wall,
-                      "ms_per_step": 1e3 * wall / args.steps,
-                      "kernel_ms_mean": float(np.mean(kms)), "kernel_ms_min": float(np.min(kms)),
-                      "best_energy_median": float(np.median(best))}
+        results[(v, tpi)] = {"evals_per_s": evals_per_step * args.steps / wall,
+                             "ms_per_step": 1e3 * wall / args.steps,
+                             "kernel_ms_mean": float(np.mean(kms)), "kernel_ms_min": float(np.min(kms)),
+                             "best_energy_median": float(np.median(best)), "threads_per_ind": tpi}
         del states, items
 
-    best_v = max(results, key=lambda v: results[v]["evals_per_s"])
-    r = results[best_v]
-    achieved = fpe * evals_per_step / (r["kernel_ms_mean"] * 1e-3) / 1e12
+    def name(key):
+        v, tpi = key
+        return dock.VARIANT_NAMES[v] + ("" if tpi == 64 else f"_t{tpi}")
+
+    # the headline is the fastest FP32 reduction (shuffle or FP32 MFMA, one
+    # or two waves per individual); the half-width split variants are
+    # reported beside it
+    fp32 = [k for k in results if k[0] in (0, 1)] or list(results)
+    best_k = max(fp32, key=lambda k: results[k]["evals_per_s"])
+    best_v = best_k[0]
+    r = results[best_k]
+    for rv in results.values():
+        rv["roofline_frac"] = w_eval * evals_per_step / (rv["kernel_ms_mean"] * 1e-3) / 1e12 / PEAK_TOPS_PACKED
     out = {
         "metric": METRIC,
         "value": r["evals_per_s"],
@@ -480,17 +524,19 @@ def main():
         "config": {"workload": w.name, "individuals": n, "iterations": iters,
                    "evals_per_step": evals_per_step, "atoms": L.n_atoms,
                    "torsions": L.n_torsions, "pairs": L.n_pairs, "grid": "64^3 x 10 maps f32",
-                   "variant": dock.VARIANT_NAMES[best_v]},
-        "variants": {dock.VARIANT_NAMES[v]: {k: round(x, 4) if isinstance(x, float) else x
-                                              for k, x in rv.items()}
-                     for v, rv in results.items()},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": traffic_bytes(),
-                     "flops_per_eval": fpe, "kernel_sha256": kernel_sha256()[:16]},
+                   "variant": dock.VARIANT_NAMES[best_v], "threads_per_ind": best_k[1]},
+        "variants": {name(key): {k: round(x, 4) if isinstance(x, float) else x for k, x in rv.items()}
+                     for key, rv in results.items()},
+        "roofline": roofline(evals_per_step, r["kernel_ms_mean"] * 1e-3, w_eval, traffic_bytes(),
+                             kernel="ls_kernel", kernel_ms_mean=r["kernel_ms_mean"],
+                             kernel_sha256=kernel_sha256()[:16]),
     }
     if args.uneven_steps > 0:
         out["uneven"] = uneven_run(args.uneven_steps, 1, tpi_override=args.uneven_tpi)
+        # every item on one wave with the shuffle reduction: the call is one
+        # persistent launch (the kernel dispatching per item on its atom
+        # layout), against the tuned per-family launches above
+        out["uneven_one_launch"] = uneven_run(args.uneven_steps, 1, use_table=False)
     if args.serve_seconds > 0:
         out["serving"] = serving_run(args.serve_seconds, args.serve_rate, variant=best_v)
     if args.lga_generations > 0:

@@ -12,6 +12,9 @@ Submodules
 dock_ref
     ligand preparation (BFS), genotype -> pose, trilinear grid term,
     intramolecular pair terms, gradient -> genotype, ADADELTA local search.
+work
+    the operation tally of one evaluation: the oracle's own functions run on
+    counting scalars (the algorithmic-work figure beside the work model).
 reduce_ref
     the block sum of 4-vectors {E, gx, gy, gz}: the exactly rounded sum and the
     paper's matrix formulation (Sec. 4.2), plus split-operand helpers.

@@ -69,6 +69,20 @@ class Prepared:
     graph_dist: np.ndarray    # [N, N] bond-graph distance
 
 
+def _norm(v, axis=-1):
+    """Euclidean norm along `axis`, kept as a length-1 axis: sqrt(sum v^2).
+    (The same reduction np.linalg.norm performs, written with plain ufuncs so
+    that the operation tally in oracle.work can run it on counting scalars.)"""
+    return np.sqrt(np.sum(v * v, axis=axis, keepdims=True))
+
+
+def _f64(a):
+    """float64 array of `a`; an object array (the counting scalars of the
+    operation tally in oracle.work) is passed through unchanged."""
+    a = np.asarray(a)
+    return a if a.dtype == object else a.astype(np.float64, copy=False)
+
+
 def _adjacency(n, bonds):
     adj = [[] for _ in range(n)]
     for u, v in bonds:
@@ -95,7 +109,8 @@ def _bfs(adj, start, blocked=None):
 
 
 def prepare(lig, ff) -> Prepared:
-    """Topology of the ligand from its bond tree.
+    """Topology of the ligand from its bond graph (a tree, or a connected
+    graph whose rings lie inside rigid fragments).
 
     Reading (the paper is silent on every item here):
     * torsion k turns the atoms reachable from b_k without crossing the bond,
@@ -119,6 +134,9 @@ def prepare(lig, ff) -> Prepared:
         a, b = (u, v) if root_dist[u] < root_dist[v] else (v, u)
         axis[k] = (a, b)
         moving[k] = _bfs(adj, b, blocked={a, b}) >= 0
+        if moving[k][a]:
+            # a bond in a ring has no side to turn: the torsion is undefined
+            raise ValueError(f"rotatable bond {int(bidx)} ({a}-{b}) lies in a ring")
     depth = np.array([sum(moving[j, axis[k, 1]] for j in range(T) if j != k)
                       for k in range(T)], dtype=np.int64)
     # fragments: BFS over non-rotatable bonds
@@ -175,7 +193,7 @@ def prepare(lig, ff) -> Prepared:
 def quat_matrix(q):
     """Active rotation matrix of the unit quaternion (w, x, y, z); q [..., 4]."""
     w, x, y, z = q[..., 0], q[..., 1], q[..., 2], q[..., 3]
-    R = np.empty(q.shape[:-1] + (3, 3))
+    R = np.empty(q.shape[:-1] + (3, 3), dtype=q.dtype)
     R[..., 0, 0] = 1 - 2 * (y * y + z * z)
     R[..., 0, 1] = 2 * (x * y - w * z)
     R[..., 0, 2] = 2 * (x * z + w * y)
@@ -209,12 +227,12 @@ def internal_coords(prep: Prepared, psi):
     used; this is the same conformation as root-first with current axes.
     """
     n = psi.shape[0]
-    y = np.broadcast_to(prep.y0, (n, prep.n_atoms, 3)).copy()
+    y = np.broadcast_to(prep.y0, (n, prep.n_atoms, 3)).astype(np.result_type(prep.y0, psi))
     for k in torsion_order(prep):
         a, b = prep.axis[k]
         p = y[:, a, :]
         u = y[:, b, :] - p
-        u = u / np.linalg.norm(u, axis=-1, keepdims=True)
+        u = u / _norm(u)
         M = prep.moving[k]
         rel = y[:, M, :] - p[:, None, :]
         y[:, M, :] = rodrigues(rel, u[:, None, :], np.repeat(psi[:, k:k + 1], M.sum(), axis=1)) \
@@ -224,10 +242,10 @@ def internal_coords(prep: Prepared, psi):
 
 def pose(prep: Prepared, genotypes):
     """World coordinates x_i = R(q/|q|) y_i + t; genotypes [n, 7+T] -> [n, N, 3]."""
-    g = np.asarray(genotypes, dtype=np.float64)
+    g = _f64(genotypes)
     t = g[:, 0:3]
     q = g[:, 3:7]
-    qh = q / np.linalg.norm(q, axis=1, keepdims=True)
+    qh = q / _norm(q, axis=1)
     y = internal_coords(prep, g[:, 7:])
     R = quat_matrix(qh)
     return np.einsum('nab,nib->nia', R, y) + t[:, None, :]
@@ -260,8 +278,8 @@ def trilinear(mp, origin, spacing, x):
     u = (xc - lo) / spacing
     c = np.clip(np.floor(u), 0, dims - 2).astype(np.int64)
     f = u - c
-    val = np.zeros(x.shape[:-1])
-    dval = np.zeros(x.shape)
+    val = np.zeros(x.shape[:-1], dtype=x.dtype)
+    dval = np.zeros(x.shape, dtype=x.dtype)
     for dz in (0, 1):
         for dy in (0, 1):
             for dx in (0, 1):
@@ -298,8 +316,8 @@ def inter_terms(prep: Prepared, grd, x):
     M = maps.shape[0]
     e_map, d_map = M - 2, M - 1
     n, N, _ = x.shape
-    e = np.zeros((n, N))
-    g = np.zeros((n, N, 3))
+    e = np.zeros((n, N), dtype=x.dtype)
+    g = np.zeros((n, N, 3), dtype=x.dtype)
     for i in range(N):
         xi = x[:, i, :]
         v, gv = trilinear(maps[int(prep.cls[i])], grd.origin, grd.spacing, xi)
@@ -340,16 +358,26 @@ def pair_energy(r2_raw, r0, eps, hb, qq, dsolv):
     r2 = np.maximum(r2_raw, R2_MIN)
     r = np.sqrt(r2)
     s = r0 / r
-    s2 = s * s
+    # 12-6 on the van der Waals pairs, 12-10 on the hydrogen-bond pairs (each
+    # form evaluated on its own pairs only)
+    hbm = np.broadcast_to(hb, r.shape)
+    vdw = ~hbm
+    epsb = np.broadcast_to(eps, r.shape)
+    e_lj = np.zeros_like(r)
+    de_lj = np.zeros_like(r)
+    sv, ev, rv = s[vdw], epsb[vdw], r[vdw]
+    s2 = sv * sv
+    s6 = s2 * s2 * s2
+    s12 = s6 * s6
+    e_lj[vdw] = ev * (s12 - 2.0 * s6)
+    de_lj[vdw] = ev * (-12.0 * s12 + 12.0 * s6) / rv
+    sh, eh, rh = s[hbm], epsb[hbm], r[hbm]
+    s2 = sh * sh
     s6 = s2 * s2 * s2
     s10 = s6 * s2 * s2
     s12 = s6 * s6
-    e_vdw = eps * (s12 - 2.0 * s6)
-    de_vdw = eps * (-12.0 * s12 + 12.0 * s6) / r
-    e_hb = eps * (5.0 * s12 - 6.0 * s10)
-    de_hb = eps * (-60.0 * s12 + 60.0 * s10) / r
-    e_lj = np.where(hb, e_hb, e_vdw)
-    de_lj = np.where(hb, de_hb, de_vdw)
+    e_lj[hbm] = eh * (5.0 * s12 - 6.0 * s10)
+    de_lj[hbm] = eh * (-60.0 * s12 + 60.0 * s10) / rh
     capped = e_lj > E_CAP
     e_lj = np.where(capped, E_CAP, e_lj)
     de_lj = np.where(capped, 0.0, de_lj)
@@ -376,7 +404,7 @@ def intra_terms(prep: Prepared, x, with_abs: bool = False):
     r2 = np.sum(d * d, axis=-1)
     e, w, *_ = pair_energy(r2, prep.r0, prep.eps, prep.pair_hb, prep.qq, prep.dsolv)
     f = w[..., None] * d                        # dE/dx_j for each pair
-    g = np.zeros((n, N, 3))
+    g = np.zeros((n, N, 3), dtype=x.dtype)
     np.add.at(g, (slice(None), j), f)
     np.add.at(g, (slice(None), i), -f)
     if with_abs:
@@ -428,21 +456,21 @@ def genotype_gradient(prep: Prepared, genotypes, x, g):
     * torsion k: u_k . sum_{i in M_k} (x_i - x_{a_k}) x g_i, with u_k the unit
       world-frame bond direction a_k -> b_k (the torque about the bond).
     """
-    gen = np.asarray(genotypes, dtype=np.float64)
+    gen = _f64(genotypes)
     n = gen.shape[0]
     t = gen[:, 0:3]
     q = gen[:, 3:7]
-    qn = np.linalg.norm(q, axis=1, keepdims=True)
+    qn = _norm(q, axis=1)
     qh = q / qn
-    out = np.zeros((n, 7 + prep.n_torsions))
+    out = np.zeros((n, 7 + prep.n_torsions), dtype=g.dtype)
     out[:, 0:3] = g.sum(axis=1)
     tau = np.cross(x - t[:, None, :], g).sum(axis=1)
-    tq = np.concatenate([np.zeros((n, 1)), tau], axis=1)
+    tq = np.concatenate([np.zeros((n, 1), dtype=tau.dtype), tau], axis=1)
     out[:, 3:7] = 2.0 / qn * quat_mul(tq, qh)
     for k in range(prep.n_torsions):
         a, b = prep.axis[k]
         u = x[:, b, :] - x[:, a, :]
-        u = u / np.linalg.norm(u, axis=-1, keepdims=True)
+        u = u / _norm(u)
         M = prep.moving[k]
         tk = np.cross(x[:, M, :] - x[:, a, None, :], g[:, M, :]).sum(axis=1)
         out[:, 7 + k] = np.sum(u * tk, axis=-1)
@@ -463,7 +491,7 @@ class ScoreResult:
 
 def score(prep: Prepared, grd, genotypes) -> ScoreResult:
     """Energy and analytic gradient of each genotype (one scoring evaluation)."""
-    gen = np.asarray(genotypes, dtype=np.float64)
+    gen = _f64(genotypes)
     x = pose(prep, gen)
     e_in, g_in = inter_terms(prep, grd, x)
     e_ia, g_ia, a_ia = intra_terms(prep, x, with_abs=True)
@@ -510,7 +538,7 @@ def adadelta_step(x, grad, acc_g2, acc_dx2, rho, eps):
     acc_dx2 = rho * acc_dx2 + (1.0 - rho) * dx * dx
     xn = x + dx
     q = xn[:, 3:7]
-    nq = np.linalg.norm(q, axis=1, keepdims=True)
+    nq = _norm(q, axis=1)
     ok = nq[:, 0] >= 1e-6
     xn[ok, 3:7] = q[ok] / nq[ok]
     xn[~ok, 3:7] = x[~ok, 3:7]

@@ -92,3 +92,12 @@ def ga_step(genotypes, energies, cand, coins, cuts, mut_coin, mut_delta,
                     child[g] = np.float32(child[g] + mut_delta[r, k, g])
             out[r, k] = child
     return out, best
+
+
+def select_rows(draws, rate):
+    """Rows that take the local search at `rate` (reading: AutoDock searches
+    each child with probability equal to the local-search rate, Sec. 2.1 for
+    the structure): row r is selected when its uniform draw is below the rate
+    (float32 comparison). Returns the selected rows in increasing order."""
+    d = np.asarray(draws, dtype=np.float32)
+    return np.array([r for r in range(d.shape[0]) if d[r] < np.float32(rate)], dtype=np.int32)

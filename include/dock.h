@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define DOCK_ABI_VERSION 7
+#define DOCK_ABI_VERSION 8
 
 /* status codes */
 #define DOCK_OK            0
@@ -139,12 +139,15 @@ typedef struct {
     int32_t n_atoms;          /* 1 .. DOCK_MAX_ATOMS */
     int32_t n_torsions;       /* 0 .. DOCK_MAX_TORSIONS */
     int32_t root_atom;        /* atom that stays on the fixed side of every torsion */
+    int32_t n_bonds;          /* n_atoms - 1 (a tree) .. 4 n_atoms (rings) */
     const double* xyz;        /* host [n_atoms][3] reference conformation (A) */
     const double* charge;     /* host [n_atoms] partial charges (e) */
     const int32_t* cls;       /* host [n_atoms] classes, < ff->n_classes */
-    const int32_t* bonds;     /* host [n_atoms-1][2]: the bond tree */
+    const int32_t* bonds;     /* host [n_bonds][2]: the bond graph, connected; rings
+                                 stay inside rigid fragments */
     const int32_t* rot_bonds; /* host [n_torsions]: indices into bonds; each an
-                                 internal bond (both ends bonded elsewhere) */
+                                 internal bond (both ends bonded elsewhere) that
+                                 lies in no ring */
     const dock_ff_params* ff; /* host */
 } dock_ligand_desc;
 
@@ -159,13 +162,16 @@ typedef struct {
 } dock_ligand_info;
 
 /* Prepares the ligand on the host (no device call). The preparation orders
- * atoms depth-first from the root (children by increasing index), turns each
- * rotatable bond into a torsion whose moving atoms form one contiguous range
- * of that order, splits the tree into rigid fragments, and keeps the atom
- * pairs that are >= 4 bonds apart and in different fragments. Errors:
- * DOCK_EINVAL if the bonds are not a tree over n_atoms atoms, a rotatable bond
- * is not internal or repeated, or a class is out of range;
- * DOCK_EUNSUPPORTED beyond the build limits. */
+ * atoms depth-first from the root (neighbours by increasing index), turns
+ * each rotatable bond into a torsion whose moving atoms (the side of the bond
+ * away from the root) form one contiguous range of that order, splits the
+ * molecule into rigid fragments (rings stay inside one), and keeps the atom
+ * pairs that are >= 4 bonds apart (shortest path in the bond graph) and in
+ * different fragments. Errors: DOCK_EINVAL if the bonds do not connect the
+ * n_atoms atoms, repeat a bond, or n_bonds is outside [n_atoms - 1,
+ * 4 n_atoms]; a rotatable bond is not internal, lies in a ring or is
+ * repeated; a class is out of range; DOCK_EUNSUPPORTED beyond the build
+ * limits. */
 int32_t dock_create_ligand(const dock_ligand_desc* desc, dock_ligand** out);
 int32_t dock_ligand_info_get(const dock_ligand* lig, dock_ligand_info* out);
 
@@ -252,7 +258,13 @@ typedef struct {
     int32_t* iters_done;         /* device [n] in/out: iterations taken so far */
     float* grad;                 /* device [n][G] out, or NULL: dE/dgenotype at the last
                                     evaluated point */
+    uint32_t flags;              /* DOCK_ITEM_PLAIN_MAPS, or 0 */
 } dock_ls_item;
+
+/* Item flag: read the planar maps even when the grid set has the
+ * corner-expanded copy bound (a layout choice per item, e.g. per size
+ * bucket of a tuning table; the values, and so the results, are the same). */
+#define DOCK_ITEM_PLAIN_MAPS 1u
 
 #define DOCK_LS_FINAL_EVAL 1u    /* evaluate the point reached after the last step */
 
@@ -262,8 +274,9 @@ typedef struct {
     float eps;                   /* conditioner, > 0 (1e-2) */
     int32_t variant;             /* default DOCK_REDUCE_* */
     int32_t threads_per_ind;     /* 0 (= 64), 64 or 128: threads (waves of 64) per
-                                    individual for ligands of 65..128 atoms; smaller
-                                    ligands always take one wave */
+                                    individual; with 128 the two waves split the
+                                    pair batches (and, past 64 atoms, the atoms);
+                                    256 is not built (DOCK_EUNSUPPORTED) */
     uint32_t flags;              /* DOCK_LS_FINAL_EVAL */
 } dock_ls_opts;
 
@@ -274,8 +287,9 @@ int32_t dock_ls_workspace_bytes(int32_t n_items, int64_t* bytes);
  * of every item in one persistent launch; items are scheduled longest first.
  * Items run in up to three kernel families: ligands of <= 64 atoms (one
  * wave per individual), larger ligands with one wave (two atoms per lane) or
- * with two waves per individual (128 threads, each wave owning 64 atoms and
- * half of the pair batches). A batch that mixes families (or both one-wave
+ * any ligand with two waves per individual (128 threads: each wave owns 64
+ * atoms, none for the second wave of a ligand of <= 64 atoms, and half of
+ * the pair batches). A batch that mixes families (or both one-wave
  * families AND reduction variants) runs as one persistent launch per family,
  * side by side: the first on `stream`, the others on streams the library
  * owns (per device), forked from and joined back into `stream` with events,
@@ -427,6 +441,39 @@ typedef struct {
 } dock_ga_step_desc;
 
 int32_t dock_ga_step(const dock_ga_step_desc* desc, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Local search on a share of the population (Sec. 2.1: the LGA improves the
+ * genotypes the GA makes by local search; AutoDock searches each child with
+ * a probability, the local-search rate). The caller draws one uniform number
+ * per row; the rows with a draw below the rate are gathered into a compact
+ * state, searched, and scattered back (the search's best genotypes and
+ * energies replace the rows: Lamarckian write-back).
+ *
+ * dock_select_rows: index_dev[k] = the k-th row r, in increasing order, with
+ * draws_dev[r] < rate (float32 comparison); *count_dev = the number of such
+ * rows. draws_dev [n] float32, index_dev [n] int32 (entries past the count
+ * are left as they were), count_dev [1] int32, device. One block of 1024
+ * threads; deterministic. Errors: DOCK_EINVAL on n < 0, NULL arrays, a NaN
+ * rate or misaligned arrays.
+ * ---------------------------------------------------------------------- */
+int32_t dock_select_rows(const float* draws_dev, int32_t n, float rate, int32_t* index_dev,
+                         int32_t* count_dev, void* stream);
+
+/* dock_gather_rows: dst_dev[k][c] = src_dev[index_dev[k]][c] for k < m and
+ * c < row_floats; src_dev [n_src][row_floats], dst_dev [m][row_floats]
+ * float32, index_dev [m] int32, device. Rows whose index lies outside
+ * [0, n_src) are left unwritten.
+ * dock_scatter_rows: dst_dev[index_dev[k]][c] = src_dev[k][c]; src_dev
+ * [m][row_floats], dst_dev [n_dst][row_floats]; indices outside [0, n_dst)
+ * are skipped; indices must be distinct (else the last write of a row is
+ * unspecified). One thread per element. m == 0 is a no-op. Errors:
+ * DOCK_EINVAL on negative sizes, row_floats < 1, more than 2^31 - 1
+ * elements, NULL or misaligned arrays. */
+int32_t dock_gather_rows(const float* src_dev, int32_t n_src, int32_t row_floats, const int32_t* index_dev,
+                         int32_t m, float* dst_dev, void* stream);
+int32_t dock_scatter_rows(const float* src_dev, int32_t m, int32_t row_floats, const int32_t* index_dev,
+                          int32_t n_dst, float* dst_dev, void* stream);
 
 #ifdef __cplusplus
 }

@@ -2,13 +2,14 @@
 
 Ligands are bucketed by atom count (width 32) and torsion count (width 8).
 For each bucket a representative synthetic ligand is timed with every
-candidate (reduction variant x threads per individual) through the C ABI and
+candidate (reduction variant x threads per individual x grid layout) through
+the C ABI and
 the fastest candidate is stored in a JSON table keyed by GPU architecture and
 bucket. `choose()` reads the table; a persistent launch over ligands of mixed
 sizes then passes each item its bucket's variant and threads per individual
 (items with different thread counts run in separate launches side by side).
-Within a kernel family the buckets share one variant when that costs at
-most 3 % in every bucket (`unify_families`).
+Within a kernel family the buckets share one variant and layout when that
+costs at most 3 % in every bucket (`unify_families`).
 
 Usage: python -m paper_2410_10447_amd.autotune [--out table.json]
 """
@@ -24,7 +25,7 @@ import numpy as np
 TABLE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_gfx950.json")
 ATOM_BUCKET = 32
 TORSION_BUCKET = 8
-DEFAULT = {"variant": 0, "threads_per_ind": 64}
+DEFAULT = {"variant": 0, "threads_per_ind": 64, "plain_maps": False}
 
 
 def bucket(n_atoms: int, n_torsions: int) -> str:
@@ -59,12 +60,16 @@ def choose(n_atoms: int, n_torsions: int, path: str = TABLE_PATH) -> dict:
 
 
 def candidates(n_atoms: int = 64):
-    """Reduction variant x threads per individual; ligands of more than 64
-    atoms may also run with two waves (128 threads) per individual."""
+    """Reduction variant x threads per individual (one wave, or two waves
+    splitting the pair batches and, past 64 atoms, the atoms) x grid layout
+    (the corner-expanded copy, or the planar maps)."""
     from . import dock
-    tpis = (64, 128) if n_atoms > 64 else (64,)
-    return [{"variant": v, "threads_per_ind": b} for b in tpis
-            for v in (dock.REDUCE_SHUFFLE, dock.REDUCE_MFMA_F32)]
+    return [{"variant": v, "threads_per_ind": b, "plain_maps": p} for p in (False, True)
+            for b in (64, 128) for v in (dock.REDUCE_SHUFFLE, dock.REDUCE_MFMA_F32)]
+
+
+def cand_key(c) -> str:
+    return f"v{c['variant']}_b{c['threads_per_ind']}" + ("_plain" if c.get("plain_maps") else "")
 
 
 def time_candidate(G, L, gen, cand, iterations=20, reps=3):
@@ -77,8 +82,9 @@ def time_candidate(G, L, gen, cand, iterations=20, reps=3):
         st = st0.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        dock.local_search([(G, L, st)], iterations, variant=cand["variant"], workspace=ws,
-                          threads_per_ind=cand.get("threads_per_ind", 64))
+        dock.local_search([dock.LsJob(G, L, st, cand["variant"], threads_per_ind=cand.get("threads_per_ind", 64),
+                                      plain_maps=cand.get("plain_maps", False))],
+                          iterations, workspace=ws)
         torch.cuda.synchronize()
         if r:
             times.append(time.perf_counter() - t0)
@@ -102,7 +108,7 @@ def tune(out: str = TABLE_PATH, n_individuals: int = 1024, iterations: int = 20,
         best, rates = None, {}
         for c in candidates(n):
             rate = time_candidate(G, L, gen, c, iterations)
-            rates[f"v{c['variant']}_b{c['threads_per_ind']}"] = rate
+            rates[cand_key(c)] = rate
             if best is None or rate > best[1]:
                 best = (c, rate)
         entry = dict(best[0])
@@ -119,44 +125,50 @@ def tune(out: str = TABLE_PATH, n_individuals: int = 1024, iterations: int = 20,
 
 
 def family(entry) -> str:
-    """Kernel family a bucket's items run in: ligands of <= 64 atoms (one atom
-    per lane), larger ligands in one wave (two per lane) or in two waves."""
-    if entry["atoms"] <= 64:
-        return "one-slot"
-    return "two-wave" if entry["threads_per_ind"] == 128 else "two-slot"
+    """Kernel family a bucket's items run in: two waves per individual, or
+    one wave with one atom per lane (<= 64 atoms) or two (larger ligands)."""
+    if entry["threads_per_ind"] == 128:
+        return "two-wave"
+    return "one-slot" if entry["atoms"] <= 64 else "two-slot"
 
 
 def unify_families(table, tol: float = 0.03):
-    """One reduction variant per kernel family where it costs little.
+    """One reduction variant and grid layout per kernel family where it
+    costs little.
 
-    A launch whose items use different variants runs the kernel that
-    dispatches per item, which holds every variant's registers; one variant
-    per family keeps the specialised kernels. Per family, the variant whose
-    worst relative loss over the family's buckets (against each bucket's best
-    candidate, at the bucket's thread count) is smallest is given to every
-    bucket of the family, if that loss is at most `tol`.
+    A launch whose items use different variants (or layouts) runs the kernel
+    that dispatches per item, which holds every variant's registers; one
+    choice per family keeps the specialised kernels. Per family, the
+    (variant, layout) whose worst relative loss over the family's buckets
+    (against each bucket's best candidate, at the bucket's thread count) is
+    smallest is given to every bucket of the family, if that loss is at most
+    `tol`.
     """
     fams = {}
     for key, e in table["buckets"].items():
         fams.setdefault(family(e), []).append(key)
     for fam, keys in fams.items():
-        best_v, best_loss = None, None
-        for v in sorted({int(k.split("_")[0][1:]) for e in (table["buckets"][k] for k in keys)
-                         for k in e["measured"]}):
+        opts = sorted({(int(k.split("_")[0][1:]), k.endswith("_plain"))
+                       for e in (table["buckets"][k] for k in keys) for k in e["measured"]})
+        best_o, best_loss = None, None
+        for v, plain in opts:
             loss = 0.0
             for key in keys:
                 e = table["buckets"][key]
-                r = e["measured"].get(f"v{v}_b{e['threads_per_ind']}")
+                r = e["measured"].get(cand_key({"variant": v, "threads_per_ind": e["threads_per_ind"],
+                                                "plain_maps": plain}))
                 loss = max(loss, 1.0 if r is None else 1.0 - r / e["evals_per_s"])
             if best_loss is None or loss < best_loss:
-                best_v, best_loss = v, loss
+                best_o, best_loss = (v, plain), loss
         if best_loss is not None and best_loss <= tol:
             for key in keys:
                 e = table["buckets"][key]
-                e["variant"] = best_v
-                e["evals_per_s"] = e["measured"][f"v{best_v}_b{e['threads_per_ind']}"]
-        table.setdefault("families", {})[fam] = {"variant": best_v, "worst_loss": best_loss,
-                                                 "unified": best_loss is not None and best_loss <= tol}
+                e["variant"], e["plain_maps"] = best_o[0], best_o[1]
+                e["evals_per_s"] = e["measured"][cand_key(e)]
+        table.setdefault("families", {})[fam] = {
+            "variant": None if best_o is None else best_o[0],
+            "plain_maps": None if best_o is None else best_o[1],
+            "worst_loss": best_loss, "unified": best_loss is not None and best_loss <= tol}
     return table
 
 

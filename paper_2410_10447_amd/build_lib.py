@@ -1,6 +1,11 @@
 """Build the HIP library libdockmi.so in-tree with hipcc for gfx950.
 
-Usage: python -m paper_2410_10447_amd.build_lib [--jobs N]
+Usage: python -m paper_2410_10447_amd.build_lib [--jobs N] [--sanitized]
+
+--sanitized builds libdockmi_san.so instead: the host code only (ligand
+preparation and the C ABI, with host stand-ins for the kernel launchers,
+csrc/dock_hoststub.cpp) compiled by g++ with AddressSanitizer and UBSan, for
+running the CPU tests of the host code under the sanitizers.
 """
 from __future__ import annotations
 
@@ -16,6 +21,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdockmi.so")
+LIB_SAN = os.path.join(PKG, "libdockmi_san.so")
+SAN_SOURCES = ["dock_abi.cpp", "dock_prep.cpp", "dock_hoststub.cpp"]
 ARCH = "gfx950"
 
 SOURCES = ["dock_kernels.hip", "dock_ga.hip", "dock_static.hip", "dock_abi.cpp", "dock_prep.cpp"]
@@ -57,7 +64,27 @@ def build(jobs: int = 3) -> str:
     return LIB
 
 
+def build_sanitized() -> str:
+    """Host code with -fsanitize=address,undefined (g++, no device code)."""
+    rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+    out_tmp = LIB_SAN + ".tmp"
+    cmd = ["g++", "-O1", "-g", "-std=c++17", "-fPIC", "-shared", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+           "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(rocm, "include"), "-I" + INCLUDE, "-I" + CSRC,
+           *[os.path.join(CSRC, s) for s in SAN_SOURCES],
+           "-L" + os.path.join(rocm, "lib"), "-lamdhip64", "-Wl,-rpath," + os.path.join(rocm, "lib"),
+           "-o", out_tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"sanitized build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(out_tmp, LIB_SAN)
+    return LIB_SAN
+
+
 if __name__ == "__main__":
+    if "--sanitized" in sys.argv:
+        print(build_sanitized())
+        sys.exit(0)
     j = 3
     if "--jobs" in sys.argv:
         j = int(sys.argv[sys.argv.index("--jobs") + 1])

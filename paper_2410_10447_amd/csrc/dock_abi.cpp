@@ -234,10 +234,12 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
         for (void* p : ptrs)
             if (!p || !aligned(p, 4)) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": NULL or misaligned state");
         if (it.grad && !aligned(it.grad, 4)) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": misaligned grad");
+        if ((it.flags & ~DOCK_ITEM_PLAIN_MAPS) != 0) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": unknown flags");
         if (iters == 0 && !fin) continue;  // nothing to do for this item
         docklaunch::DevItem& d = dev[n_dev];
         std::memset(&d, 0, sizeof(d));
         d.grid = it.grids->gp;
+        if (it.flags & DOCK_ITEM_PLAIN_MAPS) d.grid.corners = nullptr;
         d.blob = it.ligand->blob_dev;
         d.genotype = it.genotype;
         d.acc_g2 = it.acc_g2;
@@ -258,7 +260,7 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
         // evaluation: pair batches, atom slots, torsion depth, fixed part)
         cost[n_dev] = (int64_t)(iters + fin) *
                       ((int64_t)H->n_batches * 90 + (int64_t)d.slots * (150 + 20 * P.max_depth) + 500);
-        const int f = d.slots == 1 ? 2 : (tpi == 128 ? 0 : 1);
+        const int f = tpi == 128 ? 0 : (d.slots == 1 ? 2 : 1);
         fam[n_dev] = f;
         any_fam[f] = true;
         var_u = (var_u == -2 || var_u == var) ? var : -1;
@@ -538,8 +540,11 @@ int32_t dock_score_batch(const dock_grids* g, const dock_ligand* l, int32_t n, c
         return fail(DOCK_EINVAL, "dock_score_batch: pointers must be 4-byte aligned");
     float* atom_out = o ? o->atom_out : nullptr;
     if (atom_out && !aligned(atom_out, 16)) return fail(DOCK_EINVAL, "atom_out must be 16-byte aligned");
+    int32_t n_cu = 0;
+    st = device_cu_count(n_cu);
+    if (st != DOCK_OK) return st;
     hipError_t e = docklaunch::launch_score(g->gp, l->blob_dev, l->slots, n, gen, energy, grad, atom_out,
-                                            variant, (hipStream_t)stream);
+                                            variant, n_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "dock_score_batch launch");
     return ok();
 }
@@ -691,6 +696,43 @@ int32_t dock_ga_step(const dock_ga_step_desc* d, void* stream) {
     hipError_t e = docklaunch::launch_ga_step(p, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "dock_ga_step launch");
     return ok();
+}
+
+int32_t dock_select_rows(const float* draws, int32_t n, float rate, int32_t* index, int32_t* count,
+                         void* stream) {
+    if (n < 0) return fail(DOCK_EINVAL, "dock_select_rows: n < 0");
+    if (!count) return fail(DOCK_EINVAL, "dock_select_rows: NULL count");
+    if (n > 0 && (!draws || !index)) return fail(DOCK_EINVAL, "dock_select_rows: NULL draws or index");
+    if (std::isnan(rate)) return fail(DOCK_EINVAL, "dock_select_rows: NaN rate");
+    if (!aligned(count, 4) || (draws && !aligned(draws, 4)) || (index && !aligned(index, 4)))
+        return fail(DOCK_EINVAL, "dock_select_rows: arrays must be 4-byte aligned");
+    hipError_t e = docklaunch::launch_select_rows(draws, n, rate, index, count, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "dock_select_rows launch");
+    return ok();
+}
+
+static int32_t move_rows(bool gather, const float* src, float* dst, const int32_t* index, int32_t m,
+                         int32_t row, int32_t n_rows, void* stream, const char* name) {
+    if (m < 0 || row < 1 || n_rows < 0) return fail(DOCK_EINVAL, std::string(name) + ": bad sizes");
+    if ((long long)m * row > 2147483647LL || (long long)n_rows * row > 2147483647LL)
+        return fail(DOCK_EINVAL, std::string(name) + ": more than 2^31 - 1 elements");
+    if (m == 0) return ok();
+    if (!src || !dst || !index) return fail(DOCK_EINVAL, std::string(name) + ": NULL pointer");
+    if (!aligned(src, 4) || !aligned(dst, 4) || !aligned(index, 4))
+        return fail(DOCK_EINVAL, std::string(name) + ": arrays must be 4-byte aligned");
+    hipError_t e = docklaunch::launch_move_rows(gather, src, dst, index, m, row, n_rows, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, (std::string(name) + " launch").c_str());
+    return ok();
+}
+
+int32_t dock_gather_rows(const float* src, int32_t n_src, int32_t row, const int32_t* index, int32_t m,
+                         float* dst, void* stream) {
+    return move_rows(true, src, dst, index, m, row, n_src, stream, "dock_gather_rows");
+}
+
+int32_t dock_scatter_rows(const float* src, int32_t m, int32_t row, const int32_t* index, int32_t n_dst,
+                          float* dst, void* stream) {
+    return move_rows(false, src, dst, index, m, row, n_dst, stream, "dock_scatter_rows");
 }
 
 }  // extern "C"

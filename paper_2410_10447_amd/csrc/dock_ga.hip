@@ -84,9 +84,84 @@ __global__ __launch_bounds__(256) void ga_child_kernel(docklaunch::GaParams p) {
     p.children[t] = v;
 }
 
+// ---------------------------------------------------------------------------
+// Local search on a share of the children (Sec. 2.1: the LGA improves the
+// GA's genotypes by local search; AutoDock applies it at a rate below one):
+// the rows whose draw is below the rate, in increasing order, then row
+// gathers and scatters between the population and the compact search state.
+// ---------------------------------------------------------------------------
+
+// One block of 1024 threads: thread t owns rows [t * per, (t + 1) * per);
+// per-thread counts, an exclusive scan over the block (wave scans, then the
+// 16 wave totals), then each thread writes its selected rows in order.
+__global__ __launch_bounds__(1024) void select_rows_kernel(const float* __restrict__ draws, int n, float rate,
+                                                           int32_t* __restrict__ index,
+                                                           int32_t* __restrict__ count) {
+    __shared__ int wave_tot[16];
+    const int t = (int)threadIdx.x;
+    const int per = (int)(((long long)n + 1023) / 1024);
+    const long long lo_l = (long long)t * per;
+    const int lo = (int)(lo_l < n ? lo_l : n);
+    const int hi = (int)(lo_l + per < n ? lo_l + per : n);
+    int c = 0;
+    for (int r = lo; r < hi; ++r) c += draws[r] < rate ? 1 : 0;
+    // inclusive scan within the wave
+    const int lane = t & 63, w = t >> 6;
+    int incl = c;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) wave_tot[w] = incl;
+    __syncthreads();
+    int before = 0;
+    for (int v = 0; v < w; ++v) before += wave_tot[v];
+    int pos = before + incl - c;
+    for (int r = lo; r < hi; ++r)
+        if (draws[r] < rate) index[pos++] = r;
+    if (t == 1023) count[0] = before + incl;
+}
+
+// dst[k][c] = src[index[k]][c] (gather) or dst[index[k]][c] = src[k][c]
+// (scatter), one thread per element; indices outside [0, n_rows) of the
+// indexed side are skipped.
+template <bool GATHER>
+__global__ __launch_bounds__(256) void move_rows_kernel(const float* __restrict__ src, float* __restrict__ dst,
+                                                        const int32_t* __restrict__ index, int m, int row,
+                                                        int n_rows) {
+    const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (e >= (long long)m * row) return;
+    const int k = (int)(e / row), c = (int)(e - (long long)k * row);
+    const int r = index[k];
+    if (r < 0 || r >= n_rows) return;
+    if (GATHER)
+        dst[e] = src[(size_t)r * row + c];
+    else
+        dst[(size_t)r * row + c] = src[e];
+}
+
 }  // namespace
 
 namespace docklaunch {
+
+hipError_t launch_select_rows(const float* draws, int n, float rate, int32_t* index, int32_t* count,
+                              hipStream_t stream) {
+    hipLaunchKernelGGL(select_rows_kernel, dim3(1), dim3(1024), 0, stream, draws, n, rate, index, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_move_rows(bool gather, const float* src, float* dst, const int32_t* index, int m, int row,
+                            int n_rows, hipStream_t stream) {
+    const long long total = (long long)m * row;
+    if (total <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((total + 255) / 256);
+    if (gather)
+        hipLaunchKernelGGL(move_rows_kernel<true>, dim3(blocks), dim3(256), 0, stream, src, dst, index, m, row, n_rows);
+    else
+        hipLaunchKernelGGL(move_rows_kernel<false>, dim3(blocks), dim3(256), 0, stream, src, dst, index, m, row, n_rows);
+    return hipGetLastError();
+}
 
 hipError_t launch_ga_step(const GaParams& p, hipStream_t stream) {
     hipLaunchKernelGGL(ga_best_kernel, dim3((unsigned)p.n_runs), dim3(256), 0, stream, p.energies, p.pop, p.best);

@@ -693,25 +693,63 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
     // phase several times slower.)
     if constexpr (!GRAD) {
         // energies only (a search that needs no gradient): each lane sums its
-        // pairs' energies from the positions, records loaded two batches
-        // ahead; no accumulators, no force
+        // pairs' energies from the positions, in batch order; no
+        // accumulators, no force. Software pipeline: step k reads the
+        // positions of batch k + 1 from LDS before computing batch k, and
+        // loads the record of batch k + 4 (records live four steps, positions
+        // two; register sets indexed by k mod 4 and mod 2, steps unrolled by
+        // four). Prefetch indices are clamped to the last batch.
         static_assert(WAVES == 1, "the energy-only evaluation is one wave per individual");
-#pragma unroll
-        for (int s = 0; s < SLOTS; ++s) grid_load<ANY_LAYOUT>(G, L.cls[s], x[s], tv, tap[s]);
         const int nb = L.n_batches;
         const int pmask = L.pmask;
-        const auto plist = gmem(L.plist);
-        auto record = [&](int b) -> u32x4 { return plist[uniform(min(b, nb - 1)) * kWave + lane]; };
+        auto pos_i = [&](uint32_t w) { return *slot(sm.dyn, w & pmask); };
+        auto pos_j = [&](uint32_t w) { return *slot(sm.dyn, (w >> dockblob::kSlotShift) & pmask); };
         if (nb > 0) {
-            u32x4 r0 = record(0), r1 = record(1);
-            for (int k = 0; k < nb; ++k) {
-                const u32x4 rc = r0;
-                r0 = r1;
-                r1 = record(k + 2);
-                const float4 pi = *slot(sm.dyn, rc.x & pmask);
-                const float4 pj = *slot(sm.dyn, (rc.x >> dockblob::kSlotShift) & pmask);
-                e_lane += pair_force(rc, pi, pj).e;
-            }
+            const __amdgpu_buffer_rsrc_t prsrc = __builtin_amdgcn_make_buffer_rsrc(
+                const_cast<u32x4*>(L.plist), 0, nb * kWave * (int)sizeof(u32x4), kBufferWord3);
+            const int lane_off = lane * (int)sizeof(u32x4);
+            auto record = [&](int b) -> u32x4 {
+                return __builtin_amdgcn_raw_buffer_load_b128(
+                    prsrc, lane_off, uniform(min(b, nb - 1)) * kWave * (int)sizeof(u32x4), 0);
+            };
+            u32x4 R[4];
+            float4 Pi[2], Pj[2];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) R[q] = record(q);
+            Pi[0] = pos_i(R[0].x);
+            Pj[0] = pos_j(R[0].x);
+            int k = 0;
+            auto step = [&](auto residue, auto load) {
+                constexpr int r = decltype(residue)::value;  // k mod 4
+                constexpr int c = r & 1, n = (r + 1) & 1;
+                const u32x4 rn = R[(r + 1) & 3];
+                Pi[n] = pos_i(rn.x);
+                Pj[n] = pos_j(rn.x);
+                __builtin_amdgcn_sched_barrier(0);   // keep the position reads at the step's start
+                e_lane += pair_force(R[r], Pi[c], Pj[c]).e;
+                if constexpr (decltype(load)::value != 0) R[r] = record(k + 4);
+                __builtin_amdgcn_sched_barrier(0);
+                ++k;
+            };
+            using I0 = IntC<0>;
+            using I1 = IntC<1>;
+            using I2 = IntC<2>;
+            using I3 = IntC<3>;
+            using Load = IntC<1>;
+            using NoLoad = IntC<0>;
+            while (k + 4 <= nb) { step(I0(), Load()); step(I1(), Load()); step(I2(), Load()); step(I3(), Load()); }
+            // the grid-map loads follow the last record load (global loads
+            // complete in order)
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) grid_load<ANY_LAYOUT>(G, L.cls[s], x[s], tv, tap[s]);
+            __builtin_amdgcn_sched_barrier(0);
+            if (k < nb) step(I0(), NoLoad());
+            if (k < nb) step(I1(), NoLoad());
+            if (k < nb) step(I2(), NoLoad());
+        } else {
+#pragma unroll
+            for (int s = 0; s < SLOTS; ++s) grid_load<ANY_LAYOUT>(G, L.cls[s], x[s], tv, tap[s]);
         }
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) g[s][0] = g[s][1] = g[s][2] = 0.f;
@@ -969,7 +1007,12 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
 // Kernels.
 // ---------------------------------------------------------------------------
 
-template <int SLOTS, int VAR>
+// Persistent scoring kernel: each wave loads the ligand once (LDS tables and
+// per-lane registers) and evaluates genotypes ind = blockIdx.x,
+// blockIdx.x + gridDim.x, ... (independent evaluations, so a static stride
+// gives the same results as any other assignment). ANY_LAYOUT: the maps may
+// be plain or corner-expanded; otherwise the corner-expanded copy is bound.
+template <int SLOTS, int VAR, bool ANY_LAYOUT>
 __global__ __launch_bounds__(64, (SLOTS == 1 ? 3 : 2)) void score_kernel(GridParams G, const uint8_t* __restrict__ blob,
                                                    int n, const float* __restrict__ gen,
                                                    float* __restrict__ energy,
@@ -979,14 +1022,15 @@ __global__ __launch_bounds__(64, (SLOTS == 1 ? 3 : 2)) void score_kernel(GridPar
     Lig<SLOTS> L;
     load_ligand<SLOTS>(blob, sm, L);
     const int lane = lane_id();
-    const int ind = blockIdx.x;
-    if (ind >= n) return;
-    const float gene = lane < L.G ? gen[(size_t)ind * L.G + lane] : 0.f;
-    float gr;
-    float* ao = atom_out ? atom_out + (size_t)ind * L.N * 8 : nullptr;
-    const float E = evaluate<SLOTS, VAR>(G, sm, L, gene, gr, ao);
-    if (lane == 0) energy[ind] = E;
-    if (grad && lane < L.G) grad[(size_t)ind * L.G + lane] = gr;
+    const int G_ = L.G;
+    for (int ind = blockIdx.x; ind < n; ind += gridDim.x) {
+        const float gene = lane < G_ ? gen[(size_t)ind * G_ + lane] : 0.f;
+        float gr;
+        float* ao = atom_out ? atom_out + (size_t)ind * L.N * 8 : nullptr;
+        const float E = evaluate<SLOTS, VAR, 1, ANY_LAYOUT>(G, sm, L, gene, gr, ao);
+        if (lane == 0) energy[ind] = E;
+        if (grad && lane < G_) grad[(size_t)ind * G_ + lane] = gr;
+    }
 }
 
 // Solis-Wets random search (Sec. 2.1: the LGA's second local search; the
@@ -1322,15 +1366,30 @@ __global__ __launch_bounds__(1024) void block_sum4_atomic_kernel(const float4* _
     out[idx] = tot;
 }
 
+template <int SLOTS, int VAR, bool ANY>
+hipError_t launch_score_k(const GridParams& g, const uint8_t* blob, int n, const float* gen, float* energy,
+                          float* grad, float* atom_out, int n_cu, hipStream_t st) {
+    auto k = score_kernel<SLOTS, VAR, ANY>;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), 64, 0) != hipSuccess ||
+        per_cu <= 0)
+        per_cu = 2;
+    const long long resident = (long long)per_cu * (n_cu > 0 ? n_cu : 256);
+    const int blocks = (int)(n < resident ? n : resident);
+    hipLaunchKernelGGL(k, dim3(blocks), dim3(64), 0, st, g, blob, n, gen, energy, grad, atom_out);
+    return hipGetLastError();
+}
+
 template <int VAR>
 hipError_t launch_score_v(const GridParams& g, const uint8_t* blob, int slots, int n,
-                          const float* gen, float* energy, float* grad, float* atom_out,
+                          const float* gen, float* energy, float* grad, float* atom_out, int n_cu,
                           hipStream_t st) {
+    const bool any = g.corners == nullptr;
     if (slots == 1)
-        hipLaunchKernelGGL((score_kernel<1, VAR>), dim3(n), dim3(64), 0, st, g, blob, n, gen, energy, grad, atom_out);
-    else
-        hipLaunchKernelGGL((score_kernel<2, VAR>), dim3(n), dim3(64), 0, st, g, blob, n, gen, energy, grad, atom_out);
-    return hipGetLastError();
+        return any ? launch_score_k<1, VAR, true>(g, blob, n, gen, energy, grad, atom_out, n_cu, st)
+                   : launch_score_k<1, VAR, false>(g, blob, n, gen, energy, grad, atom_out, n_cu, st);
+    return any ? launch_score_k<2, VAR, true>(g, blob, n, gen, energy, grad, atom_out, n_cu, st)
+               : launch_score_k<2, VAR, false>(g, blob, n, gen, energy, grad, atom_out, n_cu, st);
 }
 
 template <int VAR>
@@ -1379,13 +1438,13 @@ namespace docklaunch {
 
 hipError_t launch_score(const GridParams& g, const uint8_t* blob, int slots, int n,
                         const float* genotypes, float* energy, float* grad, float* atom_out,
-                        int variant, hipStream_t stream) {
+                        int variant, int n_cu, hipStream_t stream) {
     switch (variant) {
-        case DOCK_REDUCE_SHUFFLE: return launch_score_v<0>(g, blob, slots, n, genotypes, energy, grad, atom_out, stream);
-        case DOCK_REDUCE_MFMA_F32: return launch_score_v<1>(g, blob, slots, n, genotypes, energy, grad, atom_out, stream);
-        case DOCK_REDUCE_MFMA_BF16: return launch_score_v<2>(g, blob, slots, n, genotypes, energy, grad, atom_out, stream);
-        case DOCK_REDUCE_MFMA_F16: return launch_score_v<3>(g, blob, slots, n, genotypes, energy, grad, atom_out, stream);
-        case DOCK_REDUCE_MFMA_BF16X3: return launch_score_v<4>(g, blob, slots, n, genotypes, energy, grad, atom_out, stream);
+        case DOCK_REDUCE_SHUFFLE: return launch_score_v<0>(g, blob, slots, n, genotypes, energy, grad, atom_out, n_cu, stream);
+        case DOCK_REDUCE_MFMA_F32: return launch_score_v<1>(g, blob, slots, n, genotypes, energy, grad, atom_out, n_cu, stream);
+        case DOCK_REDUCE_MFMA_BF16: return launch_score_v<2>(g, blob, slots, n, genotypes, energy, grad, atom_out, n_cu, stream);
+        case DOCK_REDUCE_MFMA_F16: return launch_score_v<3>(g, blob, slots, n, genotypes, energy, grad, atom_out, n_cu, stream);
+        case DOCK_REDUCE_MFMA_BF16X3: return launch_score_v<4>(g, blob, slots, n, genotypes, energy, grad, atom_out, n_cu, stream);
         default: return hipErrorInvalidValue;
     }
 }

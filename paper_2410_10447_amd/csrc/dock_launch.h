@@ -57,9 +57,11 @@ enum LsMode { kSlots1 = 1, kSlots2 = 2, kSlotsAny = 3, kTwoWave = 4 };
 
 inline int ls_block_threads(int mode) { return mode == kTwoWave ? 128 : 64; }
 
+// Persistent: at most the resident blocks of n_cu CUs, each looping over
+// genotypes with a stride of the grid size.
 hipError_t launch_score(const GridParams& g, const uint8_t* blob, int slots, int n,
                         const float* genotypes, float* energy, float* grad, float* atom_out,
-                        int variant, hipStream_t stream);
+                        int variant, int n_cu, hipStream_t stream);
 
 // variant_uniform: DOCK_REDUCE_* when every item uses it, -1 for mixed items.
 hipError_t launch_ls(const LsParams& p, int mode, int variant_uniform, int grid_blocks,
@@ -109,6 +111,14 @@ struct GaParams {
 };
 
 hipError_t launch_ga_step(const GaParams& p, hipStream_t stream);
+
+// Rows with draws[r] < rate, in increasing order, and their count (one block).
+hipError_t launch_select_rows(const float* draws, int n, float rate, int32_t* index, int32_t* count,
+                              hipStream_t stream);
+// Gather (dst[k] = src[index[k]]) or scatter (dst[index[k]] = src[k]) of m
+// rows of `row` floats; n_rows bounds the indexed side.
+hipError_t launch_move_rows(bool gather, const float* src, float* dst, const int32_t* index, int m, int row,
+                            int n_rows, hipStream_t stream);
 
 // Library-resident workspace (dock_local_search_batch_static): its size in
 // bytes, and its device address on the current device (looked up once per

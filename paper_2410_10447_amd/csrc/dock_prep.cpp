@@ -445,9 +445,13 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
             err = "non-finite coordinate or charge"; return DOCK_EINVAL;
         }
     }
-    // adjacency of the bond tree
+    // adjacency of the bond graph (a tree, or a connected graph with rings)
+    const int NB = d.n_bonds;
+    if (N > 1 && (NB < N - 1 || NB > 4 * N)) {
+        err = "n_bonds must be in [n_atoms - 1, 4 n_atoms]"; return DOCK_EINVAL;
+    }
     std::vector<std::vector<int>> adj(N);
-    for (int e = 0; e < N - 1; ++e) {
+    for (int e = 0; e < NB; ++e) {
         int u = d.bonds[2 * e], v = d.bonds[2 * e + 1];
         if (u < 0 || v < 0 || u >= N || v >= N || u == v) { err = "bond endpoint out of range"; return DOCK_EINVAL; }
         adj[u].push_back(v);
@@ -457,37 +461,65 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
         std::sort(a.begin(), a.end());
         if (std::adjacent_find(a.begin(), a.end()) != a.end()) { err = "duplicate bond"; return DOCK_EINVAL; }
     }
-    // depth-first preorder from the root, children by increasing index
+    // depth-first preorder from the root, neighbours by increasing index; the
+    // depth-first tree keeps every subtree contiguous in the order, and a
+    // rotatable bond (a bridge of the graph, checked below) is a tree edge
+    // whose subtree is exactly the side it moves
     std::vector<int> parent(N, -2), depth(N, 0), order;
     order.reserve(N);
-    std::vector<int> stack{d.root_atom};
-    parent[d.root_atom] = -1;
-    while (!stack.empty()) {
-        int u = stack.back();
-        stack.pop_back();
-        order.push_back(u);
-        for (auto it = adj[u].rbegin(); it != adj[u].rend(); ++it) {
-            int v = *it;
-            if (v == parent[u]) continue;
-            if (parent[v] != -2) { err = "bonds contain a cycle"; return DOCK_EINVAL; }
+    {
+        std::vector<std::pair<int, size_t>> stack{{d.root_atom, 0}};
+        parent[d.root_atom] = -1;
+        order.push_back(d.root_atom);
+        while (!stack.empty()) {
+            auto& top = stack.back();
+            const int u = top.first;
+            if (top.second == adj[u].size()) { stack.pop_back(); continue; }
+            const int v = adj[u][top.second++];
+            if (parent[v] != -2) continue;
             parent[v] = u;
             depth[v] = depth[u] + 1;
-            stack.push_back(v);
+            order.push_back(v);
+            stack.push_back({v, 0});
         }
     }
     if ((int)order.size() != N) { err = "bonds do not connect every atom"; return DOCK_EINVAL; }
     std::vector<int> pos(N), size(N, 1);
     for (int p = 0; p < N; ++p) pos[order[p]] = p;
     for (int p = N - 1; p > 0; --p) size[parent[order[p]]] += size[order[p]];
+    // bond-graph distances (breadth-first from every atom; rings make them
+    // shorter than depth-first tree paths)
+    std::vector<int> gdist(size_t(N) * N, -1);
+    {
+        std::vector<int> queue(N);
+        for (int s0 = 0; s0 < N; ++s0) {
+            int* dist = &gdist[size_t(s0) * N];
+            int head = 0, tail = 0;
+            dist[s0] = 0;
+            queue[tail++] = s0;
+            while (head < tail) {
+                const int u = queue[head++];
+                for (int v : adj[u])
+                    if (dist[v] < 0) { dist[v] = dist[u] + 1; queue[tail++] = v; }
+            }
+        }
+    }
 
     // torsions
     std::vector<int> tor_a(T), tor_b(T), tor_of_b(N, -1);
     for (int k = 0; k < T; ++k) {
         int e = d.rot_bonds[k];
-        if (e < 0 || e >= N - 1) { err = "rotatable bond index out of range"; return DOCK_EINVAL; }
+        if (e < 0 || e >= NB) { err = "rotatable bond index out of range"; return DOCK_EINVAL; }
         int u = d.bonds[2 * e], v = d.bonds[2 * e + 1];
+        if (parent[v] != u && parent[u] != v) { err = "rotatable bond lies in a ring"; return DOCK_EINVAL; }
         int a = (parent[v] == u) ? u : v;
         int b = (a == u) ? v : u;
+        // a tree edge is a bridge iff no non-tree bond leaves b's subtree
+        for (int p = pos[b]; p < pos[b] + size[b]; ++p)
+            for (int w : adj[order[p]]) {
+                const bool inside = pos[w] >= pos[b] && pos[w] < pos[b] + size[b];
+                if (!inside && !(order[p] == b && w == a)) { err = "rotatable bond lies in a ring"; return DOCK_EINVAL; }
+            }
         if (adj[a].size() < 2 || adj[b].size() < 2) { err = "rotatable bond is not internal"; return DOCK_EINVAL; }
         if (tor_of_b[b] >= 0) { err = "rotatable bond listed twice"; return DOCK_EINVAL; }
         tor_a[k] = a;
@@ -512,14 +544,7 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
         chain[k + 1].push_back(k);
         max_depth = std::max(max_depth, (int)chain[k + 1].size());
     }
-    // kept pairs (original indices) and their hydrogen-bond flag
-    auto graph_dist = [&](int i, int j) {
-        int a = i, b = j, da = depth[i], db = depth[j];
-        while (da > db) { a = parent[a]; --da; }
-        while (db > da) { b = parent[b]; --db; }
-        while (a != b) { a = parent[a]; b = parent[b]; --da; }
-        return depth[i] + depth[j] - 2 * da;
-    };
+    auto graph_dist = [&](int i, int j) { return gdist[size_t(i) * N + j]; };
     // kept pairs in depth-first positions (p < q), with their 12-10 table index
     struct KeptPair { int p, q, hb, table; };
     std::vector<KeptPair> plist;

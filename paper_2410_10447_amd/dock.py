@@ -13,10 +13,13 @@ from dataclasses import dataclass
 
 import numpy as np
 
-_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdockmi.so")
+# DOCKMI_LIB names another build of the same ABI (the sanitizer build of
+# the host code, libdockmi_san.so, for the CPU tests under ASan/UBSan)
+_LIB_PATH = os.environ.get("DOCKMI_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                         "libdockmi.so")
 
 # the struct layouts below follow include/dock.h of this ABI version
-ABI_VERSION = 7
+ABI_VERSION = 8
 
 DOCK_OK = 0
 DOCK_EINVAL = -1
@@ -34,6 +37,7 @@ VARIANT_NAMES = {0: "shuffle", 1: "mfma_f32", 2: "mfma_bf16", 3: "mfma_f16", 4: 
                  5: "shared_atomic"}
 
 LS_FINAL_EVAL = 1
+ITEM_PLAIN_MAPS = 1     # dock_ls_item.flags: read the planar maps
 STATIC_MAX_ITEMS = 64   # items per dock_local_search_batch_static call
 
 MAX_ATOMS = 128
@@ -45,6 +49,7 @@ ABI_SYMBOLS = (
     "dock_grids_corner_bytes", "dock_grids_bind_corners",
     "dock_create_ligand", "dock_ligand_info_get", "dock_ligand_export", "dock_ligand_upload",
     "dock_destroy_ligand", "dock_score_batch", "dock_ls_workspace_bytes",
+    "dock_select_rows", "dock_gather_rows", "dock_scatter_rows",
     "dock_local_search_batch", "dock_local_search_batch_static", "dock_block_sum4", "dock_ga_step", "dock_solis_wets_batch",
 )
 
@@ -70,7 +75,7 @@ class FFParams(C.Structure):
 
 class LigandDesc(C.Structure):
     _fields_ = [("n_atoms", C.c_int32), ("n_torsions", C.c_int32), ("root_atom", C.c_int32),
-                ("xyz", C.POINTER(C.c_double)), ("charge", C.POINTER(C.c_double)),
+                ("n_bonds", C.c_int32), ("xyz", C.POINTER(C.c_double)), ("charge", C.POINTER(C.c_double)),
                 ("cls", C.POINTER(C.c_int32)), ("bonds", C.POINTER(C.c_int32)),
                 ("rot_bonds", C.POINTER(C.c_int32)), ("ff", C.POINTER(FFParams))]
 
@@ -92,7 +97,8 @@ class LsItem(C.Structure):
                 ("threads_per_ind", C.c_int32),
                 ("genotype", C.c_void_p), ("acc_g2", C.c_void_p), ("acc_dx2", C.c_void_p),
                 ("best_genotype", C.c_void_p), ("best_energy", C.c_void_p),
-                ("energy", C.c_void_p), ("iters_done", C.c_void_p), ("grad", C.c_void_p)]
+                ("energy", C.c_void_p), ("iters_done", C.c_void_p), ("grad", C.c_void_p),
+                ("flags", C.c_uint32)]
 
 
 class LsOpts(C.Structure):
@@ -145,6 +151,9 @@ def lib():
         "dock_local_search_batch_static": ([C.POINTER(LsItem), i32, C.POINTER(LsOpts), vp], i32),
         "dock_block_sum4": ([vp, vp, i32, i32, i32, i32, vp], i32),
         "dock_ga_step": ([C.POINTER(GaStepDesc), vp], i32),
+        "dock_select_rows": ([vp, i32, C.c_float, vp, vp, vp], i32),
+        "dock_gather_rows": ([vp, i32, i32, vp, i32, vp, vp], i32),
+        "dock_scatter_rows": ([vp, i32, i32, vp, i32, vp, vp], i32),
         "dock_solis_wets_batch": ([vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, C.POINTER(SwOpts), vp, vp], i32),
     }
     for name, (args, res) in sig.items():
@@ -281,7 +290,8 @@ def ff_params(ff):
 
 
 class Ligand:
-    """Prepared ligand. `lig` has xyz, charge, cls, bonds, rot_bonds, root."""
+    """Prepared ligand. `lig` has xyz, charge, cls, bonds ([n_bonds, 2]: a tree
+    or a connected graph with rings), rot_bonds (indices into bonds), root."""
 
     def __init__(self, lig, ff, upload: bool = True, device="cuda"):
         xyz = np.ascontiguousarray(lig.xyz, dtype=np.float64)
@@ -294,6 +304,7 @@ class Ligand:
         d.n_atoms = xyz.shape[0]
         d.n_torsions = rot.shape[0]
         d.root_atom = int(getattr(lig, "root", 0))
+        d.n_bonds = bonds.shape[0]
         d.xyz = _dptr(xyz, C.c_double)
         d.charge = _dptr(chg, C.c_double)
         d.cls = _dptr(cls, C.c_int32)
@@ -441,7 +452,8 @@ class LsJob:
     iterations: int = -1
     final_eval: int = -1
     grad: object = None          # optional [n, G] CUDA tensor: gradient at the last evaluated point
-    threads_per_ind: int = 0     # 64 or 128 (ligands of 65..128 atoms), 0 defers to the call
+    threads_per_ind: int = 0     # 64 or 128, 0 defers to the call
+    plain_maps: bool = False     # read the planar maps even with the corner copy bound
 
 
 def _as_job(job):
@@ -482,6 +494,7 @@ def make_items(jobs):
         it.energy = st.energy.data_ptr()
         it.iters_done = st.iters_done.data_ptr()
         it.grad = j.grad.data_ptr() if j.grad is not None else None
+        it.flags = ITEM_PLAIN_MAPS if j.plain_maps else 0
     return arr
 
 
@@ -568,6 +581,56 @@ def ga_step(genotypes, energies, candidates, coins, cuts, mut_coin, mut_delta,
                    R, P, G, float(p_tournament), float(p_crossover), float(p_mutation), int(bool(elitism)))
     _check(lib().dock_ga_step(C.byref(d), _stream_handle(stream)))
     return children, best
+
+
+def select_rows(draws, rate: float, index=None, count=None, stream=None):
+    """Rows with draws[r] < rate, increasing (dock_select_rows): returns
+    (index [n] int32, count [1] int32), CUDA tensors; index[:count] holds
+    the rows."""
+    import torch
+    n = draws.shape[0]
+    d = draws.contiguous()
+    _need("draws", d, (n,), torch.float32)
+    if index is None:
+        index = torch.empty(max(n, 1), dtype=torch.int32, device=d.device)
+    if count is None:
+        count = torch.empty(1, dtype=torch.int32, device=d.device)
+    _need("index", index, (max(n, 1),), torch.int32, d.device)
+    _need("count", count, (1,), torch.int32, d.device)
+    _check(lib().dock_select_rows(_ptr(d), n, float(rate), _ptr(index), _ptr(count), _stream_handle(stream)))
+    return index, count
+
+
+def _rows(t):
+    return t.shape[0], (int(np.prod(t.shape[1:])) if t.dim() > 1 else 1)
+
+
+def gather_rows(src, index, m: int, stream=None):
+    """dst[k] = src[index[k]] for k < m (dock_gather_rows); src [n, ...] float32."""
+    import torch
+    s = src.contiguous()
+    if s.dtype != torch.float32:
+        raise ValueError("src must be float32")
+    n, row = _rows(s)
+    if index.dtype != torch.int32 or not index.is_contiguous() or index.shape[0] < m:
+        raise ValueError("index must be a contiguous int32 tensor of at least m entries")
+    dst = torch.empty((m,) + tuple(s.shape[1:]), dtype=torch.float32, device=s.device)
+    _check(lib().dock_gather_rows(_ptr(s), n, row, _ptr(index), m, _ptr(dst), _stream_handle(stream)))
+    return dst
+
+
+def scatter_rows(src, index, dst, stream=None):
+    """dst[index[k]] = src[k] for k < len(src), in place (dock_scatter_rows)."""
+    import torch
+    s = src.contiguous()
+    m, row = _rows(s)
+    n, row_d = _rows(dst)
+    if s.dtype != torch.float32 or dst.dtype != torch.float32 or row != row_d or not dst.is_contiguous():
+        raise ValueError("src and dst must be float32 with rows of the same size (dst contiguous)")
+    if index.dtype != torch.int32 or not index.is_contiguous() or index.shape[0] < m:
+        raise ValueError("index must be a contiguous int32 tensor of at least len(src) entries")
+    _check(lib().dock_scatter_rows(_ptr(s), m, row, _ptr(index), n, _ptr(dst), _stream_handle(stream)))
+    return dst
 
 
 def ga_draws(n_runs: int, pop: int, n_genes: int, generator, device,

@@ -11,7 +11,8 @@ problem (Sec. 2.1: a ligand with N_rot rotatable bonds against fixed receptor
 grids):
 
 * ligand: a random tree of atoms with 1.5 A bonds, 8 atom classes, Gaussian
-  partial charges, rotatable bonds picked among internal bonds;
+  partial charges, rotatable bonds picked among internal bonds; or a ligand
+  with planar rings (ring_ligand) joined by single bonds;
 * force-field table: per-class radius, well depth, solvation and volume, and
   a donor x acceptor hydrogen-bond table (synthetic ranges, seed 7);
 * grids: one map per atom type plus an electrostatic and a desolvation map,
@@ -42,7 +43,7 @@ class Ligand:
     xyz: np.ndarray        # float64 [N, 3], reference conformation (A)
     charge: np.ndarray     # float64 [N], partial charges (e)
     cls: np.ndarray        # int32 [N], atom class in [0, 8)
-    bonds: np.ndarray      # int32 [N-1, 2], (parent, child) tree edges
+    bonds: np.ndarray      # int32 [n_bonds, 2]: tree edges (parent, child), plus ring bonds
     rot_bonds: np.ndarray  # int32 [T], indices into `bonds`
     root: int = 0
     seed: int = 0
@@ -144,6 +145,106 @@ def ligand(n_atoms: int, n_torsions: int, seed: int) -> Ligand:
     xyz -= xyz.mean(axis=0)
     bonds = np.array(bonds, dtype=np.int32).reshape(-1, 2)
     internal = [b for b, (u, v) in enumerate(bonds) if degree[u] >= 2 and degree[v] >= 2]
+    t_eff = min(n_torsions, len(internal))
+    if t_eff > 0:
+        rot = np.sort(rng.choice(np.array(internal), size=t_eff, replace=False)).astype(np.int32)
+    else:
+        rot = np.zeros(0, dtype=np.int32)
+    cls = rng.integers(0, N_CLASSES, n_atoms).astype(np.int32)
+    charge = rng.normal(0.0, 0.2, n_atoms)
+    return Ligand(xyz=xyz, charge=charge, cls=cls, bonds=bonds, rot_bonds=rot,
+                  root=0, seed=seed, n_torsions_requested=n_torsions)
+
+
+RING_BOND = 1.4
+
+
+def ring_ligand(n_rings: int, n_chain: int, n_torsions: int, seed: int, ring_size: int = 6) -> Ligand:
+    """Ligand of planar rings (regular polygons with 1.4 A edges) and chain
+    atoms, joined by 1.5 A single bonds into a connected graph whose rings
+    stay inside rigid fragments.
+
+    Units (a ring or one chain atom, in a seeded random order) are attached
+    one at a time by a single bond to an atom with a free valence (ring atoms
+    take one substituent, chain atoms up to four bonds): from a ring atom the
+    bond points away from its ring's centre in the ring plane, from a chain
+    atom in a uniform direction; a new ring lies in a random plane containing
+    the bond, its attaching atom on the bond. A placement is redrawn (up to
+    200 times) until every new atom is at least 2.0 A from every existing
+    atom except the one it bonds to. Rotatable bonds are drawn among the
+    single bonds between units with both ends bonded elsewhere (never a ring
+    bond). The structure is centred on its centroid; classes and charges as
+    in `ligand`.
+    """
+    if n_rings < 0 or n_chain < 0 or n_rings + n_chain < 1 or ring_size < 3:
+        raise ValueError("need at least one unit and rings of >= 3 atoms")
+    rng = np.random.default_rng(seed)
+    units = np.array([1] * n_rings + [0] * n_chain)
+    units = units[rng.permutation(len(units))]
+    R = RING_BOND / (2.0 * np.sin(np.pi / ring_size))        # circumradius
+    xyz, bonds, degree, ring_of, centre = [], [], [], [], []
+    single = []                                              # inter-unit bonds
+
+    def ring_atoms(p0, direction, normal):
+        w = np.cross(normal, direction)
+        c = p0 + R * direction
+        th = 2.0 * np.pi * np.arange(ring_size) / ring_size
+        return c, c[None, :] + R * (np.cos(th)[:, None] * (-direction)[None, :] + np.sin(th)[:, None] * w[None, :])
+
+    for k, is_ring in enumerate(units):
+        if k == 0:
+            if is_ring:
+                d0 = _unit_vectors(rng, 1)[0]
+                n0 = np.cross(d0, _unit_vectors(rng, 1)[0])
+                c, pts = ring_atoms(np.zeros(3), d0, n0 / np.linalg.norm(n0))
+            else:
+                c, pts = None, np.zeros((1, 3))
+            base = 0
+        else:
+            placed = False
+            for _ in range(200):
+                cand = [i for i in range(len(xyz)) if degree[i] < (3 if ring_of[i] >= 0 else 4)]
+                a = int(cand[rng.integers(len(cand))])
+                if ring_of[a] >= 0:
+                    d = xyz[a] - centre[ring_of[a]]
+                    d /= np.linalg.norm(d)
+                else:
+                    d = _unit_vectors(rng, 1)[0]
+                p0 = xyz[a] + BOND_LENGTH * d
+                if is_ring:
+                    nrm = np.cross(d, _unit_vectors(rng, 1)[0])
+                    c, pts = ring_atoms(p0, d, nrm / np.linalg.norm(nrm))
+                else:
+                    c, pts = None, p0[None, :]
+                old = np.asarray(xyz)
+                dist = np.linalg.norm(old[None, :, :] - pts[:, None, :], axis=2)
+                dist[0, a] = np.inf                         # the new bond
+                if dist.min() >= MIN_NONBONDED:
+                    placed = True
+                    break
+            if not placed:
+                raise RuntimeError(f"could not place unit {k} (seed {seed})")
+            base = len(xyz)
+            single.append(len(bonds))
+            bonds.append((a, base))
+            degree[a] += 1
+        r_id = len(centre) if is_ring else -1
+        if is_ring:
+            centre.append(c)
+        for i, pt in enumerate(pts):
+            xyz.append(pt)
+            degree.append(1 if k > 0 and i == 0 else 0)
+            ring_of.append(r_id)
+        if is_ring:
+            for i in range(ring_size):
+                bonds.append((base + i, base + (i + 1) % ring_size))
+                degree[base + i] += 1
+                degree[base + (i + 1) % ring_size] += 1
+    xyz = np.asarray(xyz, dtype=np.float64)
+    xyz -= xyz.mean(axis=0)
+    n_atoms = xyz.shape[0]
+    bonds = np.array(bonds, dtype=np.int32).reshape(-1, 2)
+    internal = [b for b in single if degree[bonds[b, 0]] >= 2 and degree[bonds[b, 1]] >= 2]
     t_eff = min(n_torsions, len(internal))
     if t_eff > 0:
         rot = np.sort(rng.choice(np.array(internal), size=t_eff, replace=False)).astype(np.int32)

@@ -30,7 +30,9 @@ def ligand_from_bonds(bonds, rot_bonds, seed=0, cls=None, charge=None):
     while pending:
         for e in list(pending):
             u, v = int(e[0]), int(e[1])
-            if u in placed and v not in placed:
+            if u in placed and v in placed:          # a ring closure: topology only
+                pending.remove(e)
+            elif u in placed and v not in placed:
                 d = rng.normal(size=3)
                 xyz[v] = xyz[u] + 1.5 * d / np.linalg.norm(d)
                 placed.add(v)

@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(dock.ABI_SYMBOLS)
     for name in declared:
         assert hasattr(L, name)
-    assert L.dock_abi_version() == dock.ABI_VERSION == 7
+    assert L.dock_abi_version() == dock.ABI_VERSION == 8
 
 
 def _check_prep(lig):
@@ -52,19 +52,22 @@ def _check_prep(lig):
     assert np.array_equal(ex["pairs"], p.pairs)
     assert np.array_equal(ex["pair_hb"], p.pair_hb)
     _check_batches(ex["batches"], h.n_copies, N, p, order)
-    # the depth-first order is the one defined by the header: children in
-    # increasing index (independent recursive construction)
+    # the depth-first order is the one defined by the header: neighbours in
+    # increasing index, each atom at its first visit (independent recursive
+    # construction)
     adj = {i: [] for i in range(N)}
     for u, v in lig.bonds:
         adj[int(u)].append(int(v)); adj[int(v)].append(int(u))
     want = []
+    seen = set()
 
-    def visit(u, par):
+    def visit(u):
+        seen.add(u)
         want.append(u)
         for v in sorted(adj[u]):
-            if v != par:
-                visit(v, u)
-    visit(0, -1)
+            if v not in seen:
+                visit(v)
+    visit(0)
     assert order.tolist() == want
 
 
@@ -149,6 +152,7 @@ def _desc_from(lig, **over):
     d.n_atoms = arrs.get("n_atoms", xyz.shape[0])
     d.n_torsions = arrs.get("n_torsions", arrs["rot"].shape[0])
     d.root_atom = arrs.get("root", 0)
+    d.n_bonds = arrs.get("n_bonds", arrs["bonds"].shape[0])
     d.xyz = arrs["xyz"].ctypes.data_as(C.POINTER(C.c_double))
     d.charge = arrs["charge"].ctypes.data_as(C.POINTER(C.c_double))
     d.cls = arrs["cls"].ctypes.data_as(C.POINTER(C.c_int32))
@@ -258,6 +262,56 @@ def test_create_ligand_rejects_bad_topologies():
     assert _create(d) == dock.DOCK_EINVAL
 
 
+def test_ring_ligands_bitexact_and_ring_bonds_rejected():
+    """Ligands with rings (planar rings joined by single bonds): the C++
+    preparation matches the oracle's BFS construction; a rotatable bond
+    inside a ring, a bond count outside [N - 1, 4 N] and a disconnected
+    graph are rejected."""
+    for seed, (nr, nc, t) in enumerate([(1, 4, 2), (2, 6, 4), (3, 10, 8), (4, 20, 12), (6, 30, 20),
+                                        (1, 0, 0), (2, 0, 1), (8, 40, 32)]):
+        lig = synth.ring_ligand(nr, nc, t, 700 + seed)
+        assert lig.bonds.shape[0] == lig.n_atoms - 1 + nr
+        _check_prep(lig)
+    lig = synth.ring_ligand(2, 6, 3, 720)
+    ring_bond = lig.n_atoms - 1 + 1      # some bond of a ring: every bond not listed as single
+    single = set()
+    for k in lig.rot_bonds.tolist():
+        single.add(k)
+    deg = np.bincount(lig.bonds.ravel(), minlength=lig.n_atoms)
+    in_ring = []
+    for k, (u, v) in enumerate(lig.bonds):
+        # a bond is in a ring iff removing it leaves the graph connected
+        rest = np.delete(lig.bonds, k, axis=0)
+        adj = {i: [] for i in range(lig.n_atoms)}
+        for a, b in rest:
+            adj[int(a)].append(int(b)); adj[int(b)].append(int(a))
+        seen, stack = {0}, [0]
+        while stack:
+            x = stack.pop()
+            for y in adj[x]:
+                if y not in seen:
+                    seen.add(y); stack.append(y)
+        if len(seen) == lig.n_atoms and deg[u] >= 2 and deg[v] >= 2:
+            in_ring.append(k)
+    assert in_ring and ring_bond >= 0
+    d, keep = _desc_from(lig, rot=np.array([in_ring[0]], np.int32))
+    assert _create(d) == dock.DOCK_EINVAL and "ring" in dock.last_error()
+    with pytest.raises(ValueError):
+        R.prepare(synth.Ligand(xyz=lig.xyz, charge=lig.charge, cls=lig.cls, bonds=lig.bonds,
+                               rot_bonds=np.array([in_ring[0]], np.int32)), FF)
+    d, keep = _desc_from(lig, n_bonds=lig.n_atoms - 2)
+    assert _create(d) == dock.DOCK_EINVAL and "n_bonds" in dock.last_error()
+    d, keep = _desc_from(lig, n_bonds=4 * lig.n_atoms + 1)
+    assert _create(d) == dock.DOCK_EINVAL
+    # two rings side by side, not joined: not connected
+    a = synth.ring_ligand(1, 0, 0, 721)
+    bonds = np.concatenate([a.bonds, a.bonds + 6, np.array([[0, 3]], np.int32)])
+    xyz = np.concatenate([a.xyz, a.xyz + 10.0])
+    d, keep = _desc_from(a, bonds=bonds, xyz=xyz, charge=np.zeros(12), cls=np.zeros(12, np.int32), n_atoms=12,
+                         rot=np.zeros(0, np.int32))
+    assert _create(d) == dock.DOCK_EINVAL and "connect" in dock.last_error()
+
+
 def test_create_ligand_limits():
     big = synth.ligand(129, 3, 2)
     d, keep = _desc_from(big)
@@ -351,6 +405,29 @@ def test_batch_calls_validate_before_device_work():
     assert L.dock_block_sum4(fake, fake, 1, 2048, 0, 1, None) == dock.DOCK_EINVAL
     assert L.dock_destroy_grids(g) == 0 and L.dock_destroy_grids(g5) == 0
     assert L.dock_destroy_grids(None) == 0 and L.dock_destroy_ligand(None) == 0
+
+
+def test_row_selection_calls_validate_before_device_work():
+    L = dock.lib()
+    vp = C.c_void_p
+    fake = vp(0x1000)
+    cnt = vp(0x2000)
+    assert L.dock_select_rows(fake, -1, 0.5, fake, cnt, None) == dock.DOCK_EINVAL
+    assert L.dock_select_rows(fake, 4, 0.5, fake, None, None) == dock.DOCK_EINVAL
+    assert L.dock_select_rows(None, 4, 0.5, fake, cnt, None) == dock.DOCK_EINVAL
+    assert L.dock_select_rows(fake, 4, float("nan"), fake, cnt, None) == dock.DOCK_EINVAL
+    assert L.dock_select_rows(vp(0x1002), 4, 0.5, fake, cnt, None) == dock.DOCK_EINVAL
+    for fn in (L.dock_gather_rows, L.dock_scatter_rows):
+        assert fn(fake, 4, 0, fake, 2, fake, None) == dock.DOCK_EINVAL          # row < 1
+        assert fn(fake, -1, 3, fake, 2, fake, None) == dock.DOCK_EINVAL
+        assert fn(fake, 4, 3, fake, -2, fake, None) == dock.DOCK_EINVAL
+        assert fn(None, 4, 3, fake, 2, fake, None) == dock.DOCK_EINVAL
+        assert fn(fake, 4, 3, None, 2, fake, None) == dock.DOCK_EINVAL
+        assert fn(fake, 4, 3, fake, 2, vp(0x1001), None) == dock.DOCK_EINVAL
+        assert fn(fake, 1 << 30, 3, fake, 2, fake, None) == dock.DOCK_EINVAL    # > 2^31 - 1 elements
+    # m == 0: nothing to do (gather: m is the fifth argument, scatter: the second)
+    assert L.dock_gather_rows(None, 4, 3, None, 0, None, None) == dock.DOCK_OK
+    assert L.dock_scatter_rows(None, 0, 3, None, 4, None, None) == dock.DOCK_OK
 
 
 def test_ga_step_rejects_bad_descriptors_before_any_device_work():

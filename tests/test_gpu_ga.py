@@ -180,3 +180,71 @@ def test_lga_job_early_stop(dk):
     res = lga.run_lga(grids, lig, gen0, n_runs=2, generations=3, ls_iterations=10,
                       stop_patience=2, stop_tol=-1.0, seed=4)     # never converged
     assert not res.stopped_early and res.generations == 3
+
+
+@pytest.mark.parametrize("n,rate", [(0, 0.5), (1, 0.5), (7, 0.0), (1000, 1.0), (1023, 0.3), (1025, 0.3),
+                                    (7500, 0.06), (20000, 0.5)])
+def test_select_gather_scatter_bit_exact(dk, n, rate):
+    """Rows selected for the local search (draw < rate, increasing order)
+    against the reference selection, then a gather of those rows and a
+    scatter of modified rows back: both exact copies."""
+    from oracle import ga_ref as GR
+    rng = np.random.default_rng(n + int(rate * 100))
+    draws = rng.random(n).astype(np.float32)
+    if n > 10:
+        draws[5] = np.float32(rate)            # equal to the rate: not selected
+    want = GR.select_rows(draws, rate)
+    idx, cnt = dk.select_rows(torch.from_numpy(draws).cuda(), rate)
+    torch.cuda.synchronize()
+    m = int(cnt.item())
+    assert m == len(want)
+    assert np.array_equal(idx.cpu().numpy()[:m], want)
+    G = 17
+    pop = rng.normal(size=(n, G)).astype(np.float32)
+    sub = dk.gather_rows(torch.from_numpy(pop).cuda(), idx, m)
+    torch.cuda.synchronize()
+    assert np.array_equal(sub.cpu().numpy(), pop[want])
+    new = (sub * 2.0 + 1.0).contiguous()
+    dst = torch.from_numpy(pop).cuda()
+    dk.scatter_rows(new, idx, dst)
+    e = torch.from_numpy(rng.normal(size=n).astype(np.float32)).cuda()
+    e_new = torch.arange(m, dtype=torch.float32, device="cuda")
+    e_ref = e.cpu().numpy().copy()
+    dk.scatter_rows(e_new, idx, e)
+    torch.cuda.synchronize()
+    ref = pop.copy()
+    ref[want] = pop[want] * np.float32(2.0) + np.float32(1.0)
+    e_ref[want] = np.arange(m, dtype=np.float32)
+    assert np.array_equal(dst.cpu().numpy(), ref)
+    assert np.array_equal(e.cpu().numpy(), e_ref)
+
+
+def test_lga_job_partial_local_search_rate(dk):
+    """A docking job that searches only the children whose draw is below the
+    local-search rate (0.3): every phase searches the selected share, the
+    evaluation count is the scoring of every member plus the searches, the
+    unsearched members keep their scores, per-run best energies never rise,
+    and the reported best points meet the oracle."""
+    from oracle import dock_ref as R
+    from paper_2410_10447_amd import lga, synth
+    from tests.gpu_common import check_reported
+    wl = synth.ls_workload(200)
+    grids = dk.Grids.from_synth(wl.grids)
+    lig = dk.Ligand(wl.ligands[0], wl.ff)
+    gen0 = torch.from_numpy(np.asarray(wl.genotypes[0], np.float32)).cuda()
+    n, its = gen0.shape[0], 20
+    res = lga.run_lga(grids, lig, gen0, n_runs=4, generations=3, ls_iterations=its, seed=11, ls_rate=0.3)
+    assert res.generations == 3 and len(res.searched) == 4
+    assert all(0 < m < n for m in res.searched)
+    assert abs(np.mean(res.searched) - 0.3 * n) < 0.1 * n
+    assert res.evaluations == sum(n + m * (its + 1) for m in res.searched)
+    h = np.stack(res.history)
+    assert np.all(np.diff(h, axis=0) <= 0), h
+    prep = R.prepare(wl.ligands[0], wl.ff)
+    check_reported("lga job at rate 0.3, best points", dk, grids, lig, prep, wl.grids, res.best_genotype,
+                   res.best_energy)
+    # the same seed gives the same job, bit for bit
+    res2 = lga.run_lga(grids, lig, gen0, n_runs=4, generations=3, ls_iterations=its, seed=11, ls_rate=0.3)
+    assert res2.searched == res.searched
+    assert np.array_equal(res2.best_energy, res.best_energy)
+    assert np.array_equal(res2.best_genotype, res.best_genotype)

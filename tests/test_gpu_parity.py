@@ -258,8 +258,18 @@ def test_ls_step_map(dk, variant, tpi):
     tpi = 64 runs the 48-atom benchmark ligand in one wave; tpi = 128 runs a
     100-atom ligand with two waves per individual. The split reductions
     (BF16 2-term, FP16 2-term, BF16 3-term) are held to their bounds."""
+    _step_map(dk, variant, tpi, synth.ls_workload(64) if tpi == 64 else _two_wave_workload(64))
+
+
+@pytest.mark.parametrize("variant", FP32_VARIANTS)
+def test_ls_step_map_two_waves_small_ligand(dk, variant):
+    """Two waves per individual for the 48-atom benchmark ligand: the second
+    wave owns no atoms, only half of the pair batches."""
+    _step_map(dk, variant, 128, synth.ls_workload(64))
+
+
+def _step_map(dk, variant, tpi, w):
     from tests.gpu_common import assert_reports
-    w = synth.ls_workload(64) if tpi == 64 else _two_wave_workload(64)
     prep = R.prepare(w.ligands[0], w.ff)
     G, L, st = _ls_setup(dk, w, 64)
     grad = torch.zeros_like(st.genotype)
@@ -454,12 +464,16 @@ def test_corner_expanded_grids_identical(dk):
         Gc2 = Gc if lig_n == 48 else dk.Grids.from_synth(ww.grids)
         a = dk.LSState.start(torch.from_numpy(ww.genotypes[0]).cuda())
         b = a.clone()
+        c = a.clone()
         dk.local_search([(Gp2, LL, a)], 20, threads_per_ind=tpi)
         dk.local_search([(Gc2, LL, b)], 20, threads_per_ind=tpi)
+        # the per-item layout choice: planar maps read with the copy bound
+        dk.local_search([dk.LsJob(Gc2, LL, c, plain_maps=True)], 20, threads_per_ind=tpi)
         torch.cuda.synchronize()
-        an, bn = a.to_numpy(), b.to_numpy()
+        an, bn, cn = a.to_numpy(), b.to_numpy(), c.to_numpy()
         for f in an:
             assert np.array_equal(an[f], bn[f]), (lig_n, f)
+            assert np.array_equal(an[f], cn[f]), (lig_n, f)
 
 
 def test_ls_mixed_variants_in_one_launch(dk):
@@ -548,7 +562,8 @@ def test_ls_uneven_full_size_sampled(dk):
     Ls = [dk.Ligand(l, w.ff) for l in w.ligands]
     states = [dk.LSState.start(torch.from_numpy(g).cuda()) for g in w.genotypes]
     picks = [autotune.choose(L.n_atoms, L.n_torsions) for L in Ls]
-    jobs = [dk.LsJob(G, L, st, c["variant"], threads_per_ind=c.get("threads_per_ind", 64))
+    jobs = [dk.LsJob(G, L, st, c["variant"], threads_per_ind=c.get("threads_per_ind", 64),
+                     plain_maps=c.get("plain_maps", False))
             for L, st, c in zip(Ls, states, picks)]
     dk.local_search(jobs, w.iterations)
     torch.cuda.synchronize()
@@ -558,7 +573,7 @@ def test_ls_uneven_full_size_sampled(dk):
         s = st.to_numpy()
         assert np.all(s["iters_done"] == w.iterations)
         prep = R.prepare(lig, w.ff)
-        one_wave = L.n_atoms <= 64 or c.get("threads_per_ind", 64) == 64
+        one_wave = c.get("threads_per_ind", 64) == 64
         reps.append(check_reported(f"uneven full ligand {k} N={L.n_atoms} T={L.n_torsions}", dk, G, L, prep,
                                    w.grids, s["best_genotype"][idx], s["best_energy"][idx],
                                    variant=c["variant"], exact_rescore=one_wave, assert_ok=False))

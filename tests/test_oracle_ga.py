@@ -125,3 +125,21 @@ def test_out_of_range_draws_are_clamped():
     out, _ = GA.ga_step(gen, E, cand, coins, cuts, np.ones_like(z), z, 1.0, 1.0, 0.0, 0)
     # candidates clamp to (0, 4) and (4, 0): parents 0 and 0; cuts to (0, 7)
     assert all(np.array_equal(out[0, k], gen[0, 0]) for k in range(5))
+
+
+def test_select_rows_special_cases():
+    """Rate 0 selects nothing, rate above every draw selects every row, a
+    rate equal to a draw excludes that row (strict comparison), and the
+    selection is the set {r : draw_r < rate} in increasing order."""
+    from oracle import ga_ref as GR
+    d = np.array([0.5, 0.1, 0.9, 0.3, 0.3, 0.0], np.float32)
+    assert GR.select_rows(d, 0.0).tolist() == []
+    assert GR.select_rows(d, 1.0).tolist() == [0, 1, 2, 3, 4, 5]
+    assert GR.select_rows(d, 0.3).tolist() == [1, 5]
+    assert GR.select_rows(d, np.nextafter(np.float32(0.3), np.float32(1))).tolist() == [1, 3, 4, 5]
+    rng = np.random.default_rng(3)
+    x = rng.random(1000).astype(np.float32)
+    sel = GR.select_rows(x, 0.25)
+    assert np.array_equal(sel, np.flatnonzero(x < np.float32(0.25)))
+    assert abs(len(sel) - 250) < 60
+    assert GR.select_rows(np.zeros(0, np.float32), 0.5).shape == (0,)

@@ -1,7 +1,10 @@
 """Per-size-bucket choice of the launch options of the local search.
 
 Ligands are bucketed by atom count (width 32) and torsion count (width 8).
-For each bucket a representative synthetic ligand is timed with every
+For each bucket a representative synthetic ligand is timed, at a population
+that fills the GPU (4096 individuals: more than the 3072 one-wave
+individuals resident at once, so that a choice that doubles the waves per
+individual pays for the waves it takes from other items), with every
 candidate (reduction variant x threads per individual x grid layout) through
 the C ABI and
 the fastest candidate is stored in a JSON table keyed by GPU architecture and
@@ -92,7 +95,7 @@ def time_candidate(G, L, gen, cand, iterations=20, reps=3):
     return gen.shape[0] * (iterations + 1) / dt
 
 
-def tune(out: str = TABLE_PATH, n_individuals: int = 1024, iterations: int = 20, seed: int = 77):
+def tune(out: str = TABLE_PATH, n_individuals: int = 4096, iterations: int = 20, seed: int = 77):
     import torch
     from . import dock, synth
     grd = synth.grids(64, 10, seed)
@@ -175,7 +178,7 @@ def unify_families(table, tol: float = 0.03):
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=TABLE_PATH)
-    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--iters", type=int, default=20)
     a = ap.parse_args()
     tune(a.out, a.n, a.iters)

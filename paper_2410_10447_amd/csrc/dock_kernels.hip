@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "dock.h"
 #include "dock_blob.h"
 #include "dock_launch.h"
@@ -1370,10 +1372,17 @@ template <int SLOTS, int VAR, bool ANY>
 hipError_t launch_score_k(const GridParams& g, const uint8_t* blob, int n, const float* gen, float* energy,
                           float* grad, float* atom_out, int n_cu, hipStream_t st) {
     auto k = score_kernel<SLOTS, VAR, ANY>;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), 64, 0) != hipSuccess ||
-        per_cu <= 0)
-        per_cu = 2;
+    // resident blocks per CU, queried once per kernel (the query costs tens
+    // of microseconds of host time, as much as a small call's kernel)
+    static std::atomic<int> cached{0};
+    int per_cu = cached.load(std::memory_order_relaxed);
+    if (per_cu <= 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(k), 64, 0) !=
+                hipSuccess ||
+            per_cu <= 0)
+            per_cu = 2;
+        cached.store(per_cu, std::memory_order_relaxed);
+    }
     const long long resident = (long long)per_cu * (n_cu > 0 ? n_cu : 256);
     const int blocks = (int)(n < resident ? n : resident);
     hipLaunchKernelGGL(k, dim3(blocks), dim3(64), 0, st, g, blob, n, gen, energy, grad, atom_out);
@@ -1476,9 +1485,16 @@ hipError_t launch_ls(const LsParams& p, int mode, int variant_uniform, int grid_
 }
 
 int ls_blocks_per_cu(int mode, int variant_uniform) {
-    int nb = 0;
+    // cached per (mode, variant): the occupancy query costs host time on
+    // every call otherwise
+    static std::atomic<int> cache[5][DOCK_REDUCE_COUNT + 1];
+    const int m = mode >= 0 && mode < 5 ? mode : 0;
+    const int v = variant_uniform >= 0 && variant_uniform < DOCK_REDUCE_COUNT ? variant_uniform : DOCK_REDUCE_COUNT;
+    int nb = cache[m][v].load(std::memory_order_relaxed);
+    if (nb > 0) return nb;
     const void* k = ls_kernel_for(mode, variant_uniform);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, ls_block_threads(mode), 0) != hipSuccess) return 0;
+    cache[m][v].store(nb, std::memory_order_relaxed);
     return nb;
 }
 

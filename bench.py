@@ -202,8 +202,10 @@ def score_run(n=65536, reps=5, inner=10):
     L = dock.Ligand(w.ligands[0], w.ff)
     gen = torch.from_numpy(w.genotypes[0]).cuda()
     res = {}
-    for v in (0, 1):
-        e, g = dock.score_batch(G, L, gen, variant=v)
+    # one genotype per wave with either FP32 reduction, and two genotypes per
+    # wave (the ligand has <= 32 atoms and <= 32 genes; shuffle reduction)
+    for v, two in ((0, False), (1, False), (0, True)):
+        e, g = dock.score_batch(G, L, gen, variant=v, two_per_wave=two)
         torch.cuda.synchronize()
         times = []
         for _ in range(reps):
@@ -212,12 +214,13 @@ def score_run(n=65536, reps=5, inner=10):
             a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             a.record()
             for _ in range(inner):
-                dock.score_batch(G, L, gen, variant=v)
+                dock.score_batch(G, L, gen, variant=v, two_per_wave=two)
             b.record()
             b.synchronize()
             times.append(a.elapsed_time(b) / inner)
         ms = float(np.median(times))
-        res[dock.VARIANT_NAMES[v]] = {"ms": round(ms, 4), "evals_per_s": n / (ms * 1e-3)}
+        res[dock.VARIANT_NAMES[v] + ("_two_per_wave" if two else "")] = {"ms": round(ms, 4),
+                                                                         "evals_per_s": n / (ms * 1e-3)}
     best = min(res, key=lambda k: res[k]["ms"])
     w_eval = work_per_eval(L.n_pairs, L.n_atoms, L.n_torsions)
     return {"workload": w.name, "genotypes": n, **res,
@@ -343,7 +346,7 @@ def uneven_run(steps, warmup, use_table=True, tpi_override=0):
     for _ in range(warmup + steps):
         states = [dock.LSState.start(g) for g in gens]
         jobs = [dock.LsJob(G, L, st, c["variant"], threads_per_ind=c.get("threads_per_ind", 64),
-                           plain_maps=c.get("plain_maps", False))
+                           plain_maps=c.get("plain_maps", False), two_per_wave=c.get("two_per_wave", False))
                 for L, st, c in zip(Ls, states, pick)]
         runs.append((states, dock.make_items(jobs)))
     torch.cuda.synchronize()
@@ -366,6 +369,7 @@ def uneven_run(steps, warmup, use_table=True, tpi_override=0):
             "threads_per_ind_override": tpi_override,
             "two_wave_items": sum(1 for c in pick if c.get("threads_per_ind", 64) == 128),
             "plain_map_items": sum(1 for c in pick if c.get("plain_maps", False)),
+            "two_per_wave_items": sum(1 for c in pick if c.get("two_per_wave", False)),
             "atoms_mean": float(np.mean([L.n_atoms for L in Ls])),
             "pairs_mean": float(np.mean([L.n_pairs for L in Ls]))}
 

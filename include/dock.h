@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define DOCK_ABI_VERSION 8
+#define DOCK_ABI_VERSION 9
 
 /* status codes */
 #define DOCK_OK            0
@@ -215,7 +215,7 @@ int32_t dock_destroy_ligand(dock_ligand* lig);
 typedef struct {
     int32_t variant;          /* DOCK_REDUCE_* */
     int32_t threads_per_ind;  /* 0 (= 64) or 64; wider tiles are reserved */
-    uint32_t flags;           /* 0 */
+    uint32_t flags;           /* 0, or DOCK_EXEC_TWO_PER_WAVE */
     float* atom_out;          /* device [n][n_atoms][8] or NULL: per atom (original
                                  order) x - tx, y - ty, z - tz (the atom's position
                                  relative to the translation genes, the FP32 values
@@ -224,6 +224,10 @@ typedef struct {
                                  atom's grid energy with the outside penalty),
                                  gx, gy, gz (dE/dx of the atom), 0 */
 } dock_exec_opts;
+
+/* Scoring flag: two genotypes per wave (see DOCK_ITEM_TWO_PER_WAVE; same
+ * requirements: <= 32 atoms and <= 32 genes, the shuffle reduction). */
+#define DOCK_EXEC_TWO_PER_WAVE 1u
 
 /* genotypes_dev [n][G], energy_dev [n], grad_dev [n][G] (may be NULL): device
  * float32, 4-byte aligned. opts may be NULL (defaults). Errors: DOCK_EINVAL on
@@ -258,13 +262,20 @@ typedef struct {
     int32_t* iters_done;         /* device [n] in/out: iterations taken so far */
     float* grad;                 /* device [n][G] out, or NULL: dE/dgenotype at the last
                                     evaluated point */
-    uint32_t flags;              /* DOCK_ITEM_PLAIN_MAPS, or 0 */
+    uint32_t flags;              /* DOCK_ITEM_PLAIN_MAPS | DOCK_ITEM_TWO_PER_WAVE, or 0 */
 } dock_ls_item;
 
 /* Item flag: read the planar maps even when the grid set has the
  * corner-expanded copy bound (a layout choice per item, e.g. per size
  * bucket of a tuning table; the values, and so the results, are the same). */
 #define DOCK_ITEM_PLAIN_MAPS 1u
+/* Item flag: two individuals per wave, one per 32-lane half (individuals
+ * 2k and 2k + 1 of the item share a wave; their results do not depend on
+ * each other). Needs a ligand of at most 32 atoms and 32 genes, the
+ * shuffle reduction and one wave per individual (threads_per_ind 0 or 64),
+ * else DOCK_EUNSUPPORTED. The block sum runs over each half, so results
+ * differ from one individual per wave by rounding only. */
+#define DOCK_ITEM_TWO_PER_WAVE 2u
 
 #define DOCK_LS_FINAL_EVAL 1u    /* evaluate the point reached after the last step */
 

@@ -58,21 +58,35 @@ def load(path: str = TABLE_PATH) -> dict:
     return _cache[path]
 
 
+def two_per_wave_ok(n_atoms: int, n_torsions: int) -> bool:
+    """Two individuals fit one wave: <= 32 atoms and <= 32 genes."""
+    return n_atoms <= 32 and 7 + n_torsions <= 32
+
+
 def choose(n_atoms: int, n_torsions: int, path: str = TABLE_PATH) -> dict:
-    return dict(load(path)["buckets"].get(bucket(n_atoms, n_torsions), DEFAULT))
+    c = dict(load(path)["buckets"].get(bucket(n_atoms, n_torsions), DEFAULT))
+    if c.get("two_per_wave") and not two_per_wave_ok(n_atoms, n_torsions):
+        c["two_per_wave"] = False          # the bucket's other ligands may take it; this one cannot
+    return c
 
 
-def candidates(n_atoms: int = 64):
+def candidates(n_atoms: int = 64, n_torsions: int = 0):
     """Reduction variant x threads per individual (one wave, or two waves
     splitting the pair batches and, past 64 atoms, the atoms) x grid layout
-    (the corner-expanded copy, or the planar maps)."""
+    (the corner-expanded copy, or the planar maps); for ligands that fit,
+    also two individuals per wave (shuffle reduction, either layout)."""
     from . import dock
-    return [{"variant": v, "threads_per_ind": b, "plain_maps": p} for p in (False, True)
-            for b in (64, 128) for v in (dock.REDUCE_SHUFFLE, dock.REDUCE_MFMA_F32)]
+    out = [{"variant": v, "threads_per_ind": b, "plain_maps": p} for p in (False, True)
+           for b in (64, 128) for v in (dock.REDUCE_SHUFFLE, dock.REDUCE_MFMA_F32)]
+    if two_per_wave_ok(n_atoms, n_torsions):
+        out += [{"variant": dock.REDUCE_SHUFFLE, "threads_per_ind": 64, "plain_maps": p, "two_per_wave": True}
+                for p in (False, True)]
+    return out
 
 
 def cand_key(c) -> str:
-    return f"v{c['variant']}_b{c['threads_per_ind']}" + ("_plain" if c.get("plain_maps") else "")
+    return (f"v{c['variant']}_b{c['threads_per_ind']}" + ("_plain" if c.get("plain_maps") else "")
+            + ("_x2" if c.get("two_per_wave") else ""))
 
 
 def time_candidate(G, L, gen, cand, iterations=20, reps=3):
@@ -86,7 +100,8 @@ def time_candidate(G, L, gen, cand, iterations=20, reps=3):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         dock.local_search([dock.LsJob(G, L, st, cand["variant"], threads_per_ind=cand.get("threads_per_ind", 64),
-                                      plain_maps=cand.get("plain_maps", False))],
+                                      plain_maps=cand.get("plain_maps", False),
+                                      two_per_wave=cand.get("two_per_wave", False))],
                           iterations, workspace=ws)
         torch.cuda.synchronize()
         if r:
@@ -109,7 +124,7 @@ def tune(out: str = TABLE_PATH, n_individuals: int = 4096, iterations: int = 20,
         L = dock.Ligand(lig, ff)
         gen = torch.from_numpy(synth.genotypes(lig, grd, n_individuals, seed)).cuda()
         best, rates = None, {}
-        for c in candidates(n):
+        for c in candidates(n, lig.n_torsions):
             rate = time_candidate(G, L, gen, c, iterations)
             rates[cand_key(c)] = rate
             if best is None or rate > best[1]:
@@ -128,8 +143,11 @@ def tune(out: str = TABLE_PATH, n_individuals: int = 4096, iterations: int = 20,
 
 
 def family(entry) -> str:
-    """Kernel family a bucket's items run in: two waves per individual, or
-    one wave with one atom per lane (<= 64 atoms) or two (larger ligands)."""
+    """Kernel family a bucket's items run in: two individuals per wave, two
+    waves per individual, or one wave with one atom per lane (<= 64 atoms)
+    or two (larger ligands)."""
+    if entry.get("two_per_wave"):
+        return "two-per-wave"
     if entry["threads_per_ind"] == 128:
         return "two-wave"
     return "one-slot" if entry["atoms"] <= 64 else "two-slot"
@@ -151,7 +169,7 @@ def unify_families(table, tol: float = 0.03):
     for key, e in table["buckets"].items():
         fams.setdefault(family(e), []).append(key)
     for fam, keys in fams.items():
-        opts = sorted({(int(k.split("_")[0][1:]), k.endswith("_plain"))
+        opts = sorted({(int(k.split("_")[0][1:]), "_plain" in k)
                        for e in (table["buckets"][k] for k in keys) for k in e["measured"]})
         best_o, best_loss = None, None
         for v, plain in opts:
@@ -159,7 +177,8 @@ def unify_families(table, tol: float = 0.03):
             for key in keys:
                 e = table["buckets"][key]
                 r = e["measured"].get(cand_key({"variant": v, "threads_per_ind": e["threads_per_ind"],
-                                                "plain_maps": plain}))
+                                                "plain_maps": plain,
+                                                "two_per_wave": e.get("two_per_wave", False)}))
                 loss = max(loss, 1.0 if r is None else 1.0 - r / e["evals_per_s"])
             if best_loss is None or loss < best_loss:
                 best_o, best_loss = (v, plain), loss

@@ -131,8 +131,8 @@ int device_cu_count(int32_t& out) {
 // caller's later work still waits for both. The fork-launch-join sequence is
 // serialised, since the events are shared.
 struct SideStream {
-    hipStream_t stream[2] = {nullptr, nullptr};
-    hipEvent_t fork = nullptr, join[2] = {nullptr, nullptr};
+    hipStream_t stream[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
 };
 
 int side_stream(SideStream*& out, std::unique_lock<std::mutex>& lock) {
@@ -144,7 +144,7 @@ int side_stream(SideStream*& out, std::unique_lock<std::mutex>& lock) {
     lock = std::unique_lock<std::mutex>(mu);
     SideStream& s = (*table)[dev];
     if (!s.stream[0]) {
-        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        for (int k = 0; k < 3 && e == hipSuccess; ++k) {
             e = hipStreamCreateWithFlags(&s.stream[k], hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&s.join[k], hipEventDisableTiming);
         }
@@ -176,10 +176,10 @@ struct LsPlanBuf {
     uint8_t* table;
 };
 
-struct LsPart { int first, count, mode, variant; };
+struct LsPart { int first, count, mode, variant; int64_t units; };
 
 struct LsPlan {
-    LsPart part[3];
+    LsPart part[4];
     int n_parts = 0;
     int64_t table_bytes = 0;
 };
@@ -201,10 +201,10 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
     if ((o->flags & ~DOCK_LS_FINAL_EVAL) != 0) return fail(DOCK_EINVAL, "unknown flags");
     docklaunch::DevItem* dev = buf.dev;
     int64_t* cost = buf.cost;
-    int* fam = buf.fam;             // kernel family: 0 two-wave, 1 two-slot, 2 one-slot
+    int* fam = buf.fam;             // kernel family: 0 two-wave, 1 two-slot, 2 one-slot, 3 two per wave
     int n_dev = 0;
     int64_t total = 0;
-    bool any_fam[3] = {false, false, false};
+    bool any_fam[4] = {false, false, false, false};
     int var_u = -2;
     for (int i = 0; i < n_items; ++i) {
         const dock_ls_item& it = items[i];
@@ -212,7 +212,6 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
         if (it.n_genes != 7 + it.ligand->prep.n_torsions)
             return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": n_genes " + std::to_string(it.n_genes) +
                                          " is not the ligand's " + std::to_string(7 + it.ligand->prep.n_torsions));
-        if (!it.ligand->blob_dev) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": ligand not uploaded");
         if (it.n < 0) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": n < 0");
         int32_t st = check_grid_for_ligand(it.grids, it.ligand);
         if (st != DOCK_OK) return st;
@@ -228,13 +227,19 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
                                                 : (o->threads_per_ind != 0 ? o->threads_per_ind : 64);
         const int iters = it.iterations < 0 ? o->iterations : it.iterations;
         const int fin = it.final_eval < 0 ? ((o->flags & DOCK_LS_FINAL_EVAL) ? 1 : 0) : it.final_eval;
+        if ((it.flags & ~(DOCK_ITEM_PLAIN_MAPS | DOCK_ITEM_TWO_PER_WAVE)) != 0)
+            return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": unknown flags");
+        const bool two = (it.flags & DOCK_ITEM_TWO_PER_WAVE) != 0;
+        if (two && (it.ligand->prep.n_atoms > 32 || it.n_genes > 32 || var != DOCK_REDUCE_SHUFFLE || tpi != 64))
+            return fail(DOCK_EUNSUPPORTED, "item " + std::to_string(i) + ": two individuals per wave need <= 32 atoms, "
+                                           "<= 32 genes, the shuffle reduction and 64 threads per individual");
+        if (!it.ligand->blob_dev) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": ligand not uploaded");
         if (it.n == 0) continue;
         void* ptrs[] = {it.genotype, it.acc_g2, it.acc_dx2, it.best_genotype, it.best_energy, it.energy,
                         it.iters_done};
         for (void* p : ptrs)
             if (!p || !aligned(p, 4)) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": NULL or misaligned state");
         if (it.grad && !aligned(it.grad, 4)) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": misaligned grad");
-        if ((it.flags & ~DOCK_ITEM_PLAIN_MAPS) != 0) return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": unknown flags");
         if (iters == 0 && !fin) continue;  // nothing to do for this item
         docklaunch::DevItem& d = dev[n_dev];
         std::memset(&d, 0, sizeof(d));
@@ -260,7 +265,7 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
         // evaluation: pair batches, atom slots, torsion depth, fixed part)
         cost[n_dev] = (int64_t)(iters + fin) *
                       ((int64_t)H->n_batches * 90 + (int64_t)d.slots * (150 + 20 * P.max_depth) + 500);
-        const int f = tpi == 128 ? 0 : (d.slots == 1 ? 2 : 1);
+        const int f = two ? 3 : (tpi == 128 ? 0 : (d.slots == 1 ? 2 : 1));
         fam[n_dev] = f;
         any_fam[f] = true;
         var_u = (var_u == -2 || var_u == var) ? var : -1;
@@ -276,7 +281,7 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
     // items first, then two-slot, then one-slot, each group longest first.
     // Carrying every combination in one kernel would spill registers.
     const int var_uniform = var_u >= 0 ? var_u : -1;
-    const bool merge_one_wave = !any_fam[0] && any_fam[1] && any_fam[2] && var_uniform >= 0;
+    const bool merge_one_wave = !any_fam[0] && !any_fam[3] && any_fam[1] && any_fam[2] && var_uniform >= 0;
     auto group = [&](int i) { return merge_one_wave ? 1 : fam[i]; };
     int* idx = buf.idx;
     for (int i = 0; i < n_dev; ++i) idx[i] = i;
@@ -291,15 +296,19 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
     for (int i = 0; i < n_dev; ++i) {
         const int g = group(idx[i]);
         if (i == 0 || g != group(idx[i - 1])) {
-            const int mode = merge_one_wave ? docklaunch::kSlotsAny
-                                            : (g == 0 ? docklaunch::kTwoWave
-                                                      : (g == 1 ? docklaunch::kSlots2 : docklaunch::kSlots1));
-            plan.part[plan.n_parts++] = {i, 0, mode, -1};
+            const int mode = g == 3 ? docklaunch::kTwoPerWave
+                                    : (merge_one_wave ? docklaunch::kSlotsAny
+                                                      : (g == 0 ? docklaunch::kTwoWave
+                                                                : (g == 1 ? docklaunch::kSlots2 : docklaunch::kSlots1)));
+            plan.part[plan.n_parts++] = {i, 0, mode, -1, 0};
             ub = 0;
         }
         tab[i] = dev[idx[i]];
         tab[i].unit_begin = ub;
-        ub += tab[i].n;
+        // work units: individuals, or pairs of individuals two to a wave
+        const int units = g == 3 ? (tab[i].n + 1) / 2 : tab[i].n;
+        ub += units;
+        plan.part[plan.n_parts - 1].units += units;
         ++plan.part[plan.n_parts - 1].count;
     }
     // each launch runs the kernel specialised for its items' variant when
@@ -332,7 +341,7 @@ int32_t ls_launch(const LsPlan& plan, const LsPlanBuf& buf, void* ws, const dock
     if (st != DOCK_OK) return st;
     SideStream* side = nullptr;
     std::unique_lock<std::mutex> side_lock;
-    const int n_side = side_streams ? plan.n_parts - 1 : 0;   // at most 2
+    const int n_side = side_streams ? plan.n_parts - 1 : 0;   // at most 3
     if (n_side > 0) {
         st = side_stream(side, side_lock);
         if (st != DOCK_OK) return st;
@@ -344,8 +353,7 @@ int32_t ls_launch(const LsPlan& plan, const LsPlanBuf& buf, void* ws, const dock
     for (int k = 0; k < plan.n_parts; ++k) {
         const LsPart& pt = plan.part[k];
         if (pt.count == 0) continue;
-        int64_t units = 0;
-        for (int i = pt.first; i < pt.first + pt.count; ++i) units += tab[i].n;
+        const int64_t units = pt.units;
         int per_cu = docklaunch::ls_blocks_per_cu(pt.mode, pt.variant);
         if (per_cu <= 0) per_cu = 8;
         const int64_t resident = (int64_t)per_cu * n_cu;
@@ -533,7 +541,11 @@ int32_t dock_score_batch(const dock_grids* g, const dock_ligand* l, int32_t n, c
     if (!valid_variant(variant)) return fail(DOCK_EINVAL, "dock_score_batch: unknown variant");
     if (o && o->threads_per_ind != 0 && o->threads_per_ind != 64)
         return fail(DOCK_EUNSUPPORTED, "dock_score_batch: threads_per_ind must be 0 or 64");
-    if (o && o->flags != 0) return fail(DOCK_EINVAL, "dock_score_batch: unknown flags");
+    if (o && (o->flags & ~DOCK_EXEC_TWO_PER_WAVE) != 0) return fail(DOCK_EINVAL, "dock_score_batch: unknown flags");
+    const bool two = o && (o->flags & DOCK_EXEC_TWO_PER_WAVE);
+    if (two && (l->prep.n_atoms > 32 || 7 + l->prep.n_torsions > 32 || variant != DOCK_REDUCE_SHUFFLE))
+        return fail(DOCK_EUNSUPPORTED, "dock_score_batch: two genotypes per wave need <= 32 atoms, <= 32 genes "
+                                       "and the shuffle reduction");
     if (n == 0) return ok();
     if (!gen || !energy) return fail(DOCK_EINVAL, "dock_score_batch: NULL genotypes or energy");
     if (!aligned(gen, 4) || !aligned(energy, 4) || (grad && !aligned(grad, 4)))
@@ -543,8 +555,10 @@ int32_t dock_score_batch(const dock_grids* g, const dock_ligand* l, int32_t n, c
     int32_t n_cu = 0;
     st = device_cu_count(n_cu);
     if (st != DOCK_OK) return st;
-    hipError_t e = docklaunch::launch_score(g->gp, l->blob_dev, l->slots, n, gen, energy, grad, atom_out,
-                                            variant, n_cu, (hipStream_t)stream);
+    hipError_t e = two ? docklaunch::launch_score_two(g->gp, l->blob_dev, n, gen, energy, grad, atom_out, n_cu,
+                                                      (hipStream_t)stream)
+                       : docklaunch::launch_score(g->gp, l->blob_dev, l->slots, n, gen, energy, grad, atom_out,
+                                                  variant, n_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "dock_score_batch launch");
     return ok();
 }

@@ -14,6 +14,10 @@ hipError_t launch_score(const GridParams&, const uint8_t*, int, int, const float
                         hipStream_t) {
     return hipErrorNoDevice;
 }
+hipError_t launch_score_two(const GridParams&, const uint8_t*, int, const float*, float*, float*, float*, int,
+                            hipStream_t) {
+    return hipErrorNoDevice;
+}
 hipError_t launch_ls(const LsParams&, int, int, int, hipStream_t) { return hipErrorNoDevice; }
 int ls_blocks_per_cu(int, int) { return 0; }
 hipError_t launch_block_sum4(const float*, float*, int, int, int, int, hipStream_t) { return hipErrorNoDevice; }

@@ -1290,6 +1290,462 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two individuals per wave, for ligands of at most 32 atoms and 25 torsions
+// (G = 7 + T <= 32 genes): each 32-lane half of the wave holds one
+// individual, lane j of half h holding atom j and gene j of individual h.
+// The per-atom stages then fill twice as many lanes as with one individual
+// per wave, and the per-evaluation tail (block sum, prefix scans, gradient
+// assembly, update) serves two individuals. The pair phase walks the same
+// 64-record batches in two steps of 32 records, each half adding forces to
+// its own accumulator slots (the slots of a batch are distinct, so those of
+// a half-batch are too). The block sum is the wavefront shuffle over each
+// half; the halves never exchange values, so an individual's result does
+// not depend on the other half.
+// ---------------------------------------------------------------------------
+constexpr int kHalf = 32;
+
+struct __align__(16) Smem2 {
+    float4 dyn[2][kHalf];               // per half: positions relative to t, sqrt(kElec) q
+    union {
+        float tk[2][kMaxTors + 1][12];  // per half: torsion transforms, identity at kMaxTors
+        float4 acc[2][dockblob::kMaxSlotsSmall];  // per half: pair-force accumulators
+    } u;
+    float4 tor[kMaxTors][2];
+    uint32_t chain[kMaxFrag][kChain / 4];
+};
+
+__device__ __forceinline__ float hsel(float a, float b) { return lane_id() < kHalf ? a : b; }
+
+// Lane c of this lane's half.
+__device__ __forceinline__ float half_lane(float v, int c) { return hsel(readlane(v, c), readlane(v, kHalf + c)); }
+
+// Sum over this lane's half, every lane of the half receives it: row sums by
+// a DPP butterfly, then row 0 into row 1 and row 2 into row 3.
+__device__ __forceinline__ float half_sum(float v) {
+    v += dpp<0xB1>(v);         // quad_perm [1,0,3,2]
+    v += dpp<0x4E>(v);         // quad_perm [2,3,0,1]
+    v += dpp<0x141>(v);        // row_half_mirror
+    v += dpp<0x140>(v);        // row_mirror
+    v += dpp<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    return hsel(readlane(v, kHalf - 1), readlane(v, 2 * kHalf - 1));
+}
+
+// Inclusive prefix sum within each half.
+__device__ __forceinline__ float half_scan(float v) {
+    v += dpp<0x111>(v);          // row_shr:1
+    v += dpp<0x112>(v);          // row_shr:2
+    v += dpp<0x114>(v);          // row_shr:4
+    v += dpp<0x118>(v);          // row_shr:8
+    v += dpp<0x142, 0xa>(v);     // row_bcast:15 into rows 1 and 3
+    return v;
+}
+
+// The ligand as a two-individual wave holds it: lane j of either half the
+// atom j (per-lane registers), the shared torsion and fragment tables in LDS.
+__device__ void load_ligand2(const uint8_t* __restrict__ blob, Smem2& sm, Lig<1>& L, bool fill_lds = true) {
+    if (fill_lds) __syncthreads();  // previous users of the LDS tables are done
+    const Header* h = reinterpret_cast<const Header*>(blob);
+    const int lane = lane_id();
+    L.wv = 0;
+    L.N = uniform(h->n_atoms);
+    L.T = uniform(h->n_torsions);
+    L.NF = uniform(h->n_frag);
+    L.G = uniform(h->n_genes);
+    L.n_batches = uniform(h->n_batches);
+    L.n_copies = uniform(h->n_copies);
+    L.max_depth = uniform(h->max_depth);
+    L.stride = uniform(h->slot_stride);
+    L.pmask = L.stride * 16 - 1;
+    L.plist = uniform_ptr(reinterpret_cast<const u32x4*>(blob + h->off_plist));
+    const float4* ref = reinterpret_cast<const float4*>(blob + h->off_ref);
+    const float4* chg = reinterpret_cast<const float4*>(blob + h->off_chg);
+    const int4* iv = reinterpret_cast<const int4*>(blob + h->off_int);
+    const int a = lane & (kHalf - 1);
+    const bool ok = a < L.N;
+    const int ai = ok ? a : 0;
+    const float4 r = ref[ai], c = chg[ai];
+    const int4 ii = iv[ai];
+    L.y0[0][0] = r.x; L.y0[0][1] = r.y; L.y0[0][2] = r.z;
+    L.chg[0][0] = ok ? c.x : 0.f; L.chg[0][1] = ok ? c.y : 0.f; L.chg[0][2] = ok ? c.z : 0.f;
+    L.cls[0] = ii.x;
+    L.frag[0] = ii.y;
+    L.orig[0] = ii.z;
+    const Torsion* tr = reinterpret_cast<const Torsion*>(blob + h->off_tors);
+    if (fill_lds && lane < L.T) {
+        const Torsion t = tr[lane];
+        const int pk = t.a_pos | (t.b_pos << 8) | (t.first << 16) | (t.end << 24);
+        sm.tor[lane][0] = make_float4(t.p[0], t.p[1], t.p[2], __int_as_float(pk));
+        sm.tor[lane][1] = make_float4(t.u[0], t.u[1], t.u[2], 0.f);
+    }
+    const uint32_t* ch = reinterpret_cast<const uint32_t*>(blob + h->off_chain);
+    const int n_chain_words = L.NF * (kChain / 4);
+    uint32_t* dst = &sm.chain[0][0];
+    if (fill_lds)
+        for (int i = lane; i < n_chain_words; i += kWave) dst[i] = ch[i];
+    __syncthreads();
+}
+
+// One evaluation of E and dE/dgenotype for the two individuals of the wave.
+// `gene` is gene j of this lane's individual (j = lane % 32; j >= G
+// ignored); returns this half's E and writes this lane's gradient component
+// to `grad`. atom_out: this half's per-atom output (or nullptr).
+template <bool ANY_LAYOUT, bool GRAD = true>
+__device__ float evaluate2(const GridParams& G, Smem2& sm, const Lig<1>& L, float gene, float& grad,
+                           float* atom_out) {
+    const int lane = lane_id();
+    const int j = lane & (kHalf - 1);
+    const int h = lane >> 5;
+    const int hb = h * kHalf;
+    const int N = L.N;
+    const float tx = half_lane(gene, 0), ty = half_lane(gene, 1), tz = half_lane(gene, 2);
+    const float qw0 = half_lane(gene, 3), qx0 = half_lane(gene, 4), qy0 = half_lane(gene, 5),
+                qz0 = half_lane(gene, 6);
+    const float qinv = __builtin_amdgcn_rsqf(qw0 * qw0 + qx0 * qx0 + qy0 * qy0 + qz0 * qz0);
+    const float qw = qw0 * qinv, qx = qx0 * qinv, qy = qy0 * qinv, qz = qz0 * qinv;
+    float Rq[9];
+    Rq[0] = 1.f - 2.f * (qy * qy + qz * qz);
+    Rq[1] = 2.f * (qx * qy - qw * qz);
+    Rq[2] = 2.f * (qx * qz + qw * qy);
+    Rq[3] = 2.f * (qx * qy + qw * qz);
+    Rq[4] = 1.f - 2.f * (qx * qx + qz * qz);
+    Rq[5] = 2.f * (qy * qz - qw * qx);
+    Rq[6] = 2.f * (qx * qz - qw * qy);
+    Rq[7] = 2.f * (qy * qz + qw * qx);
+    Rq[8] = 1.f - 2.f * (qx * qx + qy * qy);
+
+    // torsion transforms of this half's individual (T <= 25, so lane 31 of
+    // each half is free to write the identity)
+    const float psi = __shfl(gene, hb + ((7 + j) & (kHalf - 1)));
+    if (j < L.T) {
+        float sn, cs;
+        sincosf(psi, &sn, &cs);
+        const float4 tp4 = sm.tor[j][0], tu4 = sm.tor[j][1];
+        const float tp[3] = {tp4.x, tp4.y, tp4.z};
+        const float ux = tu4.x, uy = tu4.y, uz = tu4.z;
+        const float oc = 1.f - cs;
+        float Rk[9];
+        Rk[0] = cs + oc * ux * ux;      Rk[1] = oc * ux * uy - sn * uz; Rk[2] = oc * ux * uz + sn * uy;
+        Rk[3] = oc * uy * ux + sn * uz; Rk[4] = cs + oc * uy * uy;      Rk[5] = oc * uy * uz - sn * ux;
+        Rk[6] = oc * uz * ux - sn * uy; Rk[7] = oc * uz * uy + sn * ux; Rk[8] = cs + oc * uz * uz;
+        float* o = sm.u.tk[h][j];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            o[4 * r + 0] = Rk[3 * r + 0];
+            o[4 * r + 1] = Rk[3 * r + 1];
+            o[4 * r + 2] = Rk[3 * r + 2];
+            o[4 * r + 3] = tp[r] - (Rk[3 * r] * tp[0] + Rk[3 * r + 1] * tp[1] + Rk[3 * r + 2] * tp[2]);
+        }
+    } else if (j == kHalf - 1) {
+        float4* o = reinterpret_cast<float4*>(sm.u.tk[h][kMaxTors]);
+        o[0] = make_float4(1.f, 0.f, 0.f, 0.f);
+        o[1] = make_float4(0.f, 1.f, 0.f, 0.f);
+        o[2] = make_float4(0.f, 0.f, 1.f, 0.f);
+    }
+    __syncthreads();
+    // atom positions relative to the rotation centre, as in `evaluate`
+    const float tv[3] = {tx, ty, tz};
+    const int n_duos = (L.max_depth + 1) >> 1;
+    float x[3];
+    {
+        float y0 = L.y0[0][0], y1 = L.y0[0][1], y2 = L.y0[0][2];
+        const uint32_t* row = sm.chain[L.frag[0]];
+        const char* tkh = reinterpret_cast<const char*>(sm.u.tk[h]);
+        for (int d = 0; d < n_duos; ++d) {
+            const uint32_t w = row[d >> 1] >> (16 * (d & 1));
+            float4 T[2][3];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const unsigned k = (w >> (8 * q)) & 255u;
+                const float4* t = reinterpret_cast<const float4*>(
+                    __builtin_assume_aligned(tkh + __umul24(k, 48u), 16));
+                T[q][0] = t[0]; T[q][1] = t[1]; T[q][2] = t[2];
+            }
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const float z0 = fmaf(T[q][0].x, y0, fmaf(T[q][0].y, y1, fmaf(T[q][0].z, y2, T[q][0].w)));
+                const float z1 = fmaf(T[q][1].x, y0, fmaf(T[q][1].y, y1, fmaf(T[q][1].z, y2, T[q][1].w)));
+                const float z2 = fmaf(T[q][2].x, y0, fmaf(T[q][2].y, y1, fmaf(T[q][2].z, y2, T[q][2].w)));
+                y0 = z0; y1 = z1; y2 = z2;
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r) x[r] = Rq[3 * r] * y0 + Rq[3 * r + 1] * y1 + Rq[3 * r + 2] * y2;
+        // entries past the last atom hold zeros (unused pair lanes may read them)
+        sm.dyn[h][j] = j < N ? make_float4(x[0], x[1], x[2], kSqrtElec * L.chg[0][1])
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    __syncthreads();
+
+    float g[3] = {0.f, 0.f, 0.f};
+    float e_lane = 0.f;
+    GridTaps tap;
+    float4* const dynh = sm.dyn[h];
+    float4* const acch = sm.u.acc[h];
+    const int pmask = L.pmask;
+    auto pos_i = [&](uint32_t w) { return *slot(dynh, w & pmask); };
+    auto pos_j = [&](uint32_t w) { return *slot(dynh, (w >> dockblob::kSlotShift) & pmask); };
+    if constexpr (GRAD) {
+        const int nslot = L.n_copies * L.stride;
+        for (int k = j; k < nslot; k += kHalf) acch[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+        __syncthreads();
+    }
+    // pair terms: step s takes records 32 (s % 2) .. 32 (s % 2) + 31 of
+    // batch s / 2, record j for lane j of either half. Software pipeline:
+    // step s reads the positions of step s + 1 before computing its own pair
+    // and loads the record of step s + 4 (register sets indexed by s mod 4
+    // and mod 2, steps unrolled by four, no loaded value copied between
+    // steps); prefetch indices are clamped to the last step.
+    const int ns = 2 * L.n_batches;
+    if (ns > 0) {
+        const __amdgpu_buffer_rsrc_t prsrc = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<u32x4*>(L.plist), 0, ns * kHalf * (int)sizeof(u32x4), kBufferWord3);
+        const int lane_off = j * (int)sizeof(u32x4);
+        auto record = [&](int s) -> u32x4 {
+            return __builtin_amdgcn_raw_buffer_load_b128(
+                prsrc, lane_off, uniform(min(s, ns - 1)) * kHalf * (int)sizeof(u32x4), 0);
+        };
+        u32x4 R[4];
+        float4 Pi[2], Pj[2];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) R[q] = record(q);
+        Pi[0] = pos_i(R[0].x);
+        Pj[0] = pos_j(R[0].x);
+        int s = 0;
+        auto step = [&](auto residue, auto load) {
+            constexpr int r = decltype(residue)::value;  // s mod 4
+            constexpr int c = r & 1, n = (r + 1) & 1;
+            const u32x4 rn = R[(r + 1) & 3];
+            Pi[n] = pos_i(rn.x);
+            Pj[n] = pos_j(rn.x);
+            __builtin_amdgcn_sched_barrier(0);
+            const PairForce F = pair_force(R[r], Pi[c], Pj[c]);
+            if constexpr (GRAD) {
+                const float4 ai = *slot(acch, F.si);
+                const float4 aj = *slot(acch, F.sj);
+                store_force(acch, F, ai, aj);
+            }
+            e_lane += F.e;
+            if constexpr (decltype(load)::value != 0) R[r] = record(s + 4);
+            __builtin_amdgcn_sched_barrier(0);
+            ++s;
+        };
+        using I0 = IntC<0>;
+        using I1 = IntC<1>;
+        using I2 = IntC<2>;
+        using I3 = IntC<3>;
+        using Load = IntC<1>;
+        using NoLoad = IntC<0>;
+        while (s + 4 <= ns) { step(I0(), Load()); step(I1(), Load()); step(I2(), Load()); step(I3(), Load()); }
+        __builtin_amdgcn_sched_barrier(0);
+        grid_load<ANY_LAYOUT>(G, L.cls[0], x, tv, tap);
+        __builtin_amdgcn_sched_barrier(0);
+        if (s < ns) step(I0(), NoLoad());
+        if (s < ns) step(I1(), NoLoad());
+        if (s < ns) step(I2(), NoLoad());
+    } else {
+        grid_load<ANY_LAYOUT>(G, L.cls[0], x, tv, tap);
+    }
+    if constexpr (GRAD) {
+        __syncthreads();
+        // each atom adds its copies in copy order
+        if (j < N)
+            for (int c = 0; c < L.n_copies; ++c) {
+                const float4 v = acch[c * L.stride + j];
+                g[0] += v.x;
+                g[1] += v.y;
+                g[2] += v.z;
+            }
+    }
+    // grid term
+    float e_atom;
+    {
+        float e, gx, gy, gz;
+        grid_term(G, tap, L.chg[0][1], L.chg[0][2], x, tv, e, gx, gy, gz);
+        const bool ok = j < N;
+        e_atom = ok ? e : 0.f;
+        g[0] = ok ? g[0] + gx : 0.f;
+        g[1] = ok ? g[1] + gy : 0.f;
+        g[2] = ok ? g[2] + gz : 0.f;
+        e_lane += e_atom;
+    }
+    if constexpr (!GRAD) {
+        grad = 0.f;
+        __syncthreads();   // the next evaluation rewrites the position table
+        return half_sum(e_lane);
+    }
+    // block sum of {E, gx, gy, gz} over each half (wavefront shuffle)
+    const float4 EG = make_float4(half_sum(e_lane), half_sum(g[0]), half_sum(g[1]), half_sum(g[2]));
+    // torsion torques: prefix sums of (g, x cross g) within each half; the
+    // half's last lane gives the torque about t
+    float P[6];
+    P[0] = g[0]; P[1] = g[1]; P[2] = g[2];
+    P[3] = x[1] * g[2] - x[2] * g[1];
+    P[4] = x[2] * g[0] - x[0] * g[2];
+    P[5] = x[0] * g[1] - x[1] * g[0];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) P[c] = half_scan(P[c]);
+    const float4 TQ = make_float4(half_lane(P[3], kHalf - 1), half_lane(P[4], kHalf - 1),
+                                  half_lane(P[5], kHalf - 1), 0.f);
+    float gpsi = 0.f;
+    {
+        const int pk = j < L.T ? __float_as_int(sm.tor[j][0].w) : (1 << 16) | (1 << 24);
+        const int t_apos = pk & 255, t_bpos = (pk >> 8) & 255;
+        const int hi = ((pk >> 24) & 255) - 1, lo = ((pk >> 16) & 255) - 1;
+        float S[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+            S[c] = __shfl(P[c], hb + (hi & (kHalf - 1))) - __shfl(P[c], hb + (lo & (kHalf - 1)));
+        const float4 xa = dynh[t_apos & (kHalf - 1)];
+        const float4 xb = dynh[t_bpos & (kHalf - 1)];
+        float ux = xb.x - xa.x, uy = xb.y - xa.y, uz = xb.z - xa.z;
+        const float il = __builtin_amdgcn_rsqf(ux * ux + uy * uy + uz * uz);
+        ux *= il; uy *= il; uz *= il;
+        const float mx = S[3] - (xa.y * S[2] - xa.z * S[1]);
+        const float my = S[4] - (xa.z * S[0] - xa.x * S[2]);
+        const float mz = S[5] - (xa.x * S[1] - xa.y * S[0]);
+        gpsi = (j < L.T) ? ux * mx + uy * my + uz * mz : 0.f;
+    }
+    {
+        const float k2 = 2.0f * qinv;
+        const float gw = -(TQ.x * qx + TQ.y * qy + TQ.z * qz);
+        const float gqx = qw * TQ.x + (TQ.y * qz - TQ.z * qy);
+        const float gqy = qw * TQ.y + (TQ.z * qx - TQ.x * qz);
+        const float gqz = qw * TQ.z + (TQ.x * qy - TQ.y * qx);
+        const float gt = __shfl(gpsi, hb + ((j - 7) & (kHalf - 1)));
+        float gr = gt;
+        gr = j == 0 ? EG.y : gr;
+        gr = j == 1 ? EG.z : gr;
+        gr = j == 2 ? EG.w : gr;
+        gr = j == 3 ? k2 * gw : gr;
+        gr = j == 4 ? k2 * gqx : gr;
+        gr = j == 5 ? k2 * gqy : gr;
+        gr = j == 6 ? k2 * gqz : gr;
+        grad = gr;
+    }
+    if (atom_out && j < N) {
+        float4* o = reinterpret_cast<float4*>(atom_out) + 2 * L.orig[0];
+        o[0] = make_float4(x[0], x[1], x[2], e_atom);
+        o[1] = make_float4(g[0], g[1], g[2], 0.f);
+    }
+    return EG.x;
+}
+
+// ADADELTA local search of the two individuals ind0 and ind0 + 1 of an item
+// (count = 1: only the first; the second half then mirrors the first and
+// writes nothing). The steps are those of local_search_one.
+template <bool ANY_LAYOUT>
+__device__ void local_search_two(const DevItem& it, int ind0, int count, Smem2& sm, const Lig<1>& L,
+                                 int iterations, float rho, float eps, bool final_eval) {
+    const int lane = lane_id();
+    const int j = lane & (kHalf - 1);
+    const int h = lane >> 5;
+    const bool live = h < count;
+    const int ind = ind0 + (live ? h : 0);
+    const int G = L.G;
+    const bool act = j < G;
+    const size_t o = (size_t)ind * G + j;
+    float x = act ? it.genotype[o] : 0.f;
+    float ag = act ? it.acc_g2[o] : 0.f;
+    float ad = act ? it.acc_dx2[o] : 0.f;
+    float bx = act ? it.best_genotype[o] : 0.f;
+    float bestE = it.best_energy[ind];
+    float lastE = it.energy[ind];
+    float lastG = 0.f;
+    for (int iter = 0; iter < iterations; ++iter) {
+        float gr;
+        const float E = evaluate2<ANY_LAYOUT>(it.grid, sm, L, x, gr, nullptr);
+        lastE = E;
+        lastG = gr;
+        if (E < bestE) { bestE = E; bx = x; }
+        gr = act ? gr : 0.f;
+        ag = rho * ag + (1.f - rho) * gr * gr;
+        const float dx = -(__builtin_amdgcn_sqrtf(ad + eps) * __builtin_amdgcn_rsqf(ag + eps)) * gr;
+        ad = rho * ad + (1.f - rho) * dx * dx;
+        float xn = x + dx;
+        const bool isq = j >= 3 && j < 7;
+        const float q2 = isq ? xn * xn : 0.f;
+        const float nq2 = (half_lane(q2, 3) + half_lane(q2, 4)) + (half_lane(q2, 5) + half_lane(q2, 6));
+        if (isq) xn = (nq2 >= 1e-12f) ? xn * __builtin_amdgcn_rsqf(nq2) : x;
+        x = act ? xn : 0.f;
+    }
+    if (final_eval) {
+        float gr;
+        const float E = evaluate2<ANY_LAYOUT>(it.grid, sm, L, x, gr, nullptr);
+        lastE = E;
+        lastG = gr;
+        if (E < bestE) { bestE = E; bx = x; }
+    }
+    if (!live) return;
+    if (act && it.grad && (iterations > 0 || final_eval)) it.grad[o] = lastG;
+    if (act) {
+        it.genotype[o] = x;
+        it.acc_g2[o] = ag;
+        it.acc_dx2[o] = ad;
+        it.best_genotype[o] = bx;
+    }
+    if (j == 0) {
+        it.best_energy[ind] = bestE;
+        it.energy[ind] = lastE;
+        it.iters_done[ind] += iterations;
+    }
+}
+
+// Persistent local-search kernel, two individuals per wave: work units are
+// pairs of individuals of one item ((n + 1) / 2 per item), pulled from the
+// counter as in ls_kernel.
+template <bool ANY_LAYOUT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void ls_kernel_two(LsParams p) {
+    __shared__ Smem2 sm;
+    int cur_item = -1;
+    while (true) {
+        int u = 0;
+        if (lane_id() == 0) u = atomicAdd(p.counter, 1);
+        u = uniform(u);
+        if (u >= p.total_units) break;
+        int lo = 0, hi = p.n_items - 1;
+        while (lo < hi) {  // last item with unit_begin <= u
+            const int mid = (lo + hi + 1) >> 1;
+            if (uniform(gmem(&p.items[mid].unit_begin)[0]) <= u) lo = mid; else hi = mid - 1;
+        }
+        const DevItem it = load_item(p.items, lo);
+        const int ind0 = 2 * (u - it.unit_begin);
+        const int count = min(2, it.n - ind0);
+        const bool reload = lo != cur_item;
+        cur_item = lo;
+        Lig<1> L;
+        load_ligand2(it.blob, sm, L, reload);
+        local_search_two<ANY_LAYOUT>(it, ind0, count, sm, L, it.iterations, p.rho, p.eps, it.final_eval != 0);
+    }
+}
+
+// Persistent scoring kernel, two genotypes per wave (ind = 2 k + half).
+template <bool ANY_LAYOUT>
+__global__ __launch_bounds__(64, 3) void score_kernel_two(GridParams G, const uint8_t* __restrict__ blob, int n,
+                                                          const float* __restrict__ gen,
+                                                          float* __restrict__ energy,
+                                                          float* __restrict__ grad,
+                                                          float* __restrict__ atom_out) {
+    __shared__ Smem2 sm;
+    Lig<1> L;
+    load_ligand2(blob, sm, L);
+    const int lane = lane_id();
+    const int j = lane & (kHalf - 1);
+    const int h = lane >> 5;
+    const int G_ = L.G;
+    const int n_pairs = (n + 1) >> 1;
+    for (int k = blockIdx.x; k < n_pairs; k += gridDim.x) {
+        const bool live = 2 * k + h < n;
+        const int ind = live ? 2 * k + h : 2 * k;
+        const float gene = j < G_ ? gen[(size_t)ind * G_ + j] : 0.f;
+        float gr;
+        float* ao = (atom_out && live) ? atom_out + (size_t)ind * L.N * 8 : nullptr;
+        const float E = evaluate2<ANY_LAYOUT>(G, sm, L, gene, gr, ao);
+        if (live && j == 0) energy[ind] = E;
+        if (live && grad && j < G_) grad[(size_t)ind * G_ + j] = gr;
+    }
+}
+
 // Sum over the first 16-lane row (lanes 16..63 ignored), every lane receives it.
 __device__ __forceinline__ float row0_sum(float v) {
     v += dpp<0xB1>(v);    // quad_perm [1,0,3,2]
@@ -1435,6 +1891,9 @@ const void* ls_kernel_2w_ptr(int var) {
 }
 
 const void* ls_kernel_for(int mode, int var) {
+    if (mode == docklaunch::kTwoPerWave)
+        return var == DOCK_REDUCE_SHUFFLE ? reinterpret_cast<const void*>(&ls_kernel_two<false>)
+                                          : reinterpret_cast<const void*>(&ls_kernel_two<true>);
     if (mode == docklaunch::kTwoWave) return ls_kernel_2w_ptr(var);
     if (mode == docklaunch::kSlots1) return ls_kernel_ptr<docklaunch::kSlots1>(var);
     if (mode == docklaunch::kSlots2) return ls_kernel_ptr<docklaunch::kSlots2>(var);
@@ -1456,6 +1915,31 @@ hipError_t launch_score(const GridParams& g, const uint8_t* blob, int slots, int
         case DOCK_REDUCE_MFMA_BF16X3: return launch_score_v<4>(g, blob, slots, n, genotypes, energy, grad, atom_out, n_cu, stream);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_score_two(const GridParams& g, const uint8_t* blob, int n, const float* genotypes,
+                            float* energy, float* grad, float* atom_out, int n_cu, hipStream_t stream) {
+    const bool any = g.corners == nullptr;
+    const void* k = any ? reinterpret_cast<const void*>(&score_kernel_two<true>)
+                        : reinterpret_cast<const void*>(&score_kernel_two<false>);
+    static std::atomic<int> cached[2];
+    int per_cu = cached[any ? 1 : 0].load(std::memory_order_relaxed);
+    if (per_cu <= 0) {
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 64, 0) != hipSuccess || per_cu <= 0) per_cu = 2;
+        cached[any ? 1 : 0].store(per_cu, std::memory_order_relaxed);
+    }
+    const long long pairs = ((long long)n + 1) / 2;
+    const long long resident = (long long)per_cu * (n_cu > 0 ? n_cu : 256);
+    const int blocks = (int)(pairs < resident ? pairs : resident);
+    GridParams gg = g;
+    const uint8_t* bb = blob;
+    int nn = n;
+    const float* gen = genotypes;
+    float* e = energy;
+    float* gr = grad;
+    float* ao = atom_out;
+    void* args[] = {&gg, &bb, &nn, &gen, &e, &gr, &ao};
+    return hipLaunchKernel(k, dim3(blocks), dim3(64), args, 0, stream);
 }
 
 hipError_t launch_sw(const GridParams& g, const uint8_t* blob, int slots, int variant, const SwParams& p,
@@ -1487,8 +1971,8 @@ hipError_t launch_ls(const LsParams& p, int mode, int variant_uniform, int grid_
 int ls_blocks_per_cu(int mode, int variant_uniform) {
     // cached per (mode, variant): the occupancy query costs host time on
     // every call otherwise
-    static std::atomic<int> cache[5][DOCK_REDUCE_COUNT + 1];
-    const int m = mode >= 0 && mode < 5 ? mode : 0;
+    static std::atomic<int> cache[docklaunch::kLsModes][DOCK_REDUCE_COUNT + 1];
+    const int m = mode >= 0 && mode < docklaunch::kLsModes ? mode : 0;
     const int v = variant_uniform >= 0 && variant_uniform < DOCK_REDUCE_COUNT ? variant_uniform : DOCK_REDUCE_COUNT;
     int nb = cache[m][v].load(std::memory_order_relaxed);
     if (nb > 0) return nb;

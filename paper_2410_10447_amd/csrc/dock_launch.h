@@ -52,8 +52,10 @@ struct LsParams {
 constexpr int64_t kWorkspaceHeader = 64;
 
 // ls kernel families: slots 1, slots 2, or both (runtime per item), all one
-// wave per individual; or two waves per individual (ligands of 65..128 atoms)
-enum LsMode { kSlots1 = 1, kSlots2 = 2, kSlotsAny = 3, kTwoWave = 4 };
+// wave per individual; two waves per individual; or two individuals per
+// wave (ligands of <= 32 atoms and <= 32 genes, shuffle reduction)
+enum LsMode { kSlots1 = 1, kSlots2 = 2, kSlotsAny = 3, kTwoWave = 4, kTwoPerWave = 5 };
+constexpr int kLsModes = 6;
 
 inline int ls_block_threads(int mode) { return mode == kTwoWave ? 128 : 64; }
 
@@ -62,6 +64,10 @@ inline int ls_block_threads(int mode) { return mode == kTwoWave ? 128 : 64; }
 hipError_t launch_score(const GridParams& g, const uint8_t* blob, int slots, int n,
                         const float* genotypes, float* energy, float* grad, float* atom_out,
                         int variant, int n_cu, hipStream_t stream);
+// Two genotypes per wave (ligands of <= 32 atoms and <= 32 genes; the
+// shuffle reduction).
+hipError_t launch_score_two(const GridParams& g, const uint8_t* blob, int n, const float* genotypes,
+                            float* energy, float* grad, float* atom_out, int n_cu, hipStream_t stream);
 
 // variant_uniform: DOCK_REDUCE_* when every item uses it, -1 for mixed items.
 hipError_t launch_ls(const LsParams& p, int mode, int variant_uniform, int grid_blocks,

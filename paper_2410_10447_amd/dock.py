@@ -19,7 +19,7 @@ _LIB_PATH = os.environ.get("DOCKMI_LIB") or os.path.join(os.path.dirname(os.path
                                                          "libdockmi.so")
 
 # the struct layouts below follow include/dock.h of this ABI version
-ABI_VERSION = 8
+ABI_VERSION = 9
 
 DOCK_OK = 0
 DOCK_EINVAL = -1
@@ -38,6 +38,8 @@ VARIANT_NAMES = {0: "shuffle", 1: "mfma_f32", 2: "mfma_bf16", 3: "mfma_f16", 4: 
 
 LS_FINAL_EVAL = 1
 ITEM_PLAIN_MAPS = 1     # dock_ls_item.flags: read the planar maps
+ITEM_TWO_PER_WAVE = 2   # dock_ls_item.flags: two individuals per wave (<= 32 atoms, <= 32 genes)
+EXEC_TWO_PER_WAVE = 1   # dock_exec_opts.flags: two genotypes per wave
 STATIC_MAX_ITEMS = 64   # items per dock_local_search_batch_static call
 
 MAX_ATOMS = 128
@@ -366,8 +368,10 @@ class Ligand:
 # ---------------------------------------------------------------------------
 
 def score_batch(grids: Grids, ligand: Ligand, genotypes, variant: int = REDUCE_SHUFFLE,
-                with_grad: bool = True, atom_out: bool = False, stream=None):
-    """Energy [n] and gradient [n, G] of each genotype row (float32 CUDA tensor)."""
+                with_grad: bool = True, atom_out: bool = False, stream=None, two_per_wave: bool = False):
+    """Energy [n] and gradient [n, G] of each genotype row (float32 CUDA tensor).
+    `two_per_wave`: two genotypes per wave (ligands of <= 32 atoms and <= 32
+    genes, the shuffle reduction)."""
     import torch
     if genotypes.dim() != 2 or genotypes.shape[1] != ligand.n_genes:
         raise ValueError(f"genotypes must be [n, {ligand.n_genes}]")
@@ -377,7 +381,7 @@ def score_batch(grids: Grids, ligand: Ligand, genotypes, variant: int = REDUCE_S
     E = torch.empty(n, dtype=torch.float32, device=gen.device)
     grad = torch.empty(n, ligand.n_genes, dtype=torch.float32, device=gen.device) if with_grad else None
     ao = torch.empty(n, ligand.n_atoms, 8, dtype=torch.float32, device=gen.device) if atom_out else None
-    o = ExecOpts(variant=variant, threads_per_ind=0, flags=0,
+    o = ExecOpts(variant=variant, threads_per_ind=0, flags=EXEC_TWO_PER_WAVE if two_per_wave else 0,
                  atom_out=(ao.data_ptr() if ao is not None else None))
     _check(lib().dock_score_batch(grids.handle, ligand.handle, n, _ptr(gen), _ptr(E), _ptr(grad),
                                   C.byref(o), _stream_handle(stream)))
@@ -454,6 +458,7 @@ class LsJob:
     grad: object = None          # optional [n, G] CUDA tensor: gradient at the last evaluated point
     threads_per_ind: int = 0     # 64 or 128, 0 defers to the call
     plain_maps: bool = False     # read the planar maps even with the corner copy bound
+    two_per_wave: bool = False   # two individuals per wave (ligands of <= 32 atoms and <= 32 genes)
 
 
 def _as_job(job):
@@ -494,7 +499,7 @@ def make_items(jobs):
         it.energy = st.energy.data_ptr()
         it.iters_done = st.iters_done.data_ptr()
         it.grad = j.grad.data_ptr() if j.grad is not None else None
-        it.flags = ITEM_PLAIN_MAPS if j.plain_maps else 0
+        it.flags = (ITEM_PLAIN_MAPS if j.plain_maps else 0) | (ITEM_TWO_PER_WAVE if j.two_per_wave else 0)
     return arr
 
 

@@ -320,20 +320,23 @@ class GpuExecutor:
         with torch.cuda.stream(self.stream):
             gen = host.to(self.device, non_blocking=True)
             st = self.dock.LSState.start(gen)
-        var, tpi, plain = -1, 0, False
+        var, tpi, plain, two = -1, 0, False, False
         if self.use_table:
             from . import autotune
             pick = autotune.choose(L.n_atoms, L.n_torsions)
             var = int(pick["variant"])
             tpi = int(pick.get("threads_per_ind", 64))
             plain = bool(pick.get("plain_maps", False))
+            two = bool(pick.get("two_per_wave", False))
         return {"ligand": L, "state": st, "grids": self.grids[spec.grid_id], "host": host,
-                "variant": var, "threads_per_ind": tpi, "plain_maps": plain}
+                "variant": var, "threads_per_ind": tpi, "plain_maps": plain,
+                "two_per_wave": two if self.use_table else False}
 
     def launch(self, plan, max_iters):
         jobs = [self.dock.LsJob(h["grids"], h["ligand"], h["state"], h["variant"], k, 1 if fin else 0,
                                 threads_per_ind=h.get("threads_per_ind", 0),
-                                plain_maps=h.get("plain_maps", False))
+                                plain_maps=h.get("plain_maps", False),
+                                two_per_wave=h.get("two_per_wave", False))
                 for h, k, fin in plan]
         need = self.dock.workspace_bytes(len(jobs))
         # a workspace per in-flight chunk: reuse one whose chunk has completed

@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(dock.ABI_SYMBOLS)
     for name in declared:
         assert hasattr(L, name)
-    assert L.dock_abi_version() == dock.ABI_VERSION == 8
+    assert L.dock_abi_version() == dock.ABI_VERSION == 9
 
 
 def _check_prep(lig):
@@ -383,6 +383,19 @@ def test_batch_calls_validate_before_device_work():
         ob = dock.LsOpts(**kw)
         assert L.dock_local_search_batch(item, 1, C.byref(ob), fake, 1 << 20, None) in (
             dock.DOCK_EINVAL, dock.DOCK_EUNSUPPORTED)
+    # two individuals per wave: only for ligands of <= 32 atoms and 32 genes
+    big = dock.Ligand(synth.ligand(40, 3, 9), FF, upload=False)
+    item2 = (dock.LsItem * 1)()
+    item2[0].grids = g.value
+    item2[0].ligand = big.handle.value
+    item2[0].n = 4
+    item2[0].n_genes = big.n_genes
+    item2[0].variant = -1
+    item2[0].flags = dock.ITEM_TWO_PER_WAVE
+    st = L.dock_local_search_batch(item2, 1, C.byref(o), fake, 1 << 20, None)
+    assert st == dock.DOCK_EUNSUPPORTED and "two individuals" in dock.last_error()
+    item2[0].flags = 4
+    assert L.dock_local_search_batch(item2, 1, C.byref(o), fake, 1 << 20, None) == dock.DOCK_EINVAL
     # the library-resident variant validates the same way, before any device work
     for bad_g in (lig.n_genes - 1, lig.n_genes + 1):
         item[0].n_genes = bad_g

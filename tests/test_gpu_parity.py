@@ -563,7 +563,7 @@ def test_ls_uneven_full_size_sampled(dk):
     states = [dk.LSState.start(torch.from_numpy(g).cuda()) for g in w.genotypes]
     picks = [autotune.choose(L.n_atoms, L.n_torsions) for L in Ls]
     jobs = [dk.LsJob(G, L, st, c["variant"], threads_per_ind=c.get("threads_per_ind", 64),
-                     plain_maps=c.get("plain_maps", False))
+                     plain_maps=c.get("plain_maps", False), two_per_wave=c.get("two_per_wave", False))
             for L, st, c in zip(Ls, states, picks)]
     dk.local_search(jobs, w.iterations)
     torch.cuda.synchronize()
@@ -573,8 +573,136 @@ def test_ls_uneven_full_size_sampled(dk):
         s = st.to_numpy()
         assert np.all(s["iters_done"] == w.iterations)
         prep = R.prepare(lig, w.ff)
-        one_wave = c.get("threads_per_ind", 64) == 64
+        one_wave = c.get("threads_per_ind", 64) == 64 and not c.get("two_per_wave", False)
         reps.append(check_reported(f"uneven full ligand {k} N={L.n_atoms} T={L.n_torsions}", dk, G, L, prep,
                                    w.grids, s["best_genotype"][idx], s["best_energy"][idx],
                                    variant=c["variant"], exact_rescore=one_wave, assert_ok=False))
     assert_reports("uneven full size, 4 best points per ligand", reps)
+
+
+# ---------------------------------------------------------------------------
+# Two individuals per wave (ligands of <= 32 atoms and <= 32 genes)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n_atoms,n_tors,n_gen", [(24, 6, 256), (32, 12, 101), (12, 3, 7), (5, 1, 3),
+                                                  (1, 0, 1), (17, 25, 64)])
+def test_score_two_per_wave_parity(dk, n_atoms, n_tors, n_gen):
+    """Two genotypes per wave (odd counts leave the last wave's second half
+    idle): each against the oracle at the kernel's own positions, and equal
+    bit for bit to the same genotypes scored in another pairing (the halves
+    are independent)."""
+    lig = synth.ligand(n_atoms, n_tors, 7000 + n_atoms)
+    grd = synth.grids(40, 10, 7001)
+    ff = synth.force_field()
+    gen = synth.genotypes(lig, grd, n_gen, 7002)
+    G = dk.Grids.from_synth(grd)
+    L = dk.Ligand(lig, ff)
+    prep = R.prepare(lig, ff)
+    gt = torch.from_numpy(gen).cuda()
+    E, g, ao = dk.score_batch(G, L, gt, atom_out=True, two_per_wave=True)
+    torch.cuda.synchronize()
+    check(f"score two per wave N={n_atoms} T={n_tors} n={n_gen}", prep, grd, gen, E.cpu().numpy(),
+          g.cpu().numpy(), ao.cpu().numpy())
+    # shifted by one: every genotype meets another partner
+    E2, g2 = dk.score_batch(G, L, torch.cat([gt[-1:], gt]), two_per_wave=True)
+    torch.cuda.synchronize()
+    assert torch.equal(E2[1:], E) and torch.equal(g2[1:], g)
+
+
+def test_score_two_per_wave_rejects_large_ligands(dk):
+    w = synth.ls_workload(4)
+    G = dk.Grids.from_synth(w.grids)
+    L = dk.Ligand(w.ligands[0], w.ff)          # 48 atoms
+    gt = torch.from_numpy(w.genotypes[0]).cuda()
+    with pytest.raises(dk.DockError):
+        dk.score_batch(G, L, gt, two_per_wave=True)
+    small = dk.Ligand(synth.ligand(20, 4, 5), w.ff)
+    with pytest.raises(dk.DockError):          # only the shuffle reduction
+        dk.score_batch(G, small, torch.zeros((2, small.n_genes), device="cuda"), variant=1,
+                       two_per_wave=True)
+
+
+def _small_ls_workload(n, n_atoms=24, n_tors=6):
+    lig = synth.ligand(n_atoms, n_tors, 7100 + n_atoms)
+    grd = synth.grids(48, 10, 7101)
+    return synth.Workload(f"ls_n{n_atoms}_t{n_tors}_g48", [lig], grd, synth.force_field(),
+                          [synth.genotypes(lig, grd, n, 7102)], iterations=30)
+
+
+@pytest.mark.parametrize("n_atoms,n_tors", [(24, 6), (32, 20)])
+def test_ls_step_map_two_per_wave(dk, n_atoms, n_tors):
+    """The search step with two individuals per wave (63 individuals: the
+    last wave holds one) against the oracle, as test_ls_step_map."""
+    from tests.gpu_common import assert_reports
+    w = _small_ls_workload(63, n_atoms, n_tors)
+    prep = R.prepare(w.ligands[0], w.ff)
+    G, L, st = _ls_setup(dk, w, 63)
+    grad = torch.zeros_like(st.genotype)
+    ws = None
+    reps, same = [], 0
+    for it in range(12):
+        s0 = st.to_numpy()
+        ws = dk.local_search([dk.LsJob(G, L, st, 0, grad=grad, two_per_wave=True)], 1, final_eval=False,
+                             workspace=ws)
+        torch.cuda.synchronize()
+        s1 = st.to_numpy()
+        g_gpu = grad.cpu().numpy().astype(np.float64)
+        x = s0["genotype"]
+        gt = torch.from_numpy(np.ascontiguousarray(x, np.float32)).cuda()
+        E_s, _, ao = dk.score_batch(G, L, gt, atom_out=True, two_per_wave=True)
+        torch.cuda.synchronize()
+        E_s, ao = E_s.cpu().numpy(), ao.cpu().numpy()
+        same += int(np.sum(E_s.view(np.uint32) == s1["energy"].view(np.uint32)))
+        reps.append(check(f"ls step {it} two per wave N={n_atoms}", prep, w.grids, x, s1["energy"], g_gpu, ao,
+                          0, assert_ok=False))
+        xn, ag, ad = R.adadelta_step(x.astype(np.float64), g_gpu, s0["acc_g2"].astype(np.float64),
+                                     s0["acc_dx2"].astype(np.float64), 0.8, 1e-2)
+        gscale = np.maximum(np.maximum(np.abs(xn), np.abs(x)), np.maximum(np.abs(xn - x), 1e-3))
+        for name, got, want, scale in (("genotype", s1["genotype"], xn, gscale),
+                                       ("acc_g2", s1["acc_g2"], ag, np.abs(ag)),
+                                       ("acc_dx2", s1["acc_dx2"], ad, np.abs(ad))):
+            err = np.abs(got - want) / np.maximum(scale, 1e-30)
+            assert np.all(err <= 1e-5), (it, name, err.max())
+        assert np.all(s1["iters_done"] == it + 1)
+    print(f"\n[ls step-map two per wave N={n_atoms}] search energies equal to a rescoring bit for bit: "
+          f"{same} of {12 * 63}", flush=True)
+    assert same == 12 * 63
+    assert_reports(f"ls step-map two per wave N={n_atoms}", reps)
+
+
+def test_two_per_wave_chunked_alone_and_mixed(dk):
+    """Two individuals per wave: chunked calls equal one call, runs are
+    deterministic, and items give the same state alone and in a batch that
+    mixes every kernel family (one-slot, two-slot, two waves, two per wave)."""
+    w = _small_ls_workload(101)
+    G, L, st_a = _ls_setup(dk, w, 101)
+    st_b, st_c, st_d = st_a.clone(), st_a.clone(), st_a.clone()
+    job = lambda st: dk.LsJob(G, L, st, 0, two_per_wave=True)
+    dk.local_search([job(st_a)], 30, final_eval=True)
+    dk.local_search([job(st_b)], 12, final_eval=False)
+    dk.local_search([job(st_b)], 18, final_eval=True)
+    dk.local_search([job(st_c)], 30, final_eval=True)
+    torch.cuda.synchronize()
+    a, b, c = st_a.to_numpy(), st_b.to_numpy(), st_c.to_numpy()
+    for f in a:
+        assert np.array_equal(a[f], b[f]), f
+        assert np.array_equal(a[f], c[f]), f
+    # mixed with the other families in one call
+    others = []
+    for n_atoms, n_tors, tpi, seed in ((48, 10, 64, 7200), (100, 14, 64, 7300), (90, 12, 128, 7400)):
+        lig = synth.ligand(n_atoms, n_tors, seed)
+        LL = dk.Ligand(lig, w.ff)
+        st = dk.LSState.start(torch.from_numpy(synth.genotypes(lig, w.grids, 40, seed + 1)).cuda())
+        others.append(dk.LsJob(G, LL, st, 0, threads_per_ind=tpi))
+    dk.local_search([job(st_d)] + others, 30, final_eval=True)
+    torch.cuda.synchronize()
+    d = st_d.to_numpy()
+    for f in a:
+        assert np.array_equal(a[f], d[f]), f
+    # and the static-workspace entry point on the same mix
+    st_e = dk.LSState.start(torch.from_numpy(w.genotypes[0][:101]).cuda())
+    dk.local_search_static([job(st_e)], 30, final_eval=True)
+    torch.cuda.synchronize()
+    e = st_e.to_numpy()
+    for f in a:
+        assert np.array_equal(a[f], e[f]), f

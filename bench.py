@@ -340,6 +340,7 @@ def uneven_run(steps, warmup, use_table=True, tpi_override=0):
     if tpi_override:
         for c in pick:
             c["threads_per_ind"] = tpi_override
+            c["two_per_wave"] = False      # two per wave takes one wave per pair of individuals
     evals = sum(g.shape[0] for g in gens) * (w.iterations + 1)
     ws = torch.empty(dock.workspace_bytes(len(Ls)), dtype=torch.uint8, device="cuda")
     runs = []
@@ -368,6 +369,7 @@ def uneven_run(steps, warmup, use_table=True, tpi_override=0):
             "single_launch": not use_table and tpi_override in (0, 64),
             "threads_per_ind_override": tpi_override,
             "two_wave_items": sum(1 for c in pick if c.get("threads_per_ind", 64) == 128),
+            "four_wave_items": sum(1 for c in pick if c.get("threads_per_ind", 64) == 256),
             "plain_map_items": sum(1 for c in pick if c.get("plain_maps", False)),
             "two_per_wave_items": sum(1 for c in pick if c.get("two_per_wave", False)),
             "atoms_mean": float(np.mean([L.n_atoms for L in Ls])),
@@ -420,15 +422,15 @@ def main():
     ap.add_argument("--variants", default="0,1,2,3,4",
                     help="reduction variants to time (0 shuffle, 1 FP32 MFMA, 2 BF16 split, 3 FP16 split, "
                          "4 BF16 x3 split); the headline takes the faster of 0 and 1")
-    ap.add_argument("--tpi", default="64,128",
-                    help="threads per individual of the benchmark runs (64: one wave; 128: two waves "
-                         "splitting the pair batches, timed for the FP32 variants)")
+    ap.add_argument("--tpi", default="64,128,256",
+                    help="threads per individual of the benchmark runs (64: one wave; 128 / 256: two / "
+                         "four waves splitting the pair batches, timed for the FP32 variants)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=48)
     ap.add_argument("--uneven-steps", type=int, default=3,
                     help="timed steps of the uneven 64-ligand batch (0 = skip)")
-    ap.add_argument("--uneven-tpi", type=int, default=0, choices=(0, 64, 128),
-                    help="threads per individual of the uneven batch's ligands over 64 atoms "
+    ap.add_argument("--uneven-tpi", type=int, default=0, choices=(0, 64, 128, 256),
+                    help="threads per individual of every ligand of the uneven batch "
                          "(0 = the autotuning table's choice)")
     ap.add_argument("--serve-seconds", type=float, default=15.0,
                     help="arrival window of the serving run (0 = skip)")
@@ -479,7 +481,8 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
 
-    combos = [(v, 64) for v in variants] + [(v, 128) for v in variants if v in (0, 1) and 128 in tpis]
+    combos = [(v, 64) for v in variants] + [(v, t) for t in (128, 256) for v in variants
+                                            if v in (0, 1) and t in tpis]
     for v, tpi in combos:
         states = [dock.LSState.start(gen0) for _ in range(args.warmup + args.steps)]
         items = [dock.make_items([dock.LsJob(G, L, s, v, threads_per_ind=tpi)]) for s in states]
@@ -507,8 +510,8 @@ def main():
         v, tpi = key
         return dock.VARIANT_NAMES[v] + ("" if tpi == 64 else f"_t{tpi}")
 
-    # the headline is the fastest FP32 reduction (shuffle or FP32 MFMA, one
-    # or two waves per individual); the half-width split variants are
+    # the headline is the fastest FP32 reduction (shuffle or FP32 MFMA, one,
+    # two or four waves per individual); the half-width split variants are
     # reported beside it
     fp32 = [k for k in results if k[0] in (0, 1)] or list(results)
     best_k = max(fp32, key=lambda k: results[k]["evals_per_s"])

@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define DOCK_ABI_VERSION 9
+#define DOCK_ABI_VERSION 10
 
 /* status codes */
 #define DOCK_OK            0
@@ -252,7 +252,7 @@ typedef struct {
     int32_t variant;             /* DOCK_REDUCE_* for this item, or -1 = opts->variant */
     int32_t iterations;          /* steps for this item, 0 .. opts->iterations, or -1 = opts */
     int32_t final_eval;          /* 1/0 overrides DOCK_LS_FINAL_EVAL for this item, -1 = opts */
-    int32_t threads_per_ind;     /* 64 or 128 for this item, 0 = opts->threads_per_ind */
+    int32_t threads_per_ind;     /* 64, 128 or 256 for this item, 0 = opts->threads_per_ind */
     float* genotype;             /* device [n][G] in/out: current point */
     float* acc_g2;               /* device [n][G] in/out: running mean of g^2 (start 0) */
     float* acc_dx2;              /* device [n][G] in/out: running mean of dx^2 (start 0) */
@@ -284,10 +284,10 @@ typedef struct {
     float rho;                   /* decay, 0 < rho < 1 (0.8) */
     float eps;                   /* conditioner, > 0 (1e-2) */
     int32_t variant;             /* default DOCK_REDUCE_* */
-    int32_t threads_per_ind;     /* 0 (= 64), 64 or 128: threads (waves of 64) per
-                                    individual; with 128 the two waves split the
-                                    pair batches (and, past 64 atoms, the atoms);
-                                    256 is not built (DOCK_EUNSUPPORTED) */
+    int32_t threads_per_ind;     /* 0 (= 64), 64, 128 or 256: threads (waves of 64)
+                                    per individual; with 128 or 256 the waves split
+                                    the pair batches (and, past 64 atoms, the first
+                                    two waves the atoms) */
     uint32_t flags;              /* DOCK_LS_FINAL_EVAL */
 } dock_ls_opts;
 
@@ -296,11 +296,12 @@ int32_t dock_ls_workspace_bytes(int32_t n_items, int64_t* bytes);
 
 /* Runs opts->iterations steps (or the item's own count) on every individual
  * of every item in one persistent launch; items are scheduled longest first.
- * Items run in up to three kernel families: ligands of <= 64 atoms (one
- * wave per individual), larger ligands with one wave (two atoms per lane) or
- * any ligand with two waves per individual (128 threads: each wave owns 64
- * atoms, none for the second wave of a ligand of <= 64 atoms, and half of
- * the pair batches). A batch that mixes families (or both one-wave
+ * Items run in up to five kernel families: ligands of <= 64 atoms (one
+ * wave per individual), larger ligands with one wave (two atoms per lane),
+ * any ligand with two or four waves per individual (128 or 256 threads: wave
+ * w owns atoms 64 w .. 64 w + 63, if the ligand has them, and the w-th run
+ * of ceil(batches / waves) pair batches), or two individuals per wave
+ * (DOCK_ITEM_TWO_PER_WAVE). A batch that mixes families (or both one-wave
  * families AND reduction variants) runs as one persistent launch per family,
  * side by side: the first on `stream`, the others on streams the library
  * owns (per device), forked from and joined back into `stream` with events,

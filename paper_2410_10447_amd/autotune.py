@@ -5,10 +5,9 @@ For each bucket a representative synthetic ligand is timed, at a population
 that fills the GPU (4096 individuals: more than the 3072 one-wave
 individuals resident at once, so that a choice that doubles the waves per
 individual pays for the waves it takes from other items), with every
-candidate (reduction variant x threads per individual x grid layout) through
-the C ABI and
-the fastest candidate is stored in a JSON table keyed by GPU architecture and
-bucket. `choose()` reads the table; a persistent launch over ligands of mixed
+candidate (reduction variant x threads per individual (64, 128, 256) x
+individuals per wave x grid layout) through the C ABI, and the fastest
+candidate is stored in a JSON table keyed by GPU architecture and bucket. `choose()` reads the table; a persistent launch over ligands of mixed
 sizes then passes each item its bucket's variant and threads per individual
 (items with different thread counts run in separate launches side by side).
 Within a kernel family the buckets share one variant and layout when that
@@ -71,13 +70,13 @@ def choose(n_atoms: int, n_torsions: int, path: str = TABLE_PATH) -> dict:
 
 
 def candidates(n_atoms: int = 64, n_torsions: int = 0):
-    """Reduction variant x threads per individual (one wave, or two waves
-    splitting the pair batches and, past 64 atoms, the atoms) x grid layout
-    (the corner-expanded copy, or the planar maps); for ligands that fit,
-    also two individuals per wave (shuffle reduction, either layout)."""
+    """Reduction variant x threads per individual (one wave, or two or four
+    waves splitting the pair batches and, past 64 atoms, the atoms) x grid
+    layout (the corner-expanded copy, or the planar maps); for ligands that
+    fit, also two individuals per wave (shuffle reduction, either layout)."""
     from . import dock
     out = [{"variant": v, "threads_per_ind": b, "plain_maps": p} for p in (False, True)
-           for b in (64, 128) for v in (dock.REDUCE_SHUFFLE, dock.REDUCE_MFMA_F32)]
+           for b in (64, 128, 256) for v in (dock.REDUCE_SHUFFLE, dock.REDUCE_MFMA_F32)]
     if two_per_wave_ok(n_atoms, n_torsions):
         out += [{"variant": dock.REDUCE_SHUFFLE, "threads_per_ind": 64, "plain_maps": p, "two_per_wave": True}
                 for p in (False, True)]
@@ -143,11 +142,13 @@ def tune(out: str = TABLE_PATH, n_individuals: int = 4096, iterations: int = 20,
 
 
 def family(entry) -> str:
-    """Kernel family a bucket's items run in: two individuals per wave, two
-    waves per individual, or one wave with one atom per lane (<= 64 atoms)
-    or two (larger ligands)."""
+    """Kernel family a bucket's items run in: two individuals per wave, four
+    or two waves per individual, or one wave with one atom per lane (<= 64
+    atoms) or two (larger ligands)."""
     if entry.get("two_per_wave"):
         return "two-per-wave"
+    if entry["threads_per_ind"] == 256:
+        return "four-wave"
     if entry["threads_per_ind"] == 128:
         return "two-wave"
     return "one-slot" if entry["atoms"] <= 64 else "two-slot"

@@ -125,14 +125,15 @@ int device_cu_count(int32_t& out) {
     return DOCK_OK;
 }
 
-// A library-owned stream per device, used to run the second persistent
-// launch of a split batch beside the first: the two are forked from the
-// caller's stream with an event and joined back into it with another, so the
-// caller's later work still waits for both. The fork-launch-join sequence is
-// serialised, since the events are shared.
+// Library-owned streams per device, used to run the second and later
+// persistent launches of a split batch beside the first: they are forked
+// from the caller's stream with an event and joined back into it with
+// others, so the caller's later work still waits for all of them. The
+// fork-launch-join sequence is serialised, since the events are shared.
+constexpr int kLsFamilies = 5;
 struct SideStream {
-    hipStream_t stream[3] = {nullptr, nullptr, nullptr};
-    hipEvent_t fork = nullptr, join[3] = {nullptr, nullptr, nullptr};
+    hipStream_t stream[kLsFamilies - 1] = {};
+    hipEvent_t fork = nullptr, join[kLsFamilies - 1] = {};
 };
 
 int side_stream(SideStream*& out, std::unique_lock<std::mutex>& lock) {
@@ -144,7 +145,7 @@ int side_stream(SideStream*& out, std::unique_lock<std::mutex>& lock) {
     lock = std::unique_lock<std::mutex>(mu);
     SideStream& s = (*table)[dev];
     if (!s.stream[0]) {
-        for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+        for (int k = 0; k < kLsFamilies - 1 && e == hipSuccess; ++k) {
             e = hipStreamCreateWithFlags(&s.stream[k], hipStreamNonBlocking);
             if (e == hipSuccess) e = hipEventCreateWithFlags(&s.join[k], hipEventDisableTiming);
         }
@@ -179,7 +180,7 @@ struct LsPlanBuf {
 struct LsPart { int first, count, mode, variant; int64_t units; };
 
 struct LsPlan {
-    LsPart part[4];
+    LsPart part[kLsFamilies];
     int n_parts = 0;
     int64_t table_bytes = 0;
 };
@@ -196,15 +197,18 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
     if (!(o->rho > 0.f && o->rho < 1.f)) return fail(DOCK_EINVAL, "rho must be in (0, 1)");
     if (!(o->eps > 0.f) || !std::isfinite(o->eps)) return fail(DOCK_EINVAL, "eps must be > 0");
     if (!valid_variant(o->variant)) return fail(DOCK_EINVAL, "unknown default variant");
-    if (o->threads_per_ind != 0 && o->threads_per_ind != 64 && o->threads_per_ind != 128)
-        return fail(DOCK_EUNSUPPORTED, "threads_per_ind must be 0, 64 or 128");
+    if (o->threads_per_ind != 0 && o->threads_per_ind != 64 && o->threads_per_ind != 128 &&
+        o->threads_per_ind != 256)
+        return fail(DOCK_EUNSUPPORTED, "threads_per_ind must be 0, 64, 128 or 256");
     if ((o->flags & ~DOCK_LS_FINAL_EVAL) != 0) return fail(DOCK_EINVAL, "unknown flags");
     docklaunch::DevItem* dev = buf.dev;
     int64_t* cost = buf.cost;
-    int* fam = buf.fam;             // kernel family: 0 two-wave, 1 two-slot, 2 one-slot, 3 two per wave
+    // kernel family: 0 four waves, 1 two waves, 2 one wave with two atom
+    // slots, 3 one wave with one slot, 4 two individuals per wave
+    int* fam = buf.fam;
     int n_dev = 0;
     int64_t total = 0;
-    bool any_fam[4] = {false, false, false, false};
+    bool any_fam[kLsFamilies] = {};
     int var_u = -2;
     for (int i = 0; i < n_items; ++i) {
         const dock_ls_item& it = items[i];
@@ -221,8 +225,9 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
             return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": iterations outside [-1, opts->iterations]");
         if (it.final_eval < -1 || it.final_eval > 1)
             return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": final_eval must be -1, 0 or 1");
-        if (it.threads_per_ind != 0 && it.threads_per_ind != 64 && it.threads_per_ind != 128)
-            return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": threads_per_ind must be 0, 64 or 128");
+        if (it.threads_per_ind != 0 && it.threads_per_ind != 64 && it.threads_per_ind != 128 &&
+            it.threads_per_ind != 256)
+            return fail(DOCK_EINVAL, "item " + std::to_string(i) + ": threads_per_ind must be 0, 64, 128 or 256");
         const int tpi = it.threads_per_ind != 0 ? it.threads_per_ind
                                                 : (o->threads_per_ind != 0 ? o->threads_per_ind : 64);
         const int iters = it.iterations < 0 ? o->iterations : it.iterations;
@@ -265,7 +270,7 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
         // evaluation: pair batches, atom slots, torsion depth, fixed part)
         cost[n_dev] = (int64_t)(iters + fin) *
                       ((int64_t)H->n_batches * 90 + (int64_t)d.slots * (150 + 20 * P.max_depth) + 500);
-        const int f = two ? 3 : (tpi == 128 ? 0 : (d.slots == 1 ? 2 : 1));
+        const int f = two ? 4 : (tpi == 256 ? 0 : (tpi == 128 ? 1 : (d.slots == 1 ? 3 : 2)));
         fam[n_dev] = f;
         any_fam[f] = true;
         var_u = (var_u == -2 || var_u == var) ? var : -1;
@@ -275,14 +280,16 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
     if (total > 2147483647LL) return fail(DOCK_EUNSUPPORTED, "more than 2^31 individuals in one call");
     if (n_dev == 0) return ok();
     // A launch carries one kernel family. The two one-wave families share one
-    // launch (kernel dispatching per item) when every item uses the same
-    // reduction variant; otherwise, or with two-wave items, there is one
-    // persistent launch per family (each with its own work counter), two-wave
-    // items first, then two-slot, then one-slot, each group longest first.
-    // Carrying every combination in one kernel would spill registers.
+    // launch (kernel dispatching per item) when they are the only ones and
+    // every item uses the same reduction variant; otherwise there is one
+    // persistent launch per family (each with its own work counter), in
+    // family order (four-wave items first, which have the longest
+    // individuals), each group longest first. Carrying every combination in
+    // one kernel would spill registers.
     const int var_uniform = var_u >= 0 ? var_u : -1;
-    const bool merge_one_wave = !any_fam[0] && !any_fam[3] && any_fam[1] && any_fam[2] && var_uniform >= 0;
-    auto group = [&](int i) { return merge_one_wave ? 1 : fam[i]; };
+    const bool merge_one_wave = !any_fam[0] && !any_fam[1] && !any_fam[4] && any_fam[2] && any_fam[3] &&
+                                var_uniform >= 0;
+    auto group = [&](int i) { return merge_one_wave ? 2 : fam[i]; };
     int* idx = buf.idx;
     for (int i = 0; i < n_dev; ++i) idx[i] = i;
     std::stable_sort(idx, idx + n_dev, [&](int a, int b) {
@@ -296,17 +303,17 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
     for (int i = 0; i < n_dev; ++i) {
         const int g = group(idx[i]);
         if (i == 0 || g != group(idx[i - 1])) {
-            const int mode = g == 3 ? docklaunch::kTwoPerWave
-                                    : (merge_one_wave ? docklaunch::kSlotsAny
-                                                      : (g == 0 ? docklaunch::kTwoWave
-                                                                : (g == 1 ? docklaunch::kSlots2 : docklaunch::kSlots1)));
+            static constexpr int kModes[kLsFamilies] = {docklaunch::kFourWave, docklaunch::kTwoWave,
+                                                        docklaunch::kSlots2, docklaunch::kSlots1,
+                                                        docklaunch::kTwoPerWave};
+            const int mode = merge_one_wave ? docklaunch::kSlotsAny : kModes[g];
             plan.part[plan.n_parts++] = {i, 0, mode, -1, 0};
             ub = 0;
         }
         tab[i] = dev[idx[i]];
         tab[i].unit_begin = ub;
         // work units: individuals, or pairs of individuals two to a wave
-        const int units = g == 3 ? (tab[i].n + 1) / 2 : tab[i].n;
+        const int units = g == 4 ? (tab[i].n + 1) / 2 : tab[i].n;
         ub += units;
         plan.part[plan.n_parts - 1].units += units;
         ++plan.part[plan.n_parts - 1].count;
@@ -341,7 +348,7 @@ int32_t ls_launch(const LsPlan& plan, const LsPlanBuf& buf, void* ws, const dock
     if (st != DOCK_OK) return st;
     SideStream* side = nullptr;
     std::unique_lock<std::mutex> side_lock;
-    const int n_side = side_streams ? plan.n_parts - 1 : 0;   // at most 3
+    const int n_side = side_streams ? plan.n_parts - 1 : 0;   // at most kLsFamilies - 1
     if (n_side > 0) {
         st = side_stream(side, side_lock);
         if (st != DOCK_OK) return st;

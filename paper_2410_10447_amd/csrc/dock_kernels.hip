@@ -248,7 +248,8 @@ __device__ __forceinline__ float4 sum4(float4 v) {
 // ---------------------------------------------------------------------------
 
 // LDS of one individual. Sized per layout: SLOTS atoms per lane and WAVES
-// waves per individual (a wave of the two-wave layout owns 64 atoms and its
+// waves per individual (a wave of the two- and four-wave layouts owns 64
+// atom positions, of which past the ligand's last atom none is used, and its
 // own range of accumulator copies). A ligand of at most 64 atoms has at most
 // 320 accumulator slots (n_copies * stride, n_copies <= 128/N + 2).
 template <int SLOTS, int WAVES = 1>
@@ -269,11 +270,11 @@ struct __align__(16) Smem {
                                     // (a | b << 8 | first << 16 | end << 24), unit axis u
     uint32_t chain[kMaxFrag][kChain / 4];  // per fragment: enclosing torsions, innermost
                                            // first, 4 per word, padded with the identity
-    // two-wave layout: each wave's prefix sums of (g, x cross g) at its atoms,
-    // and its {E, g} partial and x cross g total
-    float pre[WAVES == 2 ? 6 : 1][WAVES == 2 ? kAtoms : 1];
+    // several waves per individual: each wave's prefix sums of (g, x cross g)
+    // at its atoms, and its {E, g} partial
+    float pre[WAVES > 1 ? 6 : 1][WAVES > 1 ? kAtoms : 1];
     float4 xchg[WAVES][2];
-    int unit;                       // two-wave layout: the block's work unit
+    int unit;                       // several waves per individual: the block's work unit
 };
 
 template <int SLOTS>
@@ -282,7 +283,7 @@ struct Lig {
     int N, T, NF, G, n_batches, n_copies, max_depth;
     int stride;                     // accumulator stride (power of two >= N)
     int pmask;                      // stride * 16 - 1: slot byte offset -> position byte offset
-    int wv;                         // wave of the individual (two-wave layout), else 0
+    int wv;                         // wave of the individual (several waves per individual), else 0
     const u32x4* plist;             // pair records (dockblob::PairRec), n_batches x 64
     // per lane, per slot: atom a = lane + 64 * (slot + wv)
     float y0[SLOTS][3];
@@ -756,16 +757,18 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) g[s][0] = g[s][1] = g[s][2] = 0.f;
     } else {
-        // each wave adds into its own range of copies; a wave of the two-wave
-        // layout takes its half of the batches
+        // each wave adds into its own range of copies; with several waves per
+        // individual, wave w takes the w-th of WAVES consecutive runs of
+        // ceil(n_batches / WAVES) batches (the last runs may be short or empty)
         const int nslot = L.n_copies * L.stride;
         float4* const accw = sm.u.acc + (WAVES == 1 ? 0 : L.wv * nslot);
         for (int k = lane; k < nslot; k += kWave) accw[k] = make_float4(0.f, 0.f, 0.f, 0.f);
         __syncthreads();
         const int nb_all = L.n_batches;
-        const int half = (nb_all + 1) >> 1;
-        const int nb = WAVES == 1 ? nb_all : (L.wv == 0 ? half : nb_all - half);
-        const u32x4* const plist_at = L.plist + (WAVES == 1 || L.wv == 0 ? 0 : half * kWave);
+        const int run = (nb_all + WAVES - 1) / WAVES;
+        const int b0 = WAVES == 1 ? 0 : min(L.wv * run, nb_all);
+        const int nb = WAVES == 1 ? nb_all : min(nb_all - b0, run);
+        const u32x4* const plist_at = L.plist + b0 * kWave;
         const int pmask = L.pmask;
         // an atom's position sits at its slot's byte offset masked to one stride
         auto pos_i = [&](uint32_t w) { return *slot(sm.dyn, w & pmask); };
@@ -917,19 +920,23 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
     }
     float4 TQ = make_float4(readlane(P[SLOTS - 1][3], 63), readlane(P[SLOTS - 1][4], 63),
                             readlane(P[SLOTS - 1][5], 63), 0.f);
-    if constexpr (WAVES == 2) {
-        // the two waves' partials and prefix sums meet in LDS; both waves then
-        // hold the same totals (added in wave order) and step identically
+    if constexpr (WAVES > 1) {
+        // the waves' partials and prefix sums meet in LDS; every wave then
+        // holds the same totals (added in wave order) and steps identically
         const int a = lane + kWave * L.wv;
 #pragma unroll
         for (int c = 0; c < 6; ++c) sm.pre[c][a] = P[0][c];
         if (lane == 0) sm.xchg[L.wv][0] = EG;
         __syncthreads();
-        const float4 e0 = sm.xchg[0][0], e1 = sm.xchg[1][0];
-        EG = make_float4(e0.x + e1.x, e0.y + e1.y, e0.z + e1.z, e0.w + e1.w);
-        TQ = make_float4(sm.pre[3][kWave - 1] + sm.pre[3][2 * kWave - 1],
-                         sm.pre[4][kWave - 1] + sm.pre[4][2 * kWave - 1],
-                         sm.pre[5][kWave - 1] + sm.pre[5][2 * kWave - 1], 0.f);
+        EG = sm.xchg[0][0];
+        TQ = make_float4(sm.pre[3][kWave - 1], sm.pre[4][kWave - 1], sm.pre[5][kWave - 1], 0.f);
+#pragma unroll
+        for (int w = 1; w < WAVES; ++w) {
+            const float4 ew = sm.xchg[w][0];
+            EG = make_float4(EG.x + ew.x, EG.y + ew.y, EG.z + ew.z, EG.w + ew.w);
+            TQ = make_float4(TQ.x + sm.pre[3][(w + 1) * kWave - 1], TQ.y + sm.pre[4][(w + 1) * kWave - 1],
+                             TQ.z + sm.pre[5][(w + 1) * kWave - 1], 0.f);
+        }
     }
     float gpsi = 0.f;
     {
@@ -942,11 +949,17 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
         float S[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            if constexpr (WAVES == 2) {
-                // global prefix: wave 1's local prefix plus wave 0's total
-                const float off = sm.pre[c][kWave - 1];
-                const float ph = sm.pre[c][hi] + (hi >= kWave ? off : 0.f);
-                const float pl = sm.pre[c][lo] + (lo >= kWave ? off : 0.f);
+            if constexpr (WAVES > 1) {
+                // global prefix: a wave's local prefix plus the totals of the
+                // waves before it (added in wave order)
+                const float bh = sm.pre[c][hi], bl = sm.pre[c][lo];
+                float ph = bh, pl = bl, off = 0.f;
+#pragma unroll
+                for (int w = 1; w < WAVES; ++w) {
+                    off = w == 1 ? sm.pre[c][kWave - 1] : off + sm.pre[c][w * kWave - 1];
+                    ph = hi >= w * kWave ? bh + off : ph;
+                    pl = lo >= w * kWave ? bl + off : pl;
+                }
                 S[c] = ph - pl;
             } else {
                 float ph = __shfl(P[0][c], hi & 63);
@@ -1120,8 +1133,9 @@ __global__ __launch_bounds__(64, (SLOTS == 1 ? 3 : 2)) void sw_kernel(GridParams
 template <int SLOTS, int VAR, int WAVES = 1, bool ANY_LAYOUT = true>
 __device__ void local_search_one(const DevItem& it, int ind, Smem<SLOTS, WAVES>& sm, const Lig<SLOTS>& L,
                                  int iterations, float rho, float eps, bool final_eval) {
-    // both waves of the two-wave layout hold the genotype and take the same
-    // steps on the same totals; the first wave writes the results
+    // with several waves per individual every wave holds the genotype and
+    // takes the same steps on the same totals; the first wave writes the
+    // results
     const int lane = lane_id();
     const bool writer = WAVES == 1 || L.wv == 0;
     const int G = L.G;
@@ -1260,17 +1274,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == dock
     }
 }
 
-// Two-wave persistent local-search kernel: 128-thread blocks, one individual
-// of a 65..128-atom ligand per block, each wave owning 64 atoms and half of
-// the pair batches. The first thread takes the next unit and hands it to
-// both waves through LDS; every wave exits once the counter passes the last
-// unit.
-template <int VAR>
-__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3, 3))) void ls_kernel_2w(LsParams p) {
-    __shared__ Smem<1, 2> sm;
+// Persistent local-search kernel with WAVES (2 or 4) waves per individual:
+// one individual per block of 64 WAVES threads, wave w owning atom positions
+// 64 w .. 64 w + 63 and the w-th run of the pair batches. The first thread
+// takes the next unit and hands it to every wave through LDS; every wave
+// exits once the counter passes the last unit.
+template <int VAR, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(3, 3))) void ls_kernel_mw(LsParams p) {
+    __shared__ Smem<1, WAVES> sm;
     int cur_item = -1;
     while (true) {
-        __syncthreads();                       // the previous unit is read by both waves
+        __syncthreads();                       // the previous unit is read by every wave
         if (threadIdx.x == 0) sm.unit = atomicAdd(p.counter, 1);
         __syncthreads();
         const int u = uniform(sm.unit);
@@ -1285,8 +1299,8 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         const bool reload = lo != cur_item;
         cur_item = lo;
         Lig<1> L;
-        load_ligand<1, 2>(it.blob, sm, L, reload);
-        ls_run<1, VAR, 2>(it, ind, sm, L, p);
+        load_ligand<1, WAVES>(it.blob, sm, L, reload);
+        ls_run<1, VAR, WAVES>(it, ind, sm, L, p);
     }
 }
 
@@ -1879,14 +1893,15 @@ const void* ls_kernel_ptr(int var) {
     }
 }
 
-const void* ls_kernel_2w_ptr(int var) {
+template <int WAVES>
+const void* ls_kernel_mw_ptr(int var) {
     switch (var) {
-        case 0: return reinterpret_cast<const void*>(&ls_kernel_2w<0>);
-        case 1: return reinterpret_cast<const void*>(&ls_kernel_2w<1>);
-        case 2: return reinterpret_cast<const void*>(&ls_kernel_2w<2>);
-        case 3: return reinterpret_cast<const void*>(&ls_kernel_2w<3>);
-        case 4: return reinterpret_cast<const void*>(&ls_kernel_2w<4>);
-        default: return reinterpret_cast<const void*>(&ls_kernel_2w<-1>);
+        case 0: return reinterpret_cast<const void*>(&ls_kernel_mw<0, WAVES>);
+        case 1: return reinterpret_cast<const void*>(&ls_kernel_mw<1, WAVES>);
+        case 2: return reinterpret_cast<const void*>(&ls_kernel_mw<2, WAVES>);
+        case 3: return reinterpret_cast<const void*>(&ls_kernel_mw<3, WAVES>);
+        case 4: return reinterpret_cast<const void*>(&ls_kernel_mw<4, WAVES>);
+        default: return reinterpret_cast<const void*>(&ls_kernel_mw<-1, WAVES>);
     }
 }
 
@@ -1894,7 +1909,8 @@ const void* ls_kernel_for(int mode, int var) {
     if (mode == docklaunch::kTwoPerWave)
         return var == DOCK_REDUCE_SHUFFLE ? reinterpret_cast<const void*>(&ls_kernel_two<false>)
                                           : reinterpret_cast<const void*>(&ls_kernel_two<true>);
-    if (mode == docklaunch::kTwoWave) return ls_kernel_2w_ptr(var);
+    if (mode == docklaunch::kTwoWave) return ls_kernel_mw_ptr<2>(var);
+    if (mode == docklaunch::kFourWave) return ls_kernel_mw_ptr<4>(var);
     if (mode == docklaunch::kSlots1) return ls_kernel_ptr<docklaunch::kSlots1>(var);
     if (mode == docklaunch::kSlots2) return ls_kernel_ptr<docklaunch::kSlots2>(var);
     return ls_kernel_ptr<docklaunch::kSlotsAny>(var);

@@ -52,12 +52,12 @@ struct LsParams {
 constexpr int64_t kWorkspaceHeader = 64;
 
 // ls kernel families: slots 1, slots 2, or both (runtime per item), all one
-// wave per individual; two waves per individual; or two individuals per
-// wave (ligands of <= 32 atoms and <= 32 genes, shuffle reduction)
-enum LsMode { kSlots1 = 1, kSlots2 = 2, kSlotsAny = 3, kTwoWave = 4, kTwoPerWave = 5 };
-constexpr int kLsModes = 6;
+// wave per individual; two or four waves per individual; or two individuals
+// per wave (ligands of <= 32 atoms and <= 32 genes, shuffle reduction)
+enum LsMode { kSlots1 = 1, kSlots2 = 2, kSlotsAny = 3, kTwoWave = 4, kTwoPerWave = 5, kFourWave = 6 };
+constexpr int kLsModes = 7;
 
-inline int ls_block_threads(int mode) { return mode == kTwoWave ? 128 : 64; }
+inline int ls_block_threads(int mode) { return mode == kTwoWave ? 128 : (mode == kFourWave ? 256 : 64); }
 
 // Persistent: at most the resident blocks of n_cu CUs, each looping over
 // genotypes with a stride of the grid size.

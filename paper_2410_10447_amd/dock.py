@@ -19,7 +19,7 @@ _LIB_PATH = os.environ.get("DOCKMI_LIB") or os.path.join(os.path.dirname(os.path
                                                          "libdockmi.so")
 
 # the struct layouts below follow include/dock.h of this ABI version
-ABI_VERSION = 9
+ABI_VERSION = 10
 
 DOCK_OK = 0
 DOCK_EINVAL = -1
@@ -456,7 +456,7 @@ class LsJob:
     iterations: int = -1
     final_eval: int = -1
     grad: object = None          # optional [n, G] CUDA tensor: gradient at the last evaluated point
-    threads_per_ind: int = 0     # 64 or 128, 0 defers to the call
+    threads_per_ind: int = 0     # 64, 128 or 256, 0 defers to the call
     plain_maps: bool = False     # read the planar maps even with the corner copy bound
     two_per_wave: bool = False   # two individuals per wave (ligands of <= 32 atoms and <= 32 genes)
 
@@ -510,7 +510,7 @@ def local_search(jobs, iterations: int, rho: float = 0.8, eps: float = 1e-2,
 
     State tensors are updated in place. `workspace` (uint8 CUDA tensor) is
     allocated if not given; `items` may pass a prebuilt item array.
-    `threads_per_ind` (0/64/128) is the default for jobs that leave it at 0.
+    `threads_per_ind` (0/64/128/256) is the default for jobs that leave it at 0.
     """
     import torch
     n_items = len(jobs)

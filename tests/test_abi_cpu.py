@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(dock.ABI_SYMBOLS)
     for name in declared:
         assert hasattr(L, name)
-    assert L.dock_abi_version() == dock.ABI_VERSION == 9
+    assert L.dock_abi_version() == dock.ABI_VERSION == 10
 
 
 def _check_prep(lig):
@@ -377,7 +377,7 @@ def test_batch_calls_validate_before_device_work():
                                      C.byref(so), None, None)
         assert st == dock.DOCK_EINVAL and "n_genes" in dock.last_error()
     for bad in (dict(rho=1.0), dict(rho=0.0), dict(eps=0.0), dict(iterations=-1), dict(variant=9),
-                dict(flags=8), dict(threads_per_ind=96), dict(threads_per_ind=256)):
+                dict(flags=8), dict(threads_per_ind=96), dict(threads_per_ind=512)):
         kw = dict(iterations=10, rho=0.8, eps=1e-2, variant=0, threads_per_ind=0, flags=1)
         kw.update(bad)
         ob = dock.LsOpts(**kw)

@@ -246,7 +246,7 @@ def _two_wave_workload(n):
 
 
 @pytest.mark.parametrize("variant,tpi", [(v, 64) for v in FP32_VARIANTS] + [(v, 128) for v in FP32_VARIANTS]
-                         + [(v, 64) for v in SPLIT_VARIANTS])
+                         + [(v, 256) for v in FP32_VARIANTS] + [(v, 64) for v in SPLIT_VARIANTS])
 def test_ls_step_map(dk, variant, tpi):
     """Each GPU step is the ADADELTA update (Zeiler Alg. 1) of the GPU's own
     state and gradient, and that gradient and energy match the oracle's at the
@@ -255,17 +255,17 @@ def test_ls_step_map(dk, variant, tpi):
     for bit). (Comparing with a step taken on the oracle's gradient would mix
     the two: ADADELTA passes small gradient components through almost
     unscaled, so their absolute FP32 error, ~1e-4 of |g|, would dominate.)
-    tpi = 64 runs the 48-atom benchmark ligand in one wave; tpi = 128 runs a
-    100-atom ligand with two waves per individual. The split reductions
+    tpi = 64 runs the 48-atom benchmark ligand in one wave; tpi = 128 (256)
+    runs a 100-atom ligand with two (four) waves per individual. The split reductions
     (BF16 2-term, FP16 2-term, BF16 3-term) are held to their bounds."""
     _step_map(dk, variant, tpi, synth.ls_workload(64) if tpi == 64 else _two_wave_workload(64))
 
 
-@pytest.mark.parametrize("variant", FP32_VARIANTS)
-def test_ls_step_map_two_waves_small_ligand(dk, variant):
-    """Two waves per individual for the 48-atom benchmark ligand: the second
-    wave owns no atoms, only half of the pair batches."""
-    _step_map(dk, variant, 128, synth.ls_workload(64))
+@pytest.mark.parametrize("variant,tpi", [(v, t) for t in (128, 256) for v in FP32_VARIANTS])
+def test_ls_step_map_two_waves_small_ligand(dk, variant, tpi):
+    """Two or four waves per individual for the 48-atom benchmark ligand: the
+    waves after the first own no atoms, only their runs of pair batches."""
+    _step_map(dk, variant, tpi, synth.ls_workload(64))
 
 
 def _step_map(dk, variant, tpi, w):
@@ -308,7 +308,7 @@ def _step_map(dk, variant, tpi, w):
         assert same == 12 * 64
 
 
-@pytest.mark.parametrize("tpi", [64, 128])
+@pytest.mark.parametrize("tpi", [64, 128, 256])
 def test_ls_chunked_equals_single_and_deterministic(dk, tpi):
     w = synth.ls_workload(200) if tpi == 64 else _two_wave_workload(200)
     G, L, st_a = _ls_setup(dk, w, 200)
@@ -393,12 +393,12 @@ def test_ls_uneven_mixed_variants_alone_equals_mixed(dk):
 
 def test_ls_three_families_alone_equals_mixed(dk):
     """One call holding ligands of <= 64 atoms (one wave), larger ligands in
-    one wave and larger ligands in two waves, with mixed reduction variants,
-    runs one launch per family side by side and gives, bit for bit, what each
-    item gives alone; the two-wave items meet oracle parity at their best
-    point."""
+    one wave and ligands in two and in four waves, with mixed reduction
+    variants, runs one launch per family side by side and gives, bit for bit,
+    what each item gives alone; the multi-wave items meet oracle parity at
+    their best point."""
     spec = ((20, 4, 64), (90, 12, 128), (48, 8, 64), (128, 20, 64), (100, 14, 128), (65, 9, 128),
-            (128, 32, 128), (70, 0, 64))
+            (128, 32, 128), (70, 0, 64), (120, 24, 256), (40, 6, 256))
     ligs = [synth.ligand(n, t, 90 + n + t) for n, t, _ in spec]
     grd = synth.grids(64, 10, 91)
     ff = synth.force_field()
@@ -407,7 +407,7 @@ def test_ls_three_families_alone_equals_mixed(dk):
     gens = [torch.from_numpy(synth.genotypes(l, grd, 20 + 3 * k, 92 + k)).cuda() for k, l in enumerate(ligs)]
     mixed = [dk.LSState.start(g) for g in gens]
     alone = [m.clone() for m in mixed]
-    var = [(0, 1, 2, 0, 1, 3, 4, 0)[k] for k in range(len(ligs))]
+    var = [(0, 1, 2, 0, 1, 3, 4, 0, 1, 0)[k] for k in range(len(ligs))]
     def job(k, st):
         return dk.LsJob(G, Ls[k], st, var[k], threads_per_ind=spec[k][2])
     dk.local_search([job(k, s) for k, s in enumerate(mixed)], 15)
@@ -420,19 +420,19 @@ def test_ls_three_families_alone_equals_mixed(dk):
         for f in an:
             assert np.array_equal(an[f], mn[f]), (k, spec[k], f)
         assert np.all(mn["iters_done"] == 15)
-        if spec[k][2] == 128:
+        if spec[k][2] != 64:
             prep = R.prepare(ligs[k], ff)
-            reps.append(check_reported(f"two-wave item {k} best points", dk, G, Ls[k], prep, grd,
+            reps.append(check_reported(f"{spec[k][2] // 64}-wave item {k} best points", dk, G, Ls[k], prep, grd,
                                        mn["best_genotype"], mn["best_energy"], variant=var[k],
                                        exact_rescore=False, assert_ok=False))
     from tests.gpu_common import assert_reports
-    assert_reports("two-wave items best points", reps)
+    assert_reports("multi-wave items best points", reps)
 
 
 def test_corner_expanded_grids_identical(dk):
     """The corner-expanded copy holds the same corner values and the kernels
     do the same arithmetic on them: scores and a 20-step local search are
-    bit-identical with and without it (one-wave and two-wave ligands)."""
+    bit-identical with and without it (one-, two- and four-wave ligands)."""
     w = synth.ls_workload(64)
     L = dk.Ligand(w.ligands[0], w.ff)
     Gp = dk.Grids.from_synth(w.grids, corners=False)
@@ -457,7 +457,7 @@ def test_corner_expanded_grids_identical(dk):
         Ep, gp = dk.score_batch(Gp, L, gt, variant=v)
         Ec, gc = dk.score_batch(Gc, L, gt, variant=v)
         assert torch.equal(Ep, Ec) and torch.equal(gp, gc)
-    for lig_n, tpi in ((48, 64), (100, 128)):
+    for lig_n, tpi in ((48, 64), (100, 128), (100, 256)):
         ww = w if lig_n == 48 else _two_wave_workload(64)
         LL = L if lig_n == 48 else dk.Ligand(ww.ligands[0], ww.ff)
         Gp2 = Gp if lig_n == 48 else dk.Grids.from_synth(ww.grids, corners=False)

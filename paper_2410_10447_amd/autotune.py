@@ -2,16 +2,19 @@
 
 Ligands are bucketed by atom count (width 32) and torsion count (width 8).
 For each bucket a representative synthetic ligand is timed, at a population
-that fills the GPU (4096 individuals: more than the 3072 one-wave
-individuals resident at once, so that a choice that doubles the waves per
-individual pays for the waves it takes from other items), with every
+that fills the GPU several times over in whole rounds (12,288 individuals:
+4, 8 and 16 rounds of the 3072, 1536 and 768 individuals resident at once
+with one, two and four waves each, 2 rounds of 6144 with two per wave), so
+that a choice that takes more waves per individual pays for the waves it
+takes from other individuals and no candidate gains from a partial last
+round, with every
 candidate (reduction variant x threads per individual (64, 128, 256) x
 individuals per wave x grid layout) through the C ABI, and the fastest
 candidate is stored in a JSON table keyed by GPU architecture and bucket. `choose()` reads the table; a persistent launch over ligands of mixed
 sizes then passes each item its bucket's variant and threads per individual
 (items with different thread counts run in separate launches side by side).
 Within a kernel family the buckets share one variant and layout when that
-costs at most 3 % in every bucket (`unify_families`).
+costs at most 6 % in every bucket (`unify_families`).
 
 Usage: python -m paper_2410_10447_amd.autotune [--out table.json]
 """
@@ -109,7 +112,7 @@ def time_candidate(G, L, gen, cand, iterations=20, reps=3):
     return gen.shape[0] * (iterations + 1) / dt
 
 
-def tune(out: str = TABLE_PATH, n_individuals: int = 4096, iterations: int = 20, seed: int = 77):
+def tune(out: str = TABLE_PATH, n_individuals: int = 12288, iterations: int = 20, seed: int = 77):
     import torch
     from . import dock, synth
     grd = synth.grids(64, 10, seed)
@@ -154,13 +157,15 @@ def family(entry) -> str:
     return "one-slot" if entry["atoms"] <= 64 else "two-slot"
 
 
-def unify_families(table, tol: float = 0.03):
+def unify_families(table, tol: float = 0.06):
     """One reduction variant and grid layout per kernel family where it
     costs little.
 
     A launch whose items use different variants (or layouts) runs the kernel
-    that dispatches per item, which holds every variant's registers; one
-    choice per family keeps the specialised kernels. Per family, the
+    that dispatches per item, which holds every variant's registers (the
+    two-wave one spills 72 bytes per lane; on the uneven 64-ligand batch its
+    launch was about 4 % slower than the specialised one); one choice per
+    family keeps the specialised kernels. Per family, the
     (variant, layout) whose worst relative loss over the family's buckets
     (against each bucket's best candidate, at the bucket's thread count) is
     smallest is given to every bucket of the family, if that loss is at most
@@ -198,7 +203,7 @@ def unify_families(table, tol: float = 0.03):
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=TABLE_PATH)
-    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--n", type=int, default=12288)
     ap.add_argument("--iters", type=int, default=20)
     a = ap.parse_args()
     tune(a.out, a.n, a.iters)

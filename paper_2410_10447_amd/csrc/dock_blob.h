@@ -33,6 +33,7 @@ constexpr int kIdentity = kMaxTorsions;          // kIdentity (the identity tran
 constexpr int kBatch = 64;
 constexpr int kMaxSlots = 384;                   // n_copies * slot_stride <= kMaxSlots
 constexpr int kMaxSlotsSmall = 320;              // the same bound for ligands of <= 64 atoms
+constexpr int kMaxSlotsTiny = 288;               // and for ligands of <= 32 atoms
 
 // Accumulator (and position) stride: the smallest power of two >= n_atoms,
 // at least 16. Slots of "atoms" n_atoms .. stride-1 are never summed; unused

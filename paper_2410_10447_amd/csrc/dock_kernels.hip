@@ -1319,15 +1319,21 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(3, 3
 // ---------------------------------------------------------------------------
 constexpr int kHalf = 32;
 
+// LDS of a two-individual wave. Twelve such blocks (three waves per SIMD) must
+// fit in the CU's 160 KB after each block's LDS is rounded up to the
+// allocation granularity: 12,800 bytes per block fit, while the 13,344 bytes
+// of accumulators sized for 320 slots per half left room for eleven blocks
+// per CU. A ligand of <= 32 atoms needs at most 288 slots.
 struct __align__(16) Smem2 {
     float4 dyn[2][kHalf];               // per half: positions relative to t, sqrt(kElec) q
     union {
         float tk[2][kMaxTors + 1][12];  // per half: torsion transforms, identity at kMaxTors
-        float4 acc[2][dockblob::kMaxSlotsSmall];  // per half: pair-force accumulators
+        float4 acc[2][dockblob::kMaxSlotsTiny];   // per half: pair-force accumulators
     } u;
     float4 tor[kMaxTors][2];
     uint32_t chain[kMaxFrag][kChain / 4];
 };
+static_assert(sizeof(Smem2) <= 12800, "twelve two-individual blocks per CU");
 
 __device__ __forceinline__ float hsel(float a, float b) { return lane_id() < kHalf ? a : b; }
 

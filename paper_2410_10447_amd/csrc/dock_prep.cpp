@@ -576,8 +576,9 @@ int32_t prepare(const dock_ligand_desc& d, Prepared& P, std::string& err) {
     const int C = std::max(2, std::min(15, (2 * kBatch + N - 1) / N + 1));
     using dockblob::kMaxSlots;
     using dockblob::kMaxSlotsSmall;
+    using dockblob::kMaxSlotsTiny;
     const int S = dockblob::slot_stride(N);
-    if (C * S > (N <= 64 ? kMaxSlotsSmall : kMaxSlots)) {
+    if (C * S > (N <= 32 ? kMaxSlotsTiny : (N <= 64 ? kMaxSlotsSmall : kMaxSlots))) {
         err = "internal: accumulator slots exceed the build limit"; return DOCK_EUNSUPPORTED;
     }
     std::vector<int> degp(N, 0);

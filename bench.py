@@ -322,58 +322,71 @@ def sw_run(G, L, gen0, iterations, variant, reps=3, seed=91):
             "energy_median_start": float(E0.median()), "energy_median_end": float(st.energy.median())}
 
 
-def uneven_run(steps, warmup, use_table=True, tpi_override=0):
+def uneven_runs(steps, warmup, tpi_override=0):
     """64 ligands (atoms U{12..128}, torsions U{0..32}) x 100 individuals on one
-    96^3 x 12 grid set, 300 iterations, in one call per step (one persistent
-    launch per kernel family, side by side); each item takes its size
-    bucket's variant, threads per individual and grid layout from the
-    autotuning table (`tpi_override` forces the thread count of every
-    ligand). Without the table every item takes one wave and the shuffle
-    reduction, and the call is a single persistent launch."""
+    96^3 x 12 grid set, 300 iterations, in one call per step, planned two
+    ways: "tuned", each item with its size bucket's variant, threads per
+    individual, grid layout and individuals per wave from the autotuning
+    table (one persistent launch per kernel family, side by side;
+    `tpi_override` forces the thread count of every ligand), and
+    "one_launch", every item on one wave with the shuffle reduction (a single
+    persistent launch). The two plans' calls alternate, each call timed on its
+    own (synchronised), so that both see the same clock and thermal state;
+    each plan reports the median of its `steps` calls."""
     import torch
     from paper_2410_10447_amd import autotune, dock, synth
     w = synth.uneven_workload()
     G = dock.Grids.from_synth(w.grids)
     Ls = [dock.Ligand(l, w.ff) for l in w.ligands]
     gens = [torch.from_numpy(g).cuda() for g in w.genotypes]
-    pick = [autotune.choose(L.n_atoms, L.n_torsions) if use_table else dict(autotune.DEFAULT) for L in Ls]
+    plans = {"tuned": [autotune.choose(L.n_atoms, L.n_torsions) for L in Ls],
+             "one_launch": [dict(autotune.DEFAULT) for _ in Ls]}
     if tpi_override:
-        for c in pick:
+        for c in plans["tuned"]:
             c["threads_per_ind"] = tpi_override
             c["two_per_wave"] = False      # two per wave takes one wave per pair of individuals
     evals = sum(g.shape[0] for g in gens) * (w.iterations + 1)
     ws = torch.empty(dock.workspace_bytes(len(Ls)), dtype=torch.uint8, device="cuda")
-    runs = []
-    for _ in range(warmup + steps):
+
+    def call(pick):
         states = [dock.LSState.start(g) for g in gens]
         jobs = [dock.LsJob(G, L, st, c["variant"], threads_per_ind=c.get("threads_per_ind", 64),
                            plain_maps=c.get("plain_maps", False), two_per_wave=c.get("two_per_wave", False))
                 for L, st, c in zip(Ls, states, pick)]
-        runs.append((states, dock.make_items(jobs)))
-    torch.cuda.synchronize()
-    for k in range(warmup):
-        dock.local_search([None] * len(Ls), w.iterations, workspace=ws, items=runs[k][1])
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(warmup, warmup + steps):
-        dock.local_search([None] * len(Ls), w.iterations, workspace=ws, items=runs[k][1])
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / steps
+        items = dock.make_items(jobs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dock.local_search([None] * len(Ls), w.iterations, workspace=ws, items=items)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    for _ in range(warmup):
+        for pick in plans.values():
+            call(pick)
+    times = {k: [] for k in plans}
+    for _ in range(steps):
+        for k, pick in plans.items():
+            times[k].append(call(pick))
     work = sum(g.shape[0] * (w.iterations + 1) * work_per_eval(L.n_pairs, L.n_atoms, L.n_torsions)
                for g, L in zip(gens, Ls))
-    return {"workload": w.name, "evals_per_step": evals, "ms_per_step": 1e3 * dt,
-            "evals_per_s": evals / dt,
-            "roofline": roofline(evals, dt, work / evals,
-                                 kernel="ls_kernel (all families, wall clock per call; mean work per eval)"),
-            "variants_from_table": use_table,
-            "single_launch": not use_table and tpi_override in (0, 64),
-            "threads_per_ind_override": tpi_override,
-            "two_wave_items": sum(1 for c in pick if c.get("threads_per_ind", 64) == 128),
-            "four_wave_items": sum(1 for c in pick if c.get("threads_per_ind", 64) == 256),
-            "plain_map_items": sum(1 for c in pick if c.get("plain_maps", False)),
-            "two_per_wave_items": sum(1 for c in pick if c.get("two_per_wave", False)),
-            "atoms_mean": float(np.mean([L.n_atoms for L in Ls])),
-            "pairs_mean": float(np.mean([L.n_pairs for L in Ls]))}
+    out = {}
+    for k, pick in plans.items():
+        dt = float(np.median(times[k]))
+        out[k] = {"workload": w.name, "evals_per_step": evals, "ms_per_step": 1e3 * dt,
+                  "ms_per_call": [round(1e3 * t, 3) for t in times[k]],
+                  "evals_per_s": evals / dt,
+                  "roofline": roofline(evals, dt, work / evals,
+                                       kernel="ls_kernel (all families, wall clock per call; mean work per eval)"),
+                  "variants_from_table": k == "tuned",
+                  "single_launch": k == "one_launch",
+                  "threads_per_ind_override": tpi_override if k == "tuned" else 0,
+                  "two_wave_items": sum(1 for c in pick if c.get("threads_per_ind", 64) == 128),
+                  "four_wave_items": sum(1 for c in pick if c.get("threads_per_ind", 64) == 256),
+                  "plain_map_items": sum(1 for c in pick if c.get("plain_maps", False)),
+                  "two_per_wave_items": sum(1 for c in pick if c.get("two_per_wave", False)),
+                  "atoms_mean": float(np.mean([L.n_atoms for L in Ls])),
+                  "pairs_mean": float(np.mean([L.n_pairs for L in Ls]))}
+    return out
 
 
 def serving_run(seconds, rate, seed=4000, chunk_iters=25, max_individuals=120_000,
@@ -427,8 +440,8 @@ def main():
                          "four waves splitting the pair batches, timed for the FP32 variants)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=48)
-    ap.add_argument("--uneven-steps", type=int, default=3,
-                    help="timed steps of the uneven 64-ligand batch (0 = skip)")
+    ap.add_argument("--uneven-steps", type=int, default=5,
+                    help="timed calls per plan of the uneven 64-ligand batch (0 = skip)")
     ap.add_argument("--uneven-tpi", type=int, default=0, choices=(0, 64, 128, 256),
                     help="threads per individual of every ligand of the uneven batch "
                          "(0 = the autotuning table's choice)")
@@ -543,11 +556,12 @@ def main():
                              kernel_sha256=kernel_sha256()[:16]),
     }
     if args.uneven_steps > 0:
-        out["uneven"] = uneven_run(args.uneven_steps, 1, tpi_override=args.uneven_tpi)
-        # every item on one wave with the shuffle reduction: the call is one
-        # persistent launch (the kernel dispatching per item on its atom
-        # layout), against the tuned per-family launches above
-        out["uneven_one_launch"] = uneven_run(args.uneven_steps, 1, use_table=False)
+        # the tuned per-family launches, and every item on one wave with the
+        # shuffle reduction (one persistent launch, the kernel dispatching per
+        # item on its atom layout), calls alternating
+        u = uneven_runs(args.uneven_steps, 1, tpi_override=args.uneven_tpi)
+        out["uneven"] = u["tuned"]
+        out["uneven_one_launch"] = u["one_launch"]
     if args.serve_seconds > 0:
         out["serving"] = serving_run(args.serve_seconds, args.serve_rate, variant=best_v)
     if args.lga_generations > 0:

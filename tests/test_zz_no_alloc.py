@@ -22,19 +22,20 @@ def dk():
 
 
 def _jobs(dk, spec, grids, ff):
-    """spec: (atoms, torsions, seed, individuals, threads_per_ind, variant)."""
+    """spec: (atoms, torsions, seed, individuals, threads_per_ind, variant[, two per wave])."""
     jobs = []
-    for n_atoms, n_tors, seed, n, tpi, var in spec:
+    for n_atoms, n_tors, seed, n, tpi, var, *two in spec:
         lig = synth.ligand(n_atoms, n_tors, seed)
         L = dk.Ligand(lig, ff)
         gen = synth.genotypes(lig, grids[1], n, seed + 1)
         st = dk.LSState.start(torch.from_numpy(gen).cuda())
-        jobs.append(dk.LsJob(grids[0], L, st, var, threads_per_ind=tpi))
+        jobs.append(dk.LsJob(grids[0], L, st, var, threads_per_ind=tpi, two_per_wave=bool(two and two[0])))
     return jobs
 
 
 def _twin(dk, jobs):
-    return [dk.LsJob(j.grids, j.ligand, j.state.clone(), j.variant, threads_per_ind=j.threads_per_ind)
+    return [dk.LsJob(j.grids, j.ligand, j.state.clone(), j.variant, threads_per_ind=j.threads_per_ind,
+                     two_per_wave=j.two_per_wave)
             for j in jobs]
 
 
@@ -49,10 +50,11 @@ def test_static_workspace_equals_caller_workspace(dk):
     grd = synth.grids(48, 10, 9001)
     G = dk.Grids.from_synth(grd)
     ff = synth.force_field()
-    # first call: three kernel families (one-slot, two-slot one-wave,
-    # two-wave) and two variants, so the call has three parts
+    # first call: all five kernel families (one-slot, two-slot one-wave,
+    # two-wave, four-wave, two individuals per wave) and two variants, so the
+    # call has five parts
     spec1 = [(48, 10, 9100, 96, 64, 0), (100, 14, 9200, 40, 64, 1), (90, 12, 9300, 33, 128, 0),
-             (20, 3, 9400, 70, 64, 1)]
+             (20, 3, 9400, 70, 64, 1), (70, 9, 9600, 21, 256, 1), (24, 5, 9700, 31, 64, 0, True)]
     jobs_s = _jobs(dk, spec1, (G, grd), ff)
     jobs_r = _twin(dk, jobs_s)
     print(f"\n[no-alloc] call 1: {len(spec1)} items, {sum(s[3] for s in spec1)} individuals, 25 iterations",

@@ -13,9 +13,15 @@ How a GPU result is compared with the FP64 oracle
   u * sum_i |g_i| |x_i|, more than 1e-5 of |E| at clashes). The bounds are
   the FP32 path's: |dE| <= 1e-5 max(|E|, 1), ||dg|| <= 1e-4 max(||g||, 1).
 * Conditioning: when E is a small difference of large terms, the rounding of
-  the terms themselves (~2^-24 of each) exceeds 1e-5 of |E|. An individual
-  may then pass by |dE| <= COND_TOL * (sum of the terms' magnitudes); at most
-  COND_CAP of the individuals of a check may, and the count is printed.
+  the terms themselves (~2^-24 of each) exceeds 1e-5 of |E|; and a steep term
+  amplifies the rounding of its own argument in FP32: a pair energy moves by
+  |r dE/dr| times the relative rounding of its separation (the difference of
+  two FP32 positions, squared and summed, then rsq: about 2u), a grid energy
+  by h |grad e| times the rounding of its cell fraction (about 1.5u per
+  axis). An individual may then pass by |dE| <= COND_TOL * (sum of the terms'
+  magnitudes) + SENS_TOL * (sum over pairs of |r dE/dr| + h * sum over atoms
+  of the 1-norm of the grid gradient); at most COND_CAP of the individuals of
+  a check may, and the count is printed.
 * Kinks: the score is only piecewise smooth (trilinear cells change at grid
   faces, the box clamp at the box faces, the 12-6/12-10 term at its cap, the
   r^2 clamp). An atom within rounding reach of a kink may take the other
@@ -31,7 +37,8 @@ E_TOL = 1e-5
 G_TOL = 1e-4
 POSE_TOL = 1e-4            # A, world coordinates
 COND_TOL = 2.0 ** -20      # |dE| bound relative to the sum of the terms' magnitudes
-COND_CAP = 0.01            # share of a check's individuals that may pass only by COND_TOL
+SENS_TOL = 2.0 ** -22      # |dE| bound relative to the terms' sensitivity to their arguments' rounding
+COND_CAP = 0.01            # share of a check's individuals that may pass only by COND_TOL / SENS_TOL
 KINK_CAP = 0.03            # share of a check's individuals that may sit at a kink
 FACE_TOL_U = 2e-5          # cell units: rounding reach of a cell face (|x| <= 20 A, u <= 95)
 BOX_TOL = 1e-5             # A: rounding reach of a box face
@@ -71,6 +78,37 @@ def oracle_at(prep, grd, genotypes, x):
     tau = np.cross(x - gen[:, None, 0:3], gat).sum(axis=1)
     return R.ScoreResult(e_in.sum(axis=1) + e_ia, grad, x, gat, e_in, e_ia, tau,
                          np.abs(e_in).sum(axis=1) + a_ia)
+
+
+def interp_magnitude(prep, grd, x):
+    """Per individual, the sum over atoms of the magnitudes of the terms the
+    grid interpolation adds: sum_c w_c (|v_type,c| + |q| |v_elec,c| +
+    |q| |v_desolv,c|) over the eight corners c (the interpolant of |map|)."""
+    from oracle import dock_ref as R
+    maps = np.abs(np.asarray(grd.maps, np.float64))
+    M = maps.shape[0]
+    out = np.zeros(x.shape[0])
+    for i in range(x.shape[1]):
+        xi = x[:, i, :]
+        aq = abs(float(prep.charge[i]))
+        out += R.trilinear(maps[int(prep.cls[i])], grd.origin, grd.spacing, xi)[0]
+        out += aq * R.trilinear(maps[M - 2], grd.origin, grd.spacing, xi)[0]
+        out += aq * R.trilinear(maps[M - 1], grd.origin, grd.spacing, xi)[0]
+    return out
+
+
+def argument_sensitivity(prep, grd, x):
+    """Per individual: sum over pairs of |r dE/dr| plus h times the sum over
+    atoms of the 1-norm of the grid term's gradient, at positions x."""
+    from oracle import dock_ref as R
+    _, g_in = R.inter_terms(prep, grd, x)
+    out = grd.spacing * np.abs(g_in).sum(axis=(1, 2))
+    if prep.pairs.shape[0]:
+        d = x[:, prep.pairs[:, 1]] - x[:, prep.pairs[:, 0]]
+        r2 = np.sum(d * d, axis=-1)
+        _, w, *_ = R.pair_energy(r2, prep.r0, prep.eps, prep.pair_hb, prep.qq, prep.dsolv)
+        out = out + np.abs(w * r2).sum(axis=1)
+    return out
 
 
 def kink_mask(prep, grd, x):
@@ -141,7 +179,8 @@ def check(tag, prep, grd, genotypes, energy, grad, atom_out, variant=0, cond_cap
     escale = np.maximum(np.abs(ref.energy), 1.0)
     ee = dE / escale
     strict = ee <= E_TOL
-    cond = (~strict) & (dE <= COND_TOL * ref.e_abs)
+    sens = argument_sensitivity(prep, grd, x) if (~strict).any() else np.zeros(n)
+    cond = (~strict) & (dE <= COND_TOL * ref.e_abs + SENS_TOL * sens)
     su = SPLIT_U.get(variant, 0.0)
     coarse = su > COND_TOL
     split = (~strict) & (~cond) & (dE <= su * ref.e_abs + E_TOL * escale) if coarse else np.zeros(n, bool)
@@ -170,9 +209,15 @@ def check(tag, prep, grd, genotypes, energy, grad, atom_out, variant=0, cond_cap
               + f"; kappa max {kappa.max():.1f}); g err p50 {np.median(ge):.2e} max {ge.max():.2e} "
               f"(at a kink {int(kink.sum())}, their g err max {ge[kink].max() if kink.any() else 0.0:.2e})",
               flush=True)
+    bad = ~(strict | cond | split)
+    if bad.any():
+        ia = interp_magnitude(prep, grd, x[bad])
+        for k, b in enumerate(np.nonzero(bad)[0][:8]):
+            print(f"[{tag}] E outside the bounds: individual {b}: E {E[b]:.9g} oracle {ref.energy[b]:.9g} "
+                  f"|dE| {dE[b]:.3e}; term magnitudes {ref.e_abs[b]:.6g}; grid interpolation magnitudes "
+                  f"{ia[k]:.6g}; argument sensitivity {sens[b]:.6g}", flush=True)
     if assert_ok and n:
         assert pose_err <= POSE_TOL, (tag, pose_err)
-        bad = ~(strict | cond | split)
         assert not bad.any(), (tag, "E", np.nonzero(bad)[0][:8], ee[bad][:8])
         assert cond.mean() <= cond_cap, (tag, "conditioning share", cond.mean())
         assert kink.mean() <= kink_cap, (tag, "kink share", kink.mean())

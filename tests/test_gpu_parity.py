@@ -268,6 +268,21 @@ def test_ls_step_map_two_waves_small_ligand(dk, variant, tpi):
     _step_map(dk, variant, tpi, synth.ls_workload(64))
 
 
+def _small_workload(n_atoms, n_tors, seed, n=64):
+    lig = synth.ligand(n_atoms, n_tors, seed)
+    grd = synth.grids(48, 10, seed + 1)
+    return synth.Workload(f"ls_n{n_atoms}_t{n_tors}_g48", [lig], grd, synth.force_field(),
+                          [synth.genotypes(lig, grd, n, seed + 2)], iterations=12)
+
+
+@pytest.mark.parametrize("n_atoms,n_tors,tpi", [(12, 0, 128), (12, 0, 256), (13, 2, 256), (30, 5, 256)])
+def test_ls_step_map_tiny_ligands_several_waves(dk, n_atoms, n_tors, tpi):
+    """Ligands with one or a few pair batches on two or four waves per
+    individual: the waves past the first own no atoms, and some own no pair
+    batch either (an empty run); every step still meets the oracle."""
+    _step_map(dk, 0, tpi, _small_workload(n_atoms, n_tors, 4400 + n_atoms + tpi))
+
+
 def _step_map(dk, variant, tpi, w):
     from tests.gpu_common import assert_reports
     prep = R.prepare(w.ligands[0], w.ff)

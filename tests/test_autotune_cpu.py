@@ -42,3 +42,36 @@ def test_unify_families_within_tolerance():
     # two-wave: either variant loses > 3 % somewhere -> left per bucket
     assert b["a2_t0"]["variant"] == 0 and b["a2_t1"]["variant"] == 1
     assert table["families"]["one-slot"]["unified"] and not table["families"]["two-wave"]["unified"]
+
+
+def test_candidates_cover_the_tuning_space():
+    """Variant x threads per individual (64, 128, 256) x layout for every
+    ligand; two individuals per wave only where two fit one wave."""
+    small = autotune.candidates(16, 4)
+    large = autotune.candidates(48, 4)
+    keys_small = {autotune.cand_key(c) for c in small}
+    keys_large = {autotune.cand_key(c) for c in large}
+    for tpi in (64, 128, 256):
+        for v in (0, 1):
+            assert f"v{v}_b{tpi}" in keys_large and f"v{v}_b{tpi}_plain" in keys_large
+    assert {"v0_b64_x2", "v0_b64_plain_x2"} <= keys_small
+    assert not any(k.endswith("_x2") for k in keys_large)
+    assert not any(k.endswith("_x2") for k in {autotune.cand_key(c) for c in autotune.candidates(30, 26)})
+
+
+def test_families_and_choice_of_two_per_wave():
+    assert autotune.family({"threads_per_ind": 256, "atoms": 100}) == "four-wave"
+    assert autotune.family({"threads_per_ind": 128, "atoms": 40}) == "two-wave"
+    assert autotune.family({"threads_per_ind": 64, "atoms": 40, "two_per_wave": True}) == "two-per-wave"
+    assert autotune.family({"threads_per_ind": 64, "atoms": 100}) == "two-slot"
+    # a bucket that takes two per wave: ligands of the bucket that do not fit
+    # (more than 25 torsions) get one wave each
+    t = {"buckets": {autotune.bucket(20, 26): {"variant": 0, "threads_per_ind": 64, "plain_maps": False,
+                                                 "two_per_wave": True}}}
+    path = "/nonexistent/table.json"
+    autotune._cache[path] = t
+    try:
+        assert autotune.choose(20, 24, path)["two_per_wave"]
+        assert not autotune.choose(20, 26, path)["two_per_wave"]
+    finally:
+        autotune._cache.pop(path, None)

@@ -413,7 +413,7 @@ def test_ls_three_families_alone_equals_mixed(dk):
     what each item gives alone; the multi-wave items meet oracle parity at
     their best point."""
     spec = ((20, 4, 64), (90, 12, 128), (48, 8, 64), (128, 20, 64), (100, 14, 128), (65, 9, 128),
-            (128, 32, 128), (70, 0, 64), (120, 24, 256), (40, 6, 256))
+            (128, 32, 128), (70, 0, 64), (120, 24, 256), (40, 6, 256), (128, 32, 256))
     ligs = [synth.ligand(n, t, 90 + n + t) for n, t, _ in spec]
     grd = synth.grids(64, 10, 91)
     ff = synth.force_field()
@@ -422,7 +422,7 @@ def test_ls_three_families_alone_equals_mixed(dk):
     gens = [torch.from_numpy(synth.genotypes(l, grd, 20 + 3 * k, 92 + k)).cuda() for k, l in enumerate(ligs)]
     mixed = [dk.LSState.start(g) for g in gens]
     alone = [m.clone() for m in mixed]
-    var = [(0, 1, 2, 0, 1, 3, 4, 0, 1, 0)[k] for k in range(len(ligs))]
+    var = [(0, 1, 2, 0, 1, 3, 4, 0, 1, 0, 4)[k] for k in range(len(ligs))]
     def job(k, st):
         return dk.LsJob(G, Ls[k], st, var[k], threads_per_ind=spec[k][2])
     dk.local_search([job(k, s) for k, s in enumerate(mixed)], 15)
@@ -683,6 +683,31 @@ def test_ls_step_map_two_per_wave(dk, n_atoms, n_tors):
           f"{same} of {12 * 63}", flush=True)
     assert same == 12 * 63
     assert_reports(f"ls step-map two per wave N={n_atoms}", reps)
+
+
+def test_two_per_wave_plain_maps_identical(dk):
+    """Two per wave on the planar maps (grids without the corner copy, or the
+    per-item layout choice with it bound) gives the same scores and searches,
+    bit for bit, as on the corner-expanded copy."""
+    w = _small_ls_workload(45, 20, 9)
+    Gp = dk.Grids.from_synth(w.grids, corners=False)
+    Gc = dk.Grids.from_synth(w.grids)
+    L = dk.Ligand(w.ligands[0], w.ff)
+    gt = torch.from_numpy(w.genotypes[0]).cuda()
+    Ep, gp = dk.score_batch(Gp, L, gt, two_per_wave=True)
+    Ec, gc = dk.score_batch(Gc, L, gt, two_per_wave=True)
+    torch.cuda.synchronize()
+    assert torch.equal(Ep, Ec) and torch.equal(gp, gc)
+    a = dk.LSState.start(gt)
+    b, c = a.clone(), a.clone()
+    dk.local_search([dk.LsJob(Gp, L, a, 0, two_per_wave=True)], 20)
+    dk.local_search([dk.LsJob(Gc, L, b, 0, two_per_wave=True)], 20)
+    dk.local_search([dk.LsJob(Gc, L, c, 0, two_per_wave=True, plain_maps=True)], 20)
+    torch.cuda.synchronize()
+    an, bn, cn = a.to_numpy(), b.to_numpy(), c.to_numpy()
+    for f in an:
+        assert np.array_equal(an[f], bn[f]), f
+        assert np.array_equal(an[f], cn[f]), f
 
 
 def test_two_per_wave_chunked_alone_and_mixed(dk):

@@ -80,6 +80,26 @@ __device__ __forceinline__ float readlane(float v, int l) {
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// Ordering of LDS accesses between the lanes of one wave, where one wave is
+// everything that shares the data: a wave's LDS instructions execute in
+// program order, so it only has to keep the compiler from moving LDS
+// accesses across this point (a wavefront-scope fence orders them in the
+// compiler; the wave barrier keeps the instruction scheduler from moving
+// them). No block barrier: another wave of the block may be working on
+// something else, at another point of its code.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// The LDS ordering an evaluation needs: the wave's own when it holds the
+// whole individual, the block's when WAVES waves share it.
+template <int WAVES>
+__device__ __forceinline__ void lds_sync() {
+    if constexpr (WAVES == 1) wave_sync();
+    else __syncthreads();
+}
+
 // Wave-uniform value: lets the compiler keep it (and what is derived from it,
 // such as loop bounds and addresses) in scalar registers.
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -296,7 +316,7 @@ struct Lig {
 template <int SLOTS, int WAVES = 1>
 __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem<SLOTS, WAVES>& sm, Lig<SLOTS>& L,
                             bool fill_lds = true) {
-    if (fill_lds) __syncthreads();  // previous users of the LDS tables are done
+    if (fill_lds) lds_sync<WAVES>();  // previous users of the LDS tables are done
     const Header* h = reinterpret_cast<const Header*>(blob);
     const int lane = lane_id();
     L.wv = WAVES == 1 ? 0 : uniform((int)threadIdx.x >> 6);
@@ -338,7 +358,7 @@ __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem<SLOTS, WAVES>
     uint32_t* dst = &sm.chain[0][0];
     if (fill_lds)
         for (int i = (int)threadIdx.x; i < n_chain_words; i += kWave * WAVES) dst[i] = ch[i];
-    __syncthreads();
+    lds_sync<WAVES>();
 }
 
 // ---------------------------------------------------------------------------
@@ -639,7 +659,7 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
         o[1] = make_float4(0.f, 1.f, 0.f, 0.f);
         o[2] = make_float4(0.f, 0.f, 1.f, 0.f);
     }
-    __syncthreads();
+    lds_sync<WAVES>();
     // atom positions relative to the rotation centre: the torsions enclosing
     // the atom's fragment, innermost first (each about its reference axis,
     // which no inner torsion moves), then the rotation Rq. The translation t
@@ -682,7 +702,7 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
         sm.dyn[a] = a < N ? make_float4(x[s][0], x[s][1], x[s][2], kSqrtElec * L.chg[s][1])
                           : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    __syncthreads();
+    lds_sync<WAVES>();
 
     float g[SLOTS][3];
     float e_lane = 0.f;
@@ -763,7 +783,7 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
         const int nslot = L.n_copies * L.stride;
         float4* const accw = sm.u.acc + (WAVES == 1 ? 0 : L.wv * nslot);
         for (int k = lane; k < nslot; k += kWave) accw[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-        __syncthreads();
+        lds_sync<WAVES>();
         const int nb_all = L.n_batches;
         const int run = (nb_all + WAVES - 1) / WAVES;
         const int b0 = WAVES == 1 ? 0 : min(L.wv * run, nb_all);
@@ -856,7 +876,7 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
 #pragma unroll
             for (int s = 0; s < SLOTS; ++s) grid_load<ANY_LAYOUT>(G, L.cls[s], x[s], tv, tap[s]);
         }
-        __syncthreads();
+        lds_sync<WAVES>();
         // each atom adds its copies in copy order (range by range)
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
@@ -893,7 +913,7 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
     if constexpr (!GRAD) {
         // the block sum of E alone, in the chosen variant
         grad = 0.f;
-        __syncthreads();   // the next evaluation rewrites the position table
+        lds_sync<WAVES>();   // the next evaluation rewrites the position table
         return sum4<VAR>(make_float4(e_lane, 0.f, 0.f, 0.f)).x;
     }
 
@@ -927,7 +947,7 @@ __device__ float evaluate(const GridParams& G, Smem<SLOTS, WAVES>& sm, const Lig
 #pragma unroll
         for (int c = 0; c < 6; ++c) sm.pre[c][a] = P[0][c];
         if (lane == 0) sm.xchg[L.wv][0] = EG;
-        __syncthreads();
+        lds_sync<WAVES>();
         EG = sm.xchg[0][0];
         TQ = make_float4(sm.pre[3][kWave - 1], sm.pre[4][kWave - 1], sm.pre[5][kWave - 1], 0.f);
 #pragma unroll
@@ -1364,7 +1384,7 @@ __device__ __forceinline__ float half_scan(float v) {
 // The ligand as a two-individual wave holds it: lane j of either half the
 // atom j (per-lane registers), the shared torsion and fragment tables in LDS.
 __device__ void load_ligand2(const uint8_t* __restrict__ blob, Smem2& sm, Lig<1>& L, bool fill_lds = true) {
-    if (fill_lds) __syncthreads();  // previous users of the LDS tables are done
+    if (fill_lds) wave_sync();  // previous users of the LDS tables are done
     const Header* h = reinterpret_cast<const Header*>(blob);
     const int lane = lane_id();
     L.wv = 0;
@@ -1403,7 +1423,7 @@ __device__ void load_ligand2(const uint8_t* __restrict__ blob, Smem2& sm, Lig<1>
     uint32_t* dst = &sm.chain[0][0];
     if (fill_lds)
         for (int i = lane; i < n_chain_words; i += kWave) dst[i] = ch[i];
-    __syncthreads();
+    wave_sync();
 }
 
 // One evaluation of E and dE/dgenotype for the two individuals of the wave.
@@ -1462,7 +1482,7 @@ __device__ float evaluate2(const GridParams& G, Smem2& sm, const Lig<1>& L, floa
         o[1] = make_float4(0.f, 1.f, 0.f, 0.f);
         o[2] = make_float4(0.f, 0.f, 1.f, 0.f);
     }
-    __syncthreads();
+    wave_sync();
     // atom positions relative to the rotation centre, as in `evaluate`
     const float tv[3] = {tx, ty, tz};
     const int n_duos = (L.max_depth + 1) >> 1;
@@ -1495,7 +1515,7 @@ __device__ float evaluate2(const GridParams& G, Smem2& sm, const Lig<1>& L, floa
         sm.dyn[h][j] = j < N ? make_float4(x[0], x[1], x[2], kSqrtElec * L.chg[0][1])
                              : make_float4(0.f, 0.f, 0.f, 0.f);
     }
-    __syncthreads();
+    wave_sync();
 
     float g[3] = {0.f, 0.f, 0.f};
     float e_lane = 0.f;
@@ -1508,7 +1528,7 @@ __device__ float evaluate2(const GridParams& G, Smem2& sm, const Lig<1>& L, floa
     if constexpr (GRAD) {
         const int nslot = L.n_copies * L.stride;
         for (int k = j; k < nslot; k += kHalf) acch[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-        __syncthreads();
+        wave_sync();
     }
     // pair terms: step s takes records 32 (s % 2) .. 32 (s % 2) + 31 of
     // batch s / 2, record j for lane j of either half. Software pipeline:
@@ -1567,7 +1587,7 @@ __device__ float evaluate2(const GridParams& G, Smem2& sm, const Lig<1>& L, floa
         grid_load<ANY_LAYOUT>(G, L.cls[0], x, tv, tap);
     }
     if constexpr (GRAD) {
-        __syncthreads();
+        wave_sync();
         // each atom adds its copies in copy order
         if (j < N)
             for (int c = 0; c < L.n_copies; ++c) {
@@ -1591,7 +1611,7 @@ __device__ float evaluate2(const GridParams& G, Smem2& sm, const Lig<1>& L, floa
     }
     if constexpr (!GRAD) {
         grad = 0.f;
-        __syncthreads();   // the next evaluation rewrites the position table
+        wave_sync();   // the next evaluation rewrites the position table
         return half_sum(e_lane);
     }
     // block sum of {E, gx, gy, gz} over each half (wavefront shuffle)

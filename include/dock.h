@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define DOCK_ABI_VERSION 10
+#define DOCK_ABI_VERSION 11
 
 /* status codes */
 #define DOCK_OK            0
@@ -278,6 +278,9 @@ typedef struct {
 #define DOCK_ITEM_TWO_PER_WAVE 2u
 
 #define DOCK_LS_FINAL_EVAL 1u    /* evaluate the point reached after the last step */
+/* Run every kernel family in a launch of its own, even where they could
+ * share one (see dock_local_search_batch); the results are the same. */
+#define DOCK_LS_SEPARATE_LAUNCHES 2u
 
 typedef struct {
     int32_t iterations;          /* >= 0 steps per individual in this call */
@@ -288,7 +291,7 @@ typedef struct {
                                     per individual; with 128 or 256 the waves split
                                     the pair batches (and, past 64 atoms, the first
                                     two waves the atoms) */
-    uint32_t flags;              /* DOCK_LS_FINAL_EVAL */
+    uint32_t flags;              /* DOCK_LS_FINAL_EVAL | DOCK_LS_SEPARATE_LAUNCHES */
 } dock_ls_opts;
 
 /* Device bytes of the workspace dock_local_search_batch needs for n_items. */
@@ -301,11 +304,20 @@ int32_t dock_ls_workspace_bytes(int32_t n_items, int64_t* bytes);
  * any ligand with two or four waves per individual (128 or 256 threads: wave
  * w owns atoms 64 w .. 64 w + 63, if the ligand has them, and the w-th run
  * of ceil(batches / waves) pair batches), or two individuals per wave
- * (DOCK_ITEM_TWO_PER_WAVE). A batch that mixes families (or both one-wave
- * families AND reduction variants) runs as one persistent launch per family,
- * side by side: the first on `stream`, the others on streams the library
- * owns (per device), forked from and joined back into `stream` with events,
- * so work queued on `stream` after the call still waits for all of them.
+ * (DOCK_ITEM_TWO_PER_WAVE). A batch that mixes families still runs as one
+ * persistent launch when every item uses one reduction variant and either
+ * (a) its families are among two waves per individual, one wave for a
+ * ligand of <= 64 atoms, and two per wave, and every item reads the
+ * corner-expanded maps (128-thread blocks: a block takes the two-wave
+ * individuals first, then each of its waves takes one-wave units on its
+ * own), or (b) they are the two one-wave families (the kernel picks the
+ * atom layout per item).
+ * Otherwise, or with DOCK_LS_SEPARATE_LAUNCHES, it runs as one persistent
+ * launch per family, side by side: the first on `stream`, the others on
+ * streams the library owns (per device), forked from and joined back into
+ * `stream` with events, so work queued on `stream` after the call still
+ * waits for all of them. Every item's results are the same bit for bit
+ * whichever way it runs.
  * Items may be at different stages: a serving loop passes each job's
  * remaining steps and asks for the final evaluation only in its last call. A call of K
  * iterations without DOCK_LS_FINAL_EVAL followed by one with it gives the
@@ -318,6 +330,12 @@ int32_t dock_ls_workspace_bytes(int32_t n_items, int64_t* bytes);
 int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items,
                                 const dock_ls_opts* opts, void* workspace_dev,
                                 int64_t workspace_bytes, void* stream);
+
+/* The number of persistent launches dock_local_search_batch would make for
+ * these items and opts (0 when no item has work): the same validation, no
+ * device work, no allocation on the device. */
+int32_t dock_ls_launches(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* opts,
+                         int32_t* n_launches);
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same

@@ -177,7 +177,7 @@ struct LsPlanBuf {
     uint8_t* table;
 };
 
-struct LsPart { int first, count, mode, variant; int64_t units; };
+struct LsPart { int first, count, mode, variant; int64_t units, block_units; };
 
 struct LsPlan {
     LsPart part[kLsFamilies];
@@ -200,7 +200,7 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
     if (o->threads_per_ind != 0 && o->threads_per_ind != 64 && o->threads_per_ind != 128 &&
         o->threads_per_ind != 256)
         return fail(DOCK_EUNSUPPORTED, "threads_per_ind must be 0, 64, 128 or 256");
-    if ((o->flags & ~DOCK_LS_FINAL_EVAL) != 0) return fail(DOCK_EINVAL, "unknown flags");
+    if ((o->flags & ~(DOCK_LS_FINAL_EVAL | DOCK_LS_SEPARATE_LAUNCHES)) != 0) return fail(DOCK_EINVAL, "unknown flags");
     docklaunch::DevItem* dev = buf.dev;
     int64_t* cost = buf.cost;
     // kernel family: 0 four waves, 1 two waves, 2 one wave with two atom
@@ -209,6 +209,7 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
     int n_dev = 0;
     int64_t total = 0;
     bool any_fam[kLsFamilies] = {};
+    bool any_plain = false;
     int var_u = -2;
     for (int i = 0; i < n_items; ++i) {
         const dock_ls_item& it = items[i];
@@ -250,6 +251,7 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
         std::memset(&d, 0, sizeof(d));
         d.grid = it.grids->gp;
         if (it.flags & DOCK_ITEM_PLAIN_MAPS) d.grid.corners = nullptr;
+        any_plain = any_plain || d.grid.corners == nullptr;
         d.blob = it.ligand->blob_dev;
         d.genotype = it.genotype;
         d.acc_g2 = it.acc_g2;
@@ -264,6 +266,7 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
         d.slots = it.ligand->slots;
         d.iterations = iters;
         d.final_eval = fin;
+        d.pack = two ? 2 : 1;
         const auto& P = it.ligand->prep;
         const auto* H = reinterpret_cast<const dockblob::Header*>(P.blob.data());
         // per-individual cost: evaluations x (instruction estimate per
@@ -279,17 +282,23 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
     }
     if (total > 2147483647LL) return fail(DOCK_EUNSUPPORTED, "more than 2^31 individuals in one call");
     if (n_dev == 0) return ok();
-    // A launch carries one kernel family. The two one-wave families share one
-    // launch (kernel dispatching per item) when they are the only ones and
-    // every item uses the same reduction variant; otherwise there is one
-    // persistent launch per family (each with its own work counter), in
-    // family order (four-wave items first, which have the longest
-    // individuals), each group longest first. Carrying every combination in
-    // one kernel would spill registers.
+    // A launch carries one kernel family, or one of two mixes that share a
+    // launch when every item uses the same reduction variant: two-wave,
+    // one-slot and two-per-wave items on corner-expanded maps (one launch of
+    // 128-thread blocks, two-wave items first), or the two one-wave families
+    // (the kernel dispatching on the atom layout per item). Otherwise, or on
+    // request, there is one persistent launch per family (each with its own
+    // work counter), in family order (four-wave items first, which have the
+    // longest individuals), each group longest first. Carrying every
+    // combination in one kernel would spill registers.
     const int var_uniform = var_u >= 0 ? var_u : -1;
-    const bool merge_one_wave = !any_fam[0] && !any_fam[1] && !any_fam[4] && any_fam[2] && any_fam[3] &&
-                                var_uniform >= 0;
-    auto group = [&](int i) { return merge_one_wave ? 2 : fam[i]; };
+    const bool shared_ok = var_uniform >= 0 && !(o->flags & DOCK_LS_SEPARATE_LAUNCHES);
+    const int n_fams = (int)any_fam[0] + any_fam[1] + any_fam[2] + any_fam[3] + any_fam[4];
+    const bool unified = shared_ok && n_fams >= 2 && !any_fam[0] && !any_fam[2] && !any_plain;
+    const bool merge_one_wave = shared_ok && n_fams == 2 && any_fam[2] && any_fam[3];
+    // unified: one part, two-wave items (group 0) before the one-wave units
+    auto group = [&](int i) { return unified ? (fam[i] == 1 ? 0 : 1) : (merge_one_wave ? 2 : fam[i]); };
+    auto part_of = [&](int i) { return unified ? 0 : group(i); };
     int* idx = buf.idx;
     for (int i = 0; i < n_dev; ++i) idx[i] = i;
     std::stable_sort(idx, idx + n_dev, [&](int a, int b) {
@@ -302,20 +311,22 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
     int32_t ub = 0;
     for (int i = 0; i < n_dev; ++i) {
         const int g = group(idx[i]);
-        if (i == 0 || g != group(idx[i - 1])) {
+        if (i == 0 || part_of(idx[i]) != part_of(idx[i - 1])) {
             static constexpr int kModes[kLsFamilies] = {docklaunch::kFourWave, docklaunch::kTwoWave,
                                                         docklaunch::kSlots2, docklaunch::kSlots1,
                                                         docklaunch::kTwoPerWave};
-            const int mode = merge_one_wave ? docklaunch::kSlotsAny : kModes[g];
-            plan.part[plan.n_parts++] = {i, 0, mode, -1, 0};
+            const int mode = unified ? docklaunch::kUnified
+                                     : (merge_one_wave ? docklaunch::kSlotsAny : kModes[g]);
+            plan.part[plan.n_parts++] = {i, 0, mode, -1, 0, 0};
             ub = 0;
         }
         tab[i] = dev[idx[i]];
         tab[i].unit_begin = ub;
         // work units: individuals, or pairs of individuals two to a wave
-        const int units = g == 4 ? (tab[i].n + 1) / 2 : tab[i].n;
+        const int units = tab[i].pack == 2 ? (tab[i].n + 1) / 2 : tab[i].n;
         ub += units;
         plan.part[plan.n_parts - 1].units += units;
+        if (unified && fam[idx[i]] == 1) plan.part[plan.n_parts - 1].block_units += units;
         ++plan.part[plan.n_parts - 1].count;
     }
     // each launch runs the kernel specialised for its items' variant when
@@ -371,6 +382,7 @@ int32_t ls_launch(const LsPlan& plan, const LsPlanBuf& buf, void* ws, const dock
         p.counter = static_cast<int32_t*>(ws) + k;
         p.n_items = pt.count;
         p.total_units = (int32_t)units;
+        p.block_units = (int32_t)pt.block_units;
         p.rho = o->rho;
         p.eps = o->eps;
         hipStream_t s_k = (k == 0 || !side) ? stream : side->stream[k - 1];
@@ -597,6 +609,22 @@ int32_t dock_local_search_batch(const dock_ls_item* items, int32_t n_items, cons
     st = staging().copy_to_device(ws, table.data(), plan.table_bytes, (hipStream_t)stream);
     if (st != DOCK_OK) return st;
     return ls_launch(plan, buf, ws, o, (hipStream_t)stream, true);
+}
+
+int32_t dock_ls_launches(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* o,
+                         int32_t* n_launches) {
+    if (!n_launches) return fail(DOCK_EINVAL, "dock_ls_launches: NULL n_launches");
+    if (n_items < 0 || (n_items > 0 && !items)) return fail(DOCK_EINVAL, "dock_ls_launches: bad items");
+    std::vector<docklaunch::DevItem> dev(std::max(n_items, 1));
+    std::vector<int64_t> cost(std::max(n_items, 1));
+    std::vector<int> fam(std::max(n_items, 1)), idx(std::max(n_items, 1));
+    std::vector<uint8_t> table(docklaunch::kWorkspaceHeader + (size_t)std::max(n_items, 1) * sizeof(docklaunch::DevItem));
+    LsPlanBuf buf{dev.data(), cost.data(), fam.data(), idx.data(), table.data()};
+    LsPlan plan;
+    const int32_t st = ls_plan(items, n_items, o, buf, plan);
+    if (st != DOCK_OK) return st;
+    *n_launches = plan.n_parts;
+    return ok();
 }
 
 int32_t dock_local_search_batch_static(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* o,

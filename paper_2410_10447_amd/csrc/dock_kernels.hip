@@ -357,7 +357,7 @@ __device__ void load_ligand(const uint8_t* __restrict__ blob, Smem<SLOTS, WAVES>
     const int n_chain_words = L.NF * (kChain / 4);
     uint32_t* dst = &sm.chain[0][0];
     if (fill_lds)
-        for (int i = (int)threadIdx.x; i < n_chain_words; i += kWave * WAVES) dst[i] = ch[i];
+        for (int i = WAVES == 1 ? lane : (int)threadIdx.x; i < n_chain_words; i += kWave * WAVES) dst[i] = ch[i];
     lds_sync<WAVES>();
 }
 
@@ -1237,6 +1237,17 @@ __device__ void ls_run(const DevItem& it, int ind, Smem<SLOTS, WAVES>& sm, const
         ls_dispatch<SLOTS, WAVES>(-1, it, ind, sm, L, p);
 }
 
+// The item of work unit u: the last item with unit_begin <= u (items are
+// in unit order).
+__device__ __forceinline__ int item_of_unit(const LsParams& p, int u) {
+    int lo = 0, hi = p.n_items - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (uniform(gmem(&p.items[mid].unit_begin)[0]) <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 // The item record, read once per work unit, with every word made
 // wave-uniform (scalar registers).
 __device__ __forceinline__ DevItem load_item(const DevItem* items, int k) {
@@ -1759,6 +1770,79 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
     }
 }
 
+// One persistent launch for a batch that mixes two-wave individuals with
+// one-wave units (an individual of a ligand of <= 64 atoms, or a pair of
+// individuals two per wave): 128-thread blocks over one work counter. Units
+// [0, block_units) are the two-wave individuals (their items come first),
+// which a block takes as ls_kernel_mw does. Once the counter passes them,
+// each wave takes the remaining units on its own, in its own half of the
+// block's LDS, ordering its LDS accesses at wave scope only (the other wave
+// may be anywhere in its own unit); the unit the block took last, already
+// past the two-wave range, goes to the first wave. Every wave exits once
+// the counter passes the last unit.
+constexpr size_t kWaveLds =
+    ((sizeof(Smem2) > sizeof(Smem<1>) ? sizeof(Smem2) : sizeof(Smem<1>)) + 15) / 16 * 16;
+
+struct __align__(16) SmemUni {
+    union {
+        Smem<1, 2> two;                       // a two-wave individual
+        unsigned char wave[2][kWaveLds];      // per wave: Smem<1> or Smem2
+    } u;
+    int unit;                                 // outside the union: read after the
+                                              // waves start writing their halves
+};
+static_assert(sizeof(SmemUni) <= 20 * 1280, "six 128-thread blocks per CU");
+
+template <int VAR>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3, 3))) void ls_kernel_uni(LsParams p) {
+    __shared__ SmemUni sm;
+    int cur_item = -1;
+    int u = 0;
+    while (true) {
+        __syncthreads();                       // the previous unit is read by both waves
+        if (threadIdx.x == 0) sm.unit = atomicAdd(p.counter, 1);
+        __syncthreads();
+        u = uniform(sm.unit);
+        if (u >= p.block_units) break;
+        const int lo = item_of_unit(p, u);
+        const DevItem it = load_item(p.items, lo);
+        const bool reload = lo != cur_item;
+        cur_item = lo;
+        Lig<1> L;
+        load_ligand<1, 2>(it.blob, sm.u.two, L, reload);
+        ls_run<1, VAR, 2>(it, u - it.unit_begin, sm.u.two, L, p);
+    }
+    const int w = uniform((int)threadIdx.x >> 6);
+    unsigned char* const lds = sm.u.wave[w];
+    int next = w == 0 ? u : -1;
+    cur_item = -1;                             // the two-wave tables are gone
+    while (true) {
+        if (next < 0) {
+            int v = 0;
+            if (lane_id() == 0) v = atomicAdd(p.counter, 1);
+            next = uniform(v);
+        }
+        if (next >= p.total_units) break;
+        const int lo = item_of_unit(p, next);
+        const DevItem it = load_item(p.items, lo);
+        const bool reload = lo != cur_item;
+        cur_item = lo;
+        Lig<1> L;
+        if (it.pack == 2) {
+            Smem2& s2 = *reinterpret_cast<Smem2*>(lds);
+            const int ind0 = 2 * (next - it.unit_begin);
+            load_ligand2(it.blob, s2, L, reload);
+            local_search_two<false>(it, ind0, min(2, it.n - ind0), s2, L, it.iterations, p.rho, p.eps,
+                                    it.final_eval != 0);
+        } else {
+            Smem<1>& s1 = *reinterpret_cast<Smem<1>*>(lds);
+            load_ligand<1, 1>(it.blob, s1, L, reload);
+            ls_run<1, VAR, 1>(it, next - it.unit_begin, s1, L, p);
+        }
+        next = -1;
+    }
+}
+
 // Persistent scoring kernel, two genotypes per wave (ind = 2 k + half).
 template <bool ANY_LAYOUT>
 __global__ __launch_bounds__(64, 3) void score_kernel_two(GridParams G, const uint8_t* __restrict__ blob, int n,
@@ -1931,12 +2015,24 @@ const void* ls_kernel_mw_ptr(int var) {
     }
 }
 
+const void* ls_kernel_uni_ptr(int var) {
+    switch (var) {
+        case 0: return reinterpret_cast<const void*>(&ls_kernel_uni<0>);
+        case 1: return reinterpret_cast<const void*>(&ls_kernel_uni<1>);
+        case 2: return reinterpret_cast<const void*>(&ls_kernel_uni<2>);
+        case 3: return reinterpret_cast<const void*>(&ls_kernel_uni<3>);
+        case 4: return reinterpret_cast<const void*>(&ls_kernel_uni<4>);
+        default: return nullptr;             // the plan gives this launch one variant
+    }
+}
+
 const void* ls_kernel_for(int mode, int var) {
     if (mode == docklaunch::kTwoPerWave)
         return var == DOCK_REDUCE_SHUFFLE ? reinterpret_cast<const void*>(&ls_kernel_two<false>)
                                           : reinterpret_cast<const void*>(&ls_kernel_two<true>);
     if (mode == docklaunch::kTwoWave) return ls_kernel_mw_ptr<2>(var);
     if (mode == docklaunch::kFourWave) return ls_kernel_mw_ptr<4>(var);
+    if (mode == docklaunch::kUnified) return ls_kernel_uni_ptr(var);
     if (mode == docklaunch::kSlots1) return ls_kernel_ptr<docklaunch::kSlots1>(var);
     if (mode == docklaunch::kSlots2) return ls_kernel_ptr<docklaunch::kSlots2>(var);
     return ls_kernel_ptr<docklaunch::kSlotsAny>(var);
@@ -2005,6 +2101,7 @@ hipError_t launch_expand_corners(const GridParams& g, float* corners, hipStream_
 hipError_t launch_ls(const LsParams& p, int mode, int variant_uniform, int grid_blocks,
                      hipStream_t stream) {
     const void* k = ls_kernel_for(mode, variant_uniform);
+    if (!k) return hipErrorInvalidValue;
     LsParams pp = p;
     void* args[] = {&pp};
     return hipLaunchKernel(k, dim3(grid_blocks), dim3(ls_block_threads(mode)), args, 0, stream);
@@ -2019,7 +2116,7 @@ int ls_blocks_per_cu(int mode, int variant_uniform) {
     int nb = cache[m][v].load(std::memory_order_relaxed);
     if (nb > 0) return nb;
     const void* k = ls_kernel_for(mode, variant_uniform);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, ls_block_threads(mode), 0) != hipSuccess) return 0;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, ls_block_threads(mode), 0) != hipSuccess) return 0;
     cache[m][v].store(nb, std::memory_order_relaxed);
     return nb;
 }

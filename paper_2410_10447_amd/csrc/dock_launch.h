@@ -38,6 +38,8 @@ struct DevItem {
     int32_t unit_begin;     // first work unit (individual) of this item
     int32_t iterations;     // steps for this item
     int32_t final_eval;     // evaluate the point reached after the last step
+    int32_t pack;           // individuals per wave: 2 (two per wave), else 1
+    int32_t pad_;
 };
 
 struct LsParams {
@@ -45,6 +47,7 @@ struct LsParams {
     int32_t* counter;       // device, zero at launch
     int32_t n_items;
     int32_t total_units;
+    int32_t block_units;    // one mixed launch: units [0, block_units) take both waves of a block
     float rho, eps;
 };
 
@@ -52,12 +55,17 @@ struct LsParams {
 constexpr int64_t kWorkspaceHeader = 64;
 
 // ls kernel families: slots 1, slots 2, or both (runtime per item), all one
-// wave per individual; two or four waves per individual; or two individuals
-// per wave (ligands of <= 32 atoms and <= 32 genes, shuffle reduction)
-enum LsMode { kSlots1 = 1, kSlots2 = 2, kSlotsAny = 3, kTwoWave = 4, kTwoPerWave = 5, kFourWave = 6 };
-constexpr int kLsModes = 7;
+// wave per individual; two or four waves per individual; two individuals
+// per wave (ligands of <= 32 atoms and <= 32 genes, shuffle reduction); or
+// one launch holding two-wave individuals, one-slot individuals and pairs
+// two per wave (one variant, corner-expanded maps)
+enum LsMode { kSlots1 = 1, kSlots2 = 2, kSlotsAny = 3, kTwoWave = 4, kTwoPerWave = 5, kFourWave = 6,
+              kUnified = 7 };
+constexpr int kLsModes = 8;
 
-inline int ls_block_threads(int mode) { return mode == kTwoWave ? 128 : (mode == kFourWave ? 256 : 64); }
+inline int ls_block_threads(int mode) {
+    return (mode == kTwoWave || mode == kUnified) ? 128 : (mode == kFourWave ? 256 : 64);
+}
 
 // Persistent: at most the resident blocks of n_cu CUs, each looping over
 // genotypes with a stride of the grid size.

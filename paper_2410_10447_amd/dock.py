@@ -19,7 +19,7 @@ _LIB_PATH = os.environ.get("DOCKMI_LIB") or os.path.join(os.path.dirname(os.path
                                                          "libdockmi.so")
 
 # the struct layouts below follow include/dock.h of this ABI version
-ABI_VERSION = 10
+ABI_VERSION = 11
 
 DOCK_OK = 0
 DOCK_EINVAL = -1
@@ -37,6 +37,7 @@ VARIANT_NAMES = {0: "shuffle", 1: "mfma_f32", 2: "mfma_bf16", 3: "mfma_f16", 4: 
                  5: "shared_atomic"}
 
 LS_FINAL_EVAL = 1
+LS_SEPARATE_LAUNCHES = 2
 ITEM_PLAIN_MAPS = 1     # dock_ls_item.flags: read the planar maps
 ITEM_TWO_PER_WAVE = 2   # dock_ls_item.flags: two individuals per wave (<= 32 atoms, <= 32 genes)
 EXEC_TWO_PER_WAVE = 1   # dock_exec_opts.flags: two genotypes per wave
@@ -52,7 +53,8 @@ ABI_SYMBOLS = (
     "dock_create_ligand", "dock_ligand_info_get", "dock_ligand_export", "dock_ligand_upload",
     "dock_destroy_ligand", "dock_score_batch", "dock_ls_workspace_bytes",
     "dock_select_rows", "dock_gather_rows", "dock_scatter_rows",
-    "dock_local_search_batch", "dock_local_search_batch_static", "dock_block_sum4", "dock_ga_step", "dock_solis_wets_batch",
+    "dock_local_search_batch", "dock_local_search_batch_static", "dock_ls_launches", "dock_block_sum4",
+    "dock_ga_step", "dock_solis_wets_batch",
 )
 
 
@@ -151,6 +153,7 @@ def lib():
         "dock_ls_workspace_bytes": ([i32, C.POINTER(i64)], i32),
         "dock_local_search_batch": ([C.POINTER(LsItem), i32, C.POINTER(LsOpts), vp, i64, vp], i32),
         "dock_local_search_batch_static": ([C.POINTER(LsItem), i32, C.POINTER(LsOpts), vp], i32),
+        "dock_ls_launches": ([C.POINTER(LsItem), i32, C.POINTER(LsOpts), C.POINTER(i32)], i32),
         "dock_block_sum4": ([vp, vp, i32, i32, i32, i32, vp], i32),
         "dock_ga_step": ([C.POINTER(GaStepDesc), vp], i32),
         "dock_select_rows": ([vp, i32, C.c_float, vp, vp, vp], i32),
@@ -505,12 +508,13 @@ def make_items(jobs):
 
 def local_search(jobs, iterations: int, rho: float = 0.8, eps: float = 1e-2,
                  variant: int = REDUCE_SHUFFLE, final_eval: bool = True, workspace=None,
-                 stream=None, items=None, threads_per_ind: int = 0):
-    """ADADELTA on every (Grids, Ligand, LSState[, variant]) job, one launch.
+                 stream=None, items=None, threads_per_ind: int = 0, separate_launches: bool = False):
+    """ADADELTA on every (Grids, Ligand, LSState[, variant]) job, one call.
 
     State tensors are updated in place. `workspace` (uint8 CUDA tensor) is
     allocated if not given; `items` may pass a prebuilt item array.
     `threads_per_ind` (0/64/128/256) is the default for jobs that leave it at 0.
+    `separate_launches` runs each kernel family in a launch of its own.
     """
     import torch
     n_items = len(jobs)
@@ -522,16 +526,29 @@ def local_search(jobs, iterations: int, rho: float = 0.8, eps: float = 1e-2,
     if workspace is None or workspace.numel() < need:
         dev = torch.device("cuda")
         workspace = torch.empty(max(need, 64), dtype=torch.uint8, device=dev)
-    o = LsOpts(iterations=iterations, rho=rho, eps=eps, variant=variant,
-               threads_per_ind=threads_per_ind, flags=LS_FINAL_EVAL if final_eval else 0)
+    o = LsOpts(iterations=iterations, rho=rho, eps=eps, variant=variant, threads_per_ind=threads_per_ind,
+               flags=(LS_FINAL_EVAL if final_eval else 0) | (LS_SEPARATE_LAUNCHES if separate_launches else 0))
     _check(lib().dock_local_search_batch(items, n_items, C.byref(o), _ptr(workspace),
                                          workspace.numel(), _stream_handle(stream)))
     return workspace
 
 
+def ls_launches(jobs, iterations: int, variant: int = REDUCE_SHUFFLE, final_eval: bool = True,
+                threads_per_ind: int = 0, separate_launches: bool = False, items=None) -> int:
+    """Persistent launches local_search would make for these jobs."""
+    n_items = len(jobs)
+    if items is None:
+        items = make_items(jobs)
+    o = LsOpts(iterations=iterations, rho=0.8, eps=1e-2, variant=variant, threads_per_ind=threads_per_ind,
+               flags=(LS_FINAL_EVAL if final_eval else 0) | (LS_SEPARATE_LAUNCHES if separate_launches else 0))
+    n = C.c_int32(0)
+    _check(lib().dock_ls_launches(items, n_items, C.byref(o), C.byref(n)))
+    return n.value
+
+
 def local_search_static(jobs, iterations: int, rho: float = 0.8, eps: float = 1e-2,
                         variant: int = REDUCE_SHUFFLE, final_eval: bool = True, stream=None,
-                        items=None, threads_per_ind: int = 0):
+                        items=None, threads_per_ind: int = 0, separate_launches: bool = False):
     """local_search through dock_local_search_batch_static: the workspace is
     the library's own (at most STATIC_MAX_ITEMS jobs per call); the call
     allocates no device memory. Calls that may overlap on one GPU race."""
@@ -540,8 +557,8 @@ def local_search_static(jobs, iterations: int, rho: float = 0.8, eps: float = 1e
         items = make_items(jobs)
     elif len(items) < n_items:
         raise ValueError("items shorter than jobs")
-    o = LsOpts(iterations=iterations, rho=rho, eps=eps, variant=variant,
-               threads_per_ind=threads_per_ind, flags=LS_FINAL_EVAL if final_eval else 0)
+    o = LsOpts(iterations=iterations, rho=rho, eps=eps, variant=variant, threads_per_ind=threads_per_ind,
+               flags=(LS_FINAL_EVAL if final_eval else 0) | (LS_SEPARATE_LAUNCHES if separate_launches else 0))
     _check(lib().dock_local_search_batch_static(items, n_items, C.byref(o), _stream_handle(stream)))
 
 

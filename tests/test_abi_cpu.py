@@ -22,7 +22,7 @@ def test_library_exports_every_declared_symbol():
     assert declared == set(dock.ABI_SYMBOLS)
     for name in declared:
         assert hasattr(L, name)
-    assert L.dock_abi_version() == dock.ABI_VERSION == 10
+    assert L.dock_abi_version() == dock.ABI_VERSION == 11
 
 
 def _check_prep(lig):
@@ -377,7 +377,7 @@ def test_batch_calls_validate_before_device_work():
                                      C.byref(so), None, None)
         assert st == dock.DOCK_EINVAL and "n_genes" in dock.last_error()
     for bad in (dict(rho=1.0), dict(rho=0.0), dict(eps=0.0), dict(iterations=-1), dict(variant=9),
-                dict(flags=8), dict(threads_per_ind=96), dict(threads_per_ind=512)):
+                dict(flags=4), dict(threads_per_ind=96), dict(threads_per_ind=512)):
         kw = dict(iterations=10, rho=0.8, eps=1e-2, variant=0, threads_per_ind=0, flags=1)
         kw.update(bad)
         ob = dock.LsOpts(**kw)
@@ -410,6 +410,17 @@ def test_batch_calls_validate_before_device_work():
     st = L.dock_local_search_batch_static(many, dock.STATIC_MAX_ITEMS + 1, C.byref(o), None)
     assert st == dock.DOCK_EINVAL and "DOCK_STATIC_MAX_ITEMS" in dock.last_error()
     assert L.dock_local_search_batch_static(item, 0, C.byref(o), None) == dock.DOCK_OK   # nothing to do
+    # the launch-count query validates the same way, before any device work
+    nl = C.c_int32(-1)
+    assert L.dock_ls_launches(item, 1, C.byref(o), None) == dock.DOCK_EINVAL
+    st = L.dock_ls_launches(item, 1, C.byref(o), C.byref(nl))
+    assert st == dock.DOCK_EINVAL and "uploaded" in dock.last_error()
+    assert L.dock_ls_launches(item, 0, C.byref(o), C.byref(nl)) == dock.DOCK_OK and nl.value == 0
+    for bad in (dict(flags=4), dict(threads_per_ind=96)):
+        kw = dict(iterations=10, rho=0.8, eps=1e-2, variant=0, threads_per_ind=0, flags=1)
+        kw.update(bad)
+        ob = dock.LsOpts(**kw)
+        assert L.dock_ls_launches(item, 1, C.byref(ob), C.byref(nl)) in (dock.DOCK_EINVAL, dock.DOCK_EUNSUPPORTED)
     b = C.c_int64()
     assert L.dock_ls_workspace_bytes(3, C.byref(b)) == 0 and b.value >= 64 + 3 * 64
     assert L.dock_ls_workspace_bytes(-1, C.byref(b)) == dock.DOCK_EINVAL

@@ -685,6 +685,60 @@ def test_ls_step_map_two_per_wave(dk, n_atoms, n_tors):
     assert_reports(f"ls step-map two per wave N={n_atoms}", reps)
 
 
+def _mix_jobs(dk, spec, grd, G, ff, seed0):
+    """spec: (atoms, torsions, individuals, threads per individual, two per wave, variant)."""
+    jobs = []
+    for k, (n_atoms, n_tors, n, tpi, two, var) in enumerate(spec):
+        lig = synth.ligand(n_atoms, n_tors, seed0 + k)
+        L = dk.Ligand(lig, ff)
+        st = dk.LSState.start(torch.from_numpy(synth.genotypes(lig, grd, n, seed0 + 100 + k)).cuda())
+        jobs.append(dk.LsJob(G, L, st, var, threads_per_ind=tpi, two_per_wave=two))
+    return jobs
+
+
+@pytest.mark.parametrize("case", ["all three, shuffle", "two-wave and one-wave, FP32 MFMA",
+                                  "one-wave and two per wave"])
+def test_one_launch_equals_separate_launches(dk, case):
+    """A batch of two-wave individuals, one-wave individuals of <= 64-atom
+    ligands and pairs two per wave (one variant, corner-expanded maps) runs
+    as one launch of 128-thread blocks; every item's state equals, bit for
+    bit, what one launch per family gives, over two calls (the second with
+    the final evaluation), and through the library-resident workspace."""
+    grd = synth.grids(64, 10, 9901)
+    G = dk.Grids.from_synth(grd)
+    ff = synth.force_field()
+    two_wave = [(100, 14, 37, 128, False), (80, 6, 21, 128, False), (128, 32, 9, 128, False)]
+    one_wave = [(48, 10, 70, 64, False), (30, 4, 90, 64, False), (64, 12, 11, 64, False)]
+    pairs = [(24, 6, 55, 64, True), (16, 2, 13, 64, True), (32, 25, 8, 64, True)]
+    if case == "all three, shuffle":
+        spec, var, fams = two_wave + one_wave + pairs, 0, 3
+    elif case == "two-wave and one-wave, FP32 MFMA":
+        spec, var, fams = two_wave + one_wave, 1, 2
+    else:
+        spec, var, fams = one_wave + pairs, 0, 2
+    spec = [s + (var,) for s in spec]
+    a = _mix_jobs(dk, spec, grd, G, ff, 9910)
+    b = [dk.LsJob(j.grids, j.ligand, j.state.clone(), j.variant, threads_per_ind=j.threads_per_ind,
+                  two_per_wave=j.two_per_wave) for j in a]
+    c = [dk.LsJob(j.grids, j.ligand, j.state.clone(), j.variant, threads_per_ind=j.threads_per_ind,
+                  two_per_wave=j.two_per_wave) for j in a]
+    assert dk.ls_launches(a, 12) == 1
+    assert dk.ls_launches(a, 12, separate_launches=True) == fams
+    dk.local_search(a, 12, final_eval=False)
+    dk.local_search(b, 12, final_eval=False, separate_launches=True)
+    dk.local_search_static(c, 12, final_eval=False)
+    dk.local_search(a, 8)
+    dk.local_search(b, 8, separate_launches=True)
+    dk.local_search_static(c, 8)
+    torch.cuda.synchronize()
+    for k, (ja, jb, jc) in enumerate(zip(a, b, c)):
+        an, bn, cn = ja.state.to_numpy(), jb.state.to_numpy(), jc.state.to_numpy()
+        for f in an:
+            assert np.array_equal(an[f], bn[f]), (case, k, f)
+            assert np.array_equal(an[f], cn[f]), (case, k, f)
+        assert np.all(an["iters_done"] == 20)
+
+
 def test_two_per_wave_plain_maps_identical(dk):
     """Two per wave on the planar maps (grids without the corner copy, or the
     per-item layout choice with it bound) gives the same scores and searches,

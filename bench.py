@@ -324,23 +324,24 @@ def sw_run(G, L, gen0, iterations, variant, reps=3, seed=91):
 
 def uneven_runs(steps, warmup, tpi_override=0):
     """64 ligands (atoms U{12..128}, torsions U{0..32}) x 100 individuals on one
-    96^3 x 12 grid set, 300 iterations, in one call per step, planned two
+    96^3 x 12 grid set, 300 iterations, in one call per step, planned three
     ways: "tuned", each item with its size bucket's variant, threads per
     individual, grid layout and individuals per wave from the autotuning
-    table (one persistent launch per kernel family, side by side;
-    `tpi_override` forces the thread count of every ligand), and
-    "one_launch", every item on one wave with the shuffle reduction (a single
-    persistent launch). The two plans' calls alternate, each call timed on its
-    own (synchronised), so that both see the same clock and thermal state;
-    each plan reports the median of its `steps` calls."""
+    table (one persistent launch where the families can share one, as the
+    table arranges; `tpi_override` forces the thread count of every ligand);
+    "separate", the same items with one launch per kernel family, side by
+    side; and "one_wave", every item on one wave with the shuffle reduction
+    (one launch). The plans' calls alternate, each call timed on its own
+    (synchronised), so that all see the same clock and thermal state; each
+    plan reports the median of its `steps` calls."""
     import torch
     from paper_2410_10447_amd import autotune, dock, synth
     w = synth.uneven_workload()
     G = dock.Grids.from_synth(w.grids)
     Ls = [dock.Ligand(l, w.ff) for l in w.ligands]
     gens = [torch.from_numpy(g).cuda() for g in w.genotypes]
-    plans = {"tuned": [autotune.choose(L.n_atoms, L.n_torsions) for L in Ls],
-             "one_launch": [dict(autotune.DEFAULT) for _ in Ls]}
+    tuned = [autotune.choose(L.n_atoms, L.n_torsions) for L in Ls]
+    plans = {"tuned": tuned, "separate": tuned, "one_wave": [dict(autotune.DEFAULT) for _ in Ls]}
     if tpi_override:
         for c in plans["tuned"]:
             c["threads_per_ind"] = tpi_override
@@ -348,25 +349,30 @@ def uneven_runs(steps, warmup, tpi_override=0):
     evals = sum(g.shape[0] for g in gens) * (w.iterations + 1)
     ws = torch.empty(dock.workspace_bytes(len(Ls)), dtype=torch.uint8, device="cuda")
 
-    def call(pick):
+    def jobs_of(pick):
         states = [dock.LSState.start(g) for g in gens]
-        jobs = [dock.LsJob(G, L, st, c["variant"], threads_per_ind=c.get("threads_per_ind", 64),
+        return [dock.LsJob(G, L, st, c["variant"], threads_per_ind=c.get("threads_per_ind", 64),
                            plain_maps=c.get("plain_maps", False), two_per_wave=c.get("two_per_wave", False))
                 for L, st, c in zip(Ls, states, pick)]
-        items = dock.make_items(jobs)
+
+    def call(k, pick):
+        items = dock.make_items(jobs_of(pick))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        dock.local_search([None] * len(Ls), w.iterations, workspace=ws, items=items)
+        dock.local_search([None] * len(Ls), w.iterations, workspace=ws, items=items,
+                          separate_launches=k == "separate")
         torch.cuda.synchronize()
         return time.perf_counter() - t0
 
+    launches = {k: dock.ls_launches(jobs_of(pick), w.iterations, separate_launches=k == "separate")
+                for k, pick in plans.items()}
     for _ in range(warmup):
-        for pick in plans.values():
-            call(pick)
+        for k, pick in plans.items():
+            call(k, pick)
     times = {k: [] for k in plans}
     for _ in range(steps):
         for k, pick in plans.items():
-            times[k].append(call(pick))
+            times[k].append(call(k, pick))
     work = sum(g.shape[0] * (w.iterations + 1) * work_per_eval(L.n_pairs, L.n_atoms, L.n_torsions)
                for g, L in zip(gens, Ls))
     out = {}
@@ -377,9 +383,9 @@ def uneven_runs(steps, warmup, tpi_override=0):
                   "evals_per_s": evals / dt,
                   "roofline": roofline(evals, dt, work / evals,
                                        kernel="ls_kernel (all families, wall clock per call; mean work per eval)"),
-                  "variants_from_table": k == "tuned",
-                  "single_launch": k == "one_launch",
-                  "threads_per_ind_override": tpi_override if k == "tuned" else 0,
+                  "variants_from_table": k != "one_wave",
+                  "launches": launches[k],
+                  "threads_per_ind_override": tpi_override if k != "one_wave" else 0,
                   "two_wave_items": sum(1 for c in pick if c.get("threads_per_ind", 64) == 128),
                   "four_wave_items": sum(1 for c in pick if c.get("threads_per_ind", 64) == 256),
                   "plain_map_items": sum(1 for c in pick if c.get("plain_maps", False)),
@@ -556,12 +562,13 @@ def main():
                              kernel_sha256=kernel_sha256()[:16]),
     }
     if args.uneven_steps > 0:
-        # the tuned per-family launches, and every item on one wave with the
-        # shuffle reduction (one persistent launch, the kernel dispatching per
-        # item on its atom layout), calls alternating
+        # as tuned (one launch where the families share one), the same items
+        # with one launch per family, and every item on one wave with the
+        # shuffle reduction (one launch), calls alternating
         u = uneven_runs(args.uneven_steps, 1, tpi_override=args.uneven_tpi)
         out["uneven"] = u["tuned"]
-        out["uneven_one_launch"] = u["one_launch"]
+        out["uneven_separate_launches"] = u["separate"]
+        out["uneven_one_wave"] = u["one_wave"]
     if args.serve_seconds > 0:
         out["serving"] = serving_run(args.serve_seconds, args.serve_rate, variant=best_v)
     if args.lga_generations > 0:

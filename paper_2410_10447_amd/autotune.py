@@ -138,6 +138,7 @@ def tune(out: str = TABLE_PATH, n_individuals: int = 12288, iterations: int = 20
         table["buckets"][key] = entry
         print(key, entry, flush=True)
     unify_families(table)
+    unify_shared_launch(table)
     with open(out, "w") as f:
         json.dump(table, f, indent=1)
     _cache.pop(out, None)
@@ -197,6 +198,47 @@ def unify_families(table, tol: float = 0.06):
             "variant": None if best_o is None else best_o[0],
             "plain_maps": None if best_o is None else best_o[1],
             "worst_loss": best_loss, "unified": best_loss is not None and best_loss <= tol}
+    return table
+
+
+SHARED_FAMILIES = ("two-wave", "one-slot", "two-per-wave")
+
+
+def unify_shared_launch(table, tol: float = 0.06):
+    """One reduction variant, on the corner-expanded maps, for the kernel
+    families that can share one persistent launch (two waves per individual,
+    one wave for ligands of <= 64 atoms, two individuals per wave), where it
+    costs at most `tol` in every bucket against the bucket's best candidate
+    at its threads per individual and individuals per wave: a batch mixing
+    those families then runs as one launch. Two per wave has the shuffle
+    reduction only, so with such buckets the shuffle is the one choice."""
+    keys = [k for k, e in table["buckets"].items() if family(e) in SHARED_FAMILIES]
+    if not keys:
+        return table
+    fams = {family(table["buckets"][k]) for k in keys}
+    variants = [0] if "two-per-wave" in fams else sorted(
+        {int(m.split("_")[0][1:]) for k in keys for m in table["buckets"][k]["measured"]})
+    best_v, best_loss = None, None
+    for v in variants:
+        loss = 0.0
+        for key in keys:
+            e = table["buckets"][key]
+            best = max(r for m, r in e["measured"].items()
+                       if m.startswith("v") and m.split("_")[1] == f"b{e['threads_per_ind']}"
+                       and m.endswith("_x2") == bool(e.get("two_per_wave")))
+            r = e["measured"].get(cand_key({"variant": v, "threads_per_ind": e["threads_per_ind"],
+                                            "plain_maps": False, "two_per_wave": e.get("two_per_wave", False)}))
+            loss = max(loss, 1.0 if r is None else 1.0 - r / best)
+        if best_loss is None or loss < best_loss:
+            best_v, best_loss = v, loss
+    shared = best_loss is not None and best_loss <= tol
+    if shared:
+        for key in keys:
+            e = table["buckets"][key]
+            e["variant"], e["plain_maps"] = best_v, False
+            e["evals_per_s"] = e["measured"][cand_key(e)]
+    table["shared_launch"] = {"families": sorted(fams), "variant": best_v, "worst_loss": best_loss,
+                              "unified": shared}
     return table
 
 

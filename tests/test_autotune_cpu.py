@@ -75,3 +75,30 @@ def test_families_and_choice_of_two_per_wave():
         assert not autotune.choose(20, 26, path)["two_per_wave"]
     finally:
         autotune._cache.pop(path, None)
+
+
+def test_shared_launch_variant():
+    """The families that can share a launch take one variant on the
+    corner-expanded maps when it costs at most 6 % anywhere; with two per
+    wave among them, the shuffle (the only reduction two per wave has)."""
+    def entry(atoms, tpi, two, rates, variant):
+        e = {"atoms": atoms, "torsions": 4, "threads_per_ind": tpi, "variant": variant, "plain_maps": False,
+             "measured": rates}
+        if two:
+            e["two_per_wave"] = True
+        e["evals_per_s"] = rates[autotune.cand_key(e)]
+        return e
+    table = {"buckets": {
+        "a0_t0": entry(16, 64, True, {"v0_b64_x2": 100.0, "v0_b64": 60.0, "v1_b64": 61.0}, 0),
+        "a1_t0": entry(48, 64, False, {"v0_b64": 97.0, "v1_b64": 100.0}, 1),
+        "a2_t0": entry(80, 128, False, {"v0_b128": 99.0, "v1_b128": 100.0, "v0_b64": 80.0}, 1),
+    }}
+    autotune.unify_shared_launch(table)
+    b = table["buckets"]
+    assert table["shared_launch"]["unified"] and table["shared_launch"]["variant"] == 0
+    assert all(e["variant"] == 0 and not e["plain_maps"] for e in b.values())
+    assert b["a1_t0"]["evals_per_s"] == 97.0
+    # a loss above the tolerance leaves the buckets alone
+    table["buckets"]["a1_t0"] = entry(48, 64, False, {"v0_b64": 90.0, "v1_b64": 100.0}, 1)
+    autotune.unify_shared_launch(table)
+    assert not table["shared_launch"]["unified"] and table["buckets"]["a1_t0"]["variant"] == 1

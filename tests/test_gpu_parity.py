@@ -739,6 +739,40 @@ def test_one_launch_equals_separate_launches(dk, case):
         assert np.all(an["iters_done"] == 20)
 
 
+def test_launch_plans(dk):
+    """How many persistent launches a call makes: one for a mix of two-wave,
+    one-slot and two-per-wave items with one variant on corner-expanded
+    maps, or for the two one-wave families with one variant; one per family
+    otherwise (variants differ, an item on planar maps, four waves or two
+    atom slots per lane among families that share with others) or on
+    request."""
+    grd = synth.grids(48, 10, 9951)
+    G = dk.Grids.from_synth(grd)
+    ff = synth.force_field()
+
+    def jobs(spec, plain=()):
+        out = []
+        for k, (n_atoms, n_tors, tpi, two, var) in enumerate(spec):
+            lig = synth.ligand(n_atoms, n_tors, 9960 + k)
+            st = dk.LSState.start(torch.from_numpy(synth.genotypes(lig, grd, 3, 9970 + k)).cuda())
+            out.append(dk.LsJob(G, dk.Ligand(lig, ff), st, var, threads_per_ind=tpi, two_per_wave=two,
+                                plain_maps=k in plain))
+        return out
+    two_wave, one_slot, pair = (90, 10, 128, False, 0), (40, 5, 64, False, 0), (20, 3, 64, True, 0)
+    four, two_slot = (70, 6, 256, False, 0), (100, 8, 64, False, 0)
+    assert dk.ls_launches(jobs([one_slot]), 5) == 1
+    assert dk.ls_launches(jobs([two_wave, one_slot, pair]), 5) == 1
+    assert dk.ls_launches(jobs([two_wave, one_slot, pair]), 5, separate_launches=True) == 3
+    assert dk.ls_launches(jobs([one_slot, pair]), 5) == 1
+    assert dk.ls_launches(jobs([one_slot, pair], plain=(0,)), 5) == 2
+    assert dk.ls_launches(jobs([two_wave, one_slot[:4] + (1,)]), 5) == 2
+    assert dk.ls_launches(jobs([two_wave, one_slot, four]), 5) == 3
+    assert dk.ls_launches(jobs([two_slot, one_slot]), 5) == 1
+    assert dk.ls_launches(jobs([two_slot, one_slot]), 5, separate_launches=True) == 2
+    assert dk.ls_launches(jobs([two_slot, one_slot, two_wave]), 5) == 3
+    assert dk.ls_launches(jobs([one_slot]), 0, final_eval=False) == 0      # nothing to do
+
+
 def test_two_per_wave_plain_maps_identical(dk):
     """Two per wave on the planar maps (grids without the corner copy, or the
     per-item layout choice with it bound) gives the same scores and searches,

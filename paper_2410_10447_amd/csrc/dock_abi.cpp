@@ -347,7 +347,7 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
 }
 
 // Launches the parts of a plan whose table is already on its way to `ws`
-// on `stream`. With side streams the second and third parts run beside the
+// on `stream`. With side streams the second and later parts run beside the
 // first on library-owned streams (forked from and joined back into
 // `stream`); without, every part runs on `stream`, one after another.
 int32_t ls_launch(const LsPlan& plan, const LsPlanBuf& buf, void* ws, const dock_ls_opts* o,

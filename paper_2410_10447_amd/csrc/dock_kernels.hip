@@ -1277,11 +1277,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == dock
         if (lane_id() == 0) u = atomicAdd(p.counter, 1);
         u = uniform(u);
         if (u >= p.total_units) break;
-        int lo = 0, hi = p.n_items - 1;
-        while (lo < hi) {  // last item with unit_begin <= u
-            const int mid = (lo + hi + 1) >> 1;
-            if (uniform(gmem(&p.items[mid].unit_begin)[0]) <= u) lo = mid; else hi = mid - 1;
-        }
+        const int lo = item_of_unit(p, u);
         const DevItem it = load_item(p.items, lo);
         const int ind = u - it.unit_begin;
         // the ligand's LDS tables are refilled only when the item changes;
@@ -1320,11 +1316,7 @@ __global__ __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(3, 3
         __syncthreads();
         const int u = uniform(sm.unit);
         if (u >= p.total_units) break;
-        int lo = 0, hi = p.n_items - 1;
-        while (lo < hi) {  // last item with unit_begin <= u
-            const int mid = (lo + hi + 1) >> 1;
-            if (uniform(gmem(&p.items[mid].unit_begin)[0]) <= u) lo = mid; else hi = mid - 1;
-        }
+        const int lo = item_of_unit(p, u);
         const DevItem it = load_item(p.items, lo);
         const int ind = u - it.unit_begin;
         const bool reload = lo != cur_item;
@@ -1754,11 +1746,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
         if (lane_id() == 0) u = atomicAdd(p.counter, 1);
         u = uniform(u);
         if (u >= p.total_units) break;
-        int lo = 0, hi = p.n_items - 1;
-        while (lo < hi) {  // last item with unit_begin <= u
-            const int mid = (lo + hi + 1) >> 1;
-            if (uniform(gmem(&p.items[mid].unit_begin)[0]) <= u) lo = mid; else hi = mid - 1;
-        }
+        const int lo = item_of_unit(p, u);
         const DevItem it = load_item(p.items, lo);
         const int ind0 = 2 * (u - it.unit_begin);
         const int count = min(2, it.n - ind0);

@@ -342,7 +342,7 @@ int32_t dock_ls_launches(const dock_ls_item* items, int32_t n_items, const dock_
  * search as dock_local_search_batch, same items, opts, kernels and results
  * bit for bit, with the workspace held by the library instead of passed in.
  * Each GPU holds one library-resident workspace of
- * 64 + DOCK_STATIC_MAX_ITEMS item records (about 10 KB) until the process
+ * 64 + DOCK_STATIC_MAX_ITEMS item records (about 11 KB) until the process
  * ends; the call writes its item table there with kernel launches on
  * `stream` (the data travels in kernel arguments) and then launches the
  * search on `stream`, each kernel family after the other (no side streams).

@@ -737,6 +737,27 @@ def test_one_launch_equals_separate_launches(dk, case):
             assert np.array_equal(an[f], bn[f]), (case, k, f)
             assert np.array_equal(an[f], cn[f]), (case, k, f)
         assert np.all(an["iters_done"] == 20)
+    # items at different stages in one shared launch (a serving loop's
+    # chunk): per-item step counts and final evaluations, with a gradient out
+    its = [(5, 0), (12, 1), (0, 1), (7, -1), (3, 0), (9, 1)]
+    def staged(jobs, sep):
+        out = []
+        for k, j in enumerate(jobs):
+            n_it, fin = its[k % len(its)]
+            out.append(dk.LsJob(j.grids, j.ligand, j.state.clone(), j.variant, iterations=n_it, final_eval=fin,
+                                grad=torch.zeros_like(j.state.genotype), threads_per_ind=j.threads_per_ind,
+                                two_per_wave=j.two_per_wave))
+        return out
+    d, e = staged(a, False), staged(a, True)
+    dk.local_search(d, 12, final_eval=True)
+    dk.local_search(e, 12, final_eval=True, separate_launches=True)
+    torch.cuda.synchronize()
+    for k, (jd, je) in enumerate(zip(d, e)):
+        dn, en = jd.state.to_numpy(), je.state.to_numpy()
+        for f in dn:
+            assert np.array_equal(dn[f], en[f]), (case, "staged", k, f)
+        assert torch.equal(jd.grad, je.grad), (case, "staged grad", k)
+        assert np.all(dn["iters_done"] == 20 + its[k % len(its)][0])
 
 
 def test_launch_plans(dk):

@@ -131,6 +131,7 @@ int device_cu_count(int32_t& out) {
 // others, so the caller's later work still waits for all of them. The
 // fork-launch-join sequence is serialised, since the events are shared.
 constexpr int kLsFamilies = 5;
+static_assert(8 + kLsFamilies <= docklaunch::kWorkspaceHeader / 4, "work counters fit the workspace header");
 struct SideStream {
     hipStream_t stream[kLsFamilies - 1] = {};
     hipEvent_t fork = nullptr, join[kLsFamilies - 1] = {};
@@ -177,7 +178,11 @@ struct LsPlanBuf {
     uint8_t* table;
 };
 
-struct LsPart { int first, count, mode, variant; int64_t units, block_units; };
+struct LsPart {
+    int first, count, mode, variant;
+    int64_t units, block_units;
+    double block_work, wave_work;   // shared launch: estimated wave-slot time of either phase
+};
 
 struct LsPlan {
     LsPart part[kLsFamilies];
@@ -317,7 +322,7 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
                                                         docklaunch::kTwoPerWave};
             const int mode = unified ? docklaunch::kUnified
                                      : (merge_one_wave ? docklaunch::kSlotsAny : kModes[g]);
-            plan.part[plan.n_parts++] = {i, 0, mode, -1, 0, 0};
+            plan.part[plan.n_parts++] = {i, 0, mode, -1, 0, 0, 0.0, 0.0};
             ub = 0;
         }
         tab[i] = dev[idx[i]];
@@ -326,7 +331,18 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
         const int units = tab[i].pack == 2 ? (tab[i].n + 1) / 2 : tab[i].n;
         ub += units;
         plan.part[plan.n_parts - 1].units += units;
-        if (unified && fam[idx[i]] == 1) plan.part[plan.n_parts - 1].block_units += units;
+        if (unified) {
+            // wave-slot time: two waves per individual take about 0.6 of one
+            // wave's time on two slots; two per wave about 1.3 of it for two
+            LsPart& pt = plan.part[plan.n_parts - 1];
+            const double work = (double)cost[idx[i]] * tab[i].n;
+            if (fam[idx[i]] == 1) {
+                pt.block_units += units;
+                pt.block_work += 1.25 * work;
+            } else {
+                pt.wave_work += (tab[i].pack == 2 ? 0.65 : 1.0) * work;
+            }
+        }
         ++plan.part[plan.n_parts - 1].count;
     }
     // each launch runs the kernel specialised for its items' variant when
@@ -344,6 +360,23 @@ int32_t ls_plan(const dock_ls_item* items, int32_t n_items, const dock_ls_opts* 
         pt.variant = (v < 0 || !corners) ? -1 : v;
     }
     return ok();
+}
+
+// Blocks of a shared launch that skip the two-wave phase: the one-wave
+// units' share of the estimated work, of the grid, so that both kinds of
+// unit start at once (blocks that run out of two-wave units then turn to
+// one-wave units). On the uneven 64-ligand batch this share made the launch
+// 2-3 % faster than with every block starting on two-wave units, and than
+// one launch per family; 1.25-1.5 times it gave less, twice it a slower
+// launch.
+constexpr double kSharedWaveShare = 1.0;
+
+int shared_wave_blocks(const LsPart& pt, int grid) {
+    const double total = pt.block_work + pt.wave_work;
+    if (pt.block_units == 0) return grid;
+    if (total <= 0.0) return 0;
+    const int w = (int)(kSharedWaveShare * grid * pt.wave_work / total);
+    return std::max(0, std::min(grid, w));
 }
 
 // Launches the parts of a plan whose table is already on its way to `ws`
@@ -383,6 +416,8 @@ int32_t ls_launch(const LsPlan& plan, const LsPlanBuf& buf, void* ws, const dock
         p.n_items = pt.count;
         p.total_units = (int32_t)units;
         p.block_units = (int32_t)pt.block_units;
+        p.counter2 = static_cast<int32_t*>(ws) + 8 + k;
+        p.wave_blocks = pt.mode == docklaunch::kUnified ? shared_wave_blocks(pt, grid) : 0;
         p.rho = o->rho;
         p.eps = o->eps;
         hipStream_t s_k = (k == 0 || !side) ? stream : side->stream[k - 1];

@@ -1760,14 +1760,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 3))) void
 
 // One persistent launch for a batch that mixes two-wave individuals with
 // one-wave units (an individual of a ligand of <= 64 atoms, or a pair of
-// individuals two per wave): 128-thread blocks over one work counter. Units
-// [0, block_units) are the two-wave individuals (their items come first),
-// which a block takes as ls_kernel_mw does. Once the counter passes them,
-// each wave takes the remaining units on its own, in its own half of the
-// block's LDS, ordering its LDS accesses at wave scope only (the other wave
-// may be anywhere in its own unit); the unit the block took last, already
-// past the two-wave range, goes to the first wave. Every wave exits once
-// the counter passes the last unit.
+// individuals two per wave): 128-thread blocks, two work counters. Units
+// [0, block_units) are the two-wave individuals (their items come first):
+// a block takes them from the first counter as ls_kernel_mw does. Once that
+// counter passes them, or from the start for the last wave_blocks blocks of
+// the grid, each wave takes the remaining units from the second counter on
+// its own, in its own half of the block's LDS, ordering its LDS accesses at
+// wave scope only (the other wave may be anywhere in its own unit). Every
+// wave exits once the second counter passes the last unit.
 constexpr size_t kWaveLds =
     ((sizeof(Smem2) > sizeof(Smem<1>) ? sizeof(Smem2) : sizeof(Smem<1>)) + 15) / 16 * 16;
 
@@ -1785,31 +1785,29 @@ template <int VAR>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3, 3))) void ls_kernel_uni(LsParams p) {
     __shared__ SmemUni sm;
     int cur_item = -1;
-    int u = 0;
-    while (true) {
-        __syncthreads();                       // the previous unit is read by both waves
-        if (threadIdx.x == 0) sm.unit = atomicAdd(p.counter, 1);
-        __syncthreads();
-        u = uniform(sm.unit);
-        if (u >= p.block_units) break;
-        const int lo = item_of_unit(p, u);
-        const DevItem it = load_item(p.items, lo);
-        const bool reload = lo != cur_item;
-        cur_item = lo;
-        Lig<1> L;
-        load_ligand<1, 2>(it.blob, sm.u.two, L, reload);
-        ls_run<1, VAR, 2>(it, u - it.unit_begin, sm.u.two, L, p);
+    if ((int)blockIdx.x < (int)gridDim.x - p.wave_blocks) {
+        while (true) {
+            __syncthreads();                   // the previous unit is read by both waves
+            if (threadIdx.x == 0) sm.unit = atomicAdd(p.counter, 1);
+            __syncthreads();
+            const int u = uniform(sm.unit);
+            if (u >= p.block_units) break;
+            const int lo = item_of_unit(p, u);
+            const DevItem it = load_item(p.items, lo);
+            const bool reload = lo != cur_item;
+            cur_item = lo;
+            Lig<1> L;
+            load_ligand<1, 2>(it.blob, sm.u.two, L, reload);
+            ls_run<1, VAR, 2>(it, u - it.unit_begin, sm.u.two, L, p);
+        }
     }
     const int w = uniform((int)threadIdx.x >> 6);
     unsigned char* const lds = sm.u.wave[w];
-    int next = w == 0 ? u : -1;
     cur_item = -1;                             // the two-wave tables are gone
     while (true) {
-        if (next < 0) {
-            int v = 0;
-            if (lane_id() == 0) v = atomicAdd(p.counter, 1);
-            next = uniform(v);
-        }
+        int v = 0;
+        if (lane_id() == 0) v = atomicAdd(p.counter2, 1);
+        const int next = p.block_units + uniform(v);
         if (next >= p.total_units) break;
         const int lo = item_of_unit(p, next);
         const DevItem it = load_item(p.items, lo);
@@ -1827,7 +1825,6 @@ __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
             load_ligand<1, 1>(it.blob, s1, L, reload);
             ls_run<1, VAR, 1>(it, next - it.unit_begin, s1, L, p);
         }
-        next = -1;
     }
 }
 

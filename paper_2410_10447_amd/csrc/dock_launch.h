@@ -45,13 +45,16 @@ struct DevItem {
 struct LsParams {
     const DevItem* items;   // device
     int32_t* counter;       // device, zero at launch
+    int32_t* counter2;      // one mixed launch: the one-wave units' counter, zero at launch
     int32_t n_items;
     int32_t total_units;
     int32_t block_units;    // one mixed launch: units [0, block_units) take both waves of a block
+    int32_t wave_blocks;    // one mixed launch: the last wave_blocks blocks take one-wave units only
     float rho, eps;
 };
 
-// Workspace layout: [int32 work counters (one per launch of a call), 64 B][DevItem x n_items]
+// Workspace layout: [int32 work counters (one per launch of a call, and at
+// index 8 + k the second counter of a shared launch k), 64 B][DevItem x n_items]
 constexpr int64_t kWorkspaceHeader = 64;
 
 // ls kernel families: slots 1, slots 2, or both (runtime per item), all one

@@ -308,10 +308,11 @@ int32_t dock_ls_workspace_bytes(int32_t n_items, int64_t* bytes);
  * persistent launch when every item uses one reduction variant and either
  * (a) its families are among two waves per individual, one wave for a
  * ligand of <= 64 atoms, and two per wave, and every item reads the
- * corner-expanded maps (128-thread blocks: a block takes the two-wave
- * individuals first, then each of its waves takes one-wave units on its
- * own), or (b) they are the two one-wave families (the kernel picks the
- * atom layout per item).
+ * corner-expanded maps (128-thread blocks: most blocks take two-wave
+ * individuals first, the rest, sized by the estimated share of the work,
+ * start on one-wave units, which each wave of a block takes on its own), or
+ * (b) they are the two one-wave families (the kernel picks the atom layout
+ * per item).
  * Otherwise, or with DOCK_LS_SEPARATE_LAUNCHES, it runs as one persistent
  * launch per family, side by side: the first on `stream`, the others on
  * streams the library owns (per device), forked from and joined back into

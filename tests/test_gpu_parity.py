@@ -568,8 +568,9 @@ def test_ls_best_energy_distribution_vs_oracle(dk, variant):
 def test_ls_uneven_full_size_sampled(dk):
     """The uneven batch at full size (64 ligands of 12-128 atoms and 0-32
     torsions, 100 individuals each, one 96^3 x 12 grid set, 300 iterations,
-    variants and thread counts from the tuning table) in one call: four best
-    points of every ligand against the oracle at the kernel's positions."""
+    variants and thread counts from the tuning table) in one call, which is
+    one persistent launch: four best points of every ligand against the
+    oracle at the kernel's positions."""
     from paper_2410_10447_amd import autotune
     from tests.gpu_common import assert_reports
     w = synth.uneven_workload()
@@ -580,6 +581,7 @@ def test_ls_uneven_full_size_sampled(dk):
     jobs = [dk.LsJob(G, L, st, c["variant"], threads_per_ind=c.get("threads_per_ind", 64),
                      plain_maps=c.get("plain_maps", False), two_per_wave=c.get("two_per_wave", False))
             for L, st, c in zip(Ls, states, picks)]
+    assert dk.ls_launches(jobs, w.iterations) == 1
     dk.local_search(jobs, w.iterations)
     torch.cuda.synchronize()
     reps = []

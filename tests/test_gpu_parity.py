@@ -216,6 +216,32 @@ def test_score_unnormalised_quaternion(dk):
     assert dot.max() < 1e-5
 
 
+@pytest.mark.parametrize("two_per_wave", [False, True])
+def test_score_torsion_angles_every_quadrant(dk, two_per_wave):
+    """Torsion angles at the quadrant boundaries k pi/2 (k = -8 .. 8), 1e-3 rad
+    to either side of them, and uniform over +-3000 rad (the genes are not
+    wrapped): the kernel's torsion rotations give the oracle's pose, energy
+    and gradient in every quadrant and at large arguments."""
+    w = synth.score_workload(96)
+    gen = w.genotypes[0].copy()
+    n_tors = gen.shape[1] - 7
+    base = np.arange(-8, 9) * (np.pi / 2)
+    rng = np.random.default_rng(77)
+    vals = np.concatenate([base, base + 1e-3, base - 1e-3, rng.uniform(-3000.0, 3000.0, 45)]).astype(np.float32)
+    for i in range(gen.shape[0]):
+        gen[i, 7:] = np.roll(vals, -i * n_tors)[:n_tors]
+    prep = R.prepare(w.ligands[0], w.ff)
+    G = dk.Grids.from_synth(w.grids)
+    L = dk.Ligand(w.ligands[0], w.ff)
+    if two_per_wave:
+        E, g, ao = dk.score_batch(G, L, torch.from_numpy(gen).cuda(), atom_out=True, two_per_wave=True)
+        torch.cuda.synchronize()
+        E, g, ao = E.cpu().numpy(), g.cpu().numpy(), ao.cpu().numpy()
+    else:
+        E, g, ao = gpu_points(dk, G, L, gen, 0)
+    check(f"score torsion angles, two per wave {two_per_wave}", prep, w.grids, gen, E, g, ao)
+
+
 def test_score_empty_batch(dk):
     w = synth.score_workload(4)
     G = dk.Grids.from_synth(w.grids)

@@ -539,6 +539,8 @@ def ls_launches(jobs, iterations: int, variant: int = REDUCE_SHUFFLE, final_eval
     n_items = len(jobs)
     if items is None:
         items = make_items(jobs)
+    elif len(items) < n_items:
+        raise ValueError("items shorter than jobs")
     o = LsOpts(iterations=iterations, rho=0.8, eps=1e-2, variant=variant, threads_per_ind=threads_per_ind,
                flags=(LS_FINAL_EVAL if final_eval else 0) | (LS_SEPARATE_LAUNCHES if separate_launches else 0))
     n = C.c_int32(0)

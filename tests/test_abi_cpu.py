@@ -431,6 +431,19 @@ def test_batch_calls_validate_before_device_work():
     assert L.dock_destroy_grids(None) == 0 and L.dock_destroy_ligand(None) == 0
 
 
+def test_binding_rejects_item_arrays_shorter_than_jobs():
+    """A prebuilt item array must cover every job: the binding checks its
+    length before the library reads it (the C ABI takes a count only)."""
+    items = dock.make_items([])       # one zeroed record
+    jobs = [None, None]
+    with pytest.raises(ValueError, match="items shorter"):
+        dock.ls_launches(jobs, 1, items=items)
+    with pytest.raises(ValueError, match="items shorter"):
+        dock.local_search(jobs, 1, items=items)
+    with pytest.raises(ValueError, match="items shorter"):
+        dock.local_search_static(jobs, 1, items=items)
+
+
 def test_row_selection_calls_validate_before_device_work():
     L = dock.lib()
     vp = C.c_void_p

@@ -104,6 +104,36 @@ def test_score_parity_ls_ligand(dk, variant):
     check(f"score c1-ligand v{variant}", prep, w.grids, gen, E, g, ao, variant)
 
 
+@pytest.mark.parametrize("two_per_wave,variant", [(False, 0), (False, 1), (True, 0)])
+def test_score_full_size_sampled(dk, two_per_wave, variant):
+    """The scoring configuration the benchmark times: 65,536 genotypes of the
+    24-atom ligand in one call, a persistent grid in which every block scores
+    many genotypes in turn. A sample from the whole index range (the first
+    and last genotypes included) is scored again in a call of its own, one
+    genotype (or pair) per block: bit for bit the same energies and
+    gradients, and within the FP32 bounds of the oracle."""
+    n = 65536
+    w = synth.score_workload(n)
+    gen = w.genotypes[0]
+    prep = R.prepare(w.ligands[0], w.ff)
+    G = dk.Grids.from_synth(w.grids)
+    L = dk.Ligand(w.ligands[0], w.ff)
+    gt = torch.from_numpy(gen).cuda()
+    E, g = dk.score_batch(G, L, gt, variant=variant, two_per_wave=two_per_wave)
+    rng = np.random.default_rng(65536)
+    idx = np.unique(np.concatenate([rng.choice(n, 252, replace=False), [0, 1, n - 2, n - 1]]))
+    sel = torch.from_numpy(idx).cuda()
+    Es, gs = dk.score_batch(G, L, gt[sel], variant=variant, two_per_wave=two_per_wave)
+    torch.cuda.synchronize()
+    assert torch.equal(Es, E[sel]) and torch.equal(gs, g[sel])
+    assert bool(torch.isfinite(E).all()) and bool(torch.isfinite(g).all())
+    Ea, ga, ao = dk.score_batch(G, L, gt[sel], variant=variant, two_per_wave=two_per_wave, atom_out=True)
+    torch.cuda.synchronize()
+    assert torch.equal(Ea, Es)
+    check(f"score full size, two per wave {two_per_wave}, v{variant}", prep, w.grids, gen[idx],
+          Ea.cpu().numpy(), ga.cpu().numpy(), ao.cpu().numpy(), variant)
+
+
 @pytest.mark.parametrize("variant", SPLIT_VARIANTS)
 def test_score_split_variants_error_report(dk, variant):
     """Half-width MFMA reductions: error against FP64, stated per individual.
@@ -365,6 +395,40 @@ def test_ls_chunked_equals_single_and_deterministic(dk, tpi):
     for f in a:
         assert np.array_equal(a[f], b[f]), f
         assert np.array_equal(a[f], c[f]), f
+
+
+@pytest.mark.parametrize("family", ["one wave, shuffle", "one wave, FP32 MFMA", "two waves", "four waves",
+                                    "two per wave"])
+def test_ls_persistent_waves_take_several_units(dk, family):
+    """8000 individuals in one call: more work units than resident blocks (or
+    waves), so blocks draw further units from the work counter after their
+    first and keep the ligand's tables loaded. The state of every individual
+    equals, bit for bit, that of the same individual searched in calls of
+    1000 (fewer units than resident waves)."""
+    n, chunk, iters = 8000, 1000, 3
+    variant = 1 if family == "one wave, FP32 MFMA" else 0
+    tpi = {"two waves": 128, "four waves": 256}.get(family, 64)
+    two = family == "two per wave"
+    w = synth.score_workload(n) if two else synth.ls_workload(n)
+    G = dk.Grids.from_synth(w.grids)
+    L = dk.Ligand(w.ligands[0], w.ff)
+    gen = torch.from_numpy(w.genotypes[0][:n]).cuda()
+
+    def run(rows):
+        st = dk.LSState.start(gen[rows].contiguous())
+        dk.local_search([dk.LsJob(G, L, st, variant, threads_per_ind=tpi, two_per_wave=two)], iters)
+        return st
+
+    whole = run(slice(0, n))
+    assert dk.ls_launches([dk.LsJob(G, L, whole, variant, threads_per_ind=tpi, two_per_wave=two)], iters) == 1
+    parts = [run(slice(lo, lo + chunk)) for lo in range(0, n, chunk)]
+    torch.cuda.synchronize()
+    a = whole.to_numpy()
+    for k, st in enumerate(parts):
+        b = st.to_numpy()
+        for f in a:
+            assert np.array_equal(a[f][k * chunk:(k + 1) * chunk], b[f]), (family, k, f)
+    assert np.all(a["iters_done"] == iters)
 
 
 def test_ls_full_size_sampled(dk):

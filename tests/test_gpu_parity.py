@@ -272,6 +272,21 @@ def test_score_torsion_angles_every_quadrant(dk, two_per_wave):
     check(f"score torsion angles, two per wave {two_per_wave}", prep, w.grids, gen, E, g, ao)
 
 
+@pytest.mark.parametrize("two_per_wave", [False, True])
+def test_score_without_gradient_output(dk, two_per_wave):
+    """A null gradient pointer writes energies only: the same energies, bit
+    for bit."""
+    w = synth.score_workload(300)
+    G = dk.Grids.from_synth(w.grids)
+    L = dk.Ligand(w.ligands[0], w.ff)
+    gt = torch.from_numpy(w.genotypes[0]).cuda()
+    E, g = dk.score_batch(G, L, gt, two_per_wave=two_per_wave)
+    E2, g2 = dk.score_batch(G, L, gt, with_grad=False, two_per_wave=two_per_wave)
+    torch.cuda.synchronize()
+    assert g2 is None and g.shape == (300, L.n_genes)
+    assert torch.equal(E, E2)
+
+
 def test_score_empty_batch(dk):
     w = synth.score_workload(4)
     G = dk.Grids.from_synth(w.grids)

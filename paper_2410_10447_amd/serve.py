@@ -15,7 +15,11 @@ docking task, Sec. 1). Jobs arrive over time. The server
   while others are on the GPU start at the next chunk and their work overlaps
   in the same launch;
 * keeps up to `depth` chunks enqueued so the device never idles while the host
-  plans the next one; completion is observed through events.
+  plans the next one; completion is observed through events;
+* lets a client withdraw a job (`cancel`, or `JobSpec.cancel_at`): a queued job
+  leaves the queue; an admitted one gets no further chunk, and its state is
+  released once no enqueued chunk carries it (a chunk already on the device
+  finishes; its work on the job is discarded).
 
 Because the kernel computes every individual independently and in a fixed
 order, and a chunked search equals an unchunked one bit for bit, a job's
@@ -45,6 +49,7 @@ class JobSpec:
     arrival: float            # seconds, on the server clock
     iterations: int = 300
     n: int = 0                # individuals, when `genotypes` is a function
+    cancel_at: float = math.inf   # seconds, on the server clock: the client withdraws the job
 
     @property
     def count(self) -> int:
@@ -65,6 +70,7 @@ class JobRecord:
     chunks: int = 0
     error: str = ""
     result: object = None
+    cancelled: bool = False    # withdrawn; released at the next chunk boundary
 
     @property
     def latency(self) -> float:
@@ -75,6 +81,7 @@ class JobRecord:
 class ServeStats:
     completed: list = field(default_factory=list)
     failed: list = field(default_factory=list)
+    cancelled: list = field(default_factory=list)
     evals: int = 0
     wall: float = 0.0
     peak_device_bytes: int = 0
@@ -88,7 +95,8 @@ class ServeStats:
 
     def summary(self) -> dict:
         lat = self.latencies()
-        out = {"jobs": len(self.completed), "failed": len(self.failed), "evals": self.evals,
+        out = {"jobs": len(self.completed), "failed": len(self.failed),
+               "cancelled": len(self.cancelled), "evals": self.evals,
                "wall_s": self.wall,
                "evals_per_s": self.evals / self.wall if self.wall > 0 else 0.0,
                "chunks": self.chunks, "max_queue": self.max_queue,
@@ -153,6 +161,39 @@ class Server:
             self.stats.peak_device_bytes = max(self.stats.peak_device_bytes, self.used_bytes)
             self.inflight.append(rec)
 
+    # -- cancellation ----------------------------------------------------
+    def cancel(self, job_id, now=None) -> bool:
+        """Withdraw a queued or admitted job; False if it is not (or no
+        longer) queued or in flight."""
+        if now is None:
+            now = self.clock() - (self._t0 if self._t0 is not None else 0.0)
+        for rec in self.queue:
+            if rec.spec.job_id == job_id:
+                self.queue.remove(rec)
+                rec.cancelled = True
+                rec.error = "cancelled"
+                rec.done = now
+                self.stats.cancelled.append(rec)
+                return True
+        for rec in self.inflight:
+            if rec.spec.job_id == job_id and not rec.cancelled:
+                rec.cancelled = True
+                self._drop_cancelled(now)
+                return True
+        return False
+
+    def _drop_cancelled(self, now):
+        """Release withdrawn jobs that no enqueued chunk carries any more."""
+        carried = {id(r) for _, plan, _ in self.pending for r, _, _ in plan}
+        for rec in [r for r in self.inflight if r.cancelled and id(r) not in carried]:
+            self.inflight.remove(rec)
+            self.used_individuals -= rec.spec.count
+            self.used_bytes -= rec.footprint
+            self.ex.release(rec.handle)
+            rec.error = "cancelled"
+            rec.done = now
+            self.stats.cancelled.append(rec)
+
     # -- chunks ----------------------------------------------------------
     def _planned_iters(self, rec):
         """Steps already enqueued for rec (done + in pending chunks)."""
@@ -161,6 +202,8 @@ class Server:
     def _launch_chunk(self):
         plan = []
         for rec in self.inflight:
+            if rec.cancelled:
+                continue
             planned = self._planned_iters(rec)
             remaining = rec.spec.iterations - planned
             finished_enqueued = any(r is rec and fin for _, p, _ in self.pending for r, _, fin in p)
@@ -214,7 +257,7 @@ class Server:
                 rec.iters_done += k
                 n = rec.spec.count
                 self.stats.evals += n * (k + (1 if final else 0))
-                if final:
+                if final and not rec.cancelled:
                     rec.done = now
                     rec.result = self.ex.result(rec.handle)
                     self.ex.release(rec.handle)
@@ -222,6 +265,7 @@ class Server:
                     self.used_individuals -= n
                     self.used_bytes -= rec.footprint
                     self.stats.completed.append(rec)
+        self._drop_cancelled(now)
         return progressed
 
     def _account(self, now):
@@ -248,6 +292,8 @@ class Server:
             while i < len(arrivals) and arrivals[i].arrival <= now and arrivals[i].arrival <= horizon:
                 self.submit(arrivals[i])
                 i += 1
+            for rec in [r for r in (*self.queue, *self.inflight) if r.spec.cancel_at <= now and not r.cancelled]:
+                self.cancel(rec.spec.job_id, now)
             self._retire(now)
             self._admit(now)
             self._account(now)

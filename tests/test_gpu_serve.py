@@ -46,3 +46,26 @@ def test_alone_equals_mixed(setup):
     summ = st.summary()
     print(f"\n[serve] {summ}", flush=True)
     assert summ["p99_s"] >= summ["p50_s"] > 0
+
+
+def test_cancelled_job_leaves_the_others_unchanged(setup):
+    """A long job withdrawn while its chunks run gets no final evaluation and
+    no result, its state is released, and every other job's result is bit for
+    bit that of a run without it."""
+    ex, specs = setup
+    base = specs[:3]
+    srv0 = serve.Server(ex, max_individuals=100_000, device_budget=1 << 30, chunk_iters=16)
+    ref = {r.spec.job_id: r.result for r in srv0.run(base).completed}
+    s = specs[3]
+    long = serve.JobSpec(s.job_id, s.ligand, s.grid_id, s.genotypes, 0.0, iterations=100_000,
+                         cancel_at=0.05)
+    srv = serve.Server(ex, max_individuals=100_000, device_budget=1 << 30, chunk_iters=16)
+    st = srv.run(list(base) + [long])
+    assert [r.spec.job_id for r in st.cancelled] == [s.job_id]
+    assert st.cancelled[0].result is None and st.cancelled[0].iters_done < long.iterations
+    assert len(st.completed) == 3 and not st.failed
+    for r in st.completed:
+        assert np.array_equal(r.result["best_energy"], ref[r.spec.job_id]["best_energy"])
+        assert np.array_equal(r.result["best_genotype"], ref[r.spec.job_id]["best_genotype"])
+    assert srv.used_bytes == 0 and srv.used_individuals == 0
+    print(f"\n[serve cancel] job {s.job_id} withdrawn after {st.cancelled[0].iters_done} steps", flush=True)

@@ -1,5 +1,6 @@
 """Serving loop logic on a simulated device (no GPU): continuous batching,
-admission by footprint, FIFO, per-job step accounting, failure handling."""
+admission by footprint, FIFO, per-job step accounting, failure handling,
+cancellation."""
 import numpy as np
 import pytest
 
@@ -157,3 +158,46 @@ def test_lazy_starting_points_and_progress_reports():
     assert res_e == res_l
     assert st_l.evals == st_e.evals
     assert reports and all(b > a for a, b in zip(reports, reports[1:]))
+
+
+def test_cancel_queued_job_never_runs():
+    """A job withdrawn while it waits for admission leaves the queue; the job
+    behind it moves up."""
+    fp = serve.state_bytes(1000, 17)
+    specs = [_spec(0, 1000, 0.0), _spec(1, 1000, 0.0), _spec(2, 1000, 0.0)]
+    specs[1].cancel_at = 1e-6
+    ex, srv, st = _run(specs, max_individuals=10_000, device_budget=fp, chunk_iters=100)
+    assert [r.spec.job_id for r in st.cancelled] == [1]
+    assert st.cancelled[0].result is None and st.cancelled[0].error == "cancelled"
+    assert all(j != 1 for c in ex.launched for j, _, _ in c)
+    assert sorted(r.spec.job_id for r in st.completed) == [0, 2]
+    assert srv.used_bytes == 0 and srv.used_individuals == 0
+    assert st.summary()["cancelled"] == 1
+
+
+def test_cancel_admitted_job_stops_at_a_chunk_boundary():
+    """A job withdrawn in flight gets no further chunk and no final
+    evaluation; its state is released once no enqueued chunk carries it, and
+    the other jobs' results are those of a run without it."""
+    kw = dict(max_individuals=10_000, device_budget=1 << 30, chunk_iters=50, spe=1e-7)
+    _, _, ref = _run([_spec(0, 500, 0.0), _spec(2, 500, 0.0)], **kw)
+    specs = [_spec(0, 500, 0.0), _spec(1, 500, 0.0), _spec(2, 500, 0.0)]
+    specs[1].cancel_at = 0.01          # chunks of the three jobs take 7.5 ms each
+    ex, srv, st = _run(specs, **kw)
+    steps = sum(k for c in ex.launched for j, k, _ in c if j == 1)
+    assert 0 < steps < 300
+    assert not any(fin for c in ex.launched for j, _, fin in c if j == 1)
+    assert [r.spec.job_id for r in st.cancelled] == [1] and st.cancelled[0].result is None
+    assert 1 not in ex.live and srv.used_bytes == 0 and srv.used_individuals == 0
+    assert sorted(r.spec.job_id for r in st.completed) == [0, 2]
+    want = {r.spec.job_id: r.result for r in ref.completed}
+    assert {r.spec.job_id: r.result for r in st.completed} == want
+
+
+def test_cancel_of_unknown_or_finished_job_is_refused():
+    ex = serve.FakeExecutor()
+    srv = serve.Server(ex, max_individuals=10_000, device_budget=1 << 30, clock=ex.clock)
+    assert not srv.cancel(5)
+    st = srv.run([_spec(0, 10, 0.0, iters=20)], poll=1e-3)
+    assert len(st.completed) == 1
+    assert not srv.cancel(0) and not st.cancelled
